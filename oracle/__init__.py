@@ -1,0 +1,278 @@
+"""FP64 CPU oracle for dense swept-surface evaluation -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, the smoke check and the bench's CPU-baseline leg may import
+this package.  The product library never does, and this package imports
+nothing from the product (it shares no code with the HIP path).
+
+NumPy front end over ``sweep_oracle.c`` (built with gcc by ``oracle.build``).
+Every array is float64; positions and normals come back as (3, n_u, n_v).
+
+Methods followed (the framing paper defines none; see ``sweep_oracle.c``):
+Cox-de Boor B-spline basis and derivatives; clamped uniform and periodic
+uniform knots; double-reflection rotation-minimizing frame (Wang, Juettler,
+Zheng & Liu 2008); surface X = C + [r s t] S with normal X_v x X_u; central
+finite-difference gradient of L = sum w . X.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+
+
+class _Curve(C.Structure):
+    _fields_ = [("n", C.c_int), ("p", C.c_int), ("closed", C.c_int),
+                ("ctrl", _dp), ("knots", _dp)]
+
+
+def lib():
+    """Load the oracle library, compiling it first if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.or_nbasis.restype = C.c_int
+        L.or_nknots.restype = C.c_int
+        L.or_knots.restype = None
+        L.or_param.restype = C.c_double
+        L.or_param.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int, C.c_int]
+        L.or_span.restype = C.c_int
+        L.or_span.argtypes = [_dp, C.c_int, C.c_int, C.c_double]
+        L.or_basis.restype = None
+        L.or_basis.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
+        L.or_curve_eval.restype = None
+        L.or_curve_eval.argtypes = [C.POINTER(_Curve), _dp, C.c_double, C.c_int, _dp]
+        L.or_curve_samples.restype = None
+        L.or_frame.restype = C.c_int
+        L.or_surface_rows.restype = None
+        L.or_sweep.restype = C.c_int
+        L.or_loss.restype = C.c_double
+        L.or_fd_grad.restype = None
+        L.or_fd_grad.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int,
+                                 _dp, _dp, C.c_double, _dp, _dp]
+        L.or_loss.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, _dp]
+        L.or_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Curve:
+    """A B-spline curve: ctrl (n, 3), degree p, closed (periodic uniform) or
+    open with clamped uniform knots (knots=None) or the given knot vector."""
+
+    def __init__(self, ctrl, degree: int, closed: bool = False, knots=None):
+        self.ctrl = _f64(ctrl).reshape(-1, 3)
+        self.degree = int(degree)
+        self.closed = bool(closed)
+        self.knots = None if knots is None else _f64(knots)
+        self._c = _Curve(self.ctrl.shape[0], self.degree, int(self.closed),
+                         _ptr(self.ctrl), _ptr(self.knots))
+
+    @classmethod
+    def of(cls, spec) -> "Curve":
+        """From any object with ctrl/degree/closed/knots attributes."""
+        if isinstance(spec, Curve):
+            return spec
+        return cls(spec.ctrl, spec.degree, spec.closed, getattr(spec, "knots", None))
+
+    @property
+    def n(self) -> int:
+        return self.ctrl.shape[0]
+
+    @property
+    def ref(self):
+        return C.byref(self._c)
+
+    def knot_vector(self) -> np.ndarray:
+        L = lib()
+        nk = L.or_nknots(self.n, self.degree, int(self.closed))
+        U = np.empty(nk)
+        L.or_knots(self.n, self.degree, int(self.closed), _ptr(self.knots), _ptr(U))
+        return U
+
+    def n_basis(self) -> int:
+        return lib().or_nbasis(self.n, self.degree, int(self.closed))
+
+    def param(self, i: int, ns: int) -> float:
+        U = self.knot_vector()
+        return lib().or_param(self.n, self.degree, int(self.closed), _ptr(U), int(i), int(ns))
+
+    def params(self, ns: int) -> np.ndarray:
+        U = self.knot_vector()
+        L = lib()
+        return np.array([L.or_param(self.n, self.degree, int(self.closed), _ptr(U), i, ns)
+                         for i in range(ns)])
+
+    def span(self, u: float) -> int:
+        U = self.knot_vector()
+        return lib().or_span(_ptr(U), self.n_basis(), self.degree, float(u))
+
+    def eval(self, u: float, nd: int = 2) -> np.ndarray:
+        """(nd+1, 3): C, C', C'' at parameter u."""
+        U = self.knot_vector()
+        out = np.empty(9)
+        lib().or_curve_eval(self.ref, _ptr(U), float(u), int(nd), _ptr(out))
+        return out[: 3 * (nd + 1)].reshape(nd + 1, 3)
+
+    def samples(self, ns: int, nd: int = 2) -> Tuple[np.ndarray, ...]:
+        """Sampled points and derivatives at the ns sample parameters."""
+        pts = np.empty((ns, 3))
+        d1 = np.empty((ns, 3)) if nd >= 1 else None
+        d2 = np.empty((ns, 3)) if nd >= 2 else None
+        lib().or_curve_samples(self.ref, C.c_int(ns), _ptr(pts), _ptr(d1), _ptr(d2))
+        return tuple(a for a in (pts, d1, d2) if a is not None)
+
+
+def basis(U, p: int, span: int, u: float, nd: int = 2) -> np.ndarray:
+    """(nd+1, p+1): D^d N_{span-p+j, p}(u)."""
+    U = _f64(U)
+    out = np.empty(3 * (p + 1))
+    lib().or_basis(_ptr(U), int(p), int(span), float(u), int(nd), _ptr(out))
+    return out[: (nd + 1) * (p + 1)].reshape(nd + 1, p + 1)
+
+
+def frame(x, d1, fallback_t=None, n0=None, reorth: bool = True):
+    """Sample-level frame: returns (R (n_u, 3, 3) with columns r, s, t,
+    number of tangent-reversal fallbacks)."""
+    x, d1 = _f64(x), _f64(d1)
+    nu = x.shape[0]
+    R = np.empty((nu, 9))
+    ft = None if fallback_t is None else _f64(fallback_t)
+    n0a = None if n0 is None else _f64(n0)
+    nf = lib().or_frame(C.c_int(nu), _ptr(x), _ptr(d1), _ptr(ft), _ptr(n0a), C.c_int(int(reorth)), _ptr(R))
+    return R.reshape(nu, 3, 3).transpose(0, 2, 1).copy(), nf
+
+
+def surface_from_samples(x, d1, d2, R, S, dS, want_kappa: bool = True):
+    """Sample-level surface: R (n_u, 3, 3) columns r, s, t.  Returns
+    (pos (3,nu,nv), nrm (3,nu,nv), kappa (nu,nv))."""
+    x, d1, d2 = _f64(x), _f64(d1), _f64(d2)
+    S, dS = _f64(S), _f64(dS)
+    nu, nv = x.shape[0], S.shape[0]
+    Rr = _f64(np.asarray(R).transpose(0, 2, 1).reshape(nu, 9))
+    pos = np.empty((3, nu, nv))
+    nrm = np.empty((3, nu, nv))
+    kap = np.empty((nu, nv)) if want_kappa else None
+    lib().or_surface_rows(C.c_int(nu), C.c_int(nv), C.c_int(0), C.c_int(nu), _ptr(x), _ptr(d1), _ptr(d2),
+                          _ptr(Rr), _ptr(S), _ptr(dS), _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
+    return pos, nrm, kap
+
+
+def sweep_from_samples(x, d1, d2, S, dS, n0=None, fallback_t=None, reorth: bool = True):
+    """Frame + surface from analytic samples (used for closed-form pins)."""
+    R, nf = frame(x, d1, fallback_t, n0, reorth)
+    pos, nrm, kap = surface_from_samples(x, d1, d2, R, S, dS)
+    return pos, nrm, kap, R
+
+
+class SweepResult:
+    def __init__(self, pos, nrm, kappa, frame, n_fallback, rows):
+        self.pos, self.nrm, self.kappa, self.frame = pos, nrm, kappa, frame
+        self.n_fallback, self.rows = n_fallback, rows
+
+
+def sweep(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True,
+          rows: Optional[Tuple[int, int]] = None, want_pos=True, want_nrm=True,
+          want_kappa=True) -> SweepResult:
+    """Whole sweep O1-O8.  pos/nrm are (3, n_u, n_v) over the full grid but
+    only rows [rows[0], rows[1]) are filled when ``rows`` is given (the rest
+    is left uninitialised).  frame is (n_u, 3, 3) with columns r, s, t."""
+    P, Q = Curve.of(path), Curve.of(profile)
+    r0, r1 = (0, n_u) if rows is None else rows
+    pos = np.empty((3, n_u, n_v)) if want_pos else None
+    nrm = np.empty((3, n_u, n_v)) if want_nrm else None
+    kap = np.empty((n_u, n_v)) if want_kappa else None
+    R = np.empty((n_u, 9))
+    n0a = None if n0 is None else _f64(n0)
+    nf = lib().or_sweep(P.ref, Q.ref, C.c_int(n_u), C.c_int(n_v), _ptr(n0a), C.c_int(int(reorth)),
+                        C.c_int(r0), C.c_int(r1), _ptr(pos), _ptr(nrm), _ptr(kap), _ptr(R))
+    if nf < 0:
+        raise ValueError("oracle: bad sweep input")
+    return SweepResult(pos, nrm, kap, R.reshape(n_u, 3, 3).transpose(0, 2, 1).copy(), nf, (r0, r1))
+
+
+def path_samples(path, n_u: int):
+    """(x, C', C'', fallback tangent) of the path at the n_u u-samples."""
+    P = Curve.of(path)
+    x, d1, d2 = (np.empty((n_u, 3)) for _ in range(3))
+    ft = np.empty(3)
+    lib().or_path_samples(P.ref, C.c_int(n_u), _ptr(x), _ptr(d1), _ptr(d2), _ptr(ft))
+    return x, d1, d2, ft
+
+
+def profile_samples(profile, n_v: int):
+    """(S, S') of the profile at the n_v v-samples."""
+    return Curve.of(profile).samples(n_v, nd=1)
+
+
+def loss(path, profile, n_u: int, n_v: int, w, n0=None) -> float:
+    """L = sum w . X, w shaped (3, n_u, n_v)."""
+    P, Q = Curve.of(path), Curve.of(profile)
+    w = _f64(w)
+    assert w.shape == (3, n_u, n_v)
+    n0a = None if n0 is None else _f64(n0)
+    return lib().or_loss(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w))
+
+
+def fd_grad(path, profile, n_u: int, n_v: int, w, h: float = 1e-6, n0=None,
+            want_path=True, want_profile=True):
+    """Central-difference gradient of L = sum w . X with respect to the path
+    and profile control points: (gP (n_path, 3), gQ (n_prof, 3))."""
+    P, Q = Curve.of(path), Curve.of(profile)
+    w = _f64(w)
+    assert w.shape == (3, n_u, n_v)
+    gP = np.zeros((P.n, 3)) if want_path else None
+    gQ = np.zeros((Q.n, 3)) if want_profile else None
+    n0a = None if n0 is None else _f64(n0)
+    lib().or_fd_grad(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w), float(h), _ptr(gP), _ptr(gQ))
+    return gP, gQ
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()
+
+
+# ------------------------------------------------------------ parity metrics
+
+def bbox_diag(pos: np.ndarray) -> float:
+    """Diagonal of the axis-aligned bounding box of positions (3, ...)."""
+    p = pos.reshape(3, -1)
+    return float(np.linalg.norm(p.max(axis=1) - p.min(axis=1)))
+
+
+def compare(pos_ref, nrm_ref, kappa_ref, pos, nrm, diag: float, kappa_max: float):
+    """Parity figures of a result against the oracle on the same vertices:
+    position error relative to the bounding-box diagonal (all vertices),
+    normal error scaled by max(1, kappa) on vertices with kappa <= kappa_max,
+    and the count of masked vertices."""
+    dpos = np.abs(np.asarray(pos, np.float64) - pos_ref).max() / diag
+    out = {"pos_rel": float(dpos)}
+    if nrm is not None:
+        mask = np.isfinite(kappa_ref) & (kappa_ref <= kappa_max)
+        dn = np.linalg.norm(np.asarray(nrm, np.float64) - nrm_ref, axis=0)
+        scaled = dn / np.maximum(1.0, np.where(mask, kappa_ref, 1.0))
+        out["nrm_scaled"] = float(scaled[mask].max()) if mask.any() else 0.0
+        out["nrm_abs"] = float(dn[mask].max()) if mask.any() else 0.0
+        out["masked"] = int((~mask).sum())
+    return out
