@@ -1,0 +1,211 @@
+/*
+ * sweep.h -- C ABI of libsweep, dense evaluation of swept surfaces on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A profile curve S(v) is swept along a path curve C(u); both are B-splines
+ * given by control points, a knot vector (or the clamped / periodic uniform
+ * default) and a degree, and the caller asks for n_u x n_v samples.  For
+ * every (u_i, v_j) the library writes the vertex position
+ *     X_ij = C(u_i) + S_x(v_j) r_i + S_y(v_j) s_i + S_z(v_j) t_i
+ * and the unit normal N_ij = (X_v x X_u)/|X_v x X_u|, where (r_i, s_i, t_i) is
+ * the rotation-minimizing frame of the path at u_i computed by the
+ * double-reflection method (Wang, Juettler, Zheng & Liu, ACM TOG 27(1), 2008)
+ * as a parallel prefix product of 3x3 rotations.
+ *
+ * The framing paper (arXiv 1110.5450) only introduces the notation: a path C,
+ * a profile S and the tangent / normal / binormal of a curve.  It defines no
+ * sweep, frame or B-spline evaluation; every operation below follows the
+ * published method named at its entry point.
+ *
+ * Definitions (shared with the library's FP64 reference):
+ *   knots   open curves: clamped uniform U = (0^{p+1}, 1/(n-p), ...,
+ *           (n-p-1)/(n-p), 1^{p+1}) when no knots are given, else the given
+ *           vector (non-decreasing, finite, interior multiplicity <= p,
+ *           end multiplicity <= p+1); closed curves: periodic uniform
+ *           U_k = k over the control polygon wrapped by p points.
+ *   samples open: u_i = U_p + (U_n - U_p) * (i/(n_s-1)), both ends included;
+ *           closed: t_j = p + (m*j)/n_s, the seam not repeated.
+ *   span    U_k <= u < U_{k+1}; the last span at the right end of the domain.
+ *   tangent t_i = C'(u_i)/|C'(u_i)|; where C'(u_i) = 0 the previous sample's
+ *           tangent; at i = 0 the first nonzero control-polygon leg.
+ *   r_0     the given initial normal projected onto the plane normal to t_0
+ *           (if it is not parallel to t_0), else e_a projected, a = argmin |t_0[a]|
+ *           (ties to the smaller index); s_i = t_i x r_i.
+ *   step    M_i = H2 H1, H1 the reflection swapping x_i, x_{i+1}, H2 the one
+ *           then taking H1 t_i to t_{i+1}; when |t_{i+1} - H1 t_i|^2 <= 1e-24
+ *           (tangent reversal) the smallest rotation taking t_i to t_{i+1}
+ *           (rotation by pi about the axis-rule direction of t_i if they are
+ *           opposite); r_{i+1} = M_i r_i, re-projected and normalised.
+ *   normal  X_v = R S'(v), X_u = (|C'| - S_x a - S_y b) t + S_z t', with
+ *           a = r.C''/|C'|, b = s.C''/|C'|, t' = (C'' - (C''.t) t)/|C'| (the
+ *           derivative of the continuous rotation-minimizing frame);
+ *           N = 0 where the cross product is 0 or not finite.
+ *
+ * Memory: every buffer is allocated and owned by the caller.  Control points
+ * and outputs are DEVICE pointers; knot vectors, counts and options are HOST
+ * memory read before the call returns.  Positions and normals are written as
+ * structure-of-arrays planes: element (c, i, j) of a sweep with N = n_u*n_v
+ * vertices is at [c*N + i*n_v + j], c = x, y, z, in the output precision.
+ * The batched call concatenates these blocks: sweep k's block starts at
+ * element 3*off_k with off_k = sum_{k'<k} n_u[k']*n_v[k'].
+ *
+ * Streams and errors: work is enqueued on the given stream (a hipStream_t,
+ * NULL for the default stream) and the call returns without waiting for it.
+ * Metadata is validated on the host before anything is enqueued; a non-OK
+ * status means nothing was enqueued (except SWEEP_ERR_HIP, which reports a
+ * failed launch).  Faults inside kernels surface at the caller's next
+ * synchronisation.  sweep_last_error() returns a thread-local message for the
+ * last non-OK status.  No call aborts or exits the process.
+ */
+#ifndef SWEEP_H
+#define SWEEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWEEP_VERSION 100  /* major*100 + minor */
+#define SWEEP_MAX_DEGREE 7
+
+typedef enum {
+    SWEEP_OK = 0,
+    SWEEP_ERR_NULL_ARG = -1,      /* a required pointer is NULL */
+    SWEEP_ERR_BAD_COUNT = -2,     /* n_ctrl < degree+1, or sizes overflow */
+    SWEEP_ERR_BAD_DEGREE = -3,    /* degree outside 1..SWEEP_MAX_DEGREE */
+    SWEEP_ERR_BAD_KNOTS = -4,     /* wrong ordering, NaN, bad multiplicity */
+    SWEEP_ERR_BAD_GRID = -5,      /* n_u < 2, n_v < 3, or n_u*n_v >= 2^31 */
+    SWEEP_ERR_BAD_PRECISION = -6, /* precision not SWEEP_F32 / SWEEP_F64 */
+    SWEEP_ERR_WORKSPACE = -7,     /* workspace NULL or smaller than required */
+    SWEEP_ERR_UNSUPPORTED = -8,   /* valid but not implemented (e.g. closed path) */
+    SWEEP_ERR_HIP = -9,           /* a HIP runtime call or launch failed */
+    SWEEP_ERR_BAD_OPTION = -10    /* an option field out of range */
+} sweep_status;
+
+typedef enum { SWEEP_F32 = 0, SWEEP_F64 = 1 } sweep_precision;
+
+/* A B-spline curve. */
+typedef struct {
+    int32_t n_ctrl;      /* control points (for a closed curve: the m distinct ones) */
+    int32_t degree;      /* 1..SWEEP_MAX_DEGREE */
+    int32_t closed;      /* 0 open, 1 closed periodic uniform (profiles only) */
+    int32_t reserved;
+    const double *ctrl;  /* DEVICE, n_ctrl x 3 FP64, row-major (x, y, z) */
+    const double *knots; /* HOST, n_ctrl+degree+1 FP64, or NULL for the default
+                            knots; must be NULL for a closed curve */
+} sweep_curve;
+
+/* Options; sweep_default_options() fills the defaults noted here. */
+typedef struct {
+    int32_t out_precision;    /* SWEEP_F32 (default) or SWEEP_F64: type of pos/nrm */
+    int32_t frame_precision;  /* SWEEP_F64 (default) or SWEEP_F32: precision of the
+                                 step matrices, the frame scan and re-orthonormalisation */
+    int32_t reorthonormalize; /* 1 (default): r_i projected onto t_i^perp and
+                                 normalised, s_i = t_i x r_i; 0: r_i = P_i r_0 raw
+                                 (precision study) */
+    int32_t has_initial_normal;  /* 0 (default): axis rule; 1: use initial_normal */
+    double initial_normal[3];
+    int32_t tile_config;      /* -1 (default): tuned/automatic; >= 0 a fixed
+                                 surface-kernel configuration (sweep_tile_config_count) */
+    int32_t reserved;
+} sweep_options;
+
+/* A batch of independent sweeps.  Per-sweep arrays are HOST memory with
+ * n_sweeps entries; control points of all paths (profiles) are packed in one
+ * DEVICE buffer, sweep k's starting at point offset sum_{k'<k} path_n[k'].
+ * Knot vectors, if given, are concatenated per sweep in HOST memory. */
+typedef struct {
+    int32_t n_sweeps;
+    int32_t reserved;
+    const int32_t *path_n;       /* control points per path */
+    const int32_t *path_degree;
+    const int32_t *prof_n;       /* control points per profile */
+    const int32_t *prof_degree;
+    const int32_t *prof_closed;  /* NULL: every profile closed */
+    const int32_t *n_u;
+    const int32_t *n_v;
+    const double *path_knots;    /* NULL: clamped uniform; else path_n[k]+path_degree[k]+1 per sweep */
+    const double *prof_knots;    /* NULL: default; else one vector per OPEN profile, in sweep order */
+    const double *path_ctrl;     /* DEVICE, sum(path_n) x 3 FP64 */
+    const double *prof_ctrl;     /* DEVICE, sum(prof_n) x 3 FP64 */
+} sweep_batch;
+
+void sweep_default_options(sweep_options *opt);
+
+/*
+ * Evaluate one sweep: positions (and normals if nrm != NULL) on the
+ * n_u x n_v grid.  pos/nrm: DEVICE, 3*n_u*n_v elements of the output
+ * precision.  workspace: DEVICE, at least sweep_eval_workspace_size() bytes,
+ * 256-byte aligned; it holds knots, curve samples, step-matrix carries, the
+ * per-row frame table and the profile table, and may be reused once the
+ * stream has passed this call.  With user knots the knot copy to the device
+ * is a blocking copy from pageable memory.
+ */
+sweep_status sweep_eval(const sweep_curve *path, const sweep_curve *profile,
+                        int32_t n_u, int32_t n_v, const sweep_options *opt,
+                        void *pos, void *nrm, void *workspace, size_t ws_bytes,
+                        void *stream);
+size_t sweep_eval_workspace_size(const sweep_curve *path, const sweep_curve *profile,
+                                 int32_t n_u, int32_t n_v, const sweep_options *opt);
+
+/*
+ * Evaluate a batch of independent sweeps in one frame launch and one
+ * persistent surface launch, replayed from a HIP graph.  The first call with
+ * a new batch shape (all per-sweep host arrays, knots and options) validates
+ * it, uploads per-sweep descriptors with a blocking copy, picks the surface
+ * schedule and builds the graph; later calls with the same shape only update
+ * the graph's pointer arguments and launch it.  Sweep k's output equals
+ * sweep_eval's for that sweep (same kernels, same arithmetic).
+ * pos/nrm: DEVICE, 3*sum(n_u*n_v) elements.
+ */
+sweep_status sweep_eval_batched(const sweep_batch *batch, const sweep_options *opt,
+                                void *pos, void *nrm, void *workspace, size_t ws_bytes,
+                                void *stream);
+size_t sweep_batched_workspace_size(const sweep_batch *batch, const sweep_options *opt);
+
+/*
+ * Adjoint of the positions: given grad_pos = dL/dpos (DEVICE, same layout and
+ * precision as the batched pos output), accumulate nothing but WRITE
+ * grad_path_ctrl (DEVICE, sum(path_n) x 3 FP64) and grad_prof_ctrl (DEVICE,
+ * sum(prof_n) x 3 FP64), the gradients of L with respect to the control
+ * points.  The frame is recomputed in FP64; reductions accumulate in FP64 in
+ * a fixed order (deterministic).  Gradients through normals are not provided.
+ * At tangent reversals the step rotation is treated as locally constant.
+ */
+sweep_status sweep_backward(const sweep_batch *batch, const sweep_options *opt,
+                            const void *grad_pos, double *grad_path_ctrl,
+                            double *grad_prof_ctrl, void *workspace, size_t ws_bytes,
+                            void *stream);
+size_t sweep_backward_workspace_size(const sweep_batch *batch, const sweep_options *opt);
+
+/*
+ * Launch timing for profiling.  sweep_trace_enable(n), n > 0, makes the next
+ * n sweep_eval calls record HIP events on their stream around the frame
+ * stage (knots, curve samples, profile table, frame scan) and the surface
+ * stage; n = 0 stops recording.  sweep_trace_read waits for the recorded
+ * events, writes up to max (stage, milliseconds) pairs -- stage 0 frame,
+ * stage 1 surface -- in call order, clears the record and returns the number
+ * written (or a negative status).  Events are created by the enable call, so
+ * enable outside any graph capture.
+ */
+sweep_status sweep_trace_enable(int32_t max_calls);
+int32_t sweep_trace_read(int32_t *stage, float *ms, int32_t max);
+
+/* Number of fixed surface-kernel configurations accepted in tile_config. */
+int32_t sweep_tile_config_count(void);
+
+/* Thread-local text describing the last non-OK status on this thread. */
+const char *sweep_last_error(void);
+
+int32_t sweep_version(void);
+
+/* Free cached batch plans and HIP graphs (library-owned device memory). */
+void sweep_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEEP_H */

@@ -212,6 +212,18 @@ def sweep(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True,
     return SweepResult(pos, nrm, kap, R.reshape(n_u, 3, 3).transpose(0, 2, 1).copy(), nf, (r0, r1))
 
 
+def sweep_rows(path, profile, n_u: int, n_v: int, rows, n0=None, reorth: bool = True):
+    """Frame over all n_u samples, surface only on the listed rows.
+    Returns (pos (3, len(rows), n_v), nrm, kappa (len(rows), n_v), frame
+    (n_u, 3, 3))."""
+    rows = np.asarray(rows, dtype=np.int64)
+    x, d1, d2, ft = path_samples(path, n_u)
+    S, dS = profile_samples(profile, n_v)
+    R, _ = frame(x, d1, ft, n0, reorth)
+    pos, nrm, kap = surface_from_samples(x[rows], d1[rows], d2[rows], R[rows], S, dS)
+    return pos, nrm, kap, R
+
+
 def path_samples(path, n_u: int):
     """(x, C', C'', fallback tangent) of the path at the n_u u-samples."""
     P = Curve.of(path)

@@ -1,0 +1,314 @@
+// device_math.hpp -- small vector/matrix types and the B-spline evaluation
+// used by the sweep kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sweep {
+
+constexpr int kBlock = 256;   // threads per block in every kernel
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxDeg = 7;
+
+template <class F> struct V3 { F x, y, z; };
+
+template <class F> __device__ __forceinline__ V3<F> mk(F x, F y, F z) { return V3<F>{x, y, z}; }
+template <class F> __device__ __forceinline__ V3<F> operator+(V3<F> a, V3<F> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class F> __device__ __forceinline__ V3<F> operator-(V3<F> a, V3<F> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class F> __device__ __forceinline__ V3<F> operator*(F s, V3<F> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class F> __device__ __forceinline__ F dot(V3<F> a, V3<F> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class F> __device__ __forceinline__ V3<F> cross(V3<F> a, V3<F> b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class F> __device__ __forceinline__ V3<F> divs(V3<F> a, F s) { return {a.x / s, a.y / s, a.z / s}; }
+template <class G, class F> __device__ __forceinline__ V3<G> cvt(V3<F> a) { return {(G)a.x, (G)a.y, (G)a.z}; }
+
+// 3x3 matrix, row-major.
+template <class F> struct M3 { F m[9]; };
+
+template <class F> __device__ __forceinline__ M3<F> ident()
+{
+    M3<F> r;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r.m[k] = (k % 4 == 0) ? F(1) : F(0);
+    return r;
+}
+// a * b
+template <class F> __device__ __forceinline__ M3<F> mul(const M3<F>& a, const M3<F>& b)
+{
+    M3<F> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.m[3 * i + j] = a.m[3 * i] * b.m[j] + a.m[3 * i + 1] * b.m[3 + j] + a.m[3 * i + 2] * b.m[6 + j];
+    return r;
+}
+template <class F> __device__ __forceinline__ V3<F> apply(const M3<F>& a, V3<F> v)
+{
+    return {a.m[0] * v.x + a.m[1] * v.y + a.m[2] * v.z,
+            a.m[3] * v.x + a.m[4] * v.y + a.m[5] * v.z,
+            a.m[6] * v.x + a.m[7] * v.y + a.m[8] * v.z};
+}
+
+// ------------------------------------------------------------------ curves
+
+struct DCurve {
+    const double* __restrict__ ctrl;   // n x 3
+    const double* __restrict__ knots;  // nb + p + 1
+    int n;       // distinct control points
+    int p;       // degree
+    int closed;  // periodic uniform
+    int nb;      // basis functions: n (open) or n + p (closed)
+};
+
+__device__ __forceinline__ V3<double> ctrl_pt(const DCurve& c, int k)
+{
+    const int kk = (c.closed && k >= c.n) ? k - c.n : k;
+    const double* q = c.ctrl + 3 * (size_t)kk;
+    return {q[0], q[1], q[2]};
+}
+
+// Sample parameter i of ns.  Open: u = a + (b - a) * (i / (ns - 1)), with the
+// last sample exactly b; closed: p + (n*i)/ns.  Each operation is rounded as
+// written (no contraction), so samples that fall on a knot land on it exactly.
+__device__ __forceinline__ double sample_param(const DCurve& c, int i, int ns)
+{
+#pragma clang fp contract(off)
+    if (c.closed) return (double)c.p + (double)((long long)c.n * (long long)i) / (double)ns;
+    const double a = c.knots[c.p], b = c.knots[c.n];
+    if (i == ns - 1) return b;
+    const double f = (double)i / (double)(ns - 1);
+    const double w = b - a;
+    const double g = w * f;
+    return a + g;
+}
+
+// Largest k in [p, nb-1] with U_k <= u; nb-1 when u >= U_nb.
+__device__ __forceinline__ int find_span(const double* __restrict__ U, int nb, int p, double u)
+{
+    if (u >= U[nb]) return nb - 1;
+    int lo = p, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (U[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// C and derivatives up to order ND at u for a degree-P B-spline.
+// Basis values of degrees P, P-1, P-2 come from one triangular sweep of the
+// Cox-de Boor recursion (one division per knot interval and degree);
+// derivatives use the derivative control nets
+//   Q_k = P (P_{k+1} - P_k) / (U_{k+P+1} - U_{k+1}),
+//   R_k = (P-1)(Q_{k+1} - Q_k) / (U_{k+P+1} - U_{k+2}),
+// whose denominators are positive on a non-empty span.
+template <int P, int ND>
+__device__ __forceinline__ void curve_derivs(const DCurve& c, double u, V3<double>* out)
+{
+    const double* __restrict__ U = c.knots;
+    const int s = find_span(U, c.nb, P, u);
+    double B[P + 1];
+    double D1[P > 0 ? P : 1];
+    double D2[P > 1 ? P - 1 : 1];
+    B[0] = 1.0;
+    if (P - 1 == 0) D1[0] = 1.0;
+    if (P - 2 == 0) D2[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= P; ++q) {
+        // B holds N_{s-q+1+j, q-1}, j = 0..q-1; build N_{s-q+j, q}, j = 0..q.
+        double nb_[P + 1];
+        double carry = 0.0;
+#pragma unroll
+        for (int j = 0; j < q; ++j) {
+            const double lo = U[s - q + j + 1], hi = U[s + j + 1];
+            const double tmp = B[j] / (hi - lo);
+            nb_[j] = carry + (hi - u) * tmp;
+            carry = (u - lo) * tmp;
+        }
+        nb_[q] = carry;
+#pragma unroll
+        for (int j = 0; j <= q; ++j) B[j] = nb_[j];
+        if (q == P - 1) {
+#pragma unroll
+            for (int j = 0; j <= q; ++j) D1[j] = B[j];
+        }
+        if (q == P - 2) {
+#pragma unroll
+            for (int j = 0; j <= q; ++j) D2[j] = B[j];
+        }
+    }
+    V3<double> Pt[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) Pt[j] = ctrl_pt(c, s - P + j);
+    V3<double> C0 = mk(0.0, 0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j <= P; ++j) C0 = C0 + B[j] * Pt[j];
+    out[0] = C0;
+    if (ND >= 1) {
+        V3<double> Q1[P > 0 ? P : 1];
+#pragma unroll
+        for (int j = 0; j < P; ++j) Q1[j] = ((double)P / (U[s + j + 1] - U[s - P + j + 1])) * (Pt[j + 1] - Pt[j]);
+        V3<double> C1 = mk(0.0, 0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < P; ++j) C1 = C1 + D1[j] * Q1[j];
+        out[1] = C1;
+        if (ND >= 2) {
+            V3<double> C2 = mk(0.0, 0.0, 0.0);
+            if (P >= 2) {
+#pragma unroll
+                for (int j = 0; j + 1 < P; ++j) {
+                    const V3<double> R = ((double)(P - 1) / (U[s + j + 1] - U[s - P + j + 2])) * (Q1[j + 1] - Q1[j]);
+                    C2 = C2 + D2[j] * R;
+                }
+            }
+            out[2] = C2;
+        }
+    }
+}
+
+template <int ND>
+__device__ __noinline__ void curve_eval(const DCurve& c, double u, V3<double>* out)
+{
+    switch (c.p) {
+    case 1: curve_derivs<1, ND>(c, u, out); break;
+    case 2: curve_derivs<2, ND>(c, u, out); break;
+    case 3: curve_derivs<3, ND>(c, u, out); break;
+    case 4: curve_derivs<4, ND>(c, u, out); break;
+    case 5: curve_derivs<5, ND>(c, u, out); break;
+    case 6: curve_derivs<6, ND>(c, u, out); break;
+    default: curve_derivs<7, ND>(c, u, out); break;
+    }
+}
+
+// ----------------------------------------------------------- frame steps
+
+// Axis-rule unit vector: e_a with a = argmin |t[a]| (ties to the smaller
+// index), projected onto the plane normal to t and normalised.
+template <class F>
+__device__ __forceinline__ V3<F> axis_normal(V3<F> t)
+{
+    const F ax = fabs(t.x), ay = fabs(t.y), az = fabs(t.z);
+    int a = 0;
+    F best = ax;
+    if (ay < best) { a = 1; best = ay; }
+    if (az < best) { a = 2; }
+    const F ta = a == 0 ? t.x : (a == 1 ? t.y : t.z);
+    V3<F> q = mk(-ta * t.x, -ta * t.y, -ta * t.z);
+    if (a == 0) q.x += F(1); else if (a == 1) q.y += F(1); else q.z += F(1);
+    const F L = sqrt(dot(q, q));
+    return divs(q, L);
+}
+
+// Step rotation M_i of the double-reflection method: H1 reflects across the
+// bisector plane of the chord v1 = x_{i+1} - x_i, H2 across the plane normal
+// to v2 = t_{i+1} - H1 t_i; M = H2 H1.  A zero chord uses v1 = t_i.  When
+// |v2|^2 <= 1e-24 the smallest rotation taking t_i to t_{i+1} is used
+// (rotation by pi about the axis-rule direction for opposite tangents).
+// Returns 1 when that fallback was taken.
+template <class F>
+__device__ __forceinline__ int step_matrix(V3<F> v1, V3<F> ti, V3<F> tn, M3<F>& M)
+{
+    F c1 = dot(v1, v1);
+    if (c1 == F(0)) { v1 = ti; c1 = dot(v1, v1); }
+    const F b1 = F(2) / c1;
+    const V3<F> tL = ti - (b1 * dot(v1, ti)) * v1;
+    const V3<F> v2 = tn - tL;
+    const F c2 = dot(v2, v2);
+    if (c2 > F(1e-24)) {
+        const F b2 = F(2) / c2;
+        const F g = b1 * b2 * dot(v1, v2);
+        const F a1[3] = {v1.x, v1.y, v1.z}, a2[3] = {v2.x, v2.y, v2.z};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                M.m[3 * r + q] = (r == q ? F(1) : F(0)) - b1 * a1[r] * a1[q] - b2 * a2[r] * a2[q] + g * a2[r] * a1[q];
+        return 0;
+    }
+    const V3<F> k = cross(ti, tn);
+    const F kk = dot(k, k), c = dot(ti, tn);
+    if (kk > F(0)) {
+        const F f = (F(1) - c) / kk;
+        M.m[0] = c + f * k.x * k.x;  M.m[1] = -k.z + f * k.x * k.y; M.m[2] = k.y + f * k.x * k.z;
+        M.m[3] = k.z + f * k.y * k.x; M.m[4] = c + f * k.y * k.y;  M.m[5] = -k.x + f * k.y * k.z;
+        M.m[6] = -k.y + f * k.z * k.x; M.m[7] = k.x + f * k.z * k.y; M.m[8] = c + f * k.z * k.z;
+    } else if (c > F(0)) {
+        M = ident<F>();
+    } else {
+        const V3<F> a = axis_normal(ti);
+        const F aa[3] = {a.x, a.y, a.z};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) M.m[3 * r + q] = F(2) * aa[r] * aa[q] - (r == q ? F(1) : F(0));
+    }
+    return 1;
+}
+
+// --------------------------------------------------------- wave/block scans
+
+template <class F>
+__device__ __forceinline__ M3<F> shfl_up_m3(const M3<F>& a, int d)
+{
+    M3<F> r;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r.m[k] = __shfl_up(a.m[k], d, 64);
+    return r;
+}
+
+// Ordered product over the block, earliest element at thread 0, later
+// elements multiplied on the left.  Returns thread t's exclusive prefix
+// x_{t-1} ... x_0 (identity for t = 0) and the block total in `total`.
+// `lds` holds kWaves matrices.  Contains __syncthreads (call from all threads).
+template <class F>
+__device__ M3<F> block_exclusive_product(M3<F> x, M3<F>* lds, M3<F>& total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    M3<F> inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const M3<F> o = shfl_up_m3(inc, d);
+        if (lane >= d) inc = mul(inc, o);
+    }
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    M3<F> wave_prefix = ident<F>();
+    for (int k = 0; k < w; ++k) wave_prefix = mul(lds[k], wave_prefix);
+    M3<F> tot = ident<F>();
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) tot = mul(lds[k], tot);
+    M3<F> exc = shfl_up_m3(inc, 1);
+    if (lane == 0) exc = ident<F>();
+    total = tot;
+    __syncthreads();
+    return mul(exc, wave_prefix);
+}
+
+// Exclusive max-scan of ints over the block (identity -1); block max in `total`.
+__device__ __forceinline__ int block_exclusive_max(int x, int* lds, int& total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc = max(inc, o);
+    }
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    int wp = -1, tot = -1;
+    for (int k = 0; k < kWaves; ++k) {
+        if (k < w) wp = max(wp, lds[k]);
+        tot = max(tot, lds[k]);
+    }
+    int exc = __shfl_up(inc, 1, 64);
+    if (lane == 0) exc = -1;
+    total = tot;
+    __syncthreads();
+    return max(exc, wp);
+}
+
+}  // namespace sweep

@@ -1,0 +1,338 @@
+// sweep_abi.hip -- the C ABI declared in include/sweep.h: host-side
+// validation, workspace layout and stream-ordered launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/sweep.h"
+#include "abi_internal.hpp"
+#include "kernels.hpp"
+
+namespace sweep {
+
+static thread_local std::string g_last_error;
+
+sweep_status fail(sweep_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+sweep_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(SWEEP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------------- trace
+
+struct TraceState {
+    int capacity = 0;   // calls still to record
+    int used = 0;       // events in use
+    hipEvent_t ev[3 * 4096];
+    int calls = 0;
+};
+static TraceState g_trace;
+
+static bool trace_active() { return g_trace.capacity > 0; }
+
+// Records event k of the current call (k = 0 start, 1 frame done, 2 surface done).
+static void trace_mark(int k, hipStream_t st)
+{
+    if (!trace_active()) return;
+    const int idx = 3 * g_trace.calls + k;
+    hipEventRecord(g_trace.ev[idx], st);
+    if (k == 2) {
+        ++g_trace.calls;
+        --g_trace.capacity;
+    }
+}
+
+// ---------------------------------------------------------------- checks
+
+sweep_status check_curve_meta(int n, int p, int closed, const double* knots, const char* what, bool is_path)
+{
+    if (p < 1 || p > SWEEP_MAX_DEGREE) return fail(SWEEP_ERR_BAD_DEGREE, "%s: degree %d outside 1..%d", what, p, SWEEP_MAX_DEGREE);
+    if (closed != 0 && closed != 1) return fail(SWEEP_ERR_BAD_OPTION, "%s: closed flag %d is not 0/1", what, closed);
+    if (closed && is_path) return fail(SWEEP_ERR_UNSUPPORTED, "%s: closed paths are not supported", what);
+    if (n < p + 1) return fail(SWEEP_ERR_BAD_COUNT, "%s: %d control points for degree %d (need >= %d)", what, n, p, p + 1);
+    if (n > (1 << 24)) return fail(SWEEP_ERR_BAD_COUNT, "%s: %d control points (max 2^24)", what, n);
+    if (closed && knots) return fail(SWEEP_ERR_UNSUPPORTED, "%s: knots must be NULL for a closed curve", what);
+    if (knots) {
+        const int nk = n + p + 1;
+        for (int k = 0; k < nk; ++k) {
+            if (!std::isfinite(knots[k])) return fail(SWEEP_ERR_BAD_KNOTS, "%s: knot %d is not finite", what, k);
+            if (k > 0 && knots[k] < knots[k - 1]) return fail(SWEEP_ERR_BAD_KNOTS, "%s: knots decrease at %d", what, k);
+        }
+        // multiplicities: interior knots at most p, end knots at most p+1,
+        // and a non-empty first and last span.
+        int run = 1;
+        for (int k = 1; k <= nk; ++k) {
+            if (k < nk && knots[k] == knots[k - 1]) { ++run; continue; }
+            const int first = k - run, last = k - 1;
+            const bool interior = first > 0 && last < nk - 1;
+            if (interior && run > p) return fail(SWEEP_ERR_BAD_KNOTS, "%s: interior knot %g has multiplicity %d > degree", what, knots[last], run);
+            if (run > p + 1) return fail(SWEEP_ERR_BAD_KNOTS, "%s: knot %g has multiplicity %d > degree+1", what, knots[last], run);
+            run = 1;
+        }
+        if (!(knots[p] < knots[p + 1]) || !(knots[n - 1] < knots[n]))
+            return fail(SWEEP_ERR_BAD_KNOTS, "%s: first or last span of the domain is empty", what);
+    }
+    return SWEEP_OK;
+}
+
+static sweep_status check_curve(const sweep_curve* c, const char* what, bool is_path)
+{
+    if (!c) return fail(SWEEP_ERR_NULL_ARG, "%s is NULL", what);
+    sweep_status st = check_curve_meta(c->n_ctrl, c->degree, c->closed, c->knots, what, is_path);
+    if (st != SWEEP_OK) return st;
+    if (!c->ctrl) return fail(SWEEP_ERR_NULL_ARG, "%s: ctrl is NULL", what);
+    return SWEEP_OK;
+}
+
+sweep_status check_options(const sweep_options* o)
+{
+    if (o->out_precision != SWEEP_F32 && o->out_precision != SWEEP_F64)
+        return fail(SWEEP_ERR_BAD_PRECISION, "out_precision %d", o->out_precision);
+    if (o->frame_precision != SWEEP_F32 && o->frame_precision != SWEEP_F64)
+        return fail(SWEEP_ERR_BAD_PRECISION, "frame_precision %d", o->frame_precision);
+    if (o->reorthonormalize != 0 && o->reorthonormalize != 1)
+        return fail(SWEEP_ERR_BAD_OPTION, "reorthonormalize %d is not 0/1", o->reorthonormalize);
+    if (o->has_initial_normal != 0 && o->has_initial_normal != 1)
+        return fail(SWEEP_ERR_BAD_OPTION, "has_initial_normal %d is not 0/1", o->has_initial_normal);
+    if (o->has_initial_normal)
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(o->initial_normal[k])) return fail(SWEEP_ERR_BAD_OPTION, "initial_normal not finite");
+    if (o->tile_config < -1 || o->tile_config >= tile_config_count())
+        return fail(SWEEP_ERR_BAD_OPTION, "tile_config %d outside -1..%d", o->tile_config, tile_config_count() - 1);
+    return SWEEP_OK;
+}
+
+sweep_status check_grid(int n_u, int n_v)
+{
+    if (n_u < 2 || n_v < 3) return fail(SWEEP_ERR_BAD_GRID, "grid %d x %d (need n_u >= 2, n_v >= 3)", n_u, n_v);
+    if ((long long)n_u * (long long)n_v >= (1LL << 31))
+        return fail(SWEEP_ERR_BAD_GRID, "grid %d x %d has 2^31 or more vertices", n_u, n_v);
+    return SWEEP_OK;
+}
+
+int nbasis(int n, int p, int closed) { return closed ? n + p : n; }
+int nknots(int n, int p, int closed) { return nbasis(n, p, closed) + p + 1; }
+
+// -------------------------------------------------------------- tile table
+
+// Fixed surface configurations (tile_config >= 0); -1 picks automatically.
+static const SurfaceConfig kTiles[] = {
+    {0, 8, 0, 0, 0},  {0, 16, 0, 0, 0}, {0, 32, 0, 0, 0}, {0, 64, 0, 0, 0},
+    {0, 8, 0, 0, 1},  {0, 16, 0, 0, 1}, {0, 32, 0, 0, 1}, {0, 64, 0, 0, 1},
+    {1, 0, 2048, 0, 0}, {1, 0, 4096, 0, 0}, {1, 0, 8192, 0, 0}, {1, 0, 4096, 2048, 0},
+    {1, 0, 2048, 0, 1}, {1, 0, 4096, 0, 1}, {1, 0, 8192, 0, 1}, {1, 0, 4096, 2048, 1},
+};
+
+int tile_config_count() { return (int)(sizeof kTiles / sizeof kTiles[0]); }
+
+const SurfaceConfig& tile_config(int k) { return kTiles[k]; }
+
+// Automatic choice for a single sweep: the column-stationary kernel when its
+// columns fill whole 1024-column tiles at least 3/4 of the time, with enough
+// row groups for ~8 blocks per CU; otherwise the linear kernel.
+SurfaceConfig auto_surface_config(int n_u, int n_v, bool cols_ok)
+{
+    if (cols_ok && n_v >= 768) {
+        const int tiles = (n_v + 1023) / 1024;
+        if ((double)n_v / (tiles * 1024.0) >= 0.75) {
+            long long target = 2048;
+            int rpb = (int)std::max(1LL, std::min(64LL, (long long)n_u * tiles / target));
+            return SurfaceConfig{0, rpb, 0, 0, 0};
+        }
+    }
+    return SurfaceConfig{1, 0, 4096, 0, 0};
+}
+
+// ---------------------------------------------------------- workspace plan
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct SingleLayout {
+    size_t knots_path, knots_prof, smp, chunk_lv, fallback, agg, r_in, rows, prof_tab, total;
+};
+
+static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz)
+{
+    SingleLayout L{};
+    const int nc = (n_u + frame_chunk_size() - 1) / frame_chunk_size();
+    size_t off = 0;
+    L.knots_path = off; off = align_up(off + sizeof(double) * nknots(np, pp, 0));
+    L.knots_prof = off; off = align_up(off + sizeof(double) * nknots(nq, pq, qclosed));
+    L.smp = off;        off = align_up(off + sizeof(double) * 9 * (size_t)n_u);
+    L.chunk_lv = off;   off = align_up(off + sizeof(int) * (size_t)nc);
+    L.fallback = off;   off = align_up(off + sizeof(double) * 3);
+    L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
+    L.r_in = off;       off = align_up(off + fsz * 3 * (size_t)nc);
+    L.rows = off;       off = align_up(off + tsz * 16 * (size_t)n_u);
+    L.prof_tab = off;   off = align_up(off + tsz * 8 * (size_t)n_v);
+    L.total = off;
+    return L;
+}
+
+static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof, int n_u, int n_v,
+                               const sweep_options* o)
+{
+    const size_t fsz = o->frame_precision == SWEEP_F64 ? 8 : 4;
+    const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
+    return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz);
+}
+
+sweep_status upload_knots(const double* host_knots, int n, int p, int closed, double* dst, hipStream_t st)
+{
+    hipError_t e;
+    if (host_knots)
+        e = hipMemcpyAsync(dst, host_knots, sizeof(double) * nknots(n, p, 0), hipMemcpyHostToDevice, st);
+    else
+        e = launch_fill_knots(dst, n, p, closed, st);
+    if (e != hipSuccess) return hip_fail(e, "knots");
+    return SWEEP_OK;
+}
+
+template <class F, class T>
+static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof, int n_u, int n_v,
+                               const sweep_options* o, void* pos, void* nrm, char* ws, const SingleLayout& L,
+                               hipStream_t st)
+{
+    double* Up = (double*)(ws + L.knots_path);
+    double* Uq = (double*)(ws + L.knots_prof);
+    sweep_status s = upload_knots(path->knots, path->n_ctrl, path->degree, 0, Up, st);
+    if (s != SWEEP_OK) return s;
+    s = upload_knots(prof->knots, prof->n_ctrl, prof->degree, prof->closed, Uq, st);
+    if (s != SWEEP_OK) return s;
+    trace_mark(0, st);
+    DCurve dp{path->ctrl, Up, path->n_ctrl, path->degree, 0, nbasis(path->n_ctrl, path->degree, 0)};
+    DCurve dq{prof->ctrl, Uq, prof->n_ctrl, prof->degree, prof->closed, nbasis(prof->n_ctrl, prof->degree, prof->closed)};
+    double* smp = (double*)(ws + L.smp);
+    int* clv = (int*)(ws + L.chunk_lv);
+    double* fb = (double*)(ws + L.fallback);
+    T* rows = (T*)(ws + L.rows);
+    T* ptab = (T*)(ws + L.prof_tab);
+    hipError_t e = launch_path_samples(dp, n_u, smp, clv, fb, st);
+    if (e != hipSuccess) return hip_fail(e, "path samples");
+    e = launch_profile_table<T>(dq, n_v, ptab, st);
+    if (e != hipSuccess) return hip_fail(e, "profile table");
+    InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
+    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in), rows, st);
+    if (e != hipSuccess) return hip_fail(e, "frame");
+    trace_mark(1, st);
+    const bool cols_ok = surface_cols_supported(n_v, pos, nrm, sizeof(T));
+    SurfaceConfig cfg;
+    if (o->tile_config >= 0) {
+        cfg = tile_config(o->tile_config);
+        if (cfg.kind == 0 && !cols_ok)
+            return fail(SWEEP_ERR_UNSUPPORTED, "tile_config %d needs n_v %% 4 == 0 and 16-byte aligned outputs", o->tile_config);
+    } else {
+        cfg = auto_surface_config(n_u, n_v, cols_ok);
+    }
+    e = launch_surface<T>(rows, ptab, n_u, n_v, (T*)pos, (T*)nrm, cfg, st);
+    if (e != hipSuccess) return hip_fail(e, "surface");
+    trace_mark(2, st);
+    return SWEEP_OK;
+}
+
+}  // namespace sweep
+
+using namespace sweep;
+
+extern "C" {
+
+void sweep_default_options(sweep_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->out_precision = SWEEP_F32;
+    opt->frame_precision = SWEEP_F64;
+    opt->reorthonormalize = 1;
+    opt->has_initial_normal = 0;
+    opt->tile_config = -1;
+}
+
+size_t sweep_eval_workspace_size(const sweep_curve* path, const sweep_curve* profile, int32_t n_u, int32_t n_v,
+                                 const sweep_options* opt)
+{
+    if (!path || !profile || !opt) return 0;
+    if (check_curve_meta(path->n_ctrl, path->degree, path->closed, path->knots, "path", true) != SWEEP_OK) return 0;
+    if (check_curve_meta(profile->n_ctrl, profile->degree, profile->closed, profile->knots, "profile", false) != SWEEP_OK) return 0;
+    if (check_grid(n_u, n_v) != SWEEP_OK || check_options(opt) != SWEEP_OK) return 0;
+    return layout_for(path, profile, n_u, n_v, opt).total;
+}
+
+sweep_status sweep_eval(const sweep_curve* path, const sweep_curve* profile, int32_t n_u, int32_t n_v,
+                        const sweep_options* opt, void* pos, void* nrm, void* workspace, size_t ws_bytes,
+                        void* stream)
+{
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    sweep_status s = check_options(opt);
+    if (s != SWEEP_OK) return s;
+    if ((s = check_curve(path, "path", true)) != SWEEP_OK) return s;
+    if ((s = check_curve(profile, "profile", false)) != SWEEP_OK) return s;
+    if ((s = check_grid(n_u, n_v)) != SWEEP_OK) return s;
+    if (!pos) return fail(SWEEP_ERR_NULL_ARG, "pos is NULL");
+    const SingleLayout L = layout_for(path, profile, n_u, n_v, opt);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, L.total);
+    if (((uintptr_t)workspace) % 256 != 0) return fail(SWEEP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    const bool f64 = opt->frame_precision == SWEEP_F64, t64 = opt->out_precision == SWEEP_F64;
+    if (f64 && t64) return run_single<double, double>(path, profile, n_u, n_v, opt, pos, nrm, ws, L, st);
+    if (f64) return run_single<double, float>(path, profile, n_u, n_v, opt, pos, nrm, ws, L, st);
+    if (t64) return run_single<float, double>(path, profile, n_u, n_v, opt, pos, nrm, ws, L, st);
+    return run_single<float, float>(path, profile, n_u, n_v, opt, pos, nrm, ws, L, st);
+}
+
+sweep_status sweep_trace_enable(int32_t max_calls)
+{
+    const int cap = (int)(sizeof g_trace.ev / sizeof g_trace.ev[0]) / 3;
+    if (max_calls < 0 || max_calls > cap) return fail(SWEEP_ERR_BAD_OPTION, "trace length %d outside 0..%d", max_calls, cap);
+    if (max_calls == 0) { g_trace.capacity = 0; return SWEEP_OK; }
+    if (g_trace.calls != 0) return fail(SWEEP_ERR_BAD_OPTION, "read the previous trace first");
+    for (int k = g_trace.used; k < 3 * max_calls; ++k) {
+        hipError_t e = hipEventCreate(&g_trace.ev[k]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        g_trace.used = k + 1;
+    }
+    g_trace.capacity = max_calls;
+    return SWEEP_OK;
+}
+
+int32_t sweep_trace_read(int32_t* stage, float* ms, int32_t max)
+{
+    int n = 0;
+    for (int c = 0; c < g_trace.calls; ++c) {
+        for (int k = 0; k < 2; ++k) {
+            hipError_t e = hipEventSynchronize(g_trace.ev[3 * c + k + 1]);
+            if (e != hipSuccess) return hip_fail(e, "trace read");
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, g_trace.ev[3 * c + k], g_trace.ev[3 * c + k + 1]);
+            if (e != hipSuccess) return hip_fail(e, "trace read");
+            if (n < max && stage && ms) { stage[n] = k; ms[n] = t; ++n; }
+        }
+    }
+    g_trace.calls = 0;
+    g_trace.capacity = 0;
+    return n;
+}
+
+int32_t sweep_tile_config_count(void) { return tile_config_count(); }
+
+const char* sweep_last_error(void) { return g_last_error.c_str(); }
+
+int32_t sweep_version(void) { return SWEEP_VERSION; }
+
+}  // extern "C"

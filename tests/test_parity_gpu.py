@@ -1,0 +1,136 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on seeded
+inputs: the plain FP64 sweep, FP32 output, every degree, user knots, open and
+non-planar profiles, ragged grids spanning several frame chunks, every fixed
+surface configuration, degenerate tangents, and the full-size large sweep
+and precision-study grids on sampled rows."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import TOL, check_full, gpu_sweep, parity, say
+
+pytestmark = pytest.mark.gpu
+
+rng = np.random.default_rng(2024)
+
+
+def _spec(n_path, p, m, q, n_u, n_v, closed=True, seed=0, planar=True):
+    r = np.random.default_rng(seed)
+    P = synth.random_walk(r, n_path)
+    Q = synth.perturbed_circle(r, m)
+    if not planar:
+        Q[:, 2] = 0.1 * r.standard_normal(m)
+    return synth.SweepSpec(synth.CurveSpec(P, p), synth.CurveSpec(Q, q, closed), n_u, n_v)
+
+
+def test_plain_fp64_sweep():
+    r = check_full(synth.c1(), out_dtype=torch.float64)
+    assert r["masked"] < 0.01 * 256 * 64
+
+
+def test_plain_sweep_fp32_output():
+    check_full(synth.c1(), out_dtype=torch.float32)
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (2, 2), (3, 3), (4, 2), (5, 3), (6, 4), (7, 7), (2, 5)])
+def test_degrees(p, q):
+    check_full(_spec(max(p + 1, 12), p, max(q + 1, 9), q, 301, 37, seed=p * 10 + q), out_dtype=torch.float64)
+
+
+@pytest.mark.parametrize("n_u,n_v", [(2, 3), (3, 4), (1023, 8), (1024, 8), (1025, 12), (3000, 37), (4100, 64)])
+def test_ragged_grids_across_chunks(n_u, n_v):
+    check_full(_spec(40, 3, 8, 3, n_u, n_v, seed=n_u), out_dtype=torch.float64)
+
+
+def test_user_knots_and_open_profile():
+    P = synth.random_walk(rng, 9)
+    U = np.array([0, 0, 0, 0, .1, .1, .45, .7, .7, 1, 1, 1, 1], float)
+    Q = np.stack([np.linspace(-0.5, 0.5, 7), 0.2 * np.sin(np.arange(7)), np.zeros(7)], 1)
+    V = np.array([0, 0, 0, .3, .3, .6, .8, 1, 1, 1], float) * 2.0 - 1.0
+    spec = synth.SweepSpec(synth.CurveSpec(P, 3, knots=U), synth.CurveSpec(Q, 2, False, knots=V), 777, 29)
+    check_full(spec, out_dtype=torch.float64)
+    check_full(spec, out_dtype=torch.float32)
+
+
+def test_non_planar_profile_and_initial_normal():
+    spec = _spec(20, 3, 10, 3, 513, 40, seed=5, planar=False)
+    check_full(spec, out_dtype=torch.float64)
+    check_full(spec, out_dtype=torch.float64, n0=np.array([0.3, -0.2, 0.9]))
+
+
+def test_fp32_frame_and_raw_frame_variants():
+    spec = _spec(16, 3, 8, 3, 2048, 32, seed=7)
+    # FP32 step matrices and scan: error budget of single precision
+    check_full(spec, out_dtype=torch.float32, frame_dtype=torch.float32, tol=1e-4)
+    # no re-orthonormalisation in FP64: the defining values are unchanged
+    check_full(spec, out_dtype=torch.float64, reorth=False, tol=1e-11)
+
+
+@pytest.mark.parametrize("cfg", list(range(16)))
+def test_every_fixed_surface_config(cfg):
+    check_full(_spec(30, 3, 12, 3, 150, 1024, seed=11), out_dtype=torch.float32, tile_config=cfg)
+    check_full(_spec(30, 3, 12, 3, 97, 516, seed=12), out_dtype=torch.float64, tile_config=cfg)
+
+
+def test_tangent_reversal():
+    P = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 0, 0]])
+    Q = synth.perturbed_circle(rng, 6)
+    spec = synth.SweepSpec(synth.CurveSpec(P, 1), synth.CurveSpec(Q, 3, True), 11, 16)
+    check_full(spec, out_dtype=torch.float64)
+
+
+def test_stationary_run_across_chunks_and_zero_start():
+    # a stationary segment of ~1700 samples spanning chunk boundaries
+    P = np.array([[0.0, 0, 0], [1.0, 0.5, 0], [1.0, 0.5, 0], [2.0, 2.0, 1.0]])
+    Q = synth.perturbed_circle(rng, 7)
+    spec = synth.SweepSpec(synth.CurveSpec(P, 1), synth.CurveSpec(Q, 2, True), 5000, 9)
+    check_full(spec, out_dtype=torch.float64)
+    P2 = np.array([[1.0, 1, 1], [1.0, 1, 1], [2.0, 3.0, 1.0], [4.0, 3.0, 0.0], [5, 5, 5]])
+    spec2 = synth.SweepSpec(synth.CurveSpec(P2, 1), synth.CurveSpec(Q, 2, True), 3001, 9)
+    check_full(spec2, out_dtype=torch.float64)
+
+
+def test_deterministic_and_stream():
+    spec = _spec(50, 3, 16, 3, 2000, 100, seed=3)
+    a, na = gpu_sweep(spec)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b, nb = gpu_sweep(spec, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(na, nb)
+
+
+def _sampled(spec, rows, out_dtype, frame_dtype=torch.float64, tol=None):
+    say(f"[case] sampled n_u={spec.n_u} n_v={spec.n_v} rows={len(rows)} out={out_dtype} frame={frame_dtype}")
+    pos, nrm = gpu_sweep(spec, out_dtype, frame_dtype)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(rows, device=pos.device)
+    gp = pos.index_select(1, idx).cpu().numpy()
+    gn = nrm.index_select(1, idx).cpu().numpy()
+    # bounding box of the whole surface: the path samples' box widened by the profile radius
+    x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
+    rp, rn, rk, R = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
+    diag = float(np.linalg.norm(x.max(0) - x.min(0)))
+    del pos, nrm
+    torch.cuda.empty_cache()
+    ok, r = parity(rp, rn, rk, gp, gn, TOL[out_dtype] if tol is None else tol, diag=diag)
+    say("   ", r)
+    assert ok, r
+
+
+def test_large_sweep_full_size_sampled_rows():
+    spec = synth.c2()
+    rows = np.unique(np.concatenate([[0, 1, 1023, 1024, 1025, 4095, 4096, spec.n_u - 2, spec.n_u - 1],
+                                     rng.integers(0, spec.n_u, 24)]))
+    _sampled(spec, rows, torch.float32)
+
+
+def test_precision_study_grid_sampled_rows():
+    spec = synth.c3()
+    rows = np.unique(np.concatenate([[0, 1, spec.n_u // 2, spec.n_u - 1], rng.integers(0, spec.n_u, 24)]))
+    _sampled(spec, rows, torch.float32)
+    _sampled(spec, rows, torch.float32, frame_dtype=torch.float32, tol=1e-3)
