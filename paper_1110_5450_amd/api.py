@@ -92,3 +92,133 @@ def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree:
     path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None)
     prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None)
     return L.sweep_eval_workspace_size(path, prof, n_u, n_v, make_options(out_dtype, frame_dtype))
+
+
+class Batch:
+    """A batch of independent sweeps packed for sweep_eval_batched /
+    sweep_backward.  Control points are packed into one device float64 buffer
+    per curve kind; per-sweep counts, degrees, grid sizes and knot vectors
+    stay in host memory.  Sweep k's output block starts at element
+    3 * offsets[k] of the flat position (normal) buffer."""
+
+    def __init__(self, path_ctrl: Sequence, path_degree: Sequence[int], prof_ctrl: Sequence,
+                 prof_degree: Sequence[int], n_u: Sequence[int], n_v: Sequence[int], *, prof_closed=None,
+                 path_knots=None, prof_knots=None, device="cuda"):
+        n = len(path_ctrl)
+        self.n_sweeps = n
+        as_np = lambda a: np.ascontiguousarray(a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else a,
+                                               dtype=np.float64).reshape(-1, 3)
+        P = [as_np(a) for a in path_ctrl]
+        Q = [as_np(a) for a in prof_ctrl]
+        self.path_n = np.array([a.shape[0] for a in P], np.int32)
+        self.prof_n = np.array([a.shape[0] for a in Q], np.int32)
+        self.path_degree = np.array(path_degree, np.int32)
+        self.prof_degree = np.array(prof_degree, np.int32)
+        self.n_u = np.array(n_u, np.int32)
+        self.n_v = np.array(n_v, np.int32)
+        self.prof_closed = None if prof_closed is None else np.array(prof_closed, np.int32)
+        # Knot vectors: all paths or none; all open profiles or none.
+        if path_knots is not None and any(k is None for k in path_knots):
+            raise ValueError("path_knots must give a vector for every path (or be None)")
+        self.path_knots = None if path_knots is None else np.ascontiguousarray(np.concatenate(
+            [np.asarray(k, np.float64) for k in path_knots]))
+        self.prof_knots = None
+        if prof_knots is not None:
+            closed = self.prof_closed if self.prof_closed is not None else np.ones(n, np.int32)
+            if any((k is None) != bool(c) for k, c in zip(prof_knots, closed)):
+                raise ValueError("prof_knots must give a vector for every open profile and None for closed ones")
+            ks = [np.asarray(k, np.float64) for k in prof_knots if k is not None]
+            self.prof_knots = np.ascontiguousarray(np.concatenate(ks)) if ks else None
+        self.path_ctrl = torch.as_tensor(np.concatenate(P)).to(device)
+        self.prof_ctrl = torch.as_tensor(np.concatenate(Q)).to(device)
+        sizes = self.n_u.astype(np.int64) * self.n_v.astype(np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        self.n_vertices = int(sizes.sum())
+        self.path_offsets = np.concatenate([[0], np.cumsum(self.path_n)[:-1]]).astype(np.int64)
+        self.prof_offsets = np.concatenate([[0], np.cumsum(self.prof_n)[:-1]]).astype(np.int64)
+
+    @classmethod
+    def from_specs(cls, specs, device="cuda") -> "Batch":
+        """From objects with path/profile (ctrl, degree, closed, knots), n_u, n_v."""
+        pk = [s.path.knots for s in specs]
+        qk = [s.profile.knots for s in specs]
+        return cls([s.path.ctrl for s in specs], [s.path.degree for s in specs],
+                   [s.profile.ctrl for s in specs], [s.profile.degree for s in specs],
+                   [s.n_u for s in specs], [s.n_v for s in specs],
+                   prof_closed=[int(s.profile.closed) for s in specs],
+                   path_knots=None if all(k is None for k in pk) else pk,
+                   prof_knots=None if all(k is None for k in qk) else qk, device=device)
+
+    def c_struct(self) -> L.SweepBatch:
+        ip = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+        dp = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+        return L.SweepBatch(self.n_sweeps, 0, ip(self.path_n), ip(self.path_degree), ip(self.prof_n),
+                            ip(self.prof_degree), ip(self.prof_closed), ip(self.n_u), ip(self.n_v),
+                            dp(self.path_knots), dp(self.prof_knots),
+                            self.path_ctrl.data_ptr(), self.prof_ctrl.data_ptr())
+
+    def view(self, flat: torch.Tensor, k: int) -> torch.Tensor:
+        """Sweep k's (3, n_u, n_v) block of a flat batched output."""
+        o, nu, nv = int(self.offsets[k]), int(self.n_u[k]), int(self.n_v[k])
+        return flat[3 * o: 3 * o + 3 * nu * nv].view(3, nu, nv)
+
+    def path_slice(self, k: int) -> slice:
+        return slice(int(self.path_offsets[k]), int(self.path_offsets[k] + self.path_n[k]))
+
+    def prof_slice(self, k: int) -> slice:
+        return slice(int(self.prof_offsets[k]), int(self.prof_offsets[k] + self.prof_n[k]))
+
+
+def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
+                       reorthonormalize: bool = True, initial_normal=None, tile_config: int = -1,
+                       normals: bool = True, out=None, workspace: Optional[torch.Tensor] = None, stream=None):
+    """Flat positions (3 * total vertices) and normals (or None) of a batch."""
+    b = batch.c_struct()
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config)
+    ws_bytes = L.sweep_batched_workspace_size(b, opt)
+    if ws_bytes == 0:
+        L.check(L.sweep_eval_batched(b, opt, 0, 0, 0, 0, 0))
+    dev = batch.path_ctrl.device
+    if out is None:
+        pos = torch.empty(3 * batch.n_vertices, dtype=out_dtype, device=dev)
+        nrm = torch.empty(3 * batch.n_vertices, dtype=out_dtype, device=dev) if normals else None
+    else:
+        pos, nrm = out
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    L.check(L.sweep_eval_batched(b, opt, pos.data_ptr(), nrm.data_ptr() if nrm is not None else 0,
+                                 workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+    return pos, nrm
+
+
+def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
+    return L.sweep_batched_workspace_size(batch.c_struct(), make_options(out_dtype, frame_dtype))
+
+
+def sweep_backward(batch: Batch, grad_pos: torch.Tensor, *, initial_normal=None, workspace=None, stream=None):
+    """Gradients of L with dL/dpos = grad_pos (flat, like the batched output;
+    its dtype is the output precision) with respect to the packed path and
+    profile control points: (g_path (sum path_n, 3), g_prof (sum prof_n, 3)),
+    float64."""
+    b = batch.c_struct()
+    if grad_pos.dtype not in _DT:
+        raise TypeError("grad_pos must be float32 or float64")
+    g = grad_pos.contiguous()
+    if g.numel() != 3 * batch.n_vertices:
+        raise ValueError("grad_pos has the wrong size")
+    opt = make_options(g.dtype, torch.float64, True, initial_normal)
+    ws_bytes = L.sweep_backward_workspace_size(b, opt)
+    if ws_bytes == 0:
+        L.check(L.sweep_backward(b, opt, 0, 0, 0, 0, 0, 0))
+    dev = batch.path_ctrl.device
+    gP = torch.empty((int(batch.path_n.sum()), 3), dtype=torch.float64, device=dev)
+    gQ = torch.empty((int(batch.prof_n.sum()), 3), dtype=torch.float64, device=dev)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    L.check(L.sweep_backward(b, opt, g.data_ptr(), gP.data_ptr(), gQ.data_ptr(), workspace.data_ptr(),
+                             workspace.numel(), _stream_handle(stream)))
+    return gP, gQ
+
+
+def backward_workspace_size(batch: Batch, out_dtype=torch.float32) -> int:
+    return L.sweep_backward_workspace_size(batch.c_struct(), make_options(out_dtype, torch.float64))

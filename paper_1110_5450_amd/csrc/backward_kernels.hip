@@ -1,0 +1,405 @@
+// backward_kernels.hip -- adjoint of the positions with respect to the path
+// and profile control points, for a batch.  With w = dL/dX and
+// X_ij = x_i + S_x r_i + S_y s_i + S_z t_i:
+//   dL/dx_i (direct)    = sum_j w_ij
+//   dL/dr_i, ds_i, dt_i = sum_j S_{x,y,z}(v_j) w_ij
+//   dL/dS_j             = sum_i R_i^T w_ij
+// The frame is r_{i+1} = M_i r_i with M_i R_i = R_{i+1} (exact arithmetic),
+// so the adjoint recurrence rbar_i = rbar_i^dir + M_i^T rbar_{i+1} becomes a
+// suffix sum in frame coordinates: R_i^T rbar_i = sum_{k>=i} R_k^T rbar_k^dir.
+// Each step M_i = H2 H1 is then differentiated through its two reflections
+// (chord x_{i+1} - x_i and tangents t_i, t_{i+1}), t = C'/|C'| through the
+// normalisation, r_0 through the initial-normal rule, and x, C' to the
+// control points through the basis functions.  Every sum runs in FP64 in a
+// fixed order: the result does not depend on scheduling.
+//
+// kbw_reduce   one wave per (sweep, group of kBwRowGroup rows, 64 columns):
+//              streaming read of w, per-row partials (wave butterfly sums),
+//              per-column partials over the group.
+// kbw_adjoint  one block per sweep: finishes the partial sums, runs the
+//              suffix sum, the per-sample adjoint and the per-control-point
+//              gathers.
+#include "frame_common.hpp"
+
+namespace sweep {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = v + __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
+                                                     const int4* __restrict__ units, int n_units,
+                                                     const T* __restrict__ grad, const double* __restrict__ rows,
+                                                     const double* __restrict__ ptab, double* __restrict__ rowpart,
+                                                     double* __restrict__ colpart)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int unit = blockIdx.x * kWaves + wave;
+    if (unit >= n_units) return;
+    const int4 un = units[unit];
+    const BatchDesc d = descs[un.x];
+    const int g = un.y, seg = un.z;
+    const int j = seg * 64 + lane;
+    const bool vj = j < d.n_v;
+    double Sx = 0.0, Sy = 0.0, Sz = 0.0;
+    if (vj) {
+        const double* q = ptab + 8 * (d.ptab_off + j);
+        Sx = q[0]; Sy = q[1]; Sz = q[2];
+    }
+    const size_t N = (size_t)d.n_u * (size_t)d.n_v;
+    const T* w0 = grad + 3 * (size_t)d.out_off;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    const int i0 = g * kBwRowGroup, i1 = min(d.n_u, i0 + kBwRowGroup);
+    for (int i = i0; i < i1; ++i) {
+        const double* R = rows + 16 * (d.row_off + i);
+        double w[3] = {0.0, 0.0, 0.0};
+        if (vj) {
+            const size_t v = (size_t)i * (size_t)d.n_v + (size_t)j;
+            w[0] = (double)w0[v]; w[1] = (double)w0[N + v]; w[2] = (double)w0[2 * N + v];
+        }
+        double part[12];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            part[c] = w[c];
+            part[3 + c] = Sx * w[c];
+            part[6 + c] = Sy * w[c];
+            part[9 + c] = Sz * w[c];
+        }
+#pragma unroll
+        for (int e = 0; e < 12; ++e) part[e] = wave_sum(part[e]);
+        if (lane < 12) {
+            double v = part[0];
+#pragma unroll
+            for (int e = 1; e < 12; ++e) v = lane == e ? part[e] : v;
+            rowpart[12 * (d.rowpart_off + (size_t)seg * d.n_u + i) + lane] = v;
+        }
+        h0 += R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
+        h1 += R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
+        h2 += R[9] * w[0] + R[10] * w[1] + R[11] * w[2];
+    }
+    if (vj) {
+        double* q = colpart + 3 * (d.colpart_off + (size_t)g * d.n_v + j);
+        q[0] = h0; q[1] = h1; q[2] = h2;
+    }
+}
+
+// Basis values N_{s-P+j,P}(u) and first derivatives, j = 0..P.
+template <int P>
+__device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, double* N, double* dN)
+{
+    double Uk[2 * P + 1];
+#pragma unroll
+    for (int m = 0; m < 2 * P; ++m) Uk[m] = knot(c, s - P + 1 + m);
+    double B[P + 1];
+    double D1[P > 0 ? P : 1];
+    B[0] = 1.0;
+    if (P - 1 == 0) D1[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= P; ++q) {
+        double nb_[P + 1];
+        double carry = 0.0;
+#pragma unroll
+        for (int j = 0; j < q; ++j) {
+            const double lo = Uk[P - q + j], hi = Uk[P + j];
+            const double tmp = B[j] / (hi - lo);
+            nb_[j] = carry + (hi - u) * tmp;
+            carry = (u - lo) * tmp;
+        }
+        nb_[q] = carry;
+#pragma unroll
+        for (int j = 0; j <= q; ++j) B[j] = nb_[j];
+        if (q == P - 1) {
+#pragma unroll
+            for (int j = 0; j <= q; ++j) D1[j] = B[j];
+        }
+    }
+    // C' = sum_j D1[j] Q_j with Q_j = P (P_{j+1} - P_j) / (U_{s+j+1} - U_{s-P+j+1})
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        double v = 0.0;
+        if (j >= 1) v += D1[j - 1] / (Uk[P + j - 1] - Uk[j - 1]);
+        if (j < P) v -= D1[j] / (Uk[P + j] - Uk[j]);
+        N[j] = B[j];
+        dN[j] = (double)P * v;
+    }
+}
+
+// Basis of sample i of ns (any degree up to kMaxDeg): span and values.
+__device__ __forceinline__ int sample_basis(const DCurve& c, int i, int ns, double* N, double* dN)
+{
+    const double u = sample_param(c, i, ns);
+    const int s = sample_span(c, i, ns, u);
+    switch (c.p) {
+    case 1: basis_vals<1>(c, u, s, N, dN); break;
+    case 2: basis_vals<2>(c, u, s, N, dN); break;
+    case 3: basis_vals<3>(c, u, s, N, dN); break;
+    case 4: basis_vals<4>(c, u, s, N, dN); break;
+    case 5: basis_vals<5>(c, u, s, N, dN); break;
+    case 6: basis_vals<6>(c, u, s, N, dN); break;
+    default: basis_vals<7>(c, u, s, N, dN); break;
+    }
+    return s;
+}
+
+// Adjoint of H(v) w = w - (2 (v.w)/(v.v)) v with respect to v, given the
+// adjoint zb of H(v) w.
+__device__ __forceinline__ V3<double> reflect_adj(V3<double> v, V3<double> w, V3<double> zb)
+{
+    const double c = dot(v, v), vw = dot(v, w), vz = dot(v, zb);
+    return (-2.0 / c) * (vz * w + vw * zb) + (4.0 * vw * vz / (c * c)) * v;
+}
+
+struct StepAdj {
+    V3<double> x0, x1, t0, t1;   // contributions to samples i and i+1
+};
+
+// Adjoint of r_{i+1} = H2 H1 r_i with respect to (x_i, x_{i+1}, t_i, t_{i+1}),
+// given yb = dL/dr_{i+1}.  A tangent-reversal step (|v2|^2 <= 1e-24) is
+// treated as locally constant.
+__device__ __forceinline__ StepAdj step_adjoint(V3<double> xa, V3<double> xb, V3<double> ta, V3<double> tb,
+                                                V3<double> ra, V3<double> yb)
+{
+    StepAdj o;
+    const V3<double> z = mk(0.0, 0.0, 0.0);
+    o.x0 = z; o.x1 = z; o.t0 = z; o.t1 = z;
+    V3<double> v1 = xb - xa;
+    double c1 = dot(v1, v1);
+    const bool zero_chord = c1 == 0.0;
+    if (zero_chord) { v1 = ta; c1 = dot(v1, v1); }
+    const double b1 = 2.0 / c1;
+    const V3<double> rL = ra - (b1 * dot(v1, ra)) * v1;
+    const V3<double> tL = ta - (b1 * dot(v1, ta)) * v1;
+    const V3<double> v2 = tb - tL;
+    const double c2 = dot(v2, v2);
+    if (!(c2 > 1e-24)) return o;
+    const double b2 = 2.0 / c2;
+    const V3<double> v2b = reflect_adj(v2, rL, yb);
+    const V3<double> y1b = yb - (b2 * dot(v2, yb)) * v2;
+    V3<double> v1b = reflect_adj(v1, ra, y1b);
+    const V3<double> tLb = mk(-v2b.x, -v2b.y, -v2b.z);
+    o.t1 = v2b;
+    o.t0 = tLb - (b1 * dot(v1, tLb)) * v1;
+    v1b = v1b + reflect_adj(v1, ta, tLb);
+    if (zero_chord) o.t0 = o.t0 + v1b;
+    else { o.x1 = v1b; o.x0 = mk(-v1b.x, -v1b.y, -v1b.z); }
+    return o;
+}
+
+struct RowRec {
+    V3<double> x, r, s, t;
+    double L;
+};
+__device__ __forceinline__ RowRec row_at(const double* R)
+{
+    return RowRec{mk(R[0], R[1], R[2]), mk(R[3], R[4], R[5]), mk(R[6], R[7], R[8]), mk(R[9], R[10], R[11]), R[12]};
+}
+
+// Inclusive suffix sum of 3-vectors over the block (thread 255 first); block
+// total in `total`.  Fixed combination order.
+__device__ V3<double> block_suffix_sum(V3<double> v, double (*lds)[3], V3<double>& total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double ox = __shfl_down(v.x, d, 64), oy = __shfl_down(v.y, d, 64), oz = __shfl_down(v.z, d, 64);
+        if (lane + d < 64) v = v + mk(ox, oy, oz);
+    }
+    if (lane == 0) { lds[w][0] = v.x; lds[w][1] = v.y; lds[w][2] = v.z; }
+    __syncthreads();
+    V3<double> later = mk(0.0, 0.0, 0.0), tot = later;
+    for (int k = kWaves - 1; k >= 0; --k) {
+        const V3<double> a = mk(lds[k][0], lds[k][1], lds[k][2]);
+        if (k > w) later = later + a;
+        tot = tot + a;
+    }
+    total = tot;
+    __syncthreads();
+    return v + later;
+}
+
+__global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restrict__ descs,
+                                                      const double* __restrict__ path_ctrl,
+                                                      const double* __restrict__ prof_ctrl,
+                                                      const double* __restrict__ knots, InitialNormal n0,
+                                                      const double* __restrict__ rows, const double* rowpart,
+                                                      const double* colpart, double* rowacc, double* colacc,
+                                                      double* rho, double* sgrad, int* spans_u, double* qgrad,
+                                                      int* spans_v, double* __restrict__ gP, double* __restrict__ gQ)
+{
+    __shared__ double lds3[kWaves][3];
+    const BatchDesc d = descs[blockIdx.x];
+    const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
+                      d.n_path, d.p_path, 0, d.n_path};
+    const DCurve prof{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
+                      d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof};
+    const int n_u = d.n_u, n_v = d.n_v;
+    const double* rows_k = rows + 16 * d.row_off;
+    double* racc = rowacc + 12 * d.row_off;
+    double* cacc = colacc + 3 * d.ptab_off;
+    double* rho_k = rho + 3 * d.row_off;
+    double* sg = sgrad + 24 * d.row_off;
+    int* su = spans_u + d.row_off;
+    double* qg = qgrad + 24 * d.ptab_off;
+    int* sv = spans_v + d.ptab_off;
+
+    // 1. finish the partial sums (fixed order over segments / groups)
+    for (int i = threadIdx.x; i < n_u; i += kBlock) {
+        double a[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) a[e] = 0.0;
+        for (int sgi = 0; sgi < d.nseg; ++sgi) {
+            const double* q = rowpart + 12 * (d.rowpart_off + (size_t)sgi * n_u + i);
+#pragma unroll
+            for (int e = 0; e < 12; ++e) a[e] += q[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 12; ++e) racc[12 * (size_t)i + e] = a[e];
+    }
+    for (int j = threadIdx.x; j < n_v; j += kBlock) {
+        double h[3] = {0.0, 0.0, 0.0};
+        for (int g = 0; g < d.ngroup; ++g) {
+            const double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
+            h[0] += q[0]; h[1] += q[1]; h[2] += q[2];
+        }
+        cacc[3 * (size_t)j] = h[0]; cacc[3 * (size_t)j + 1] = h[1]; cacc[3 * (size_t)j + 2] = h[2];
+    }
+    __threadfence();
+    __syncthreads();
+
+    // 2. rho_i = sum_{k >= i} R_k^T rbar_k^dir, chunks from the last one
+    const int nc = (n_u + kBlock - 1) / kBlock;
+    V3<double> carry = mk(0.0, 0.0, 0.0);
+    for (int b = nc - 1; b >= 0; --b) {
+        const int i = b * kBlock + threadIdx.x;
+        V3<double> di = mk(0.0, 0.0, 0.0);
+        if (i < n_u) {
+            const RowRec R = row_at(rows_k + 16 * (size_t)i);
+            const double* a = racc + 12 * (size_t)i;
+            const V3<double> Gr = mk(a[3], a[4], a[5]), Gs = mk(a[6], a[7], a[8]);
+            const V3<double> rb = Gr + cross(Gs, R.t);
+            di = mk(dot(R.r, rb), dot(R.s, rb), dot(R.t, rb));
+        }
+        V3<double> total;
+        const V3<double> sfx = block_suffix_sum(di, lds3, total) + carry;
+        if (i < n_u) { rho_k[3 * (size_t)i] = sfx.x; rho_k[3 * (size_t)i + 1] = sfx.y; rho_k[3 * (size_t)i + 2] = sfx.z; }
+        carry = carry + total;
+    }
+    __threadfence();
+    __syncthreads();
+
+    // 3. per-sample adjoint of x_i and C'_i, and their basis contributions
+    for (int i = threadIdx.x; i < n_u; i += kBlock) {
+        const RowRec R = row_at(rows_k + 16 * (size_t)i);
+        const double* a = racc + 12 * (size_t)i;
+        const V3<double> g = mk(a[0], a[1], a[2]), Gs = mk(a[6], a[7], a[8]), Gt = mk(a[9], a[10], a[11]);
+        V3<double> xb = g;
+        V3<double> tb = Gt + cross(R.r, Gs);
+        const V3<double> rh = mk(rho_k[3 * (size_t)i], rho_k[3 * (size_t)i + 1], rho_k[3 * (size_t)i + 2]);
+        const V3<double> rbar_i = rh.x * R.r + rh.y * R.s + rh.z * R.t;
+        if (i + 1 < n_u) {
+            const RowRec Rn = row_at(rows_k + 16 * (size_t)(i + 1));
+            const V3<double> rn = mk(rho_k[3 * (size_t)(i + 1)], rho_k[3 * (size_t)(i + 1) + 1], rho_k[3 * (size_t)(i + 1) + 2]);
+            const V3<double> yb = rn.x * Rn.r + rn.y * Rn.s + rn.z * Rn.t;
+            const StepAdj sa = step_adjoint(R.x, Rn.x, R.t, Rn.t, R.r, yb);
+            xb = xb + sa.x0;
+            tb = tb + sa.t0;
+        }
+        if (i >= 1) {
+            const RowRec Rp = row_at(rows_k + 16 * (size_t)(i - 1));
+            const StepAdj sa = step_adjoint(Rp.x, R.x, Rp.t, R.t, Rp.r, rbar_i);
+            xb = xb + sa.x1;
+            tb = tb + sa.t1;
+        }
+        if (i == 0) {
+            // r_0 = q/|q|, q = e - (e.t_0) t_0 with e the initial normal or e_a
+            V3<double> e;
+            bool user = false;
+            if (n0.enabled) {
+                const V3<double> nn = mk(n0.v[0], n0.v[1], n0.v[2]);
+                const V3<double> q = nn - dot(nn, R.t) * R.t;
+                if (sqrt(dot(q, q)) > 1e-8) { e = nn; user = true; }
+            }
+            if (!user) {
+                const double ax = fabs(R.t.x), ay = fabs(R.t.y), az = fabs(R.t.z);
+                int k = 0;
+                double best = ax;
+                if (ay < best) { k = 1; best = ay; }
+                if (az < best) k = 2;
+                e = mk(k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0);
+            }
+            const double et = dot(e, R.t);
+            const V3<double> q = e - et * R.t;
+            const double ql = sqrt(dot(q, q));
+            const V3<double> qb = divs(rbar_i - dot(R.r, rbar_i) * R.r, ql);
+            tb = tb - (et * qb + dot(qb, R.t) * e);
+        }
+        // t = C'/|C'|; samples with C' = 0 carry a tangent and pass no gradient
+        V3<double> cb = mk(0.0, 0.0, 0.0);
+        if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L);
+        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1];
+        const int s = sample_basis(path, i, n_u, Nv, dN);
+        su[i] = s;
+        for (int j = 0; j <= path.p; ++j) {
+            const V3<double> c = Nv[j] * xb + dN[j] * cb;
+            double* q = sg + 24 * (size_t)i + 3 * j;
+            q[0] = c.x; q[1] = c.y; q[2] = c.z;
+        }
+    }
+    // profile samples: dL/dS_j = h_j to the profile basis
+    for (int j = threadIdx.x; j < n_v; j += kBlock) {
+        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1];
+        const int s = sample_basis(prof, j, n_v, Nv, dN);
+        sv[j] = s;
+        const V3<double> h = mk(cacc[3 * (size_t)j], cacc[3 * (size_t)j + 1], cacc[3 * (size_t)j + 2]);
+        for (int l = 0; l <= prof.p; ++l) {
+            double* q = qg + 24 * (size_t)j + 3 * l;
+            q[0] = Nv[l] * h.x; q[1] = Nv[l] * h.y; q[2] = Nv[l] * h.z;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+
+    // 4. gathers per control point over the samples whose span covers it
+    //    (spans are non-decreasing in the sample index)
+    for (int k = threadIdx.x; k < d.n_path; k += kBlock) {
+        int lo = 0, hi = n_u;   // first sample with span >= k
+        while (lo < hi) { const int m = (lo + hi) >> 1; if (su[m] >= k) hi = m; else lo = m + 1; }
+        V3<double> acc = mk(0.0, 0.0, 0.0);
+        for (int i = lo; i < n_u && su[i] - path.p <= k; ++i) {
+            const double* q = sg + 24 * (size_t)i + 3 * (k - (su[i] - path.p));
+            acc = acc + mk(q[0], q[1], q[2]);
+        }
+        double* o = gP + 3 * (d.path_ctrl_off + k);
+        o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+    }
+    for (int l = threadIdx.x; l < d.n_prof; l += kBlock) {
+        V3<double> acc = mk(0.0, 0.0, 0.0);
+        // basis indices wrapping onto control point l: l, and l + m on a closed curve
+        for (int kk = l; kk < prof.nb; kk += d.n_prof) {
+            int lo = 0, hi = n_v;
+            while (lo < hi) { const int m = (lo + hi) >> 1; if (sv[m] >= kk) hi = m; else lo = m + 1; }
+            for (int j = lo; j < n_v && sv[j] - prof.p <= kk; ++j) {
+                const double* q = qg + 24 * (size_t)j + 3 * (kk - (sv[j] - prof.p));
+                acc = acc + mk(q[0], q[1], q[2]);
+            }
+            if (!prof.closed) break;
+        }
+        double* o = gQ + 3 * (d.prof_ctrl_off + l);
+        o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+    }
+}
+
+BackwardKernels backward_kernels(bool t64)
+{
+    BackwardKernels k;
+    k.reduce = t64 ? (const void*)&kbw_reduce<double> : (const void*)&kbw_reduce<float>;
+    k.adjoint = (const void*)&kbw_adjoint;
+    return k;
+}
+
+}  // namespace sweep

@@ -1,31 +1,465 @@
-// batched_abi.hip -- batched evaluation and the adjoint (C ABI).
+// batched_abi.hip -- sweep_eval_batched: plans keyed by batch shape, each
+// holding the per-sweep descriptors and surface tile list in device memory
+// and a two-node HIP graph (frames, surface) that is replayed per call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <vector>
+
 #include "abi_internal.hpp"
+
+namespace sweep {
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Validated, flattened metadata of a batch plus the options that shape the
+// kernels; equality of two keys means the same plan applies.
+struct BatchKey {
+    int device = 0;
+    std::vector<int32_t> ints;     // per sweep: n_path p_path n_prof p_prof closed n_u n_v, then option ints
+    std::vector<double> dbls;      // knots, initial normal
+    bool operator==(const BatchKey& o) const { return device == o.device && ints == o.ints && dbls == o.dbls; }
+};
+
+struct BatchLayout {
+    size_t rows, ptab, agg, r_in, total;
+    long long n_rows = 0, n_vs = 0, n_chunks = 0, n_vertices = 0;
+    long long n_rowpart = 0, n_colpart = 0, n_units = 0;
+};
+
+// Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
+struct BackwardLayout {
+    size_t rows, ptab, agg, r_in, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
+};
+
+static BackwardLayout backward_layout(const BatchLayout& L)
+{
+    BackwardLayout B{};
+    size_t off = 0;
+    auto seg = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+    B.rows = seg(8 * 16 * (size_t)L.n_rows);
+    B.ptab = seg(8 * 8 * (size_t)L.n_vs);
+    B.agg = seg(8 * 9 * (size_t)L.n_chunks);
+    B.r_in = seg(8 * 3 * (size_t)L.n_chunks);
+    B.rowpart = seg(8 * 12 * (size_t)L.n_rowpart);
+    B.colpart = seg(8 * 3 * (size_t)L.n_colpart);
+    B.rowacc = seg(8 * 12 * (size_t)L.n_rows);
+    B.colacc = seg(8 * 3 * (size_t)L.n_vs);
+    B.rho = seg(8 * 3 * (size_t)L.n_rows);
+    B.sgrad = seg(8 * 24 * (size_t)L.n_rows);
+    B.spans_u = seg(4 * (size_t)L.n_rows);
+    B.qgrad = seg(8 * 24 * (size_t)L.n_vs);
+    B.spans_v = seg(4 * (size_t)L.n_vs);
+    B.total = off;
+    return B;
+}
+
+static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, BatchKey* key, BatchLayout* lay,
+                                std::vector<BatchDesc>* descs, std::vector<double>* knots)
+{
+    if (!b) return fail(SWEEP_ERR_NULL_ARG, "batch is NULL");
+    if (!o) return fail(SWEEP_ERR_NULL_ARG, "options are NULL");
+    sweep_status st = check_options(o);
+    if (st != SWEEP_OK) return st;
+    if (b->n_sweeps < 1) return fail(SWEEP_ERR_BAD_COUNT, "n_sweeps %d < 1", b->n_sweeps);
+    if (!b->path_n || !b->path_degree || !b->prof_n || !b->prof_degree || !b->n_u || !b->n_v)
+        return fail(SWEEP_ERR_NULL_ARG, "a per-sweep array is NULL");
+    const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
+    const size_t fsz = o->frame_precision == SWEEP_F64 ? 8 : 4;
+    const int chunk = frame_chunk_size();
+    long long path_off = 0, prof_off = 0, pk_off = 0, qk_off = 0;
+    BatchLayout L{};
+    if (key) key->ints.reserve(7 * (size_t)b->n_sweeps + 8);
+    for (int k = 0; k < b->n_sweeps; ++k) {
+        const int np = b->path_n[k], pp = b->path_degree[k], nq = b->prof_n[k], pq = b->prof_degree[k];
+        const int qc = b->prof_closed ? b->prof_closed[k] : 1;
+        const int nu = b->n_u[k], nv = b->n_v[k];
+        char what[64];
+        std::snprintf(what, sizeof what, "sweep %d path", k);
+        const double* pk = b->path_knots ? b->path_knots + pk_off : nullptr;
+        if ((st = check_curve_meta(np, pp, 0, pk, what, true)) != SWEEP_OK) return st;
+        std::snprintf(what, sizeof what, "sweep %d profile", k);
+        const double* qk = (b->prof_knots && !qc) ? b->prof_knots + qk_off : nullptr;
+        if ((st = check_curve_meta(nq, pq, qc, qk, what, false)) != SWEEP_OK) return st;
+        if ((st = check_grid(nu, nv)) != SWEEP_OK) {
+            return fail(st, "sweep %d: %s", k, sweep_last_error());
+        }
+        const long long nc = (nu + chunk - 1) / chunk;
+        const int nseg = (nv + 63) / 64;
+        const int ngroup = (nu + kBwRowGroup - 1) / kBwRowGroup;
+        if (descs) {
+            BatchDesc d{};
+            d.n_path = np; d.p_path = pp; d.n_prof = nq; d.p_prof = pq;
+            d.closed_prof = qc; d.n_u = nu; d.n_v = nv;
+            fastdiv_constants(nv, &d.fd_m, &d.fd_shift);
+            d.path_ctrl_off = path_off; d.prof_ctrl_off = prof_off;
+            d.path_knot_off = pk ? (long long)knots->size() : -1;
+            if (pk) knots->insert(knots->end(), pk, pk + np + pp + 1);
+            d.prof_knot_off = qk ? (long long)knots->size() : -1;
+            if (qk) knots->insert(knots->end(), qk, qk + nq + pq + 1);
+            d.out_off = L.n_vertices; d.row_off = L.n_rows; d.ptab_off = L.n_vs; d.chunk_off = L.n_chunks;
+            d.rowpart_off = L.n_rowpart; d.colpart_off = L.n_colpart; d.nseg = nseg; d.ngroup = ngroup;
+            descs->push_back(d);
+        }
+        if (key) {
+            const int32_t v[7] = {np, pp, nq, pq, qc, nu, nv};
+            key->ints.insert(key->ints.end(), v, v + 7);
+            if (pk) key->dbls.insert(key->dbls.end(), pk, pk + np + pp + 1);
+            if (qk) key->dbls.insert(key->dbls.end(), qk, qk + nq + pq + 1);
+        }
+        if (b->path_knots) pk_off += np + pp + 1;
+        if (b->prof_knots && !qc) qk_off += nq + pq + 1;
+        path_off += np; prof_off += nq;
+        L.n_vertices += (long long)nu * nv;
+        L.n_rows += nu; L.n_vs += nv; L.n_chunks += nc;
+        L.n_rowpart += (long long)nseg * nu; L.n_colpart += (long long)ngroup * nv;
+        L.n_units += (long long)nseg * ngroup;
+    }
+    if (!b->path_ctrl || !b->prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "control point buffer is NULL");
+    size_t off = 0;
+    L.rows = off; off = align_up(off + tsz * 16 * (size_t)L.n_rows);
+    L.ptab = off; off = align_up(off + tsz * 8 * (size_t)L.n_vs);
+    L.agg = off;  off = align_up(off + fsz * 9 * (size_t)L.n_chunks);
+    L.r_in = off; off = align_up(off + fsz * 3 * (size_t)L.n_chunks);
+    L.total = off;
+    if (lay) *lay = L;
+    if (key) {
+        const int32_t v[5] = {o->out_precision, o->frame_precision, o->reorthonormalize, o->has_initial_normal,
+                              o->tile_config};
+        key->ints.insert(key->ints.end(), v, v + 5);
+        if (o->has_initial_normal) key->dbls.insert(key->dbls.end(), o->initial_normal, o->initial_normal + 3);
+    }
+    return SWEEP_OK;
+}
+
+// Argument block of the two graph nodes; the node parameter arrays point here.
+struct FramesArgs {
+    const BatchDesc* descs;
+    const double* path_ctrl;
+    const double* prof_ctrl;
+    const double* knots;
+    InitialNormal n0;
+    int reorth;
+    void* agg;
+    void* r_in;
+    void* rows;
+    void* ptab;
+};
+struct SurfaceArgs {
+    const BatchDesc* descs;
+    const int2* tiles;
+    const void* rows;
+    const void* ptab;
+    void* pos;
+    void* nrm;
+};
+
+struct Plan {
+    BatchKey key;
+    BatchLayout lay;
+    int n_sweeps = 0;
+    int n_tiles = 0;
+    bool with_nrm = false;
+    BatchDesc* d_descs = nullptr;
+    int2* d_tiles = nullptr;
+    int4* d_units = nullptr;       // adjoint reduction units, built on the first backward call
+    int n_units = 0;
+    double* d_knots = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t n_frames = nullptr, n_surface = nullptr;
+    hipKernelNodeParams p_frames{}, p_surface{};
+    FramesArgs fa{};
+    SurfaceArgs sa{};
+    void* fa_ptrs[10];
+    void* sa_ptrs[6];
+    ~Plan()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (d_descs) hipFree(d_descs);
+        if (d_tiles) hipFree(d_tiles);
+        if (d_units) hipFree(d_units);
+        if (d_knots) hipFree(d_knots);
+    }
+};
+
+static std::mutex g_mu;
+static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
+static const size_t kMaxPlans = 16;
+
+static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, bool with_nrm, BatchKey&& key,
+                               std::unique_ptr<Plan>& out)
+{
+    std::unique_ptr<Plan> P(new Plan());
+    std::vector<BatchDesc> descs;
+    std::vector<double> knots;
+    sweep_status st = check_batch(b, o, nullptr, &P->lay, &descs, &knots);
+    if (st != SWEEP_OK) return st;
+    P->key = std::move(key);
+    P->n_sweeps = b->n_sweeps;
+    P->with_nrm = with_nrm;
+    // surface tiles: (sweep, first local vertex) in sweep order
+    const int tv = batched_tile_vertices();
+    std::vector<int2> tiles;
+    for (int k = 0; k < b->n_sweeps; ++k) {
+        const long long N = (long long)b->n_u[k] * b->n_v[k];
+        for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
+    }
+    if (tiles.size() > 0x7fffffffull) return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many surface tiles");
+    P->n_tiles = (int)tiles.size();
+    hipError_t e;
+    if ((e = hipMalloc(&P->d_descs, sizeof(BatchDesc) * descs.size())) != hipSuccess) return hip_fail(e, "plan alloc");
+    if ((e = hipMalloc(&P->d_tiles, sizeof(int2) * tiles.size())) != hipSuccess) return hip_fail(e, "plan alloc");
+    if (!knots.empty() && (e = hipMalloc(&P->d_knots, sizeof(double) * knots.size())) != hipSuccess)
+        return hip_fail(e, "plan alloc");
+    if ((e = hipMemcpy(P->d_descs, descs.data(), sizeof(BatchDesc) * descs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "plan upload");
+    if ((e = hipMemcpy(P->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "plan upload");
+    if (!knots.empty() &&
+        (e = hipMemcpy(P->d_knots, knots.data(), sizeof(double) * knots.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "plan upload");
+
+    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : SurfaceConfig{1, 0, 1024, 1};
+    const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
+                                             with_nrm, cfg.nontemporal != 0);
+    // argument blocks are compared bytewise on every call: clear the padding
+    std::memset(&P->fa, 0, sizeof P->fa);
+    std::memset(&P->sa, 0, sizeof P->sa);
+    P->fa.descs = P->d_descs;
+    P->fa.knots = P->d_knots;
+    P->fa.n0.enabled = o->has_initial_normal;
+    for (int c = 0; c < 3; ++c) P->fa.n0.v[c] = o->initial_normal[c];
+    P->fa.reorth = o->reorthonormalize;
+    P->sa.descs = P->d_descs;
+    P->sa.tiles = P->d_tiles;
+    void* fa[10] = {&P->fa.descs, &P->fa.path_ctrl, &P->fa.prof_ctrl, &P->fa.knots, &P->fa.n0, &P->fa.reorth,
+                    &P->fa.agg, &P->fa.r_in, &P->fa.rows, &P->fa.ptab};
+    void* sa[6] = {&P->sa.descs, &P->sa.tiles, &P->sa.rows, &P->sa.ptab, &P->sa.pos, &P->sa.nrm};
+    std::memcpy(P->fa_ptrs, fa, sizeof fa);
+    std::memcpy(P->sa_ptrs, sa, sizeof sa);
+    P->p_frames.func = const_cast<void*>(K.frames);
+    P->p_frames.gridDim = dim3(b->n_sweeps);
+    P->p_frames.blockDim = dim3(kBlock);
+    P->p_frames.sharedMemBytes = 0;
+    P->p_frames.kernelParams = P->fa_ptrs;
+    P->p_frames.extra = nullptr;
+    P->p_surface.func = const_cast<void*>(K.surface);
+    P->p_surface.gridDim = dim3(P->n_tiles);
+    P->p_surface.blockDim = dim3(kBlock);
+    P->p_surface.sharedMemBytes = 0;
+    P->p_surface.kernelParams = P->sa_ptrs;
+    P->p_surface.extra = nullptr;
+    if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
+    if ((e = hipGraphAddKernelNode(&P->n_frames, P->graph, nullptr, 0, &P->p_frames)) != hipSuccess)
+        return hip_fail(e, "graph frames node");
+    if ((e = hipGraphAddKernelNode(&P->n_surface, P->graph, &P->n_frames, 1, &P->p_surface)) != hipSuccess)
+        return hip_fail(e, "graph surface node");
+    if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, "graph instantiate");
+    out = std::move(P);
+    return SWEEP_OK;
+}
+
+// Finds or builds the plan of this batch shape (caller holds g_mu).
+static sweep_status get_plan(const sweep_batch* b, const sweep_options* o, bool with_nrm, BatchKey&& key, Plan** out)
+{
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+        if ((*it)->key == key) {
+            g_plans.splice(g_plans.begin(), g_plans, it);
+            *out = g_plans.front().get();
+            return SWEEP_OK;
+        }
+    }
+    std::unique_ptr<Plan> np;
+    sweep_status st = build_plan(b, o, with_nrm, std::move(key), np);
+    if (st != SWEEP_OK) return st;
+    g_plans.push_front(std::move(np));
+    while (g_plans.size() > kMaxPlans) g_plans.pop_back();
+    *out = g_plans.front().get();
+    return SWEEP_OK;
+}
+
+static size_t batched_ws_size(const sweep_batch* b, const sweep_options* o)
+{
+    BatchLayout L;
+    if (check_batch(b, o, nullptr, &L, nullptr, nullptr) != SWEEP_OK) return 0;
+    return L.total;
+}
+
+}  // namespace sweep
 
 using namespace sweep;
 
 extern "C" {
 
-size_t sweep_batched_workspace_size(const sweep_batch* batch, const sweep_options* opt) { (void)batch; (void)opt; return 0; }
+size_t sweep_batched_workspace_size(const sweep_batch* batch, const sweep_options* opt)
+{
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    return batched_ws_size(batch, opt);
+}
 
 sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* opt, void* pos, void* nrm,
                                 void* workspace, size_t ws_bytes, void* stream)
 {
-    (void)batch; (void)opt; (void)pos; (void)nrm; (void)workspace; (void)ws_bytes; (void)stream;
-    return fail(SWEEP_ERR_UNSUPPORTED, "not built yet");
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    BatchKey key;
+    BatchLayout L;
+    sweep_status st = check_batch(batch, opt, &key, &L, nullptr, nullptr);
+    if (st != SWEEP_OK) return st;
+    if (!pos) return fail(SWEEP_ERR_NULL_ARG, "pos is NULL");
+    if (!workspace || ws_bytes < L.total)
+        return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, L.total);
+    if (((uintptr_t)workspace) % 256 != 0) return fail(SWEEP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    hipError_t e = hipGetDevice(&key.device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    key.ints.push_back(nrm ? 1 : 0);
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    Plan* P = nullptr;
+    if ((st = get_plan(batch, opt, nrm != nullptr, std::move(key), &P)) != SWEEP_OK) return st;
+    char* ws = (char*)workspace;
+    FramesArgs fa;
+    std::memcpy(&fa, &P->fa, sizeof fa);
+    fa.path_ctrl = batch->path_ctrl;
+    fa.prof_ctrl = batch->prof_ctrl;
+    fa.agg = ws + L.agg;
+    fa.r_in = ws + L.r_in;
+    fa.rows = ws + L.rows;
+    fa.ptab = ws + L.ptab;
+    SurfaceArgs sa;
+    std::memcpy(&sa, &P->sa, sizeof sa);
+    sa.rows = ws + L.rows;
+    sa.ptab = ws + L.ptab;
+    sa.pos = pos;
+    sa.nrm = nrm;
+    if (std::memcmp(&fa, &P->fa, sizeof fa) != 0) {
+        P->fa = fa;
+        if ((e = hipGraphExecKernelNodeSetParams(P->exec, P->n_frames, &P->p_frames)) != hipSuccess)
+            return hip_fail(e, "graph update");
+    }
+    if (std::memcmp(&sa, &P->sa, sizeof sa) != 0) {
+        P->sa = sa;
+        if ((e = hipGraphExecKernelNodeSetParams(P->exec, P->n_surface, &P->p_surface)) != hipSuccess)
+            return hip_fail(e, "graph update");
+    }
+    if ((e = hipGraphLaunch(P->exec, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "graph launch");
+    return SWEEP_OK;
 }
 
-size_t sweep_backward_workspace_size(const sweep_batch* batch, const sweep_options* opt) { (void)batch; (void)opt; return 0; }
+size_t sweep_backward_workspace_size(const sweep_batch* batch, const sweep_options* opt)
+{
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    BatchLayout L;
+    if (check_batch(batch, opt, nullptr, &L, nullptr, nullptr) != SWEEP_OK) return 0;
+    return backward_layout(L).total;
+}
 
 sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, const void* grad_pos,
                             double* grad_path_ctrl, double* grad_prof_ctrl, void* workspace, size_t ws_bytes,
                             void* stream)
 {
-    (void)batch; (void)opt; (void)grad_pos; (void)grad_path_ctrl; (void)grad_prof_ctrl; (void)workspace; (void)ws_bytes; (void)stream;
-    return fail(SWEEP_ERR_UNSUPPORTED, "not built yet");
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    BatchKey key;
+    BatchLayout L;
+    sweep_status st = check_batch(batch, opt, &key, &L, nullptr, nullptr);
+    if (st != SWEEP_OK) return st;
+    if (!grad_pos || !grad_path_ctrl || !grad_prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "a gradient buffer is NULL");
+    const BackwardLayout B = backward_layout(L);
+    if (!workspace || ws_bytes < B.total)
+        return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, B.total);
+    if (((uintptr_t)workspace) % 256 != 0) return fail(SWEEP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    hipError_t e = hipGetDevice(&key.device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    key.ints.push_back(1);   // plans are shared with the forward call that writes normals
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    Plan* P = nullptr;
+    if ((st = get_plan(batch, opt, true, std::move(key), &P)) != SWEEP_OK) return st;
+    if (!P->d_units) {
+        std::vector<int4> units;
+        units.reserve((size_t)L.n_units);
+        for (int k = 0; k < batch->n_sweeps; ++k) {
+            const int ng = (batch->n_u[k] + kBwRowGroup - 1) / kBwRowGroup, ns = (batch->n_v[k] + 63) / 64;
+            for (int g = 0; g < ng; ++g)
+                for (int sg = 0; sg < ns; ++sg) units.push_back(make_int4(k, g, sg, 0));
+        }
+        if ((e = hipMalloc(&P->d_units, sizeof(int4) * units.size())) != hipSuccess) return hip_fail(e, "plan alloc");
+        if ((e = hipMemcpy(P->d_units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "plan upload");
+        P->n_units = (int)units.size();
+    }
+    hipStream_t sm = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    const BatchedKernels FK = batched_kernels(true, true, false, false);
+    const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64);
+    {
+        FramesArgs fa = P->fa;
+        fa.path_ctrl = batch->path_ctrl;
+        fa.prof_ctrl = batch->prof_ctrl;
+        fa.reorth = 1;
+        fa.agg = ws + B.agg;
+        fa.r_in = ws + B.r_in;
+        fa.rows = ws + B.rows;
+        fa.ptab = ws + B.ptab;
+        void* args[10] = {&fa.descs, &fa.path_ctrl, &fa.prof_ctrl, &fa.knots, &fa.n0, &fa.reorth,
+                          &fa.agg, &fa.r_in, &fa.rows, &fa.ptab};
+        if ((e = hipLaunchKernel(FK.frames, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward frames");
+    }
+    {
+        const BatchDesc* descs = P->d_descs;
+        const int4* units = P->d_units;
+        int n_units = P->n_units;
+        const void* g = grad_pos;
+        const void* rows = ws + B.rows;
+        const void* ptab = ws + B.ptab;
+        void* rowpart = ws + B.rowpart;
+        void* colpart = ws + B.colpart;
+        void* args[8] = {&descs, &units, &n_units, &g, &rows, &ptab, &rowpart, &colpart};
+        const unsigned grid = (unsigned)((n_units + kWaves - 1) / kWaves);
+        if ((e = hipLaunchKernel(BK.reduce, dim3(grid), dim3(kBlock), args, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward reduce");
+    }
+    {
+        const BatchDesc* descs = P->d_descs;
+        const double* pc = batch->path_ctrl;
+        const double* qc = batch->prof_ctrl;
+        const double* kn = P->d_knots;
+        InitialNormal n0 = P->fa.n0;
+        const void* rows = ws + B.rows;
+        const void* rowpart = ws + B.rowpart;
+        const void* colpart = ws + B.colpart;
+        void* rowacc = ws + B.rowacc;
+        void* colacc = ws + B.colacc;
+        void* rho = ws + B.rho;
+        void* sgrad = ws + B.sgrad;
+        void* spans_u = ws + B.spans_u;
+        void* qgrad = ws + B.qgrad;
+        void* spans_v = ws + B.spans_v;
+        double* gp = grad_path_ctrl;
+        double* gq = grad_prof_ctrl;
+        void* args[17] = {&descs, &pc, &qc, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc, &rho,
+                          &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq};
+        if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward adjoint");
+    }
+    return SWEEP_OK;
 }
 
-void sweep_release_caches(void) {}
-
+void sweep_release_caches(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_plans.clear();
 }
+
+}  // extern "C"

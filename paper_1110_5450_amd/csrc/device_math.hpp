@@ -57,7 +57,7 @@ template <class F> __device__ __forceinline__ V3<F> apply(const M3<F>& a, V3<F> 
 
 struct DCurve {
     const double* __restrict__ ctrl;   // n x 3
-    const double* __restrict__ knots;  // nb + p + 1
+    const double* __restrict__ knots;  // nb + p + 1 given knots, or nullptr for the default vector
     int n;       // distinct control points
     int p;       // degree
     int closed;  // periodic uniform
@@ -71,6 +71,17 @@ __device__ __forceinline__ V3<double> ctrl_pt(const DCurve& c, int k)
     return {q[0], q[1], q[2]};
 }
 
+// Knot k: the given vector, else periodic U_k = k, else clamped uniform
+// 0 (k <= p), 1 (k >= n), (k-p)/(n-p) as one correctly rounded division.
+__device__ __forceinline__ double knot(const DCurve& c, int k)
+{
+    if (c.knots) return c.knots[k];
+    if (c.closed) return (double)k;
+    if (k <= c.p) return 0.0;
+    if (k >= c.n) return 1.0;
+    return (double)(k - c.p) / (double)(c.n - c.p);
+}
+
 // Sample parameter i of ns.  Open: u = a + (b - a) * (i / (ns - 1)), with the
 // last sample exactly b; closed: p + (n*i)/ns.  Each operation is rounded as
 // written (no contraction), so samples that fall on a knot land on it exactly.
@@ -78,7 +89,7 @@ __device__ __forceinline__ double sample_param(const DCurve& c, int i, int ns)
 {
 #pragma clang fp contract(off)
     if (c.closed) return (double)c.p + (double)((long long)c.n * (long long)i) / (double)ns;
-    const double a = c.knots[c.p], b = c.knots[c.n];
+    const double a = knot(c, c.p), b = knot(c, c.n);
     if (i == ns - 1) return b;
     const double f = (double)i / (double)(ns - 1);
     const double w = b - a;
@@ -86,11 +97,22 @@ __device__ __forceinline__ double sample_param(const DCurve& c, int i, int ns)
     return a + g;
 }
 
-// Largest k in [p, nb-1] with U_k <= u; nb-1 when u >= U_nb.
-__device__ __forceinline__ int find_span(const double* __restrict__ U, int nb, int p, double u)
+// Span of sample i: the largest k in [p, nb-1] with U_k <= u (nb-1 at the
+// right end).  For the default knots the comparison U_k <= u_i is a
+// comparison of two correctly rounded quotients of small integers, which
+// agrees with the comparison of the exact rationals, so the span follows
+// from integer arithmetic: p + floor(i (n-p) / (ns-1)) (open) or
+// p + floor(n i / ns) (closed).  Given knots: binary search.
+__device__ __forceinline__ int sample_span(const DCurve& c, int i, int ns, double u)
 {
-    if (u >= U[nb]) return nb - 1;
-    int lo = p, hi = nb - 1;
+    if (!c.knots) {
+        if (c.closed) return c.p + (int)(((long long)c.n * (long long)i) / ns);
+        const int s = c.p + (int)(((long long)i * (long long)(c.n - c.p)) / (ns - 1));
+        return s < c.n - 1 ? s : c.n - 1;
+    }
+    const double* __restrict__ U = c.knots;
+    if (u >= U[c.nb]) return c.nb - 1;
+    int lo = c.p, hi = c.nb - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (U[mid] <= u) lo = mid; else hi = mid - 1;
@@ -98,7 +120,7 @@ __device__ __forceinline__ int find_span(const double* __restrict__ U, int nb, i
     return lo;
 }
 
-// C and derivatives up to order ND at u for a degree-P B-spline.
+// C and derivatives up to order ND at u (in span s) for a degree-P B-spline.
 // Basis values of degrees P, P-1, P-2 come from one triangular sweep of the
 // Cox-de Boor recursion (one division per knot interval and degree);
 // derivatives use the derivative control nets
@@ -106,10 +128,12 @@ __device__ __forceinline__ int find_span(const double* __restrict__ U, int nb, i
 //   R_k = (P-1)(Q_{k+1} - Q_k) / (U_{k+P+1} - U_{k+2}),
 // whose denominators are positive on a non-empty span.
 template <int P, int ND>
-__device__ __forceinline__ void curve_derivs(const DCurve& c, double u, V3<double>* out)
+__device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V3<double>* out)
 {
-    const double* __restrict__ U = c.knots;
-    const int s = find_span(U, c.nb, P, u);
+    double Uk[2 * P + 1];   // U_{s-P+1+m}, m = 0..2P-1 (index 2P unused)
+#pragma unroll
+    for (int m = 0; m < 2 * P; ++m) Uk[m] = knot(c, s - P + 1 + m);
+#define UK(k) Uk[(k) - (s - P + 1)]
     double B[P + 1];
     double D1[P > 0 ? P : 1];
     double D2[P > 1 ? P - 1 : 1];
@@ -123,7 +147,7 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, V3<doubl
         double carry = 0.0;
 #pragma unroll
         for (int j = 0; j < q; ++j) {
-            const double lo = U[s - q + j + 1], hi = U[s + j + 1];
+            const double lo = Uk[P - q + j], hi = Uk[P + j];   // U_{s-q+j+1}, U_{s+j+1}
             const double tmp = B[j] / (hi - lo);
             nb_[j] = carry + (hi - u) * tmp;
             carry = (u - lo) * tmp;
@@ -150,7 +174,7 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, V3<doubl
     if (ND >= 1) {
         V3<double> Q1[P > 0 ? P : 1];
 #pragma unroll
-        for (int j = 0; j < P; ++j) Q1[j] = ((double)P / (U[s + j + 1] - U[s - P + j + 1])) * (Pt[j + 1] - Pt[j]);
+        for (int j = 0; j < P; ++j) Q1[j] = ((double)P / (Uk[P + j] - Uk[j])) * (Pt[j + 1] - Pt[j]);
         V3<double> C1 = mk(0.0, 0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < P; ++j) C1 = C1 + D1[j] * Q1[j];
@@ -160,26 +184,37 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, V3<doubl
             if (P >= 2) {
 #pragma unroll
                 for (int j = 0; j + 1 < P; ++j) {
-                    const V3<double> R = ((double)(P - 1) / (U[s + j + 1] - U[s - P + j + 2])) * (Q1[j + 1] - Q1[j]);
+                    const V3<double> R = ((double)(P - 1) / (Uk[P + j] - Uk[j + 1])) * (Q1[j + 1] - Q1[j]);
                     C2 = C2 + D2[j] * R;
                 }
             }
             out[2] = C2;
         }
     }
+#undef UK
 }
 
+// Sample i of ns: parameter, span and derivatives up to order ND.
+template <int P, int ND>
+__device__ __forceinline__ void sample_derivs(const DCurve& c, int i, int ns, V3<double>* out)
+{
+    const double u = sample_param(c, i, ns);
+    curve_derivs<P, ND>(c, u, sample_span(c, i, ns, u), out);
+}
+
+// Runtime degree dispatch (uniform branch) for kernels that serve curves of
+// any degree.
 template <int ND>
-__device__ __noinline__ void curve_eval(const DCurve& c, double u, V3<double>* out)
+__device__ __forceinline__ void sample_derivs_any(const DCurve& c, int i, int ns, V3<double>* out)
 {
     switch (c.p) {
-    case 1: curve_derivs<1, ND>(c, u, out); break;
-    case 2: curve_derivs<2, ND>(c, u, out); break;
-    case 3: curve_derivs<3, ND>(c, u, out); break;
-    case 4: curve_derivs<4, ND>(c, u, out); break;
-    case 5: curve_derivs<5, ND>(c, u, out); break;
-    case 6: curve_derivs<6, ND>(c, u, out); break;
-    default: curve_derivs<7, ND>(c, u, out); break;
+    case 1: sample_derivs<1, ND>(c, i, ns, out); break;
+    case 2: sample_derivs<2, ND>(c, i, ns, out); break;
+    case 3: sample_derivs<3, ND>(c, i, ns, out); break;
+    case 4: sample_derivs<4, ND>(c, i, ns, out); break;
+    case 5: sample_derivs<5, ND>(c, i, ns, out); break;
+    case 6: sample_derivs<6, ND>(c, i, ns, out); break;
+    default: sample_derivs<7, ND>(c, i, ns, out); break;
     }
 }
 

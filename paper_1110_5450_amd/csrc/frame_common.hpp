@@ -1,0 +1,149 @@
+// frame_common.hpp -- device steps of the frame computation shared by the
+// single-sweep kernels (frame_kernels.hip) and the batched kernel
+// (batched_kernels.hip).  Both call these same functions in the same order on
+// the same values, so a sweep evaluated alone or inside a batch produces
+// bitwise identical row records.
+#pragma once
+
+#include "device_math.hpp"
+#include "kernels.hpp"
+
+namespace sweep {
+
+// Samples per chunk of the frame scan: one per thread.
+constexpr int kChunk = kBlock;
+
+__device__ __forceinline__ V3<double> unit_of(V3<double> d) { return divs(d, sqrt(dot(d, d))); }
+
+// Positions and resolved tangents of sample i (this thread) and i+1.
+struct StepInputs {
+    V3<double> x0, x1, t0, t1;
+    bool has_step;   // i + 1 < n_u
+};
+
+// Tangent resolution for the step i -> i+1 of one block.  Inputs: own sample
+// (x0, d0 = C'_i, valid0), next sample (x1, d1, valid1, has_step), lv = the
+// last sample <= i with C' != 0 (or -1) and d_lv = its C' (used when i itself
+// is not valid), fallback tangent fb.
+__device__ __forceinline__ StepInputs resolve_step(V3<double> x0, V3<double> d0, bool valid0, V3<double> x1,
+                                                   V3<double> d1, bool valid1, bool has_step, int lv,
+                                                   V3<double> d_lv, V3<double> fb)
+{
+    StepInputs s;
+    s.x0 = x0;
+    s.x1 = has_step ? x1 : x0;
+    s.has_step = has_step;
+    s.t0 = valid0 ? unit_of(d0) : (lv >= 0 ? unit_of(d_lv) : fb);
+    s.t1 = (has_step && valid1) ? unit_of(d1) : s.t0;
+    return s;
+}
+
+template <class F>
+__device__ __forceinline__ M3<F> step_of(const StepInputs& s)
+{
+    M3<F> M = ident<F>();
+    if (s.has_step) step_matrix<F>(cvt<F>(s.x1 - s.x0), cvt<F>(s.t0), cvt<F>(s.t1), M);
+    return M;
+}
+
+// Initial normal r_0 from the resolved t_0: the given normal projected onto
+// t_0^perp when that projection exceeds 1e-8, else the axis rule.
+__device__ __forceinline__ V3<double> initial_normal(V3<double> t0, const InitialNormal& n0)
+{
+    if (n0.enabled) {
+        const V3<double> n = mk(n0.v[0], n0.v[1], n0.v[2]);
+        const V3<double> q = n - dot(n, t0) * t0;
+        const double L = sqrt(dot(q, q));
+        if (L > 1e-8) return divs(q, L);
+    }
+    return axis_normal(t0);
+}
+
+// r_in[c] = (A_{c-1} ... A_0) r_0 for c < n_chunks, by one block (all threads).
+template <class F>
+__device__ void carry_scan(const F* agg, int n_chunks, V3<double> r0d, F* __restrict__ r_in, M3<F>* lds_m)
+{
+    const V3<F> r0 = cvt<F>(r0d);
+    constexpr int kPer = 4;
+    M3<F> running = ident<F>();
+    for (int base = 0; base < n_chunks; base += kBlock * kPer) {
+        M3<F> A[kPer];
+        M3<F> prod = ident<F>();
+        const int c0 = base + threadIdx.x * kPer;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int c = c0 + k;
+            if (c < n_chunks) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) A[k].m[e] = __builtin_nontemporal_load(agg + 9 * (size_t)c + e);
+            } else {
+                A[k] = ident<F>();
+            }
+            prod = mul(A[k], prod);
+        }
+        M3<F> total;
+        M3<F> ex = mul(block_exclusive_product<F>(prod, lds_m, total), running);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int c = c0 + k;
+            if (c < n_chunks) {
+                const V3<F> r = apply(ex, r0);
+                r_in[3 * (size_t)c] = r.x; r_in[3 * (size_t)c + 1] = r.y; r_in[3 * (size_t)c + 2] = r.z;
+            }
+            ex = mul(A[k], ex);
+        }
+        running = mul(total, running);
+    }
+}
+
+// Row record of sample i: x, r (re-orthonormalised if asked), s = t x r, t,
+// |C'|, a = r.C''/|C'|, b = s.C''/|C'| (0 where C' = 0), in precision T.
+template <class F, class T>
+__device__ __forceinline__ void write_row(const StepInputs& s, const M3<F>& ex, const F* rb, V3<double> C1,
+                                          V3<double> C2, int reorth, T* __restrict__ q)
+{
+    const V3<F> t = cvt<F>(s.t0);
+    V3<F> r = apply(ex, mk(rb[0], rb[1], rb[2]));
+    if (reorth) {
+        const V3<F> w = r - dot(r, t) * t;
+        r = divs(w, (F)sqrt(dot(w, w)));
+    }
+    const V3<F> sv = cross(t, r);
+    const double L = sqrt(dot(C1, C1));
+    F a = F(0), b = F(0);
+    if (L > 0.0) {
+        const V3<F> c2 = cvt<F>(C2);
+        a = dot(r, c2) / (F)L;
+        b = dot(sv, c2) / (F)L;
+    }
+    q[0] = (T)s.x0.x; q[1] = (T)s.x0.y; q[2] = (T)s.x0.z;
+    q[3] = (T)r.x; q[4] = (T)r.y; q[5] = (T)r.z;
+    q[6] = (T)sv.x; q[7] = (T)sv.y; q[8] = (T)sv.z;
+    q[9] = (T)t.x; q[10] = (T)t.y; q[11] = (T)t.z;
+    q[12] = (T)L; q[13] = (T)a; q[14] = (T)b; q[15] = T(0);
+}
+
+// Profile record of sample j: S (3), S' (3), 0, 0.
+template <class T>
+__device__ __forceinline__ void write_profile(const DCurve& prof, int j, int n_v, T* __restrict__ tab)
+{
+    V3<double> o[2];
+    sample_derivs_any<1>(prof, j, n_v, o);
+    T* q = tab + 8 * (size_t)j;
+    q[0] = (T)o[0].x; q[1] = (T)o[0].y; q[2] = (T)o[0].z;
+    q[3] = (T)o[1].x; q[4] = (T)o[1].y; q[5] = (T)o[1].z;
+    q[6] = T(0); q[7] = T(0);
+}
+
+// Unit direction of the first nonzero control-polygon leg, else e_z.
+__device__ __forceinline__ V3<double> first_leg(const DCurve& path)
+{
+    for (int k = 0; k + 1 < path.n; ++k) {
+        const V3<double> d = ctrl_pt(path, k + 1) - ctrl_pt(path, k);
+        const double L2 = dot(d, d);
+        if (L2 > 0.0) return divs(d, sqrt(L2));
+    }
+    return mk(0.0, 0.0, 1.0);
+}
+
+}  // namespace sweep

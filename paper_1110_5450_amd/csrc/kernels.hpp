@@ -16,24 +16,22 @@ struct InitialNormal {
 
 int frame_chunk_size();
 
-// Default knot vector (clamped uniform, or periodic U_k = k) written on the device.
-hipError_t launch_fill_knots(double* U, int n, int p, int closed, hipStream_t st);
-
-hipError_t launch_path_samples(const DCurve& path, int n_u, double* smp, int* chunk_lv, double* fallback_t,
-                               hipStream_t st);
+// Path samples (x, C', C'' as SoA planes of n_u doubles), per-chunk last
+// valid sample, fallback tangent, ticket reset, and the profile table.
 template <class T>
-hipError_t launch_profile_table(const DCurve& prof, int n_v, T* tab, hipStream_t st);
+hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
+                       double* fallback_t, unsigned* ticket, T* ptab, hipStream_t st);
+// Frame scan and row table (16 values per u-row).
 template <class F, class T>
-hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t,
+hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, unsigned* ticket,
                         InitialNormal n0, int reorth, F* agg, F* r_in, T* rows, hipStream_t st);
 
 // Surface write of one sweep from its row table (16 values per u-row) and
 // profile table (8 values per v-sample).
 struct SurfaceConfig {
-    int kind;           // 0: column-stationary vector stores, 1: linear dword stores
-    int rows_per_block; // kind 0
-    int tile_vertices;  // kind 1: vertices per block-tile (multiple of 256)
-    int grid;           // kind 1: persistent grid size (0 = one block per tile)
+    int kind;           // 0: column tiles (n_v >= 256), 1: linear with LDS-staged rows (any shape)
+    int rows_per_block; // kind 0: rows R per block
+    int tile_vertices;  // kind 1: vertices per block, 256*K with K in {1, 2, 4, 8}
     int nontemporal;    // nontemporal stores
 };
 
@@ -41,6 +39,47 @@ template <class T>
 hipError_t launch_surface(const T* rows, const T* prof, int n_u, int n_v, T* pos, T* nrm,
                           const SurfaceConfig& cfg, hipStream_t st);
 
-bool surface_cols_supported(int n_v, const void* pos, const void* nrm, size_t elem);
+
+// ----------------------------------------------------------------- batched
+
+// Per-sweep descriptor of a batch (device array, filled on the host).
+struct BatchDesc {
+    int n_path, p_path, n_prof, p_prof;
+    int closed_prof, n_u, n_v, fd_shift;
+    unsigned long long fd_m;       // floor(v / n_v) = (v * fd_m) >> fd_shift for v < 2^31
+    long long path_ctrl_off;       // in points
+    long long prof_ctrl_off;
+    long long path_knot_off;       // into the batch knot array, -1 = default knots
+    long long prof_knot_off;
+    long long out_off;             // vertex offset: positions start at element 3 * out_off
+    long long row_off;             // first row record
+    long long ptab_off;            // first profile record
+    long long chunk_off;           // first chunk product / entry normal
+    long long rowpart_off;         // adjoint: first per-segment row partial (12 doubles each)
+    long long colpart_off;         // adjoint: first per-group column partial (3 doubles each)
+    int nseg, ngroup;              // adjoint: 64-column segments, row groups
+};
+
+// Rows per reduction group in the adjoint's streaming read of dL/dX.
+constexpr int kBwRowGroup = 16;
+
+struct BackwardKernels {
+    const void* reduce;
+    const void* adjoint;
+};
+BackwardKernels backward_kernels(bool t64);
+
+// Fast division constants for 0 <= v < 2^31.
+void fastdiv_constants(int d, unsigned long long* m, int* shift);
+
+struct BatchedKernels {
+    const void* frames;
+    const void* surface;
+};
+// Kernel entry points for a precision combination (host stubs usable as
+// graph kernel-node functions).
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal);
+// Vertices per surface block in the batched surface kernel.
+int batched_tile_vertices();
 
 }  // namespace sweep

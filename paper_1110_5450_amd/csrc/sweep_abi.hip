@@ -131,30 +131,25 @@ int nknots(int n, int p, int closed) { return nbasis(n, p, closed) + p + 1; }
 
 // Fixed surface configurations (tile_config >= 0); -1 picks automatically.
 static const SurfaceConfig kTiles[] = {
-    {0, 8, 0, 0, 0},  {0, 16, 0, 0, 0}, {0, 32, 0, 0, 0}, {0, 64, 0, 0, 0},
-    {0, 8, 0, 0, 1},  {0, 16, 0, 0, 1}, {0, 32, 0, 0, 1}, {0, 64, 0, 0, 1},
-    {1, 0, 2048, 0, 0}, {1, 0, 4096, 0, 0}, {1, 0, 8192, 0, 0}, {1, 0, 4096, 2048, 0},
-    {1, 0, 2048, 0, 1}, {1, 0, 4096, 0, 1}, {1, 0, 8192, 0, 1}, {1, 0, 4096, 2048, 1},
+    {0, 1, 0, 0}, {0, 2, 0, 0}, {0, 4, 0, 0}, {0, 8, 0, 0},
+    {0, 1, 0, 1}, {0, 2, 0, 1}, {0, 4, 0, 1}, {0, 8, 0, 1},
+    {1, 0, 256, 0}, {1, 0, 512, 0}, {1, 0, 1024, 0}, {1, 0, 2048, 0},
+    {1, 0, 256, 1}, {1, 0, 512, 1}, {1, 0, 1024, 1}, {1, 0, 2048, 1},
 };
 
 int tile_config_count() { return (int)(sizeof kTiles / sizeof kTiles[0]); }
 
 const SurfaceConfig& tile_config(int k) { return kTiles[k]; }
 
-// Automatic choice for a single sweep: the column-stationary kernel when its
-// columns fill whole 1024-column tiles at least 3/4 of the time, with enough
-// row groups for ~8 blocks per CU; otherwise the linear kernel.
-SurfaceConfig auto_surface_config(int n_u, int n_v, bool cols_ok)
+// Automatic choice for a single sweep (nontemporal stores, which measured
+// 15-25 % faster for this write-once output): column tiles of one row when
+// n_v fills whole 256-column tiles, otherwise the linear kernel with 4
+// vertices per lane.
+SurfaceConfig auto_surface_config(int n_u, int n_v)
 {
-    if (cols_ok && n_v >= 768) {
-        const int tiles = (n_v + 1023) / 1024;
-        if ((double)n_v / (tiles * 1024.0) >= 0.75) {
-            long long target = 2048;
-            int rpb = (int)std::max(1LL, std::min(64LL, (long long)n_u * tiles / target));
-            return SurfaceConfig{0, rpb, 0, 0, 0};
-        }
-    }
-    return SurfaceConfig{1, 0, 4096, 0, 0};
+    (void)n_u;
+    if (n_v % 256 == 0) return SurfaceConfig{0, 1, 0, 1};
+    return SurfaceConfig{1, 0, 1024, 1};
 }
 
 // ---------------------------------------------------------- workspace plan
@@ -162,7 +157,7 @@ SurfaceConfig auto_surface_config(int n_u, int n_v, bool cols_ok)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, fallback, agg, r_in, rows, prof_tab, total;
+    size_t knots_path, knots_prof, smp, chunk_lv, fallback, ticket, agg, r_in, rows, prof_tab, total;
 };
 
 static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz)
@@ -175,6 +170,7 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
     L.smp = off;        off = align_up(off + sizeof(double) * 9 * (size_t)n_u);
     L.chunk_lv = off;   off = align_up(off + sizeof(int) * (size_t)nc);
     L.fallback = off;   off = align_up(off + sizeof(double) * 3);
+    L.ticket = off;     off = align_up(off + sizeof(unsigned));
     L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
     L.r_in = off;       off = align_up(off + fsz * 3 * (size_t)nc);
     L.rows = off;       off = align_up(off + tsz * 16 * (size_t)n_u);
@@ -191,13 +187,12 @@ static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof,
     return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz);
 }
 
-sweep_status upload_knots(const double* host_knots, int n, int p, int closed, double* dst, hipStream_t st)
+// Copies given knots to the device (a blocking copy from pageable memory);
+// default knots are computed on the fly by the kernels (dst unused).
+sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, hipStream_t st)
 {
-    hipError_t e;
-    if (host_knots)
-        e = hipMemcpyAsync(dst, host_knots, sizeof(double) * nknots(n, p, 0), hipMemcpyHostToDevice, st);
-    else
-        e = launch_fill_knots(dst, n, p, closed, st);
+    if (!host_knots) return SWEEP_OK;
+    hipError_t e = hipMemcpyAsync(dst, host_knots, sizeof(double) * nknots(n, p, 0), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "knots");
     return SWEEP_OK;
 }
@@ -209,35 +204,29 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
 {
     double* Up = (double*)(ws + L.knots_path);
     double* Uq = (double*)(ws + L.knots_prof);
-    sweep_status s = upload_knots(path->knots, path->n_ctrl, path->degree, 0, Up, st);
+    sweep_status s = upload_knots(path->knots, path->n_ctrl, path->degree, Up, st);
     if (s != SWEEP_OK) return s;
-    s = upload_knots(prof->knots, prof->n_ctrl, prof->degree, prof->closed, Uq, st);
+    s = upload_knots(prof->knots, prof->n_ctrl, prof->degree, Uq, st);
     if (s != SWEEP_OK) return s;
     trace_mark(0, st);
-    DCurve dp{path->ctrl, Up, path->n_ctrl, path->degree, 0, nbasis(path->n_ctrl, path->degree, 0)};
-    DCurve dq{prof->ctrl, Uq, prof->n_ctrl, prof->degree, prof->closed, nbasis(prof->n_ctrl, prof->degree, prof->closed)};
+    DCurve dp{path->ctrl, path->knots ? Up : nullptr, path->n_ctrl, path->degree, 0,
+              nbasis(path->n_ctrl, path->degree, 0)};
+    DCurve dq{prof->ctrl, prof->knots ? Uq : nullptr, prof->n_ctrl, prof->degree, prof->closed,
+              nbasis(prof->n_ctrl, prof->degree, prof->closed)};
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
+    unsigned* ticket = (unsigned*)(ws + L.ticket);
     T* rows = (T*)(ws + L.rows);
     T* ptab = (T*)(ws + L.prof_tab);
-    hipError_t e = launch_path_samples(dp, n_u, smp, clv, fb, st);
-    if (e != hipSuccess) return hip_fail(e, "path samples");
-    e = launch_profile_table<T>(dq, n_v, ptab, st);
-    if (e != hipSuccess) return hip_fail(e, "profile table");
+    hipError_t e = launch_prep<T>(dp, n_u, dq, n_v, smp, clv, fb, ticket, ptab, st);
+    if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
-    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in), rows, st);
+    e = launch_frame<F, T>(smp, n_u, clv, fb, ticket, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
+                           rows, st);
     if (e != hipSuccess) return hip_fail(e, "frame");
     trace_mark(1, st);
-    const bool cols_ok = surface_cols_supported(n_v, pos, nrm, sizeof(T));
-    SurfaceConfig cfg;
-    if (o->tile_config >= 0) {
-        cfg = tile_config(o->tile_config);
-        if (cfg.kind == 0 && !cols_ok)
-            return fail(SWEEP_ERR_UNSUPPORTED, "tile_config %d needs n_v %% 4 == 0 and 16-byte aligned outputs", o->tile_config);
-    } else {
-        cfg = auto_surface_config(n_u, n_v, cols_ok);
-    }
+    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : auto_surface_config(n_u, n_v);
     e = launch_surface<T>(rows, ptab, n_u, n_v, (T*)pos, (T*)nrm, cfg, st);
     if (e != hipSuccess) return hip_fail(e, "surface");
     trace_mark(2, st);
