@@ -4,14 +4,21 @@
 One step = one sweep_eval call over the large single sweep (path: cubic,
 1024 control points, 3-D random walk; profile: closed cubic, 64 control
 points, radius 0.3 +-10 %; grid 65536 x 1024 = 67,108,864 vertices; FP32
-positions and normals, FP64 frame scan): knots, curve samples, profile table,
-frame scan, row table and surface write, all in libsweep's HIP kernels.
-Inputs (control points) are resident in device memory before timing.
+positions and normals, FP64 frame scan): curve samples, profile table, frame
+scan, row table and surface write, all in libsweep's HIP kernels.  Inputs
+(control points) are resident in device memory before timing.
 
 Prints one JSON line: vertices/s over the timed steps, the surface kernel's
 roofline figures (HIP events around every surface launch in the timed
-region, on the launch stream), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+region, on the launch stream), the error against the FP64 oracle on sampled
+rows, the variants named by the metric (plain FP64 output; the 4096-sweep
+batch in one graph launch versus the same sweeps as FP64 single calls; the
+adjoint), and the FP64 CPU oracle timed on the same workload.
+
+`--precision-study` instead prints the precision-study report (FP32 / FP64
+frame scan, with and without re-orthonormalisation, on the 1,048,576 x 32
+grid): time, frame error and orthonormality drift against the oracle, and
+surface error on sampled rows.
 """
 
 from __future__ import annotations
@@ -41,9 +48,9 @@ def surface_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(n_launch_bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current surface kernel source."""
+def stored_traffic():
+    """HBM bytes per launch of the surface kernel from the committed rocprofv3
+    counter summary, if it was taken on the current surface kernel source."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -54,38 +61,66 @@ def stored_traffic(n_launch_bytes_alg: float):
     return c.get("hbm_bytes_per_launch")
 
 
-def time_gpu(spec, steps, warmup, out_dtype, trace=True):
+def _dev_spec(spec, dev):
+    import torch
+    return torch.as_tensor(spec.path.ctrl).to(dev), torch.as_tensor(spec.profile.ctrl).to(dev)
+
+
+def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
+    """Wall time of `steps` sweep_eval calls, the per-call (frame, surface)
+    stage times from the library's HIP events, and optionally the outputs."""
     import torch
     from paper_1110_5450_amd import _lib, api
 
+    frame_dtype = frame_dtype or torch.float64
     dev = torch.device("cuda:0")
-    P = torch.as_tensor(spec.path.ctrl).to(dev)
-    Q = torch.as_tensor(spec.profile.ctrl).to(dev)
+    P, Q = _dev_spec(spec, dev)
     pos = torch.empty((3, spec.n_u, spec.n_v), dtype=out_dtype, device=dev)
     nrm = torch.empty_like(pos)
-    ws = torch.empty(api.eval_workspace_size(P.shape[0], 3, Q.shape[0], 3, spec.n_u, spec.n_v,
-                                             out_dtype=out_dtype), dtype=torch.uint8, device=dev)
+    ws = torch.empty(api.eval_workspace_size(P.shape[0], spec.path.degree, Q.shape[0], spec.profile.degree,
+                                             spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype),
+                     dtype=torch.uint8, device=dev)
 
     def step():
-        api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v,
-                       out_dtype=out_dtype, out=(pos, nrm), workspace=ws)
+        api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v, out_dtype=out_dtype,
+                       frame_dtype=frame_dtype, out=(pos, nrm), workspace=ws)
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    if trace:
-        _lib.check(_lib.sweep_trace_enable(steps))
+    _lib.check(_lib.sweep_trace_enable(steps))
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rec = _lib.sweep_trace_read() if trace else []
+    rec = _lib.sweep_trace_read()
     surf = [ms for st, ms in rec if st == 1]
     frame = [ms for st, ms in rec if st == 0]
-    del pos, nrm, ws
+    out = (pos, nrm) if keep else None
+    if not keep:
+        del pos, nrm
+    del ws
     torch.cuda.empty_cache()
-    return t1 - t0, surf, frame
+    return t1 - t0, surf, frame, out
+
+
+def sampled_error(spec, pos, nrm, rows, tol):
+    """Parity figures of a GPU result on sampled rows against the oracle."""
+    import numpy as np
+    import torch
+    import oracle
+
+    idx = torch.as_tensor(rows, device=pos.device)
+    gp = pos.index_select(1, idx).double().cpu().numpy()
+    gn = nrm.index_select(1, idx).double().cpu().numpy()
+    x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
+    rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
+    diag = float(np.linalg.norm(x.max(0) - x.min(0)))
+    r = oracle.compare(rp, rn, rk, gp, gn, diag, 1e6)
+    r["rows"] = len(rows)
+    r["tolerance"] = tol
+    return r
 
 
 def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 20):
@@ -109,6 +144,152 @@ def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 20):
     }
 
 
+def batched_variants(steps: int):
+    """The 4096-sweep batch: one graph launch (FP32) versus the same sweeps as
+    single FP64 calls."""
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+
+    specs = synth.c4()
+    b = api.Batch.from_specs(specs)
+    N = b.n_vertices
+    ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
+    pos = torch.empty(3 * N, dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pos)
+    for _ in range(2):
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(steps):
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_ms = ev[0].elapsed_time(ev[1]) / steps
+    del pos, nrm, ws
+    torch.cuda.empty_cache()
+    # the same sweeps, one FP64 sweep_eval call each
+    Ps = [torch.as_tensor(s.path.ctrl).cuda() for s in specs]
+    Qs = [torch.as_tensor(s.profile.ctrl).cuda() for s in specs]
+    maxN = max(s.n_u * s.n_v for s in specs)
+    buf = torch.empty(2 * 3 * maxN, dtype=torch.float64, device="cuda")
+    wsz = max(api.eval_workspace_size(s.path.n, s.path.degree, s.profile.n, s.profile.degree, s.n_u, s.n_v,
+                                      out_dtype=torch.float64) for s in specs)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+
+    def singles():
+        for k, s in enumerate(specs):
+            n3 = 3 * s.n_u * s.n_v
+            p = buf[:n3].view(3, s.n_u, s.n_v)
+            q = buf[n3:2 * n3].view(3, s.n_u, s.n_v)
+            api.sweep_eval(Ps[k], s.path.degree, Qs[k], s.profile.degree, s.n_u, s.n_v,
+                           out_dtype=torch.float64, out=(p, q), workspace=ws)
+
+    singles()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles()
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    del buf, ws
+    torch.cuda.empty_cache()
+    return {
+        "workload": "4096 sweeps: path cps U{8..512}, profile cps U{4..64}, degrees U{2,3}, "
+                    "n_u log-U[16,4096], n_v log-U[8,256]",
+        "vertices": N,
+        "batched_fp32_graph": {"vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
+                               "gpu_ms_per_step": gpu_ms, "output_GBps": 24.0 * N / (gpu_ms * 1e-3) / 1e9},
+        "single_calls_fp64": {"vertices_per_s": N / el64, "ms_per_pass": 1e3 * el64, "calls": len(specs)},
+    }
+
+
+def adjoint_variant(steps: int):
+    """The differentiation workload: 256 sweeps of 1024 x 64, FP32, backward."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+
+    specs = synth.c5()
+    b = api.Batch.from_specs(specs)
+    N = b.n_vertices
+    g = torch.randn(3 * N, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        api.sweep_backward(b, g, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.sweep_backward(b, g, workspace=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fw = torch.empty(3 * N, dtype=torch.float32, device="cuda")
+    fn = torch.empty_like(fw)
+    wsf = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        api.sweep_eval_batched(b, out=(fw, fn), workspace=wsf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.sweep_eval_batched(b, out=(fw, fn), workspace=wsf)
+    torch.cuda.synchronize()
+    elf = time.perf_counter() - t0
+    return {"workload": "256 sweeps, 64/16 cps, 1024x64, FP32", "vertices": N,
+            "forward_ms": 1e3 * elf / steps, "backward_ms": 1e3 * el / steps,
+            "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9}
+
+
+def precision_study(steps: int = 5):
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from paper_1110_5450_amd import api
+
+    spec = synth.c3()
+    n_u, n_v = spec.n_u, spec.n_v
+    P = torch.as_tensor(spec.path.ctrl).cuda()
+    x, d1, d2, ft = oracle.path_samples(spec.path, n_u)
+    R, _ = oracle.frame(x, d1, ft)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([[0, 1, n_u // 2, n_u - 1], rng.integers(0, n_u, 28)]))
+    rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, n_u, n_v, rows)
+    diag = float(np.linalg.norm(x.max(0) - x.min(0)))
+    out = {"workload": f"precision study: plain-sweep curves at {n_u}x{n_v}, FP32 output", "variants": []}
+    for fd in (torch.float64, torch.float32):
+        for reorth in (True, False):
+            fr = api.sweep_frames(P, 3, n_u, out_dtype=torch.float64, frame_dtype=fd,
+                                  reorthonormalize=reorth).cpu().numpy()
+            Rg = fr[:, 3:12].reshape(-1, 3, 3).transpose(0, 2, 1)
+            G = np.einsum("nki,nkj->nij", Rg, Rg)
+            drift = float(np.abs(G - np.eye(3)).max())
+            ferr = float(np.abs(Rg - R).max())
+            # the rotation about t accumulated by the scan, against the oracle's
+            ang = np.arctan2(np.einsum("na,na->n", Rg[:, :, 0], R[:, :, 1]),
+                             np.einsum("na,na->n", Rg[:, :, 0], R[:, :, 0]))
+            el, surf, frame, (pos, nrm) = time_single(spec, steps, 1, torch.float32, fd, keep=True) if reorth else \
+                (None, None, None, (None, None))
+            rec = {"frame_dtype": str(fd).replace("torch.", ""), "reorthonormalize": reorth,
+                   "frame_max_abs_err": ferr, "twist_angle_max_err_rad": float(np.abs(ang).max()),
+                   "orthonormality_drift": drift}
+            if reorth:
+                idx = torch.as_tensor(rows, device=pos.device)
+                r = oracle.compare(rp, rn, rk, pos.index_select(1, idx).double().cpu().numpy(),
+                                   nrm.index_select(1, idx).double().cpu().numpy(), diag, 1e6)
+                rec.update({"surface_pos_rel_err": r["pos_rel"], "surface_nrm_scaled_err": r["nrm_scaled"],
+                            "masked": r["masked"], "frame_ms": sum(frame) / len(frame),
+                            "surface_ms": sum(surf) / len(surf),
+                            "vertices_per_s": n_u * n_v * steps / el})
+                del pos, nrm
+                torch.cuda.empty_cache()
+            out["variants"].append(rec)
+            log(rec)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,25 +297,36 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--precision-study", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep shards "
               f"across GPUs only by design, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import synth
+
+    if args.precision_study:
+        print(json.dumps(precision_study()), flush=True)
+        return
 
     spec = synth.c2()
     N = spec.n_u * spec.n_v
     log(f"[bench] large sweep {spec.n_u}x{spec.n_v} FP32 out / FP64 frame, warmup {args.warmup}, steps {args.steps}")
-    el, surf, frame = time_gpu(spec, args.steps, args.warmup, torch.float32)
+    el, surf, frame, res = time_single(spec, args.steps, args.warmup, torch.float32, keep=True)
     ms_step = 1e3 * el / args.steps
     value = N * args.steps / el
     bytes_alg = 24.0 * N  # 6 FP32 planes, write-only
     surf_ms = sum(surf) / len(surf)
     achieved = bytes_alg / (surf_ms * 1e-3) / 1e9
     log(f"[bench] {ms_step:.3f} ms/step, surface {surf_ms:.3f} ms, frame {sum(frame) / len(frame):.3f} ms")
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, spec.n_u - 1], rng.integers(0, spec.n_u, 14)]))
+    err = sampled_error(spec, res[0], res[1], rows, 1e-5)
+    del res
+    torch.cuda.empty_cache()
     out = {
         "metric": METRIC, "value": value, "unit": "vertices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -144,19 +336,24 @@ def main():
                    "n_u": spec.n_u, "n_v": spec.n_v, "vertices": N, "frame_dtype": "f64",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(bytes_alg),
-                     "kernel": "k_surface_cols<float> (surface write)", "alg_bytes_per_launch": bytes_alg,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
+                     "kernel": "k_surface_tiles<float> (surface write)", "alg_bytes_per_launch": bytes_alg,
                      "avg_launch_ms": surf_ms},
         "stages_ms": {"frame": sum(frame) / len(frame), "surface": surf_ms},
+        "error_vs_oracle": err,
     }
     if not args.no_variants:
-        el64, surf64, frame64 = time_gpu(spec, max(3, args.steps // 4), 1, torch.float64)
         steps64 = max(3, args.steps // 4)
+        el64, surf64, frame64, _ = time_single(spec, steps64, 1, torch.float64)
         s64 = sum(surf64) / len(surf64)
         out["variants"] = {
             "plain_fp64_out": {"vertices_per_s": N * steps64 / el64, "ms_per_step": 1e3 * el64 / steps64,
                                "surface_ms": s64, "surface_GBps": 48.0 * N / (s64 * 1e-3) / 1e9},
         }
+        log("[bench] batched ...")
+        out["variants"]["batched"] = batched_variants(max(3, args.steps // 4))
+        log("[bench] adjoint ...")
+        out["variants"]["adjoint"] = adjoint_variant(max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec)

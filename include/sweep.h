@@ -151,6 +151,17 @@ size_t sweep_eval_workspace_size(const sweep_curve *path, const sweep_curve *pro
                                  int32_t n_u, int32_t n_v, const sweep_options *opt);
 
 /*
+ * The moving frame alone: for each u-sample i of the path, write the 16-value
+ * row record (x_i[3], r_i[3], s_i[3], t_i[3], |C'(u_i)|, a_i, b_i, 0) with
+ * a = r.C''/|C'|, b = s.C''/|C'|, in the output precision, to frames (DEVICE,
+ * 16*n_u elements).  Same kernels and options as sweep_eval (frame
+ * precision, re-orthonormalisation, initial normal).
+ */
+sweep_status sweep_frames(const sweep_curve *path, int32_t n_u, const sweep_options *opt, void *frames,
+                          void *workspace, size_t ws_bytes, void *stream);
+size_t sweep_frames_workspace_size(const sweep_curve *path, int32_t n_u, const sweep_options *opt);
+
+/*
  * Evaluate a batch of independent sweeps in one frame launch and one
  * persistent surface launch, replayed from a HIP graph.  The first call with
  * a new batch shape (all per-sweep host arrays, knots and options) validates

@@ -69,6 +69,10 @@ def lib():
         L.sweep_eval_workspace_size.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32,
                                                 C.c_int32, C.POINTER(SweepOptions)]
         L.sweep_eval_workspace_size.restype = sz
+        L.sweep_frames.argtypes = [C.POINTER(SweepCurve), C.c_int32, C.POINTER(SweepOptions), vp, vp, sz, vp]
+        L.sweep_frames.restype = C.c_int32
+        L.sweep_frames_workspace_size.argtypes = [C.POINTER(SweepCurve), C.c_int32, C.POINTER(SweepOptions)]
+        L.sweep_frames_workspace_size.restype = sz
         L.sweep_eval_batched.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, sz, vp]
         L.sweep_eval_batched.restype = C.c_int32
         L.sweep_batched_workspace_size.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions)]
@@ -122,6 +126,15 @@ def sweep_eval(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: S
 
 def sweep_eval_workspace_size(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: SweepOptions) -> int:
     return lib().sweep_eval_workspace_size(C.byref(path), C.byref(profile), n_u, n_v, C.byref(opt))
+
+
+def sweep_frames(path: SweepCurve, n_u: int, opt: SweepOptions, frames: int, workspace: int, ws_bytes: int,
+                 stream: int) -> int:
+    return lib().sweep_frames(C.byref(path), n_u, C.byref(opt), frames, workspace, ws_bytes, stream)
+
+
+def sweep_frames_workspace_size(path: SweepCurve, n_u: int, opt: SweepOptions) -> int:
+    return lib().sweep_frames_workspace_size(C.byref(path), n_u, C.byref(opt))
 
 
 def sweep_eval_batched(batch: SweepBatch, opt: SweepOptions, pos: int, nrm: int, workspace: int,

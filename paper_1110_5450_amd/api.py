@@ -87,6 +87,25 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
     return pos, nrm
 
 
+def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
+                 out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
+                 initial_normal=None, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame."""
+    pc = _check_ctrl(path_ctrl, "path_ctrl")
+    pk, pkp = _knots_ptr(path_knots)
+    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
+    ws_bytes = L.sweep_frames_workspace_size(path, int(n_u), opt)
+    if ws_bytes == 0:
+        L.check(L.sweep_frames(path, int(n_u), opt, 0, 0, 0, 0))
+    out = torch.empty((n_u, 16), dtype=out_dtype, device=pc.device)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=pc.device)
+    L.check(L.sweep_frames(path, int(n_u), opt, out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                           _stream_handle(stream)))
+    return out
+
+
 def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree: int, n_u: int, n_v: int, *,
                         prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
     path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None)

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         }
         cacc[3 * (size_t)j] = h[0]; cacc[3 * (size_t)j + 1] = h[1]; cacc[3 * (size_t)j + 2] = h[2];
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
 
     // 2. rho_i = sum_{k >= i} R_k^T rbar_k^dir, chunks from the last one
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         if (i < n_u) { rho_k[3 * (size_t)i] = sfx.x; rho_k[3 * (size_t)i + 1] = sfx.y; rho_k[3 * (size_t)i + 2] = sfx.z; }
         carry = carry + total;
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
 
     // 3. per-sample adjoint of x_i and C'_i, and their basis contributions
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
             q[0] = Nv[l] * h.x; q[1] = Nv[l] * h.y; q[2] = Nv[l] * h.z;
         }
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
 
     // 4. gathers per control point over the samples whose span covers it

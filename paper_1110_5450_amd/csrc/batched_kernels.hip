@@ -103,10 +103,10 @@ __global__ __launch_bounds__(kBlock) void kb_frames(const BatchDesc* __restrict_
         block_exclusive_product<F>(step_of<F>(s), lds_m, total);
         if (threadIdx.x < 9) agg_k[9 * (size_t)b + threadIdx.x] = total.m[threadIdx.x];
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
     carry_scan<F>(agg_k, nc, initial_normal(mk(t0s[0], t0s[1], t0s[2]), n0), rin_k, lds_m);
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
     cs = ChunkState{-1, mk(0.0, 0.0, 0.0)};
     T* rows_k = rows + 16 * d.row_off;

@@ -5,6 +5,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// FP contraction is off for everything in this header and frame_common.hpp
+// (curve evaluation, step rotations, block products): each product and sum
+// is rounded where written, so a function inlined into different kernels
+// gives bitwise identical results (single-sweep and batched paths agree).
+#pragma clang fp contract(off)
+
 namespace sweep {
 
 constexpr int kBlock = 256;   // threads per block in every kernel
@@ -347,3 +353,6 @@ __device__ __forceinline__ int block_exclusive_max(int x, int* lds, int& total)
 }
 
 }  // namespace sweep
+
+// back to the default (contraction across statements) for code that follows
+#pragma clang fp contract(fast)

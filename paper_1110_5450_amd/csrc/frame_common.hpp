@@ -8,6 +8,8 @@
 #include "device_math.hpp"
 #include "kernels.hpp"
 
+#pragma clang fp contract(off)
+
 namespace sweep {
 
 // Samples per chunk of the frame scan: one per thread.
@@ -147,3 +149,6 @@ __device__ __forceinline__ V3<double> first_leg(const DCurve& path)
 }
 
 }  // namespace sweep
+
+// back to the default (contraction across statements) for code that follows
+#pragma clang fp contract(fast)

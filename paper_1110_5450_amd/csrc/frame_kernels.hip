@@ -5,12 +5,15 @@
 // k_prep          C, C', C'' at every u-sample (FP64, SoA planes) and, per
 //                 chunk of kChunk samples, the last sample with C' != 0;
 //                 S, S' at every v-sample (the profile table, in the output
-//                 precision); the fallback tangent; resets the ticket counter.
+//                 precision); the fallback tangent.
 // k_frame_reduce  per chunk: tangents (a sample with C' = 0 takes the tangent
 //                 of the last sample before it with C' != 0), step rotations
-//                 M_i and their ordered product A_b.  The last block to finish
-//                 (ticket counter; no block waits on another) scans the A_b
-//                 and writes r_in[b] = (A_{b-1} ... A_0) r_0.
+//                 M_i and their ordered product A_b.
+// k_frame_carry   one block: scans the A_b and writes the normal entering
+//                 each chunk, r_in[b] = (A_{b-1} ... A_0) r_0.  (A separate
+//                 launch: a last-block hand-off inside k_frame_reduce needs a
+//                 device-scope fence per block, whose L2 write-back across the
+//                 eight XCDs measured 37 us at 256 chunks and 360 us at 4096.)
 // k_frame_apply   per chunk: block exclusive product of the M_i applied to
 //                 r_in[b], re-orthonormalisation, and the row table
 //                 (x, r, s, t, |C'|, a, b) in the output precision.
@@ -32,8 +35,7 @@ __device__ __forceinline__ V3<double> smp_get(const double* __restrict__ smp, si
 template <int P, class T>
 __global__ __launch_bounds__(kBlock) void k_prep(DCurve path, int n_u, DCurve prof, int n_v, int ncu,
                                                  double* __restrict__ smp, int* __restrict__ chunk_lv,
-                                                 double* __restrict__ fallback_t, unsigned* __restrict__ ticket,
-                                                 T* __restrict__ ptab)
+                                                 double* __restrict__ fallback_t, T* __restrict__ ptab)
 {
     __shared__ int lds[kWaves];
     if ((int)blockIdx.x >= ncu) {
@@ -59,7 +61,6 @@ __global__ __launch_bounds__(kBlock) void k_prep(DCurve path, int n_u, DCurve pr
     block_exclusive_max(best, lds, total);
     if (threadIdx.x == 0) chunk_lv[blockIdx.x] = total;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *ticket = 0u;
         // used only when C'(u_0) = 0
         const V3<double> t = first_leg(path);
         fallback_t[0] = t.x; fallback_t[1] = t.y; fallback_t[2] = t.z;
@@ -72,13 +73,18 @@ __device__ StepInputs load_step_inputs(const double* __restrict__ smp, int n_u, 
                                        const double* __restrict__ fallback_t, int* lds_i)
 {
     const size_t nu = (size_t)n_u;
-    const int i = blockIdx.x * kChunk + threadIdx.x;
-    // last sample with C' != 0 before this chunk
-    int carry = -1;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) carry = max(carry, chunk_lv[b]);
+    const int base = blockIdx.x * kChunk;
+    const int i = base + threadIdx.x;
     int total;
-    block_exclusive_max(carry, lds_i, total);
-    carry = total;
+    // The last sample with C' != 0 before this chunk matters only when the
+    // chunk's first sample has C' = 0 (a block-uniform test).
+    int carry = -1;
+    const V3<double> dfirst = smp_get(smp, nu, 1, base);
+    if (blockIdx.x > 0 && !(dot(dfirst, dfirst) > 0.0)) {
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) carry = max(carry, chunk_lv[b]);
+        block_exclusive_max(carry, lds_i, total);
+        carry = total;
+    }
     const bool has_step = i + 1 < n_u;
     V3<double> x0 = mk(0.0, 0.0, 0.0), d0 = x0, x1 = x0, d1 = x0;
     if (i < n_u) { x0 = smp_get(smp, nu, 0, i); d0 = smp_get(smp, nu, 1, i); }
@@ -95,26 +101,26 @@ __device__ StepInputs load_step_inputs(const double* __restrict__ smp, int n_u, 
 template <class F>
 __global__ __launch_bounds__(kBlock) void k_frame_reduce(const double* __restrict__ smp, int n_u,
                                                          const int* __restrict__ chunk_lv,
-                                                         const double* __restrict__ fallback_t, F* agg,
-                                                         unsigned* ticket, InitialNormal n0, F* __restrict__ r_in)
+                                                         const double* __restrict__ fallback_t, F* __restrict__ agg)
 {
     __shared__ int lds_i[kWaves];
     __shared__ M3<F> lds_m[kWaves];
-    __shared__ unsigned my_ticket;
     const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i);
     M3<F> total;
     block_exclusive_product<F>(step_of<F>(s), lds_m, total);
     if (threadIdx.x < 9) agg[9 * (size_t)blockIdx.x + threadIdx.x] = total.m[threadIdx.x];
-    // publish, then take a ticket; the block holding the last ticket does the carry scan
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) my_ticket = atomicAdd(ticket, 1u);
-    __syncthreads();
-    if (my_ticket != gridDim.x - 1) return;
-    __threadfence();
+}
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_frame_carry(const F* __restrict__ agg, int n_chunks,
+                                                        const double* __restrict__ smp, int n_u,
+                                                        const double* __restrict__ fallback_t, InitialNormal n0,
+                                                        F* __restrict__ r_in)
+{
+    __shared__ M3<F> lds_m[kWaves];
     const V3<double> d = smp_get(smp, (size_t)n_u, 1, 0);
     const V3<double> t0 = dot(d, d) > 0.0 ? unit_of(d) : mk(fallback_t[0], fallback_t[1], fallback_t[2]);
-    carry_scan<F>(agg, (int)gridDim.x, initial_normal(t0, n0), r_in, lds_m);
+    carry_scan<F>(agg, n_chunks, initial_normal(t0, n0), r_in, lds_m);
 }
 
 template <class F, class T>
@@ -142,14 +148,14 @@ int frame_chunk_size() { return kChunk; }
 
 template <class T>
 hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
-                       double* fallback_t, unsigned* ticket, T* ptab, hipStream_t st)
+                       double* fallback_t, T* ptab, hipStream_t st)
 {
     const int ncu = (n_u + kChunk - 1) / kChunk;
     const int ncv = (n_v + kBlock - 1) / kBlock;
     const dim3 grid(ncu + ncv);
 #define SWEEP_CASE(P) \
     case P: hipLaunchKernelGGL((k_prep<P, T>), grid, dim3(kBlock), 0, st, path, n_u, prof, n_v, ncu, smp, chunk_lv, \
-                               fallback_t, ticket, ptab); break;
+                               fallback_t, ptab); break;
     switch (path.p) {
         SWEEP_CASE(1) SWEEP_CASE(2) SWEEP_CASE(3) SWEEP_CASE(4) SWEEP_CASE(5) SWEEP_CASE(6) SWEEP_CASE(7)
     default: return hipErrorInvalidValue;
@@ -157,25 +163,25 @@ hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v,
 #undef SWEEP_CASE
     return hipGetLastError();
 }
-template hipError_t launch_prep<float>(const DCurve&, int, const DCurve&, int, double*, int*, double*, unsigned*,
-                                       float*, hipStream_t);
-template hipError_t launch_prep<double>(const DCurve&, int, const DCurve&, int, double*, int*, double*, unsigned*,
-                                        double*, hipStream_t);
+template hipError_t launch_prep<float>(const DCurve&, int, const DCurve&, int, double*, int*, double*, float*,
+                                       hipStream_t);
+template hipError_t launch_prep<double>(const DCurve&, int, const DCurve&, int, double*, int*, double*, double*,
+                                        hipStream_t);
 
 template <class F, class T>
-hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, unsigned* ticket,
-                        InitialNormal n0, int reorth, F* agg, F* r_in, T* rows, hipStream_t st)
+hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, InitialNormal n0,
+                        int reorth, F* agg, F* r_in, T* rows, hipStream_t st)
 {
     const int nc = (n_u + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_frame_reduce<F>, dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t, agg, ticket,
-                       n0, r_in);
+    hipLaunchKernelGGL(k_frame_reduce<F>, dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t, agg);
+    hipLaunchKernelGGL(k_frame_carry<F>, dim3(1), dim3(kBlock), 0, st, agg, nc, smp, n_u, fallback_t, n0, r_in);
     hipLaunchKernelGGL((k_frame_apply<F, T>), dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t, r_in,
                        reorth, rows);
     return hipGetLastError();
 }
 #define SWEEP_INST(F, T)                                                                                       \
-    template hipError_t launch_frame<F, T>(const double*, int, const int*, const double*, unsigned*, InitialNormal, \
-                                           int, F*, F*, T*, hipStream_t);
+    template hipError_t launch_frame<F, T>(const double*, int, const int*, const double*, InitialNormal, int, F*, F*, \
+                                           T*, hipStream_t);
 SWEEP_INST(double, float)
 SWEEP_INST(double, double)
 SWEEP_INST(float, float)

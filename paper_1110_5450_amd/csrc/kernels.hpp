@@ -17,14 +17,14 @@ struct InitialNormal {
 int frame_chunk_size();
 
 // Path samples (x, C', C'' as SoA planes of n_u doubles), per-chunk last
-// valid sample, fallback tangent, ticket reset, and the profile table.
+// valid sample, fallback tangent, and the profile table.
 template <class T>
 hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
-                       double* fallback_t, unsigned* ticket, T* ptab, hipStream_t st);
+                       double* fallback_t, T* ptab, hipStream_t st);
 // Frame scan and row table (16 values per u-row).
 template <class F, class T>
-hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, unsigned* ticket,
-                        InitialNormal n0, int reorth, F* agg, F* r_in, T* rows, hipStream_t st);
+hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, InitialNormal n0,
+                        int reorth, F* agg, F* r_in, T* rows, hipStream_t st);
 
 // Surface write of one sweep from its row table (16 values per u-row) and
 // profile table (8 values per v-sample).

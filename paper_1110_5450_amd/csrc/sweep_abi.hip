@@ -157,7 +157,7 @@ SurfaceConfig auto_surface_config(int n_u, int n_v)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, fallback, ticket, agg, r_in, rows, prof_tab, total;
+    size_t knots_path, knots_prof, smp, chunk_lv, fallback, agg, r_in, rows, prof_tab, total;
 };
 
 static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz)
@@ -170,7 +170,6 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
     L.smp = off;        off = align_up(off + sizeof(double) * 9 * (size_t)n_u);
     L.chunk_lv = off;   off = align_up(off + sizeof(int) * (size_t)nc);
     L.fallback = off;   off = align_up(off + sizeof(double) * 3);
-    L.ticket = off;     off = align_up(off + sizeof(unsigned));
     L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
     L.r_in = off;       off = align_up(off + fsz * 3 * (size_t)nc);
     L.rows = off;       off = align_up(off + tsz * 16 * (size_t)n_u);
@@ -197,6 +196,29 @@ sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, h
     return SWEEP_OK;
 }
 
+// Frame stage only: knots, path samples and the frame scan into `rows`.
+template <class F, class T>
+static sweep_status run_frames(const sweep_curve* path, int n_u, const sweep_options* o, T* rows, char* ws,
+                               const SingleLayout& L, hipStream_t st)
+{
+    double* Up = (double*)(ws + L.knots_path);
+    sweep_status s = upload_knots(path->knots, path->n_ctrl, path->degree, Up, st);
+    if (s != SWEEP_OK) return s;
+    DCurve dp{path->ctrl, path->knots ? Up : nullptr, path->n_ctrl, path->degree, 0,
+              nbasis(path->n_ctrl, path->degree, 0)};
+    DCurve dq{nullptr, nullptr, 1, 1, 0, 1};
+    double* smp = (double*)(ws + L.smp);
+    int* clv = (int*)(ws + L.chunk_lv);
+    double* fb = (double*)(ws + L.fallback);
+    hipError_t e = launch_prep<T>(dp, n_u, dq, 0, smp, clv, fb, (T*)nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "curve samples");
+    InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
+    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
+                           rows, st);
+    if (e != hipSuccess) return hip_fail(e, "frame");
+    return SWEEP_OK;
+}
+
 template <class F, class T>
 static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof, int n_u, int n_v,
                                const sweep_options* o, void* pos, void* nrm, char* ws, const SingleLayout& L,
@@ -216,13 +238,12 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
-    unsigned* ticket = (unsigned*)(ws + L.ticket);
     T* rows = (T*)(ws + L.rows);
     T* ptab = (T*)(ws + L.prof_tab);
-    hipError_t e = launch_prep<T>(dp, n_u, dq, n_v, smp, clv, fb, ticket, ptab, st);
+    hipError_t e = launch_prep<T>(dp, n_u, dq, n_v, smp, clv, fb, ptab, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
-    e = launch_frame<F, T>(smp, n_u, clv, fb, ticket, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
+    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
                            rows, st);
     if (e != hipSuccess) return hip_fail(e, "frame");
     trace_mark(1, st);
@@ -316,6 +337,39 @@ int32_t sweep_trace_read(int32_t* stage, float* ms, int32_t max)
     g_trace.calls = 0;
     g_trace.capacity = 0;
     return n;
+}
+
+size_t sweep_frames_workspace_size(const sweep_curve* path, int32_t n_u, const sweep_options* opt)
+{
+    if (!path || !opt) return 0;
+    if (check_curve_meta(path->n_ctrl, path->degree, path->closed, path->knots, "path", true) != SWEEP_OK) return 0;
+    if (n_u < 2 || check_options(opt) != SWEEP_OK) return 0;
+    const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
+    return single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0).total;
+}
+
+sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_options* opt, void* frames,
+                          void* workspace, size_t ws_bytes, void* stream)
+{
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    sweep_status s = check_options(opt);
+    if (s != SWEEP_OK) return s;
+    if ((s = check_curve(path, "path", true)) != SWEEP_OK) return s;
+    if (n_u < 2 || n_u >= (1 << 30)) return fail(SWEEP_ERR_BAD_GRID, "n_u %d outside 2..2^30-1", n_u);
+    if (!frames) return fail(SWEEP_ERR_NULL_ARG, "frames is NULL");
+    const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
+    const SingleLayout L = single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0);
+    if (!workspace || ws_bytes < L.total)
+        return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, L.total);
+    if (((uintptr_t)workspace) % 256 != 0) return fail(SWEEP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    const bool f64 = opt->frame_precision == SWEEP_F64, t64 = opt->out_precision == SWEEP_F64;
+    if (f64 && t64) return run_frames<double, double>(path, n_u, opt, (double*)frames, ws, L, st);
+    if (f64) return run_frames<double, float>(path, n_u, opt, (float*)frames, ws, L, st);
+    if (t64) return run_frames<float, double>(path, n_u, opt, (double*)frames, ws, L, st);
+    return run_frames<float, float>(path, n_u, opt, (float*)frames, ws, L, st);
 }
 
 int32_t sweep_tile_config_count(void) { return tile_config_count(); }

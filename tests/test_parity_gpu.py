@@ -134,3 +134,28 @@ def test_precision_study_grid_sampled_rows():
     rows = np.unique(np.concatenate([[0, 1, spec.n_u // 2, spec.n_u - 1], rng.integers(0, spec.n_u, 24)]))
     _sampled(spec, rows, torch.float32)
     _sampled(spec, rows, torch.float32, frame_dtype=torch.float32, tol=1e-3)
+
+
+@pytest.mark.parametrize("name,n_u", [("c1", 256), ("c1", 5000), ("c3", 1048576), ("c2", 65536)])
+def test_frames_match_oracle(name, n_u):
+    """The whole frame (every u-sample) against the oracle's sequential FP64
+    recurrence.  A product of n rotations carries O(n eps) rounding in either
+    evaluation order, so the bound is 8 n eps (worst case); the measured
+    difference is printed."""
+    from paper_1110_5450_amd import api
+    spec = synth.config(name)
+    say(f"[case] frames {name} n_u={n_u}")
+    rows = api.sweep_frames(torch.as_tensor(spec.path.ctrl).cuda(), spec.path.degree, n_u).cpu().numpy()
+    x, d1, d2, ft = oracle.path_samples(spec.path, n_u)
+    R, _ = oracle.frame(x, d1, ft)
+    eps = np.finfo(float).eps
+    dx = np.abs(rows[:, 0:3] - x).max() / max(1.0, np.abs(x).max())
+    dR = max(np.abs(rows[:, 3 + 3 * c: 6 + 3 * c] - R[:, :, c]).max() for c in range(3))
+    L = np.linalg.norm(d1, axis=1)
+    a = np.einsum("ia,ia->i", R[:, :, 0], d2) / L
+    b = np.einsum("ia,ia->i", R[:, :, 1], d2) / L
+    dab = max(np.abs(rows[:, 13] - a).max(), np.abs(rows[:, 14] - b).max()) / max(1.0, np.abs(d2).max() / L.min())
+    G = np.einsum("nki,nkj->nij", rows[:, 3:12].reshape(-1, 3, 3).transpose(0, 2, 1), rows[:, 3:12].reshape(-1, 3, 3).transpose(0, 2, 1))
+    drift = np.abs(G - np.eye(3)).max()
+    say(f"    x {dx:.2e}  frame {dR:.2e} (bound {8 * n_u * eps:.1e})  a,b {dab:.2e}  orthonormality {drift:.2e}")
+    assert dx <= 1e-14 and dR <= 8 * n_u * eps and dab <= 1e-10 and drift <= 1e-14
