@@ -204,6 +204,25 @@ size_t sweep_backward_workspace_size(const sweep_batch *batch, const sweep_optio
 sweep_status sweep_trace_enable(int32_t max_calls);
 int32_t sweep_trace_read(int32_t *stage, float *ms, int32_t max);
 
+/*
+ * Surface-kernel autotuner.  Evaluates the sweep once, then times every fixed
+ * surface configuration on it with HIP events on `stream` (the call waits for
+ * the stream), using the caller's buffers, and records the fastest under the
+ * shape class (device architecture and CU count, output precision,
+ * n_v % 256 == 0, floor(log2 n_v), floor(log2 n_u*n_v)).  Later calls with
+ * tile_config = -1 in the same class use the recorded configuration.  When
+ * the environment variable SWEEP_TUNE_CACHE names a file, the table is read
+ * from it on first use and rewritten (to a temporary file, then renamed)
+ * after each tuning.  best_config / best_ms may be NULL.
+ */
+sweep_status sweep_autotune(const sweep_curve *path, const sweep_curve *profile, int32_t n_u, int32_t n_v,
+                            const sweep_options *opt, void *pos, void *nrm, void *workspace, size_t ws_bytes,
+                            void *stream, int32_t *best_config, float *best_ms);
+
+/* The surface configuration tile_config = -1 selects for this shape and
+ * output precision (the tuned one if recorded, else the built-in rule). */
+int32_t sweep_surface_config_for(int32_t n_u, int32_t n_v, int32_t out_precision);
+
 /* Number of fixed surface-kernel configurations accepted in tile_config. */
 int32_t sweep_tile_config_count(void);
 

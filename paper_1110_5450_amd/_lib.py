@@ -85,6 +85,11 @@ def lib():
         L.sweep_trace_enable.restype = C.c_int32
         L.sweep_trace_read.argtypes = [_ip, C.POINTER(C.c_float), C.c_int32]
         L.sweep_trace_read.restype = C.c_int32
+        L.sweep_autotune.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32, C.c_int32,
+                                     C.POINTER(SweepOptions), vp, vp, vp, sz, vp, _ip, C.POINTER(C.c_float)]
+        L.sweep_autotune.restype = C.c_int32
+        L.sweep_surface_config_for.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.sweep_surface_config_for.restype = C.c_int32
         L.sweep_tile_config_count.argtypes = []
         L.sweep_tile_config_count.restype = C.c_int32
         L.sweep_last_error.argtypes = []
@@ -168,6 +173,20 @@ def sweep_trace_read(max_records: int = 8192):
     if n < 0:
         raise SweepError(n, last_error())
     return [(int(st[k]), float(ms[k])) for k in range(n)]
+
+
+def sweep_autotune(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: SweepOptions,
+                   pos: int, nrm: int, workspace: int, ws_bytes: int, stream: int):
+    """Returns (status, best_config, best_ms)."""
+    best = C.c_int32(-1)
+    ms = C.c_float(0.0)
+    st = lib().sweep_autotune(C.byref(path), C.byref(profile), n_u, n_v, C.byref(opt), pos, nrm, workspace,
+                              ws_bytes, stream, C.byref(best), C.byref(ms))
+    return st, best.value, ms.value
+
+
+def sweep_surface_config_for(n_u: int, n_v: int, out_precision: int) -> int:
+    return lib().sweep_surface_config_for(n_u, n_v, out_precision)
 
 
 def sweep_tile_config_count() -> int:

@@ -87,6 +87,39 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
     return pos, nrm
 
 
+def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tensor, prof_degree: int,
+                   n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
+                   out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
+                   initial_normal=None, normals: bool = True, stream=None):
+    """Times every surface configuration on this sweep and records the
+    fastest for its shape class; returns (best_config, best_ms, pos, nrm)."""
+    pc = _check_ctrl(path_ctrl, "path_ctrl")
+    qc = _check_ctrl(prof_ctrl, "prof_ctrl")
+    pk, pkp = _knots_ptr(path_knots)
+    qk, qkp = _knots_ptr(prof_knots)
+    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp)
+    prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
+    ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
+    if ws_bytes == 0:
+        L.check(L.sweep_eval(path, prof, int(n_u), int(n_v), opt, 0, 0, 0, 0, 0))
+    dev = pc.device
+    pos = torch.empty((3, n_u, n_v), dtype=out_dtype, device=dev)
+    nrm = torch.empty((3, n_u, n_v), dtype=out_dtype, device=dev) if normals else None
+    workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    st, best, ms = L.sweep_autotune(path, prof, int(n_u), int(n_v), opt, pos.data_ptr(),
+                                    nrm.data_ptr() if nrm is not None else 0, workspace.data_ptr(),
+                                    workspace.numel(), _stream_handle(stream))
+    L.check(st)
+    return best, ms, pos, nrm
+
+
+def surface_config_for(n_u: int, n_v: int, out_dtype=torch.float32) -> int:
+    """Configuration index that tile_config=-1 selects for this shape."""
+    return L.sweep_surface_config_for(int(n_u), int(n_v),
+                                      L.SWEEP_F64 if out_dtype == torch.float64 else L.SWEEP_F32)
+
+
 def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
                  out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
                  initial_normal=None, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

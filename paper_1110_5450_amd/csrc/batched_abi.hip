@@ -26,14 +26,14 @@ struct BatchKey {
 };
 
 struct BatchLayout {
-    size_t rows, ptab, agg, r_in, total;
+    size_t rows, ptab, agg, r_in, chunk_lv, chunk_fix, total;
     long long n_rows = 0, n_vs = 0, n_chunks = 0, n_vertices = 0;
     long long n_rowpart = 0, n_colpart = 0, n_units = 0;
 };
 
 // Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
 struct BackwardLayout {
-    size_t rows, ptab, agg, r_in, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
+    size_t rows, ptab, agg, r_in, chunk_lv, chunk_fix, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
 };
 
 static BackwardLayout backward_layout(const BatchLayout& L)
@@ -45,6 +45,8 @@ static BackwardLayout backward_layout(const BatchLayout& L)
     B.ptab = seg(8 * 8 * (size_t)L.n_vs);
     B.agg = seg(8 * 9 * (size_t)L.n_chunks);
     B.r_in = seg(8 * 3 * (size_t)L.n_chunks);
+    B.chunk_lv = seg(4 * (size_t)L.n_chunks);
+    B.chunk_fix = seg(4 * (size_t)L.n_chunks);
     B.rowpart = seg(8 * 12 * (size_t)L.n_rowpart);
     B.colpart = seg(8 * 3 * (size_t)L.n_colpart);
     B.rowacc = seg(8 * 12 * (size_t)L.n_rows);
@@ -125,6 +127,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     L.ptab = off; off = align_up(off + tsz * 8 * (size_t)L.n_vs);
     L.agg = off;  off = align_up(off + fsz * 9 * (size_t)L.n_chunks);
     L.r_in = off; off = align_up(off + fsz * 3 * (size_t)L.n_chunks);
+    L.chunk_lv = off; off = align_up(off + 4 * (size_t)L.n_chunks);
+    L.chunk_fix = off; off = align_up(off + 4 * (size_t)L.n_chunks);
     L.total = off;
     if (lay) *lay = L;
     if (key) {
@@ -136,9 +140,13 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     return SWEEP_OK;
 }
 
-// Argument block of the two graph nodes; the node parameter arrays point here.
-struct FramesArgs {
+// Argument values of one graph node; its parameter array points into this
+// block.  `chunks` is the node's own (sweep, chunk) list.
+struct NodeArgs {
     const BatchDesc* descs;
+    const int2* chunks;
+    const int2* vchunks;
+    const int2* tiles;
     const double* path_ctrl;
     const double* prof_ctrl;
     const double* knots;
@@ -146,17 +154,38 @@ struct FramesArgs {
     int reorth;
     void* agg;
     void* r_in;
+    void* chunk_lv;
+    void* chunk_fix;
     void* rows;
     void* ptab;
-};
-struct SurfaceArgs {
-    const BatchDesc* descs;
-    const int2* tiles;
-    const void* rows;
-    const void* ptab;
     void* pos;
     void* nrm;
 };
+
+enum NodeKind { kProfile, kPrep, kCarry, kApply, kSurface };
+
+struct GNode {
+    NodeKind kind;
+    int deg;
+    hipGraphNode_t node = nullptr;
+    hipKernelNodeParams prm{};
+    NodeArgs a{};
+    void* ptrs[8];
+};
+
+// Parameter array of a node kind (pointers into n.a).
+static int node_args(GNode& n)
+{
+    NodeArgs& A = n.a;
+    void** q = n.ptrs;
+    switch (n.kind) {
+    case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 5; }
+    case kPrep: { void* v[] = {&A.descs, &A.chunks, &A.path_ctrl, &A.knots, &A.agg, &A.chunk_lv, &A.chunk_fix}; std::memcpy(q, v, sizeof v); return 7; }
+    case kCarry: { void* v[] = {&A.descs, &A.path_ctrl, &A.knots, &A.n0, &A.agg, &A.chunk_lv, &A.chunk_fix, &A.r_in}; std::memcpy(q, v, sizeof v); return 8; }
+    case kApply: { void* v[] = {&A.descs, &A.chunks, &A.path_ctrl, &A.knots, &A.reorth, &A.chunk_lv, &A.r_in, &A.rows}; std::memcpy(q, v, sizeof v); return 8; }
+    default: { void* v[] = {&A.descs, &A.tiles, &A.rows, &A.ptab, &A.pos, &A.nrm}; std::memcpy(q, v, sizeof v); return 6; }
+    }
+}
 
 struct Plan {
     BatchKey key;
@@ -171,12 +200,12 @@ struct Plan {
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t n_frames = nullptr, n_surface = nullptr;
-    hipKernelNodeParams p_frames{}, p_surface{};
-    FramesArgs fa{};
-    SurfaceArgs sa{};
-    void* fa_ptrs[10];
-    void* sa_ptrs[6];
+    int2* d_chunks[8] = {};        // (sweep, chunk) of every path chunk, by path degree
+    int n_chunks[8] = {};
+    int2* d_vchunks = nullptr;     // (sweep, chunk) of every profile chunk
+    int n_vchunks = 0;
+    NodeArgs a{};                  // values shared by all nodes
+    std::vector<std::unique_ptr<GNode>> nodes;
     ~Plan()
     {
         if (exec) hipGraphExecDestroy(exec);
@@ -184,6 +213,9 @@ struct Plan {
         if (d_descs) hipFree(d_descs);
         if (d_tiles) hipFree(d_tiles);
         if (d_units) hipFree(d_units);
+        for (int p = 0; p < 8; ++p)
+            if (d_chunks[p]) hipFree(d_chunks[p]);
+        if (d_vchunks) hipFree(d_vchunks);
         if (d_knots) hipFree(d_knots);
     }
 };
@@ -203,63 +235,92 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     P->key = std::move(key);
     P->n_sweeps = b->n_sweeps;
     P->with_nrm = with_nrm;
-    // surface tiles: (sweep, first local vertex) in sweep order
+    // surface tiles: (sweep, first local vertex) in sweep order; frame
+    // chunks: (sweep, chunk) of every 256 u-samples (grouped by path degree)
+    // and of every 256 v-samples
     const int tv = batched_tile_vertices();
-    std::vector<int2> tiles;
+    std::vector<int2> tiles, vchunks, chunks[8];
     for (int k = 0; k < b->n_sweeps; ++k) {
         const long long N = (long long)b->n_u[k] * b->n_v[k];
         for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
+        for (int c = 0; c * kBlock < b->n_u[k]; ++c) chunks[b->path_degree[k]].push_back(make_int2(k, c));
+        for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
-    if (tiles.size() > 0x7fffffffull) return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many surface tiles");
+    if (tiles.size() > 0x7fffffffull || vchunks.size() > 0x7fffffffull)
+        return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
     P->n_tiles = (int)tiles.size();
+    P->n_vchunks = (int)vchunks.size();
     hipError_t e;
-    if ((e = hipMalloc(&P->d_descs, sizeof(BatchDesc) * descs.size())) != hipSuccess) return hip_fail(e, "plan alloc");
-    if ((e = hipMalloc(&P->d_tiles, sizeof(int2) * tiles.size())) != hipSuccess) return hip_fail(e, "plan alloc");
-    if (!knots.empty() && (e = hipMalloc(&P->d_knots, sizeof(double) * knots.size())) != hipSuccess)
-        return hip_fail(e, "plan alloc");
-    if ((e = hipMemcpy(P->d_descs, descs.data(), sizeof(BatchDesc) * descs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t r = hipMalloc(dst, bytes);
+        if (r != hipSuccess) return r;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    if ((e = upload((void**)&P->d_descs, descs.data(), sizeof(BatchDesc) * descs.size())) != hipSuccess ||
+        (e = upload((void**)&P->d_tiles, tiles.data(), sizeof(int2) * tiles.size())) != hipSuccess ||
+        (e = upload((void**)&P->d_vchunks, vchunks.data(), sizeof(int2) * vchunks.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
-    if ((e = hipMemcpy(P->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "plan upload");
-    if (!knots.empty() &&
-        (e = hipMemcpy(P->d_knots, knots.data(), sizeof(double) * knots.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        if (chunks[p].size() > 0x7fffffffull) return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
+        P->n_chunks[p] = (int)chunks[p].size();
+        if (!chunks[p].empty() &&
+            (e = upload((void**)&P->d_chunks[p], chunks[p].data(), sizeof(int2) * chunks[p].size())) != hipSuccess)
+            return hip_fail(e, "plan upload");
+    }
+    if (!knots.empty() && (e = upload((void**)&P->d_knots, knots.data(), sizeof(double) * knots.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
 
     const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : SurfaceConfig{1, 0, 1024, 1};
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
                                              with_nrm, cfg.nontemporal != 0);
     // argument blocks are compared bytewise on every call: clear the padding
-    std::memset(&P->fa, 0, sizeof P->fa);
-    std::memset(&P->sa, 0, sizeof P->sa);
-    P->fa.descs = P->d_descs;
-    P->fa.knots = P->d_knots;
-    P->fa.n0.enabled = o->has_initial_normal;
-    for (int c = 0; c < 3; ++c) P->fa.n0.v[c] = o->initial_normal[c];
-    P->fa.reorth = o->reorthonormalize;
-    P->sa.descs = P->d_descs;
-    P->sa.tiles = P->d_tiles;
-    void* fa[10] = {&P->fa.descs, &P->fa.path_ctrl, &P->fa.prof_ctrl, &P->fa.knots, &P->fa.n0, &P->fa.reorth,
-                    &P->fa.agg, &P->fa.r_in, &P->fa.rows, &P->fa.ptab};
-    void* sa[6] = {&P->sa.descs, &P->sa.tiles, &P->sa.rows, &P->sa.ptab, &P->sa.pos, &P->sa.nrm};
-    std::memcpy(P->fa_ptrs, fa, sizeof fa);
-    std::memcpy(P->sa_ptrs, sa, sizeof sa);
-    P->p_frames.func = const_cast<void*>(K.frames);
-    P->p_frames.gridDim = dim3(b->n_sweeps);
-    P->p_frames.blockDim = dim3(kBlock);
-    P->p_frames.sharedMemBytes = 0;
-    P->p_frames.kernelParams = P->fa_ptrs;
-    P->p_frames.extra = nullptr;
-    P->p_surface.func = const_cast<void*>(K.surface);
-    P->p_surface.gridDim = dim3(P->n_tiles);
-    P->p_surface.blockDim = dim3(kBlock);
-    P->p_surface.sharedMemBytes = 0;
-    P->p_surface.kernelParams = P->sa_ptrs;
-    P->p_surface.extra = nullptr;
+    std::memset(&P->a, 0, sizeof P->a);
+    NodeArgs& A = P->a;
+    A.descs = P->d_descs;
+    A.vchunks = P->d_vchunks;
+    A.tiles = P->d_tiles;
+    A.knots = P->d_knots;
+    A.n0.enabled = o->has_initial_normal;
+    for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
+    A.reorth = o->reorthonormalize;
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
-    if ((e = hipGraphAddKernelNode(&P->n_frames, P->graph, nullptr, 0, &P->p_frames)) != hipSuccess)
-        return hip_fail(e, "graph frames node");
-    if ((e = hipGraphAddKernelNode(&P->n_surface, P->graph, &P->n_frames, 1, &P->p_surface)) != hipSuccess)
-        return hip_fail(e, "graph surface node");
+    auto add = [&](NodeKind kind, int deg, const void* fn, unsigned grid,
+                   const std::vector<hipGraphNode_t>& deps) -> hipError_t {
+        std::unique_ptr<GNode> n(new GNode());
+        n->kind = kind;
+        n->deg = deg;
+        std::memcpy(&n->a, &P->a, sizeof n->a);
+        if (kind == kPrep || kind == kApply) n->a.chunks = P->d_chunks[deg];
+        node_args(*n);
+        n->prm.func = const_cast<void*>(fn);
+        n->prm.gridDim = dim3(grid);
+        n->prm.blockDim = dim3(kBlock);
+        n->prm.sharedMemBytes = 0;
+        n->prm.kernelParams = n->ptrs;
+        n->prm.extra = nullptr;
+        hipError_t r = hipGraphAddKernelNode(&n->node, P->graph, deps.empty() ? nullptr : deps.data(), deps.size(),
+                                             &n->prm);
+        P->nodes.push_back(std::move(n));
+        return r;
+    };
+    std::vector<hipGraphNode_t> preps, applies;
+    if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
+    const hipGraphNode_t profile_node = P->nodes.back()->node;
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        if (!P->n_chunks[p]) continue;
+        if ((e = add(kPrep, p, K.prep[p], (unsigned)P->n_chunks[p], {})) != hipSuccess) return hip_fail(e, "graph node");
+        preps.push_back(P->nodes.back()->node);
+    }
+    if ((e = add(kCarry, 0, K.carry, (unsigned)b->n_sweeps, preps)) != hipSuccess) return hip_fail(e, "graph node");
+    const hipGraphNode_t carry_node = P->nodes.back()->node;
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        if (!P->n_chunks[p]) continue;
+        if ((e = add(kApply, p, K.apply[p], (unsigned)P->n_chunks[p], {carry_node})) != hipSuccess)
+            return hip_fail(e, "graph node");
+        applies.push_back(P->nodes.back()->node);
+    }
+    applies.push_back(profile_node);
+    if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, applies)) != hipSuccess) return hip_fail(e, "graph node");
     if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
         return hip_fail(e, "graph instantiate");
     out = std::move(P);
@@ -326,29 +387,27 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     Plan* P = nullptr;
     if ((st = get_plan(batch, opt, nrm != nullptr, std::move(key), &P)) != SWEEP_OK) return st;
     char* ws = (char*)workspace;
-    FramesArgs fa;
-    std::memcpy(&fa, &P->fa, sizeof fa);
-    fa.path_ctrl = batch->path_ctrl;
-    fa.prof_ctrl = batch->prof_ctrl;
-    fa.agg = ws + L.agg;
-    fa.r_in = ws + L.r_in;
-    fa.rows = ws + L.rows;
-    fa.ptab = ws + L.ptab;
-    SurfaceArgs sa;
-    std::memcpy(&sa, &P->sa, sizeof sa);
-    sa.rows = ws + L.rows;
-    sa.ptab = ws + L.ptab;
-    sa.pos = pos;
-    sa.nrm = nrm;
-    if (std::memcmp(&fa, &P->fa, sizeof fa) != 0) {
-        P->fa = fa;
-        if ((e = hipGraphExecKernelNodeSetParams(P->exec, P->n_frames, &P->p_frames)) != hipSuccess)
-            return hip_fail(e, "graph update");
-    }
-    if (std::memcmp(&sa, &P->sa, sizeof sa) != 0) {
-        P->sa = sa;
-        if ((e = hipGraphExecKernelNodeSetParams(P->exec, P->n_surface, &P->p_surface)) != hipSuccess)
-            return hip_fail(e, "graph update");
+    NodeArgs A;
+    std::memcpy(&A, &P->a, sizeof A);
+    A.path_ctrl = batch->path_ctrl;
+    A.prof_ctrl = batch->prof_ctrl;
+    A.agg = ws + L.agg;
+    A.r_in = ws + L.r_in;
+    A.chunk_lv = ws + L.chunk_lv;
+    A.chunk_fix = ws + L.chunk_fix;
+    A.rows = ws + L.rows;
+    A.ptab = ws + L.ptab;
+    A.pos = pos;
+    A.nrm = nrm;
+    if (std::memcmp(&A, &P->a, sizeof A) != 0) {
+        P->a = A;
+        for (auto& n : P->nodes) {
+            const int2* own = n->a.chunks;
+            std::memcpy(&n->a, &A, sizeof A);
+            n->a.chunks = own;
+            if ((e = hipGraphExecKernelNodeSetParams(P->exec, n->node, &n->prm)) != hipSuccess)
+                return hip_fail(e, "graph update");
+        }
     }
     if ((e = hipGraphLaunch(P->exec, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "graph launch");
     return SWEEP_OK;
@@ -403,18 +462,34 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
     const BatchedKernels FK = batched_kernels(true, true, false, false);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64);
     {
-        FramesArgs fa = P->fa;
-        fa.path_ctrl = batch->path_ctrl;
-        fa.prof_ctrl = batch->prof_ctrl;
-        fa.reorth = 1;
-        fa.agg = ws + B.agg;
-        fa.r_in = ws + B.r_in;
-        fa.rows = ws + B.rows;
-        fa.ptab = ws + B.ptab;
-        void* args[10] = {&fa.descs, &fa.path_ctrl, &fa.prof_ctrl, &fa.knots, &fa.n0, &fa.reorth,
-                          &fa.agg, &fa.r_in, &fa.rows, &fa.ptab};
-        if ((e = hipLaunchKernel(FK.frames, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
+        // FP64 frame recomputation with re-orthonormalisation: profile, prep, carry, apply
+        GNode n;
+        std::memcpy(&n.a, &P->a, sizeof n.a);
+        n.a.path_ctrl = batch->path_ctrl;
+        n.a.prof_ctrl = batch->prof_ctrl;
+        n.a.reorth = 1;
+        n.a.agg = ws + B.agg;
+        n.a.r_in = ws + B.r_in;
+        n.a.chunk_lv = ws + B.chunk_lv;
+        n.a.chunk_fix = ws + B.chunk_fix;
+        n.a.rows = ws + B.rows;
+        n.a.ptab = ws + B.ptab;
+        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid) -> hipError_t {
+            n.kind = kind;
+            n.a.chunks = (kind == kPrep || kind == kApply) ? P->d_chunks[deg] : nullptr;
+            node_args(n);
+            return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, 0, sm);
+        };
+        if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
+            if (P->n_chunks[p] && (e = launch(kPrep, p, FK.prep[p], (unsigned)P->n_chunks[p])) != hipSuccess)
+                return hip_fail(e, "backward frames");
+        if ((e = launch(kCarry, 0, FK.carry, (unsigned)batch->n_sweeps)) != hipSuccess)
+            return hip_fail(e, "backward frames");
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
+            if (P->n_chunks[p] && (e = launch(kApply, p, FK.apply[p], (unsigned)P->n_chunks[p])) != hipSuccess)
+                return hip_fail(e, "backward frames");
     }
     {
         const BatchDesc* descs = P->d_descs;
@@ -435,7 +510,7 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         const double* pc = batch->path_ctrl;
         const double* qc = batch->prof_ctrl;
         const double* kn = P->d_knots;
-        InitialNormal n0 = P->fa.n0;
+        InitialNormal n0 = P->a.n0;
         const void* rows = ws + B.rows;
         const void* rowpart = ws + B.rowpart;
         const void* colpart = ws + B.colpart;

@@ -17,14 +17,16 @@ struct InitialNormal {
 int frame_chunk_size();
 
 // Path samples (x, C', C'' as SoA planes of n_u doubles), per-chunk last
-// valid sample, fallback tangent, and the profile table.
-template <class T>
-hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
-                       double* fallback_t, T* ptab, hipStream_t st);
-// Frame scan and row table (16 values per u-row).
+// valid sample, chunk products of the step rotations (or a flag), fallback
+// tangent, and the profile table.
 template <class F, class T>
-hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const double* fallback_t, InitialNormal n0,
-                        int reorth, F* agg, F* r_in, T* rows, hipStream_t st);
+hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
+                       int* chunk_fix, double* fallback_t, F* agg, T* ptab, hipStream_t st);
+// Carry scan and row table (16 values per u-row).
+template <class F, class T>
+hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const int* chunk_fix,
+                        const double* fallback_t, InitialNormal n0, int reorth, F* agg, F* r_in, T* rows,
+                        hipStream_t st);
 
 // Surface write of one sweep from its row table (16 values per u-row) and
 // profile table (8 values per v-sample).
@@ -73,7 +75,10 @@ BackwardKernels backward_kernels(bool t64);
 void fastdiv_constants(int d, unsigned long long* m, int* shift);
 
 struct BatchedKernels {
-    const void* frames;
+    const void* profile;
+    const void* prep[8];    // by path degree (index 0 unused)
+    const void* carry;
+    const void* apply[8];   // by path degree
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as

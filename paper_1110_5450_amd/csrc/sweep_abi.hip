@@ -5,8 +5,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/sweep.h"
 #include "abi_internal.hpp"
@@ -141,15 +146,114 @@ int tile_config_count() { return (int)(sizeof kTiles / sizeof kTiles[0]); }
 
 const SurfaceConfig& tile_config(int k) { return kTiles[k]; }
 
-// Automatic choice for a single sweep (nontemporal stores, which measured
-// 15-25 % faster for this write-once output): column tiles of one row when
-// n_v fills whole 256-column tiles, otherwise the linear kernel with 4
-// vertices per lane.
-SurfaceConfig auto_surface_config(int n_u, int n_v)
+// ----------------------------------------------------------------- tuning
+
+struct TuneKey {
+    std::string arch;
+    int cus, t64, nv256, lnv, ln;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(arch, cus, t64, nv256, lnv, ln) < std::tie(o.arch, o.cus, o.t64, o.nv256, o.lnv, o.ln);
+    }
+};
+struct TuneVal {
+    int config;
+    float ms;
+};
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tuned;
+static bool g_tune_loaded = false;
+static std::string g_arch;
+static int g_cus = -1;
+
+static int ilog2(long long v)
 {
-    (void)n_u;
+    int l = 0;
+    while (v > 1) { v >>= 1; ++l; }
+    return l;
+}
+
+static void device_identity()
+{
+    if (g_cus >= 0) return;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        g_arch = prop.gcnArchName;
+        const size_t colon = g_arch.find(':');
+        if (colon != std::string::npos) g_arch.resize(colon);
+        g_cus = prop.multiProcessorCount;
+    } else {
+        (void)hipGetLastError();
+        g_arch = "unknown";
+        g_cus = 0;
+    }
+}
+
+static TuneKey tune_key(int n_u, int n_v, int t64)
+{
+    device_identity();
+    return TuneKey{g_arch, g_cus, t64, n_v % 256 == 0 ? 1 : 0, ilog2(n_v), ilog2((long long)n_u * n_v)};
+}
+
+// Cache file: one entry per line,
+//   arch cus t64 nv256 lnv ln config ms
+static void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SWEEP_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[64];
+        TuneKey k;
+        TuneVal v;
+        if (line[0] == '#') continue;
+        if (std::sscanf(line, "%63s %d %d %d %d %d %d %f", arch, &k.cus, &k.t64, &k.nv256, &k.lnv, &k.ln, &v.config,
+                        &v.ms) == 8 &&
+            v.config >= 0 && v.config < tile_config_count()) {
+            k.arch = arch;
+            g_tuned[k] = v;
+        }
+    }
+    std::fclose(f);
+}
+
+static void tune_save_locked()
+{
+    const char* path = std::getenv("SWEEP_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "# sweep surface tuning: arch cus t64 nv256 log2_nv log2_vertices config ms\n");
+    for (const auto& e : g_tuned)
+        std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", e.first.arch.c_str(), e.first.cus, e.first.t64,
+                     e.first.nv256, e.first.lnv, e.first.ln, e.second.config, e.second.ms);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+// Built-in rule (nontemporal stores measured 15-25 % faster for this
+// write-once output): column tiles of one row when n_v fills whole
+// 256-column tiles, otherwise the linear kernel with 4 vertices per lane.
+static SurfaceConfig rule_surface_config(int n_v)
+{
     if (n_v % 256 == 0) return SurfaceConfig{0, 1, 0, 1};
     return SurfaceConfig{1, 0, 1024, 1};
+}
+
+SurfaceConfig auto_surface_config(int n_u, int n_v, int t64)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load_locked();
+    const auto it = g_tuned.find(tune_key(n_u, n_v, t64));
+    if (it != g_tuned.end()) return tile_config(it->second.config);
+    return rule_surface_config(n_v);
 }
 
 // ---------------------------------------------------------- workspace plan
@@ -157,7 +261,7 @@ SurfaceConfig auto_surface_config(int n_u, int n_v)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, fallback, agg, r_in, rows, prof_tab, total;
+    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, total;
 };
 
 static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz)
@@ -169,6 +273,7 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
     L.knots_prof = off; off = align_up(off + sizeof(double) * nknots(nq, pq, qclosed));
     L.smp = off;        off = align_up(off + sizeof(double) * 9 * (size_t)n_u);
     L.chunk_lv = off;   off = align_up(off + sizeof(int) * (size_t)nc);
+    L.chunk_fix = off;  off = align_up(off + sizeof(int) * (size_t)nc);
     L.fallback = off;   off = align_up(off + sizeof(double) * 3);
     L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
     L.r_in = off;       off = align_up(off + fsz * 3 * (size_t)nc);
@@ -210,10 +315,11 @@ static sweep_status run_frames(const sweep_curve* path, int n_u, const sweep_opt
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
-    hipError_t e = launch_prep<T>(dp, n_u, dq, 0, smp, clv, fb, (T*)nullptr, st);
+    int* cfx = (int*)(ws + L.chunk_fix);
+    hipError_t e = launch_prep<F, T>(dp, n_u, dq, 0, smp, clv, cfx, fb, (F*)(ws + L.agg), (T*)nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
-    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
+    e = launch_frame<F, T>(smp, n_u, clv, cfx, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
                            rows, st);
     if (e != hipSuccess) return hip_fail(e, "frame");
     return SWEEP_OK;
@@ -238,16 +344,18 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
+    int* cfx = (int*)(ws + L.chunk_fix);
     T* rows = (T*)(ws + L.rows);
     T* ptab = (T*)(ws + L.prof_tab);
-    hipError_t e = launch_prep<T>(dp, n_u, dq, n_v, smp, clv, fb, ptab, st);
+    hipError_t e = launch_prep<F, T>(dp, n_u, dq, n_v, smp, clv, cfx, fb, (F*)(ws + L.agg), ptab, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
-    e = launch_frame<F, T>(smp, n_u, clv, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
+    e = launch_frame<F, T>(smp, n_u, clv, cfx, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
                            rows, st);
     if (e != hipSuccess) return hip_fail(e, "frame");
     trace_mark(1, st);
-    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : auto_surface_config(n_u, n_v);
+    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config)
+                                                   : auto_surface_config(n_u, n_v, o->out_precision == SWEEP_F64);
     e = launch_surface<T>(rows, ptab, n_u, n_v, (T*)pos, (T*)nrm, cfg, st);
     if (e != hipSuccess) return hip_fail(e, "surface");
     trace_mark(2, st);
@@ -370,6 +478,70 @@ sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_opti
     if (f64) return run_frames<double, float>(path, n_u, opt, (float*)frames, ws, L, st);
     if (t64) return run_frames<float, double>(path, n_u, opt, (double*)frames, ws, L, st);
     return run_frames<float, float>(path, n_u, opt, (float*)frames, ws, L, st);
+}
+
+sweep_status sweep_autotune(const sweep_curve* path, const sweep_curve* profile, int32_t n_u, int32_t n_v,
+                            const sweep_options* opt, void* pos, void* nrm, void* workspace, size_t ws_bytes,
+                            void* stream, int32_t* best_config, float* best_ms)
+{
+    sweep_options o;
+    if (opt) o = *opt; else sweep_default_options(&o);
+    o.tile_config = -1;
+    sweep_status s = sweep_eval(path, profile, n_u, n_v, &o, pos, nrm, workspace, ws_bytes, stream);
+    if (s != SWEEP_OK) return s;
+    const SingleLayout L = layout_for(path, profile, n_u, n_v, &o);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev0, ev1;
+    hipError_t e;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e, "autotune");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) { hipEventDestroy(ev0); return hip_fail(e, "autotune"); }
+    const bool t64 = o.out_precision == SWEEP_F64;
+    const char* ws = (const char*)workspace;
+    int best = -1;
+    float best_t = 0.f;
+    const int reps = 5;
+    for (int c = 0; c < tile_config_count() && e == hipSuccess; ++c) {
+        const SurfaceConfig& cfg = tile_config(c);
+        auto run = [&]() -> hipError_t {
+            return t64 ? launch_surface<double>((const double*)(ws + L.rows), (const double*)(ws + L.prof_tab), n_u,
+                                                n_v, (double*)pos, (double*)nrm, cfg, st)
+                       : launch_surface<float>((const float*)(ws + L.rows), (const float*)(ws + L.prof_tab), n_u, n_v,
+                                               (float*)pos, (float*)nrm, cfg, st);
+        };
+        if ((e = run()) != hipSuccess) break;   // warm-up
+        if ((e = hipEventRecord(ev0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+        if (e != hipSuccess || (e = hipEventRecord(ev1, st)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess)
+            break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) break;
+        ms /= reps;
+        if (best < 0 || ms < best_t) { best = c; best_t = ms; }
+    }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_load_locked();
+        g_tuned[tune_key(n_u, n_v, t64)] = TuneVal{best, best_t};
+        tune_save_locked();
+    }
+    if (best_config) *best_config = best;
+    if (best_ms) *best_ms = best_t;
+    return SWEEP_OK;
+}
+
+int32_t sweep_surface_config_for(int32_t n_u, int32_t n_v, int32_t out_precision)
+{
+    const SurfaceConfig c = auto_surface_config(n_u, n_v, out_precision == SWEEP_F64);
+    for (int k = 0; k < tile_config_count(); ++k) {
+        const SurfaceConfig& t = tile_config(k);
+        if (t.kind == c.kind && t.rows_per_block == c.rows_per_block && t.tile_vertices == c.tile_vertices &&
+            t.nontemporal == c.nontemporal)
+            return k;
+    }
+    return -1;
 }
 
 int32_t sweep_tile_config_count(void) { return tile_config_count(); }

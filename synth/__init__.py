@@ -35,7 +35,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "CurveSpec", "SweepSpec", "random_walk", "perturbed_circle",
+    "CurveSpec", "SweepSpec", "random_walk", "perturbed_circle", "single",
     "config", "c1", "c2", "c3", "c4", "c5", "loss_weights",
 ]
 
@@ -85,8 +85,10 @@ def perturbed_circle(rng: np.random.Generator, m: int, radius: float = 0.3,
     return np.stack([radii * np.cos(ang), radii * np.sin(ang), np.zeros(m)], axis=1)
 
 
-def _single(seed: int, n_path: int, n_prof: int, n_u: int, n_v: int,
-            p_path: int = 3, p_prof: int = 3) -> SweepSpec:
+def single(seed: int, n_path: int, n_prof: int, n_u: int, n_v: int,
+           p_path: int = 3, p_prof: int = 3) -> SweepSpec:
+    """One open path (random walk) and one closed profile (perturbed circle)
+    drawn from the seed."""
     rng = np.random.default_rng(seed)
     path = random_walk(rng, n_path)
     prof = perturbed_circle(rng, n_prof)
@@ -94,11 +96,11 @@ def _single(seed: int, n_path: int, n_prof: int, n_u: int, n_v: int,
 
 
 def c1() -> SweepSpec:
-    return _single(1, 16, 8, 256, 64)
+    return single(1, 16, 8, 256, 64)
 
 
 def c2(n_u: int = 65536, n_v: int = 1024) -> SweepSpec:
-    return _single(2, 1024, 64, n_u, n_v)
+    return single(2, 1024, 64, n_u, n_v)
 
 
 def c3(n_u: int = 1048576, n_v: int = 32) -> SweepSpec:
