@@ -155,7 +155,7 @@ def batched_variants(steps: int):
     b = api.Batch.from_specs(specs)
     N = b.n_vertices
     ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
-    pos = torch.empty(3 * N, dtype=torch.float32, device="cuda")
+    pos = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pos)
     for _ in range(2):
         api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
@@ -216,7 +216,7 @@ def adjoint_variant(steps: int):
     specs = synth.c5()
     b = api.Batch.from_specs(specs)
     N = b.n_vertices
-    g = torch.randn(3 * N, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    g = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
     ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
     for _ in range(2):
         api.sweep_backward(b, g, workspace=ws)
@@ -226,7 +226,7 @@ def adjoint_variant(steps: int):
         api.sweep_backward(b, g, workspace=ws)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    fw = torch.empty(3 * N, dtype=torch.float32, device="cuda")
+    fw = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     fn = torch.empty_like(fw)
     wsf = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
     for _ in range(2):

@@ -46,8 +46,13 @@
  * memory read before the call returns.  Positions and normals are written as
  * structure-of-arrays planes: element (c, i, j) of a sweep with N = n_u*n_v
  * vertices is at [c*N + i*n_v + j], c = x, y, z, in the output precision.
- * The batched call concatenates these blocks: sweep k's block starts at
- * element 3*off_k with off_k = sum_{k'<k} n_u[k']*n_v[k'].
+ * The batched calls concatenate per-sweep blocks whose planes are padded:
+ * sweep k has plane stride P_k = n_u[k]*n_v[k] rounded up to a multiple of
+ * 64 elements, its block starts at element off_k = 3 * sum_{k'<k} P_{k'},
+ * and element (c, i, j) is at [off_k + c*P_k + i*n_v[k] + j].  The padding
+ * elements are written as 0 by sweep_eval_batched and ignored by
+ * sweep_backward.  (With 256-byte aligned buffers every plane then starts
+ * on a cache-line boundary; see sweep_batched_output_elems.)
  *
  * Streams and errors: work is enqueued on the given stream (a hipStream_t,
  * NULL for the default stream) and the call returns without waiting for it.
@@ -169,12 +174,17 @@ size_t sweep_frames_workspace_size(const sweep_curve *path, int32_t n_u, const s
  * schedule and builds the graph; later calls with the same shape only update
  * the graph's pointer arguments and launch it.  Sweep k's output equals
  * sweep_eval's for that sweep (same kernels, same arithmetic).
- * pos/nrm: DEVICE, 3*sum(n_u*n_v) elements.
+ * pos/nrm: DEVICE, sweep_batched_output_elems(batch) elements in the padded
+ * batched layout, best 256-byte aligned.
  */
 sweep_status sweep_eval_batched(const sweep_batch *batch, const sweep_options *opt,
                                 void *pos, void *nrm, void *workspace, size_t ws_bytes,
                                 void *stream);
 size_t sweep_batched_workspace_size(const sweep_batch *batch, const sweep_options *opt);
+/* Elements of one batched output buffer: 3 * sum_k P_k (padded layout
+ * above); 0 if batch, n_u or n_v is NULL, n_sweeps < 1 or a count is
+ * negative.  Counts are not otherwise validated. */
+int64_t sweep_batched_output_elems(const sweep_batch *batch);
 
 /*
  * Adjoint of the positions: given grad_pos = dL/dpos (DEVICE, same layout and

@@ -77,6 +77,8 @@ def lib():
         L.sweep_eval_batched.restype = C.c_int32
         L.sweep_batched_workspace_size.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions)]
         L.sweep_batched_workspace_size.restype = sz
+        L.sweep_batched_output_elems.argtypes = [C.POINTER(SweepBatch)]
+        L.sweep_batched_output_elems.restype = C.c_int64
         L.sweep_backward.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp, sz, vp]
         L.sweep_backward.restype = C.c_int32
         L.sweep_backward_workspace_size.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions)]
@@ -155,6 +157,10 @@ def sweep_backward(batch: SweepBatch, opt: SweepOptions, grad_pos: int, grad_pat
                    grad_prof_ctrl: int, workspace: int, ws_bytes: int, stream: int) -> int:
     return lib().sweep_backward(C.byref(batch), C.byref(opt), grad_pos, grad_path_ctrl, grad_prof_ctrl,
                                 workspace, ws_bytes, stream)
+
+
+def sweep_batched_output_elems(batch: SweepBatch) -> int:
+    return lib().sweep_batched_output_elems(C.byref(batch))
 
 
 def sweep_backward_workspace_size(batch: SweepBatch, opt: SweepOptions) -> int:

@@ -49,6 +49,19 @@ def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonorm
     return o
 
 
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def _check_out(t: torch.Tensor, numel: int, dtype, what: str) -> None:
+    """An output buffer must hold at least `numel` contiguous elements of
+    `dtype` on a GPU: the kernels write through its raw pointer."""
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor")
+    if t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, {numel} are written")
+
+
 def _stream_handle(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
@@ -78,10 +91,13 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
         nrm = torch.empty((3, n_u, n_v), dtype=out_dtype, device=dev) if normals else None
     else:
         pos, nrm = out
-    if workspace is None or workspace.numel() < ws_bytes:
+        _check_out(pos, 3 * n_u * n_v, out_dtype, "out[0]")
+        if nrm is not None:
+            _check_out(nrm, 3 * n_u * n_v, out_dtype, "out[1]")
+    if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     st = L.sweep_eval(path, prof, int(n_u), int(n_v), opt, pos.data_ptr(),
-                      nrm.data_ptr() if nrm is not None else 0, workspace.data_ptr(), workspace.numel(),
+                      nrm.data_ptr() if nrm is not None else 0, workspace.data_ptr(), _nbytes(workspace),
                       _stream_handle(stream))
     L.check(st)
     return pos, nrm
@@ -109,7 +125,7 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
     workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     st, best, ms = L.sweep_autotune(path, prof, int(n_u), int(n_v), opt, pos.data_ptr(),
                                     nrm.data_ptr() if nrm is not None else 0, workspace.data_ptr(),
-                                    workspace.numel(), _stream_handle(stream))
+                                    _nbytes(workspace), _stream_handle(stream))
     L.check(st)
     return best, ms, pos, nrm
 
@@ -132,9 +148,9 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
     if ws_bytes == 0:
         L.check(L.sweep_frames(path, int(n_u), opt, 0, 0, 0, 0))
     out = torch.empty((n_u, 16), dtype=out_dtype, device=pc.device)
-    if workspace is None or workspace.numel() < ws_bytes:
+    if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=pc.device)
-    L.check(L.sweep_frames(path, int(n_u), opt, out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+    L.check(L.sweep_frames(path, int(n_u), opt, out.data_ptr(), workspace.data_ptr(), _nbytes(workspace),
                            _stream_handle(stream)))
     return out
 
@@ -150,8 +166,12 @@ class Batch:
     """A batch of independent sweeps packed for sweep_eval_batched /
     sweep_backward.  Control points are packed into one device float64 buffer
     per curve kind; per-sweep counts, degrees, grid sizes and knot vectors
-    stay in host memory.  Sweep k's output block starts at element
-    3 * offsets[k] of the flat position (normal) buffer."""
+    stay in host memory.  Flat outputs use the padded batched layout: sweep
+    k's planes have stride plane[k] (n_u*n_v rounded up to a multiple of
+    PLANE_ALIGN elements) and its block starts at element offsets[k]; a flat
+    buffer holds out_elems elements (view() gives a sweep's block)."""
+
+    PLANE_ALIGN = 64
 
     def __init__(self, path_ctrl: Sequence, path_degree: Sequence[int], prof_ctrl: Sequence,
                  prof_degree: Sequence[int], n_u: Sequence[int], n_v: Sequence[int], *, prof_closed=None,
@@ -184,7 +204,10 @@ class Batch:
         self.path_ctrl = torch.as_tensor(np.concatenate(P)).to(device)
         self.prof_ctrl = torch.as_tensor(np.concatenate(Q)).to(device)
         sizes = self.n_u.astype(np.int64) * self.n_v.astype(np.int64)
-        self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        a = self.PLANE_ALIGN
+        self.plane = (sizes + a - 1) // a * a
+        self.offsets = np.concatenate([[0], np.cumsum(3 * self.plane)[:-1]]).astype(np.int64)
+        self.out_elems = int(3 * self.plane.sum())
         self.n_vertices = int(sizes.sum())
         self.path_offsets = np.concatenate([[0], np.cumsum(self.path_n)[:-1]]).astype(np.int64)
         self.prof_offsets = np.concatenate([[0], np.cumsum(self.prof_n)[:-1]]).astype(np.int64)
@@ -210,9 +233,18 @@ class Batch:
                             self.path_ctrl.data_ptr(), self.prof_ctrl.data_ptr())
 
     def view(self, flat: torch.Tensor, k: int) -> torch.Tensor:
-        """Sweep k's (3, n_u, n_v) block of a flat batched output."""
-        o, nu, nv = int(self.offsets[k]), int(self.n_u[k]), int(self.n_v[k])
-        return flat[3 * o: 3 * o + 3 * nu * nv].view(3, nu, nv)
+        """Sweep k's (3, n_u, n_v) block of a flat batched output (a view with
+        plane stride plane[k])."""
+        o, nu, nv, P = int(self.offsets[k]), int(self.n_u[k]), int(self.n_v[k]), int(self.plane[k])
+        return flat[o: o + 3 * P].view(3, P)[:, :nu * nv].view(3, nu, nv)
+
+    def pack(self, blocks, dtype=torch.float32) -> torch.Tensor:
+        """A flat buffer in the batched layout from per-sweep (3, n_u, n_v)
+        blocks (padding 0)."""
+        flat = torch.zeros(self.out_elems, dtype=dtype, device=self.path_ctrl.device)
+        for k, blk in enumerate(blocks):
+            self.view(flat, k).copy_(torch.as_tensor(blk))
+        return flat
 
     def path_slice(self, k: int) -> slice:
         return slice(int(self.path_offsets[k]), int(self.path_offsets[k] + self.path_n[k]))
@@ -232,14 +264,17 @@ def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=tor
         L.check(L.sweep_eval_batched(b, opt, 0, 0, 0, 0, 0))
     dev = batch.path_ctrl.device
     if out is None:
-        pos = torch.empty(3 * batch.n_vertices, dtype=out_dtype, device=dev)
-        nrm = torch.empty(3 * batch.n_vertices, dtype=out_dtype, device=dev) if normals else None
+        pos = torch.empty(batch.out_elems, dtype=out_dtype, device=dev)
+        nrm = torch.empty(batch.out_elems, dtype=out_dtype, device=dev) if normals else None
     else:
         pos, nrm = out
-    if workspace is None or workspace.numel() < ws_bytes:
+        _check_out(pos, batch.out_elems, out_dtype, "out[0]")
+        if nrm is not None:
+            _check_out(nrm, batch.out_elems, out_dtype, "out[1]")
+    if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     L.check(L.sweep_eval_batched(b, opt, pos.data_ptr(), nrm.data_ptr() if nrm is not None else 0,
-                                 workspace.data_ptr(), workspace.numel(), _stream_handle(stream)))
+                                 workspace.data_ptr(), _nbytes(workspace), _stream_handle(stream)))
     return pos, nrm
 
 
@@ -256,7 +291,7 @@ def sweep_backward(batch: Batch, grad_pos: torch.Tensor, *, initial_normal=None,
     if grad_pos.dtype not in _DT:
         raise TypeError("grad_pos must be float32 or float64")
     g = grad_pos.contiguous()
-    if g.numel() != 3 * batch.n_vertices:
+    if g.numel() != batch.out_elems:
         raise ValueError("grad_pos has the wrong size")
     opt = make_options(g.dtype, torch.float64, True, initial_normal)
     ws_bytes = L.sweep_backward_workspace_size(b, opt)
@@ -265,10 +300,10 @@ def sweep_backward(batch: Batch, grad_pos: torch.Tensor, *, initial_normal=None,
     dev = batch.path_ctrl.device
     gP = torch.empty((int(batch.path_n.sum()), 3), dtype=torch.float64, device=dev)
     gQ = torch.empty((int(batch.prof_n.sum()), 3), dtype=torch.float64, device=dev)
-    if workspace is None or workspace.numel() < ws_bytes:
+    if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     L.check(L.sweep_backward(b, opt, g.data_ptr(), gP.data_ptr(), gQ.data_ptr(), workspace.data_ptr(),
-                             workspace.numel(), _stream_handle(stream)))
+                             _nbytes(workspace), _stream_handle(stream)))
     return gP, gQ
 
 

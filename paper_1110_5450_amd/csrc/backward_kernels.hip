@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         const double* q = ptab + 8 * (d.ptab_off + j);
         Sx = q[0]; Sy = q[1]; Sz = q[2];
     }
-    const size_t N = (size_t)d.n_u * (size_t)d.n_v;
-    const T* w0 = grad + 3 * (size_t)d.out_off;
+    const size_t N = (size_t)d.plane;   // plane stride of the batched layout
+    const T* w0 = grad + d.out_off;
     double h0 = 0.0, h1 = 0.0, h2 = 0.0;
     const int i0 = g * kBwRowGroup, i1 = min(d.n_u, i0 + kBwRowGroup);
     for (int i = i0; i < i1; ++i) {

@@ -1,6 +1,8 @@
-// batched_abi.hip -- sweep_eval_batched: plans keyed by batch shape, each
-// holding the per-sweep descriptors and surface tile list in device memory
-// and a two-node HIP graph (frames, surface) that is replayed per call.
+// batched_abi.hip -- sweep_eval_batched and sweep_backward: plans keyed by
+// batch shape, each holding the per-sweep descriptors, the per-degree sweep
+// lists and the surface tile list in device memory, and a HIP graph
+// (profile tables and one frame node per path degree, then the surface)
+// that is replayed per call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +17,7 @@
 namespace sweep {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+static long long plane_stride(long long n) { return (n + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign; }
 
 // Validated, flattened metadata of a batch plus the options that shape the
 // kernels; equality of two keys means the same plan applies.
@@ -26,14 +29,14 @@ struct BatchKey {
 };
 
 struct BatchLayout {
-    size_t rows, ptab, agg, r_in, chunk_lv, chunk_fix, total;
-    long long n_rows = 0, n_vs = 0, n_chunks = 0, n_vertices = 0;
+    size_t rows, ptab, total;
+    long long n_rows = 0, n_vs = 0, n_vertices = 0, n_out = 0;
     long long n_rowpart = 0, n_colpart = 0, n_units = 0;
 };
 
 // Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
 struct BackwardLayout {
-    size_t rows, ptab, agg, r_in, chunk_lv, chunk_fix, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
+    size_t rows, ptab, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
 };
 
 static BackwardLayout backward_layout(const BatchLayout& L)
@@ -43,10 +46,6 @@ static BackwardLayout backward_layout(const BatchLayout& L)
     auto seg = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
     B.rows = seg(8 * 16 * (size_t)L.n_rows);
     B.ptab = seg(8 * 8 * (size_t)L.n_vs);
-    B.agg = seg(8 * 9 * (size_t)L.n_chunks);
-    B.r_in = seg(8 * 3 * (size_t)L.n_chunks);
-    B.chunk_lv = seg(4 * (size_t)L.n_chunks);
-    B.chunk_fix = seg(4 * (size_t)L.n_chunks);
     B.rowpart = seg(8 * 12 * (size_t)L.n_rowpart);
     B.colpart = seg(8 * 3 * (size_t)L.n_colpart);
     B.rowacc = seg(8 * 12 * (size_t)L.n_rows);
@@ -71,8 +70,6 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     if (!b->path_n || !b->path_degree || !b->prof_n || !b->prof_degree || !b->n_u || !b->n_v)
         return fail(SWEEP_ERR_NULL_ARG, "a per-sweep array is NULL");
     const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
-    const size_t fsz = o->frame_precision == SWEEP_F64 ? 8 : 4;
-    const int chunk = frame_chunk_size();
     long long path_off = 0, prof_off = 0, pk_off = 0, qk_off = 0;
     BatchLayout L{};
     if (key) key->ints.reserve(7 * (size_t)b->n_sweeps + 8);
@@ -90,7 +87,6 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         if ((st = check_grid(nu, nv)) != SWEEP_OK) {
             return fail(st, "sweep %d: %s", k, sweep_last_error());
         }
-        const long long nc = (nu + chunk - 1) / chunk;
         const int nseg = (nv + 63) / 64;
         const int ngroup = (nu + kBwRowGroup - 1) / kBwRowGroup;
         if (descs) {
@@ -103,7 +99,9 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             if (pk) knots->insert(knots->end(), pk, pk + np + pp + 1);
             d.prof_knot_off = qk ? (long long)knots->size() : -1;
             if (qk) knots->insert(knots->end(), qk, qk + nq + pq + 1);
-            d.out_off = L.n_vertices; d.row_off = L.n_rows; d.ptab_off = L.n_vs; d.chunk_off = L.n_chunks;
+            d.out_off = L.n_out;
+            d.plane = plane_stride((long long)nu * nv);
+            d.row_off = L.n_rows; d.ptab_off = L.n_vs;
             d.rowpart_off = L.n_rowpart; d.colpart_off = L.n_colpart; d.nseg = nseg; d.ngroup = ngroup;
             descs->push_back(d);
         }
@@ -117,7 +115,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         if (b->prof_knots && !qc) qk_off += nq + pq + 1;
         path_off += np; prof_off += nq;
         L.n_vertices += (long long)nu * nv;
-        L.n_rows += nu; L.n_vs += nv; L.n_chunks += nc;
+        L.n_out += 3 * plane_stride((long long)nu * nv);
+        L.n_rows += nu; L.n_vs += nv;
         L.n_rowpart += (long long)nseg * nu; L.n_colpart += (long long)ngroup * nv;
         L.n_units += (long long)nseg * ngroup;
     }
@@ -125,10 +124,6 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     size_t off = 0;
     L.rows = off; off = align_up(off + tsz * 16 * (size_t)L.n_rows);
     L.ptab = off; off = align_up(off + tsz * 8 * (size_t)L.n_vs);
-    L.agg = off;  off = align_up(off + fsz * 9 * (size_t)L.n_chunks);
-    L.r_in = off; off = align_up(off + fsz * 3 * (size_t)L.n_chunks);
-    L.chunk_lv = off; off = align_up(off + 4 * (size_t)L.n_chunks);
-    L.chunk_fix = off; off = align_up(off + 4 * (size_t)L.n_chunks);
     L.total = off;
     if (lay) *lay = L;
     if (key) {
@@ -141,10 +136,10 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
 }
 
 // Argument values of one graph node; its parameter array points into this
-// block.  `chunks` is the node's own (sweep, chunk) list.
+// block.  `sweeps` is a frame node's own sweep list.
 struct NodeArgs {
     const BatchDesc* descs;
-    const int2* chunks;
+    const int* sweeps;
     const int2* vchunks;
     const int2* tiles;
     const double* path_ctrl;
@@ -152,17 +147,13 @@ struct NodeArgs {
     const double* knots;
     InitialNormal n0;
     int reorth;
-    void* agg;
-    void* r_in;
-    void* chunk_lv;
-    void* chunk_fix;
     void* rows;
     void* ptab;
     void* pos;
     void* nrm;
 };
 
-enum NodeKind { kProfile, kPrep, kCarry, kApply, kSurface };
+enum NodeKind { kProfile, kFrame, kSurface };
 
 struct GNode {
     NodeKind kind;
@@ -180,9 +171,7 @@ static int node_args(GNode& n)
     void** q = n.ptrs;
     switch (n.kind) {
     case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 5; }
-    case kPrep: { void* v[] = {&A.descs, &A.chunks, &A.path_ctrl, &A.knots, &A.agg, &A.chunk_lv, &A.chunk_fix}; std::memcpy(q, v, sizeof v); return 7; }
-    case kCarry: { void* v[] = {&A.descs, &A.path_ctrl, &A.knots, &A.n0, &A.agg, &A.chunk_lv, &A.chunk_fix, &A.r_in}; std::memcpy(q, v, sizeof v); return 8; }
-    case kApply: { void* v[] = {&A.descs, &A.chunks, &A.path_ctrl, &A.knots, &A.reorth, &A.chunk_lv, &A.r_in, &A.rows}; std::memcpy(q, v, sizeof v); return 8; }
+    case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.knots, &A.n0, &A.reorth, &A.rows}; std::memcpy(q, v, sizeof v); return 7; }
     default: { void* v[] = {&A.descs, &A.tiles, &A.rows, &A.ptab, &A.pos, &A.nrm}; std::memcpy(q, v, sizeof v); return 6; }
     }
 }
@@ -200,8 +189,8 @@ struct Plan {
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int2* d_chunks[8] = {};        // (sweep, chunk) of every path chunk, by path degree
-    int n_chunks[8] = {};
+    int* d_sweeps[8] = {};         // sweeps by path degree, longest n_u first
+    int n_deg[8] = {};
     int2* d_vchunks = nullptr;     // (sweep, chunk) of every profile chunk
     int n_vchunks = 0;
     NodeArgs a{};                  // values shared by all nodes
@@ -214,11 +203,15 @@ struct Plan {
         if (d_tiles) hipFree(d_tiles);
         if (d_units) hipFree(d_units);
         for (int p = 0; p < 8; ++p)
-            if (d_chunks[p]) hipFree(d_chunks[p]);
+            if (d_sweeps[p]) hipFree(d_sweeps[p]);
         if (d_vchunks) hipFree(d_vchunks);
         if (d_knots) hipFree(d_knots);
     }
 };
+
+// Batched surface configuration for tile_config = -1: linear tiles of 1024
+// vertices with nontemporal stores.
+static SurfaceConfig batched_surface_config() { return SurfaceConfig{1, 0, 1024, 1}; }
 
 static std::mutex g_mu;
 static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
@@ -235,17 +228,22 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     P->key = std::move(key);
     P->n_sweeps = b->n_sweeps;
     P->with_nrm = with_nrm;
-    // surface tiles: (sweep, first local vertex) in sweep order; frame
-    // chunks: (sweep, chunk) of every 256 u-samples (grouped by path degree)
-    // and of every 256 v-samples
-    const int tv = batched_tile_vertices();
-    std::vector<int2> tiles, vchunks, chunks[8];
+    // surface tiles: (sweep, first local vertex) in sweep order; sweeps by
+    // path degree, longest first (the frame blocks' work is proportional to
+    // n_u); profile chunks: (sweep, chunk) of every 256 v-samples
+    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : batched_surface_config();
+    // column-tile configurations map to one-row-sized linear tiles
+    const int tv = cfg.kind == 1 ? cfg.tile_vertices : kBlock;
+    std::vector<int2> tiles, vchunks;
+    std::vector<int> sweeps[8];
     for (int k = 0; k < b->n_sweeps; ++k) {
         const long long N = (long long)b->n_u[k] * b->n_v[k];
         for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
-        for (int c = 0; c * kBlock < b->n_u[k]; ++c) chunks[b->path_degree[k]].push_back(make_int2(k, c));
+        sweeps[b->path_degree[k]].push_back(k);
         for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
+    for (auto& l : sweeps)
+        std::stable_sort(l.begin(), l.end(), [&](int x, int y) { return b->n_u[x] > b->n_u[y]; });
     if (tiles.size() > 0x7fffffffull || vchunks.size() > 0x7fffffffull)
         return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
     P->n_tiles = (int)tiles.size();
@@ -261,18 +259,16 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         (e = upload((void**)&P->d_vchunks, vchunks.data(), sizeof(int2) * vchunks.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-        if (chunks[p].size() > 0x7fffffffull) return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
-        P->n_chunks[p] = (int)chunks[p].size();
-        if (!chunks[p].empty() &&
-            (e = upload((void**)&P->d_chunks[p], chunks[p].data(), sizeof(int2) * chunks[p].size())) != hipSuccess)
+        P->n_deg[p] = (int)sweeps[p].size();
+        if (!sweeps[p].empty() &&
+            (e = upload((void**)&P->d_sweeps[p], sweeps[p].data(), sizeof(int) * sweeps[p].size())) != hipSuccess)
             return hip_fail(e, "plan upload");
     }
     if (!knots.empty() && (e = upload((void**)&P->d_knots, knots.data(), sizeof(double) * knots.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
 
-    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : SurfaceConfig{1, 0, 1024, 1};
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
-                                             with_nrm, cfg.nontemporal != 0);
+                                             with_nrm, cfg.nontemporal != 0, tv);
     // argument blocks are compared bytewise on every call: clear the padding
     std::memset(&P->a, 0, sizeof P->a);
     NodeArgs& A = P->a;
@@ -290,7 +286,7 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         n->kind = kind;
         n->deg = deg;
         std::memcpy(&n->a, &P->a, sizeof n->a);
-        if (kind == kPrep || kind == kApply) n->a.chunks = P->d_chunks[deg];
+        if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg];
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
@@ -303,24 +299,16 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         P->nodes.push_back(std::move(n));
         return r;
     };
-    std::vector<hipGraphNode_t> preps, applies;
+    std::vector<hipGraphNode_t> before_surface;
     if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
-    const hipGraphNode_t profile_node = P->nodes.back()->node;
+    before_surface.push_back(P->nodes.back()->node);
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-        if (!P->n_chunks[p]) continue;
-        if ((e = add(kPrep, p, K.prep[p], (unsigned)P->n_chunks[p], {})) != hipSuccess) return hip_fail(e, "graph node");
-        preps.push_back(P->nodes.back()->node);
+        if (!P->n_deg[p]) continue;
+        if ((e = add(kFrame, p, K.frame[p], (unsigned)P->n_deg[p], {})) != hipSuccess) return hip_fail(e, "graph node");
+        before_surface.push_back(P->nodes.back()->node);
     }
-    if ((e = add(kCarry, 0, K.carry, (unsigned)b->n_sweeps, preps)) != hipSuccess) return hip_fail(e, "graph node");
-    const hipGraphNode_t carry_node = P->nodes.back()->node;
-    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-        if (!P->n_chunks[p]) continue;
-        if ((e = add(kApply, p, K.apply[p], (unsigned)P->n_chunks[p], {carry_node})) != hipSuccess)
-            return hip_fail(e, "graph node");
-        applies.push_back(P->nodes.back()->node);
-    }
-    applies.push_back(profile_node);
-    if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, applies)) != hipSuccess) return hip_fail(e, "graph node");
+    if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, before_surface)) != hipSuccess)
+        return hip_fail(e, "graph node");
     if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
         return hip_fail(e, "graph instantiate");
     out = std::move(P);
@@ -359,6 +347,17 @@ using namespace sweep;
 
 extern "C" {
 
+int64_t sweep_batched_output_elems(const sweep_batch* batch)
+{
+    if (!batch || batch->n_sweeps < 1 || !batch->n_u || !batch->n_v) return 0;
+    long long n = 0;
+    for (int k = 0; k < batch->n_sweeps; ++k) {
+        if (batch->n_u[k] < 0 || batch->n_v[k] < 0) return 0;
+        n += 3 * plane_stride((long long)batch->n_u[k] * batch->n_v[k]);
+    }
+    return n;
+}
+
 size_t sweep_batched_workspace_size(const sweep_batch* batch, const sweep_options* opt)
 {
     sweep_options def;
@@ -391,10 +390,6 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     std::memcpy(&A, &P->a, sizeof A);
     A.path_ctrl = batch->path_ctrl;
     A.prof_ctrl = batch->prof_ctrl;
-    A.agg = ws + L.agg;
-    A.r_in = ws + L.r_in;
-    A.chunk_lv = ws + L.chunk_lv;
-    A.chunk_fix = ws + L.chunk_fix;
     A.rows = ws + L.rows;
     A.ptab = ws + L.ptab;
     A.pos = pos;
@@ -402,9 +397,9 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     if (std::memcmp(&A, &P->a, sizeof A) != 0) {
         P->a = A;
         for (auto& n : P->nodes) {
-            const int2* own = n->a.chunks;
+            const int* own = n->a.sweeps;
             std::memcpy(&n->a, &A, sizeof A);
-            n->a.chunks = own;
+            n->a.sweeps = own;
             if ((e = hipGraphExecKernelNodeSetParams(P->exec, n->node, &n->prm)) != hipSuccess)
                 return hip_fail(e, "graph update");
         }
@@ -459,36 +454,27 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
     }
     hipStream_t sm = (hipStream_t)stream;
     char* ws = (char*)workspace;
-    const BatchedKernels FK = batched_kernels(true, true, false, false);
+    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64);
     {
-        // FP64 frame recomputation with re-orthonormalisation: profile, prep, carry, apply
+        // FP64 frame recomputation with re-orthonormalisation: profile tables, frames
         GNode n;
         std::memcpy(&n.a, &P->a, sizeof n.a);
         n.a.path_ctrl = batch->path_ctrl;
         n.a.prof_ctrl = batch->prof_ctrl;
         n.a.reorth = 1;
-        n.a.agg = ws + B.agg;
-        n.a.r_in = ws + B.r_in;
-        n.a.chunk_lv = ws + B.chunk_lv;
-        n.a.chunk_fix = ws + B.chunk_fix;
         n.a.rows = ws + B.rows;
         n.a.ptab = ws + B.ptab;
         auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid) -> hipError_t {
             n.kind = kind;
-            n.a.chunks = (kind == kPrep || kind == kApply) ? P->d_chunks[deg] : nullptr;
+            n.a.sweeps = kind == kFrame ? P->d_sweeps[deg] : nullptr;
             node_args(n);
             return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, 0, sm);
         };
         if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
         for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
-            if (P->n_chunks[p] && (e = launch(kPrep, p, FK.prep[p], (unsigned)P->n_chunks[p])) != hipSuccess)
-                return hip_fail(e, "backward frames");
-        if ((e = launch(kCarry, 0, FK.carry, (unsigned)batch->n_sweeps)) != hipSuccess)
-            return hip_fail(e, "backward frames");
-        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
-            if (P->n_chunks[p] && (e = launch(kApply, p, FK.apply[p], (unsigned)P->n_chunks[p])) != hipSuccess)
+            if (P->n_deg[p] && (e = launch(kFrame, p, FK.frame[p], (unsigned)P->n_deg[p])) != hipSuccess)
                 return hip_fail(e, "backward frames");
     }
     {

@@ -53,14 +53,19 @@ struct BatchDesc {
     long long prof_ctrl_off;
     long long path_knot_off;       // into the batch knot array, -1 = default knots
     long long prof_knot_off;
-    long long out_off;             // vertex offset: positions start at element 3 * out_off
+    long long out_off;             // element offset of the sweep's output block (3 planes)
+    long long plane;               // plane stride: n_u*n_v rounded up to kPlaneAlign
     long long row_off;             // first row record
     long long ptab_off;            // first profile record
-    long long chunk_off;           // first chunk product / entry normal
     long long rowpart_off;         // adjoint: first per-segment row partial (12 doubles each)
     long long colpart_off;         // adjoint: first per-group column partial (3 doubles each)
     int nseg, ngroup;              // adjoint: 64-column segments, row groups
 };
+
+// Batched output planes start on multiples of this many elements (256 B in
+// FP32): nontemporal stores into planes that start mid-cache-line write
+// partial lines and ran at half the bandwidth on MI355X.
+constexpr int kPlaneAlign = 64;
 
 // Rows per reduction group in the adjoint's streaming read of dL/dX.
 constexpr int kBwRowGroup = 16;
@@ -76,15 +81,12 @@ void fastdiv_constants(int d, unsigned long long* m, int* shift);
 
 struct BatchedKernels {
     const void* profile;
-    const void* prep[8];    // by path degree (index 0 unused)
-    const void* carry;
-    const void* apply[8];   // by path degree
+    const void* frame[8];   // by path degree (index 0 unused)
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as
 // graph kernel-node functions).
-BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal);
-// Vertices per surface block in the batched surface kernel.
-int batched_tile_vertices();
+// tile_vertices = vertices per surface block: 256, 512, 1024 or 2048.
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices);
 
 }  // namespace sweep

@@ -22,8 +22,7 @@ def _rel(a, b):
 def _check(specs, out_dtype, tol, seed=55):
     b = api.Batch.from_specs(specs)
     ws = synth.loss_weights(specs, seed)
-    flat = np.concatenate([w.reshape(-1) for w in ws])
-    g = torch.as_tensor(flat, dtype=out_dtype).cuda()
+    g = b.pack(ws, out_dtype)
     gP, gQ = api.sweep_backward(b, g)
     torch.cuda.synchronize()
     gP, gQ = gP.cpu().numpy(), gQ.cpu().numpy()
@@ -56,7 +55,7 @@ def test_adjoint_fp32_differentiation_workload_sampled():
     say(f"[case] adjoint FP32, {len(specs)} sweeps 1024x64 (FD on 3 sweeps)")
     b = api.Batch.from_specs(specs)
     ws = synth.loss_weights(specs, 55)
-    g = torch.as_tensor(np.concatenate([w.reshape(-1) for w in ws]), dtype=torch.float32).cuda()
+    g = b.pack(ws, torch.float32)
     gP, gQ = api.sweep_backward(b, g)
     torch.cuda.synchronize()
     gP, gQ = gP.cpu().numpy(), gQ.cpu().numpy()
@@ -78,7 +77,7 @@ def test_autograd_function_and_gradcheck():
     b = api.Batch.from_specs([spec])
     Pt = torch.as_tensor(P).cuda().requires_grad_(True)
     Qt = torch.as_tensor(Q).cuda().requires_grad_(True)
-    w = torch.randn(3 * spec.n_u * spec.n_v, dtype=torch.float64, device="cuda")
+    w = torch.randn(b.out_elems, dtype=torch.float64, device="cuda")
     pos, nrm = dsweep(Pt, Qt, b, out_dtype=torch.float64)
     (pos * w).sum().backward()
     assert Pt.grad is not None and Qt.grad is not None

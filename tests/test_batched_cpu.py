@@ -38,3 +38,33 @@ def test_batched_validation():
     b.n_sweeps = 0
     st = L.sweep_eval_batched(b, L.default_options(), 0x100000, 0, 0x100000, 1 << 40, 0)
     assert L.STATUS[st] == "SWEEP_ERR_BAD_COUNT"
+
+
+def test_batched_output_elems_padded_layout():
+    # plane stride = n_u*n_v rounded up to 64 elements
+    b, keep = _batch([100, 7, 64], [10, 9, 3])
+    assert L.sweep_batched_output_elems(b) == 3 * (1024 + 64 + 192)
+    b, keep = _batch([64, 64], [64, 1], n=2)
+    assert L.sweep_batched_output_elems(b) == 3 * (4096 + 64)
+    b.n_sweeps = 0
+    assert L.sweep_batched_output_elems(b) == 0
+
+
+def test_python_batch_layout_matches_abi():
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+    specs = synth.c4(n_sweeps=40, seed=3)
+    b = api.Batch.from_specs(specs, device="cpu")
+    assert b.out_elems == L.sweep_batched_output_elems(b.c_struct())
+    assert np.all(b.plane % 64 == 0) and np.all(b.plane - b.n_u * b.n_v < 64)
+    assert np.all(np.diff(b.offsets) == 3 * b.plane[:-1])
+    flat = torch.arange(b.out_elems, dtype=torch.float64)
+    for k in (0, 17, 39):
+        v = b.view(flat, k)
+        assert v.shape == (3, specs[k].n_u, specs[k].n_v)
+        assert float(v[1, 0, 0]) == b.offsets[k] + b.plane[k]
+        assert float(v[2, -1, -1]) == b.offsets[k] + 2 * b.plane[k] + specs[k].n_u * specs[k].n_v - 1
+    blocks = [np.full((3, s.n_u, s.n_v), k + 1.0) for k, s in enumerate(specs)]
+    packed = b.pack(blocks, torch.float64)
+    assert float(packed.sum()) == sum((k + 1.0) * 3 * s.n_u * s.n_v for k, s in enumerate(specs))
