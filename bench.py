@@ -123,7 +123,7 @@ def sampled_error(spec, pos, nrm, rows, tol):
     return r
 
 
-def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 20):
+def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 1000):
     """The oracle as it stands on the same workload: the whole grid (frame
     scan, positions and normals in FP64), repeated until about target_s of
     work has run."""

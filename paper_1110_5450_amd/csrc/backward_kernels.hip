@@ -13,9 +13,9 @@
 // control points through the basis functions.  Every sum runs in FP64 in a
 // fixed order: the result does not depend on scheduling.
 //
-// kbw_reduce   one wave per (sweep, group of kBwRowGroup rows, 64 columns):
-//              streaming read of w, per-row partials (wave butterfly sums),
-//              per-column partials over the group.
+// kbw_reduce   one wave per (sweep, group of G rows, 64 columns): streaming
+//              read of w through an LDS tile, per-row partials over the 64
+//              columns and per-column partials over the G rows.
 // kbw_adjoint  one block per sweep: finishes the partial sums, runs the
 //              suffix sum, the per-sample adjoint and the per-control-point
 //              gathers.
@@ -23,13 +23,13 @@
 
 namespace sweep {
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = v + __shfl_xor(v, d, 64);
-    return v;
-}
-
+// One wave per unit (sweep, group of G rows, segment of 64 columns); every
+// wave of the block reaches the barriers.  The wave stages its G x 64 tile
+// of w (three planes) in LDS with coalesced loads, then
+//   lane = column j:            h_j += R_i^T w_ij over the G rows,
+//   lane = (component c, row r): the 12 row sums over the 64 columns,
+// each a sequential sum in a fixed order.  Rows are padded to 65 elements so
+// that both passes read LDS without bank conflicts.
 template <class T>
 __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
                                                      const int4* __restrict__ units, int n_units,
@@ -37,54 +37,74 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
                                                      const double* __restrict__ ptab, double* __restrict__ rowpart,
                                                      double* __restrict__ colpart)
 {
+    constexpr int G = bw_row_group<T>();
+    __shared__ T lw[kWaves][3][G][65];
+    __shared__ double ls[kWaves][3][64];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int unit = blockIdx.x * kWaves + wave;
-    if (unit >= n_units) return;
-    const int4 un = units[unit];
-    const BatchDesc d = descs[un.x];
+    const bool live = unit < n_units;   // wave-uniform
+    int4 un = make_int4(0, 0, 0, 0);
+    if (live) un = units[unit];
+    const BatchDesc& d = descs[un.x];
+    const int n_u = d.n_u, n_v = d.n_v;
     const int g = un.y, seg = un.z;
+    const int i0 = g * G;
+    const int nr = live ? min(G, n_u - i0) : 0;
     const int j = seg * 64 + lane;
-    const bool vj = j < d.n_v;
-    double Sx = 0.0, Sy = 0.0, Sz = 0.0;
-    if (vj) {
-        const double* q = ptab + 8 * (d.ptab_off + j);
-        Sx = q[0]; Sy = q[1]; Sz = q[2];
-    }
-    const size_t N = (size_t)d.plane;   // plane stride of the batched layout
-    const T* w0 = grad + d.out_off;
-    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-    const int i0 = g * kBwRowGroup, i1 = min(d.n_u, i0 + kBwRowGroup);
-    for (int i = i0; i < i1; ++i) {
-        const double* R = rows + 16 * (d.row_off + i);
-        double w[3] = {0.0, 0.0, 0.0};
+    const bool vj = live && j < n_v;
+    {
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0;
         if (vj) {
-            const size_t v = (size_t)i * (size_t)d.n_v + (size_t)j;
-            w[0] = (double)w0[v]; w[1] = (double)w0[N + v]; w[2] = (double)w0[2 * N + v];
+            const double* q = ptab + 8 * (d.ptab_off + j);
+            S0 = q[0]; S1 = q[1]; S2 = q[2];
         }
-        double part[12];
+        ls[wave][0][lane] = S0; ls[wave][1][lane] = S1; ls[wave][2][lane] = S2;
+        const size_t P = (size_t)d.plane;   // plane stride of the batched layout
+        const T* w0 = grad + d.out_off;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            part[c] = w[c];
-            part[3 + c] = Sx * w[c];
-            part[6 + c] = Sy * w[c];
-            part[9 + c] = Sz * w[c];
+        for (int r = 0; r < G; ++r) {
+            T a = T(0), b = T(0), c = T(0);
+            if (vj && r < nr) {
+                const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
+                a = __builtin_nontemporal_load(w0 + v);
+                b = __builtin_nontemporal_load(w0 + P + v);
+                c = __builtin_nontemporal_load(w0 + 2 * P + v);
+            }
+            lw[wave][0][r][lane] = a; lw[wave][1][r][lane] = b; lw[wave][2][r][lane] = c;
         }
-#pragma unroll
-        for (int e = 0; e < 12; ++e) part[e] = wave_sum(part[e]);
-        if (lane < 12) {
-            double v = part[0];
-#pragma unroll
-            for (int e = 1; e < 12; ++e) v = lane == e ? part[e] : v;
-            rowpart[12 * (d.rowpart_off + (size_t)seg * d.n_u + i) + lane] = v;
-        }
-        h0 += R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
-        h1 += R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
-        h2 += R[9] * w[0] + R[10] * w[1] + R[11] * w[2];
     }
+    __syncthreads();
     if (vj) {
-        double* q = colpart + 3 * (d.colpart_off + (size_t)g * d.n_v + j);
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+        const double* R0 = rows + 16 * (d.row_off + i0);
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            if (r < nr) {
+                const double* R = R0 + 16 * r;
+                const double w[3] = {(double)lw[wave][0][r][lane], (double)lw[wave][1][r][lane],
+                                     (double)lw[wave][2][r][lane]};
+                h0 += R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
+                h1 += R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
+                h2 += R[9] * w[0] + R[10] * w[1] + R[11] * w[2];
+            }
+        }
+        double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
         q[0] = h0; q[1] = h1; q[2] = h2;
+    }
+    const int r = lane % G, c = lane / G;
+    if (live && c < 3 && r < nr) {
+        const int ncol = min(64, n_v - seg * 64);
+        double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+        for (int jj = 0; jj < ncol; ++jj) {
+            const double w = (double)lw[wave][c][r][jj];
+            a0 += w;
+            ax += ls[wave][0][jj] * w;
+            ay += ls[wave][1][jj] * w;
+            az += ls[wave][2][jj] * w;
+        }
+        double* q = rowpart + 12 * (d.rowpart_off + (size_t)seg * n_u + i0 + r);
+        q[c] = a0; q[3 + c] = ax; q[6 + c] = ay; q[9 + c] = az;
     }
 }
 
@@ -190,6 +210,20 @@ __device__ __forceinline__ StepAdj step_adjoint(V3<double> xa, V3<double> xb, V3
     return o;
 }
 
+// Threads per output in the adjoint's gathers.
+constexpr int kMaxParts = 8;
+
+// First index in the non-decreasing v[0..n) with v[index] >= key (n if none).
+__device__ __forceinline__ int lower_bound_int(const int* v, int n, int key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (v[m] >= key) hi = m; else lo = m + 1;
+    }
+    return lo;
+}
+
 struct RowRec {
     V3<double> x, r, s, t;
     double L;
@@ -232,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
                                                       int* spans_v, double* __restrict__ gP, double* __restrict__ gQ)
 {
     __shared__ double lds3[kWaves][3];
+    __shared__ double lpart[kBlock][3];
     const BatchDesc d = descs[blockIdx.x];
     const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
                       d.n_path, d.p_path, 0, d.n_path};
@@ -260,13 +295,33 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
 #pragma unroll
         for (int e = 0; e < 12; ++e) racc[12 * (size_t)i + e] = a[e];
     }
-    for (int j = threadIdx.x; j < n_v; j += kBlock) {
-        double h[3] = {0.0, 0.0, 0.0};
-        for (int g = 0; g < d.ngroup; ++g) {
-            const double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
-            h[0] += q[0]; h[1] += q[1]; h[2] += q[2];
+    {
+        // column sums over the row groups: `parts` threads per column, each
+        // over a contiguous range of groups, combined in part order
+        const int parts = n_v <= kBlock ? min(kMaxParts, kBlock / n_v) : 1;
+        for (int t = threadIdx.x; t < n_v * parts; t += kBlock) {
+            const int j = t / parts, part = t % parts;
+            const int g0 = (int)((long long)d.ngroup * part / parts);
+            const int g1 = (int)((long long)d.ngroup * (part + 1) / parts);
+            double h[3] = {0.0, 0.0, 0.0};
+            for (int g = g0; g < g1; ++g) {
+                const double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
+                h[0] += q[0]; h[1] += q[1]; h[2] += q[2];
+            }
+            if (parts == 1) {
+                cacc[3 * (size_t)j] = h[0]; cacc[3 * (size_t)j + 1] = h[1]; cacc[3 * (size_t)j + 2] = h[2];
+            } else {
+                lpart[t][0] = h[0]; lpart[t][1] = h[1]; lpart[t][2] = h[2];
+            }
         }
-        cacc[3 * (size_t)j] = h[0]; cacc[3 * (size_t)j + 1] = h[1]; cacc[3 * (size_t)j + 2] = h[2];
+        __syncthreads();
+        if (parts > 1)
+            for (int j = threadIdx.x; j < n_v; j += kBlock) {
+                V3<double> h = mk(0.0, 0.0, 0.0);
+                for (int part = 0; part < parts; ++part)
+                    h = h + mk(lpart[j * parts + part][0], lpart[j * parts + part][1], lpart[j * parts + part][2]);
+                cacc[3 * (size_t)j] = h.x; cacc[3 * (size_t)j + 1] = h.y; cacc[3 * (size_t)j + 2] = h.z;
+            }
     }
     __threadfence_block();
     __syncthreads();
@@ -365,32 +420,74 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
     __syncthreads();
 
     // 4. gathers per control point over the samples whose span covers it
-    //    (spans are non-decreasing in the sample index)
-    for (int k = threadIdx.x; k < d.n_path; k += kBlock) {
-        int lo = 0, hi = n_u;   // first sample with span >= k
-        while (lo < hi) { const int m = (lo + hi) >> 1; if (su[m] >= k) hi = m; else lo = m + 1; }
-        V3<double> acc = mk(0.0, 0.0, 0.0);
-        for (int i = lo; i < n_u && su[i] - path.p <= k; ++i) {
-            const double* q = sg + 24 * (size_t)i + 3 * (k - (su[i] - path.p));
-            acc = acc + mk(q[0], q[1], q[2]);
-        }
-        double* o = gP + 3 * (d.path_ctrl_off + k);
-        o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
-    }
-    for (int l = threadIdx.x; l < d.n_prof; l += kBlock) {
-        V3<double> acc = mk(0.0, 0.0, 0.0);
-        // basis indices wrapping onto control point l: l, and l + m on a closed curve
-        for (int kk = l; kk < prof.nb; kk += d.n_prof) {
-            int lo = 0, hi = n_v;
-            while (lo < hi) { const int m = (lo + hi) >> 1; if (sv[m] >= kk) hi = m; else lo = m + 1; }
-            for (int j = lo; j < n_v && sv[j] - prof.p <= kk; ++j) {
-                const double* q = qg + 24 * (size_t)j + 3 * (kk - (sv[j] - prof.p));
+    //    (spans are non-decreasing in the sample index, so these samples are
+    //    a contiguous range); `parts` threads per control point each sum a
+    //    contiguous piece, combined in part order
+    {
+        const int parts = d.n_path <= kBlock ? min(kMaxParts, kBlock / d.n_path) : 1;
+        for (int t = threadIdx.x; t < d.n_path * parts; t += kBlock) {
+            const int k = t / parts, part = t % parts;
+            const int lo = lower_bound_int(su, n_u, k);              // first span >= k
+            const int hi = lower_bound_int(su, n_u, k + path.p + 1);  // first span - p > k
+            const int a = lo + (int)((long long)(hi - lo) * part / parts);
+            const int b = lo + (int)((long long)(hi - lo) * (part + 1) / parts);
+            V3<double> acc = mk(0.0, 0.0, 0.0);
+            for (int i = a; i < b; ++i) {
+                const double* q = sg + 24 * (size_t)i + 3 * (k - (su[i] - path.p));
                 acc = acc + mk(q[0], q[1], q[2]);
             }
-            if (!prof.closed) break;
+            if (parts == 1) {
+                double* o = gP + 3 * (d.path_ctrl_off + k);
+                o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+            } else {
+                lpart[t][0] = acc.x; lpart[t][1] = acc.y; lpart[t][2] = acc.z;
+            }
         }
-        double* o = gQ + 3 * (d.prof_ctrl_off + l);
-        o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+        __syncthreads();
+        if (parts > 1)
+            for (int k = threadIdx.x; k < d.n_path; k += kBlock) {
+                V3<double> acc = mk(0.0, 0.0, 0.0);
+                for (int part = 0; part < parts; ++part)
+                    acc = acc + mk(lpart[k * parts + part][0], lpart[k * parts + part][1], lpart[k * parts + part][2]);
+                double* o = gP + 3 * (d.path_ctrl_off + k);
+                o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+            }
+        __syncthreads();
+    }
+    {
+        // basis indices wrapping onto control point l: l, and l + m, ... on
+        // a closed curve
+        const int parts = d.n_prof <= kBlock ? min(kMaxParts, kBlock / d.n_prof) : 1;
+        for (int t = threadIdx.x; t < d.n_prof * parts; t += kBlock) {
+            const int l = t / parts, part = t % parts;
+            V3<double> acc = mk(0.0, 0.0, 0.0);
+            for (int kk = l; kk < prof.nb; kk += d.n_prof) {
+                const int lo = lower_bound_int(sv, n_v, kk);
+                const int hi = lower_bound_int(sv, n_v, kk + prof.p + 1);
+                const int a = lo + (int)((long long)(hi - lo) * part / parts);
+                const int b = lo + (int)((long long)(hi - lo) * (part + 1) / parts);
+                for (int j = a; j < b; ++j) {
+                    const double* q = qg + 24 * (size_t)j + 3 * (kk - (sv[j] - prof.p));
+                    acc = acc + mk(q[0], q[1], q[2]);
+                }
+                if (!prof.closed) break;
+            }
+            if (parts == 1) {
+                double* o = gQ + 3 * (d.prof_ctrl_off + l);
+                o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+            } else {
+                lpart[t][0] = acc.x; lpart[t][1] = acc.y; lpart[t][2] = acc.z;
+            }
+        }
+        __syncthreads();
+        if (parts > 1)
+            for (int l = threadIdx.x; l < d.n_prof; l += kBlock) {
+                V3<double> acc = mk(0.0, 0.0, 0.0);
+                for (int part = 0; part < parts; ++part)
+                    acc = acc + mk(lpart[l * parts + part][0], lpart[l * parts + part][1], lpart[l * parts + part][2]);
+                double* o = gQ + 3 * (d.prof_ctrl_off + l);
+                o[0] = acc.x; o[1] = acc.y; o[2] = acc.z;
+            }
     }
 }
 

@@ -88,7 +88,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             return fail(st, "sweep %d: %s", k, sweep_last_error());
         }
         const int nseg = (nv + 63) / 64;
-        const int ngroup = (nu + kBwRowGroup - 1) / kBwRowGroup;
+        const int G = bw_row_group_for(o->out_precision == SWEEP_F64);
+        const int ngroup = (nu + G - 1) / G;
         if (descs) {
             BatchDesc d{};
             d.n_path = np; d.p_path = pp; d.n_prof = nq; d.p_prof = pq;
@@ -443,7 +444,8 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         std::vector<int4> units;
         units.reserve((size_t)L.n_units);
         for (int k = 0; k < batch->n_sweeps; ++k) {
-            const int ng = (batch->n_u[k] + kBwRowGroup - 1) / kBwRowGroup, ns = (batch->n_v[k] + 63) / 64;
+            const int G = bw_row_group_for(opt->out_precision == SWEEP_F64);
+            const int ng = (batch->n_u[k] + G - 1) / G, ns = (batch->n_v[k] + 63) / 64;
             for (int g = 0; g < ng; ++g)
                 for (int sg = 0; sg < ns; ++sg) units.push_back(make_int4(k, g, sg, 0));
         }

@@ -67,8 +67,11 @@ struct BatchDesc {
 // partial lines and ran at half the bandwidth on MI355X.
 constexpr int kPlaneAlign = 64;
 
-// Rows per reduction group in the adjoint's streaming read of dL/dX.
-constexpr int kBwRowGroup = 16;
+// Rows per reduction group in the adjoint's streaming read of dL/dX (the
+// LDS tile of a wave holds G x 65 values per plane).
+template <class T>
+constexpr int bw_row_group() { return sizeof(T) == 8 ? 8 : 16; }
+inline int bw_row_group_for(bool t64) { return t64 ? 8 : 16; }
 
 struct BackwardKernels {
     const void* reduce;
