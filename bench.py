@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "swept-surface vertices/s (pos+normal) and % HBM peak; batched/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+COPY_CAL_BYTES = 512 << 20
 COUNTERS = os.path.join(ROOT, "profiles", "surface_c2_counters.json")
 SURFACE_SRC = os.path.join(ROOT, "paper_1110_5450_amd", "csrc", "surface_kernels.hip")
 
@@ -298,6 +299,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--precision-study", action="store_true")
+    ap.add_argument("--variants-only", action="store_true",
+                    help="run only the batched (4096 sweeps) and adjoint (256 sweeps) variants and print them")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 512 MiB device copy (3 launches) whose counter readings scale "
+                         "the surface kernel's HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep shards "
@@ -311,6 +317,23 @@ def main():
     if args.precision_study:
         print(json.dumps(precision_study()), flush=True)
         return
+    if args.variants_only:
+        log("[bench] batched ...")
+        v = {"batched": batched_variants(args.steps)}
+        log("[bench] adjoint ...")
+        v["adjoint"] = adjoint_variant(args.steps)
+        print(json.dumps(v), flush=True)
+        return
+
+    if args.copy_calibration:
+        src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {COPY_CAL_BYTES} bytes read and written")
+        del src, dst
+        torch.cuda.empty_cache()
 
     spec = synth.c2()
     N = spec.n_u * spec.n_v

@@ -421,7 +421,9 @@ sweep_status sweep_trace_enable(int32_t max_calls)
     if (max_calls == 0) { g_trace.capacity = 0; return SWEEP_OK; }
     if (g_trace.calls != 0) return fail(SWEEP_ERR_BAD_OPTION, "read the previous trace first");
     for (int k = g_trace.used; k < 3 * max_calls; ++k) {
-        hipError_t e = hipEventCreate(&g_trace.ev[k]);
+        // timing-only events: no system-scope fence (cache write-back) when
+        // they complete, so tracing does not slow the traced work
+        hipError_t e = hipEventCreateWithFlags(&g_trace.ev[k], hipEventDisableSystemFence);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         g_trace.used = k + 1;
     }
