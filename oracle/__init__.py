@@ -31,7 +31,7 @@ _dp = C.POINTER(C.c_double)
 
 class _Curve(C.Structure):
     _fields_ = [("n", C.c_int), ("p", C.c_int), ("closed", C.c_int),
-                ("ctrl", _dp), ("knots", _dp)]
+                ("ctrl", _dp), ("knots", _dp), ("weights", _dp)]
 
 
 def lib():
@@ -79,22 +79,27 @@ def _f64(a) -> np.ndarray:
 
 class Curve:
     """A B-spline curve: ctrl (n, 3), degree p, closed (periodic uniform) or
-    open with clamped uniform knots (knots=None) or the given knot vector."""
+    open with clamped uniform knots (knots=None) or the given knot vector;
+    with weights (n positive values) a rational (NURBS) curve."""
 
-    def __init__(self, ctrl, degree: int, closed: bool = False, knots=None):
+    def __init__(self, ctrl, degree: int, closed: bool = False, knots=None, weights=None):
         self.ctrl = _f64(ctrl).reshape(-1, 3)
         self.degree = int(degree)
         self.closed = bool(closed)
         self.knots = None if knots is None else _f64(knots)
+        self.weights = None if weights is None else _f64(weights).reshape(-1)
+        if self.weights is not None and self.weights.shape[0] != self.ctrl.shape[0]:
+            raise ValueError("one weight per control point")
         self._c = _Curve(self.ctrl.shape[0], self.degree, int(self.closed),
-                         _ptr(self.ctrl), _ptr(self.knots))
+                         _ptr(self.ctrl), _ptr(self.knots), _ptr(self.weights))
 
     @classmethod
     def of(cls, spec) -> "Curve":
-        """From any object with ctrl/degree/closed/knots attributes."""
+        """From any object with ctrl/degree/closed/knots(/weights) attributes."""
         if isinstance(spec, Curve):
             return spec
-        return cls(spec.ctrl, spec.degree, spec.closed, getattr(spec, "knots", None))
+        return cls(spec.ctrl, spec.degree, spec.closed, getattr(spec, "knots", None),
+                   getattr(spec, "weights", None))
 
     @property
     def n(self) -> int:

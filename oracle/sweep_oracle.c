@@ -34,11 +34,13 @@
 #define OR_MAXP 7
 
 typedef struct {
-    int n;               /* control points; for a closed curve the m distinct ones */
-    int p;               /* degree, 1..7 */
-    int closed;          /* 0 open (clamped uniform or user knots), 1 periodic uniform */
-    const double *ctrl;  /* n x 3 row-major */
-    const double *knots; /* open: n+p+1 values or NULL (clamped uniform); closed: ignored */
+    int n;                 /* control points; for a closed curve the m distinct ones */
+    int p;                 /* degree, 1..7 */
+    int closed;            /* 0 open (clamped uniform or user knots), 1 periodic uniform */
+    const double *ctrl;    /* n x 3 row-major */
+    const double *knots;   /* open: n+p+1 values or NULL (clamped uniform); closed: ignored */
+    const double *weights; /* NULL: polynomial B-spline; else n positive weights (NURBS),
+                              wrapped with the control points on a closed curve */
 } or_curve;
 
 /* ---------------------------------------------------------------- O1 knots */
@@ -134,13 +136,55 @@ static const double *ctrl_pt(const or_curve *c, int k)
     return c->ctrl + 3 * (size_t)(c->closed ? k % c->n : k);
 }
 
-/* C^{(d)}(u) = sum_k D^d N_{k,p}(u) P~_k for d = 0..nd; out[d*3 + c]. */
+static double weight_of(const or_curve *c, int k)
+{
+    return c->weights[c->closed ? k % c->n : k];
+}
+
+/* Rational (NURBS) curve, The NURBS Book ch. 4: in homogeneous coordinates
+ * A(u) = sum_k N_{k,p}(u) w_k P_k and W(u) = sum_k N_{k,p}(u) w_k are
+ * polynomial B-splines, C = A / W, and the derivatives follow from
+ * A^{(d)} = sum_{i=0}^{d} binom(d, i) W^{(i)} C^{(d-i)} (Leibniz rule on
+ * A = W C), solved for C^{(d)} in the order d = 0, 1, 2. */
+static void rational_eval(const or_curve *c, const double *B, int span, int nd, double *out)
+{
+    double A[3][3], W[3];
+    for (int d = 0; d <= nd; ++d) {
+        double a[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
+        for (int j = 0; j <= c->p; ++j) {
+            int k = span - c->p + j;
+            const double *P = ctrl_pt(c, k);
+            double wk = weight_of(c, k);
+            double b = B[d * (c->p + 1) + j];
+            a[0] += b * (wk * P[0]);
+            a[1] += b * (wk * P[1]);
+            a[2] += b * (wk * P[2]);
+            wsum += b * wk;
+        }
+        for (int e = 0; e < 3; ++e) A[d][e] = a[e];
+        W[d] = wsum;
+    }
+    static const double binom[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 2, 1}};
+    for (int d = 0; d <= nd; ++d)
+        for (int e = 0; e < 3; ++e) {
+            double v = A[d][e];
+            for (int i = 1; i <= d; ++i) v -= binom[d][i] * W[i] * out[3 * (d - i) + e];
+            out[3 * d + e] = v / W[0];
+        }
+}
+
+/* C^{(d)}(u) = sum_k D^d N_{k,p}(u) P~_k for d = 0..nd; out[d*3 + c]
+ * (rational curves: see rational_eval). */
 void or_curve_eval(const or_curve *c, const double *U, double u, int nd, double *out)
 {
     double B[3 * (OR_MAXP + 1)];
     int nb = or_nbasis(c->n, c->p, c->closed);
     int span = or_span(U, nb, c->p, u);
     or_basis(U, c->p, span, u, nd, B);
+    if (c->weights) {
+        rational_eval(c, B, span, nd, out);
+        return;
+    }
     for (int d = 0; d <= nd; ++d) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j <= c->p; ++j) {

@@ -43,13 +43,15 @@ __all__ = [
 @dataclass
 class CurveSpec:
     """A B-spline curve as the boundary takes it: control points (n x 3,
-    float64, row-major), degree, closed flag (periodic uniform) and optional
-    user knot vector (open curves only)."""
+    float64, row-major), degree, closed flag (periodic uniform), optional
+    user knot vector (open curves only) and optional weights (n positive
+    values: a rational curve)."""
 
     ctrl: np.ndarray
     degree: int
     closed: bool = False
     knots: Optional[np.ndarray] = None
+    weights: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:

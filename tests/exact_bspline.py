@@ -54,19 +54,20 @@ def de_boor(U: Sequence[F], P: Sequence[Sequence[F]], p: int, u: F) -> List[F]:
             lo = U[j + k - p]
             hi = U[j + 1 + k - r]
             a = (u - lo) / (hi - lo) if hi != lo else F(0)
-            d[j] = [(1 - a) * d[j - 1][c] + a * d[j][c] for c in range(3)]
+            d[j] = [(1 - a) * d[j - 1][c] + a * d[j][c] for c in range(len(d[j]))]
     return d[p]
 
 
 def derivative_net(U: Sequence[F], P: Sequence[Sequence[F]], p: int):
     """Control points and knots of C' (degree p-1)."""
     Q = []
+    dim = len(P[0])
     for k in range(len(P) - 1):
         den = U[k + p + 1] - U[k + 1]
         if den == 0:
-            Q.append([F(0)] * 3)
+            Q.append([F(0)] * dim)
         else:
-            Q.append([p * (P[k + 1][c] - P[k][c]) / den for c in range(3)])
+            Q.append([p * (P[k + 1][c] - P[k][c]) / den for c in range(dim)])
     return list(U[1:-1]), Q
 
 
@@ -74,9 +75,10 @@ def derivatives(U: Sequence[F], P: Sequence[Sequence[F]], p: int, u: F, nd: int)
     """[C(u), C'(u), ..., C^(nd)(u)]; derivatives above the degree are 0."""
     out = []
     Uc, Pc, pc = list(U), [list(x) for x in P], p
+    dim = len(P[0])
     for d in range(nd + 1):
         if pc < 0:
-            out.append([F(0)] * 3)
+            out.append([F(0)] * dim)
             continue
         out.append(de_boor(Uc, Pc, pc, u))
         if pc == 0:
@@ -85,6 +87,23 @@ def derivatives(U: Sequence[F], P: Sequence[Sequence[F]], p: int, u: F, nd: int)
         Uc, Pc = derivative_net(Uc, Pc, pc)
         pc -= 1
     return out
+
+
+def rational_derivatives(U: Sequence[F], P: Sequence[Sequence[F]], w: Sequence[F], p: int, u: F) -> List[List[F]]:
+    """[C, C', C''] of the rational curve with weights w: the homogeneous
+    curve (w P, w) is evaluated exactly (points and derivative nets above),
+    C = A / W, and the derivatives of the quotient are taken in expanded form
+        C'  = (A' W - A W') / W^2,
+        C'' = (A'' W^2 - A W'' W - 2 A' W' W + 2 A W'^2) / W^3."""
+    Pw = [[w[k] * P[k][c] for c in range(3)] + [w[k]] for k in range(len(P))]
+    H = derivatives(U, Pw, p, u, 2)
+    A = [H[d][:3] for d in range(3)]
+    W = [H[d][3] for d in range(3)]
+    C0 = [A[0][c] / W[0] for c in range(3)]
+    C1 = [(A[1][c] * W[0] - A[0][c] * W[1]) / (W[0] ** 2) for c in range(3)]
+    C2 = [(A[2][c] * W[0] ** 2 - A[0][c] * W[2] * W[0] - 2 * A[1][c] * W[1] * W[0] + 2 * A[0][c] * W[1] ** 2)
+          / (W[0] ** 3) for c in range(3)]
+    return [C0, C1, C2]
 
 
 def to_frac(a) -> List[List[F]]:
