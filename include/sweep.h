@@ -23,6 +23,10 @@
  *           vector (non-decreasing, finite, interior multiplicity <= p,
  *           end multiplicity <= p+1); closed curves: periodic uniform
  *           U_k = k over the control polygon wrapped by p points.
+ *   rational with weights w_k (NURBS, Piegl & Tiller, The NURBS Book ch. 4):
+ *           C(u) = sum_k N_k(u) w_k P_k / sum_k N_k(u) w_k, derivatives from
+ *           the homogeneous curve (w P, w) by the quotient rule; a closed
+ *           curve wraps its weights with its control points.
  *   samples open: u_i = U_p + (U_n - U_p) * (i/(n_s-1)), both ends included;
  *           closed: t_j = p + (m*j)/n_s, the seam not repeated.
  *   span    U_k <= u < U_{k+1}; the last span at the right end of the domain.
@@ -72,7 +76,7 @@
 extern "C" {
 #endif
 
-#define SWEEP_VERSION 100  /* major*100 + minor */
+#define SWEEP_VERSION 101  /* major*100 + minor */
 #define SWEEP_MAX_DEGREE 7
 
 typedef enum {
@@ -100,6 +104,10 @@ typedef struct {
     const double *ctrl;  /* DEVICE, n_ctrl x 3 FP64, row-major (x, y, z) */
     const double *knots; /* HOST, n_ctrl+degree+1 FP64, or NULL for the default
                             knots; must be NULL for a closed curve */
+    const double *weights; /* DEVICE, n_ctrl FP64 weights (a rational curve, see
+                              "rational" above), or NULL (polynomial B-spline);
+                              weights must be positive and finite -- they are
+                              device data and not checked */
 } sweep_curve;
 
 /* Options; sweep_default_options() fills the defaults noted here. */
@@ -135,6 +143,9 @@ typedef struct {
     const double *prof_knots;    /* NULL: default; else one vector per OPEN profile, in sweep order */
     const double *path_ctrl;     /* DEVICE, sum(path_n) x 3 FP64 */
     const double *prof_ctrl;     /* DEVICE, sum(prof_n) x 3 FP64 */
+    const double *path_weights;  /* DEVICE, sum(path_n) FP64 packed like path_ctrl, or NULL
+                                    (every path polynomial) */
+    const double *prof_weights;  /* DEVICE, sum(prof_n) FP64, or NULL */
 } sweep_batch;
 
 void sweep_default_options(sweep_options *opt);
@@ -192,7 +203,9 @@ int64_t sweep_batched_output_elems(const sweep_batch *batch);
  * grad_path_ctrl (DEVICE, sum(path_n) x 3 FP64) and grad_prof_ctrl (DEVICE,
  * sum(prof_n) x 3 FP64), the gradients of L with respect to the control
  * points.  The frame is recomputed in FP64; reductions accumulate in FP64 in
- * a fixed order (deterministic).  Gradients through normals are not provided.
+ * a fixed order (deterministic).  Gradients through normals, and with
+ * respect to weights (rational curves: weights are held fixed), are not
+ * provided.
  * At tangent reversals the step rotation is treated as locally constant.
  */
 sweep_status sweep_backward(const sweep_batch *batch, const sweep_options *opt,

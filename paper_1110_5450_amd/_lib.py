@@ -27,7 +27,7 @@ _ip = C.POINTER(C.c_int32)
 
 class SweepCurve(C.Structure):
     _fields_ = [("n_ctrl", C.c_int32), ("degree", C.c_int32), ("closed", C.c_int32), ("reserved", C.c_int32),
-                ("ctrl", C.c_void_p), ("knots", _dp)]
+                ("ctrl", C.c_void_p), ("knots", _dp), ("weights", C.c_void_p)]
 
 
 class SweepOptions(C.Structure):
@@ -41,7 +41,8 @@ class SweepBatch(C.Structure):
                 ("path_n", _ip), ("path_degree", _ip), ("prof_n", _ip), ("prof_degree", _ip),
                 ("prof_closed", _ip), ("n_u", _ip), ("n_v", _ip),
                 ("path_knots", _dp), ("prof_knots", _dp),
-                ("path_ctrl", C.c_void_p), ("prof_ctrl", C.c_void_p)]
+                ("path_ctrl", C.c_void_p), ("prof_ctrl", C.c_void_p),
+                ("path_weights", C.c_void_p), ("prof_weights", C.c_void_p)]
 
 
 class SweepError(RuntimeError):

@@ -28,6 +28,25 @@ def _check_ctrl(t: torch.Tensor, what: str) -> torch.Tensor:
     return t.contiguous()
 
 
+def _weights(w, n: int, what: str) -> Optional[torch.Tensor]:
+    """Device float64 weights (n,) or None; positivity is the caller's
+    responsibility (device data is not inspected)."""
+    if w is None:
+        return None
+    if not isinstance(w, torch.Tensor) or not w.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if w.dtype != torch.float64:
+        raise TypeError(f"{what} must be float64")
+    w = w.contiguous().reshape(-1)
+    if w.shape[0] != n:
+        raise ValueError(f"{what} needs {n} values, got {w.shape[0]}")
+    return w
+
+
+def _wptr(w: Optional[torch.Tensor]) -> Optional[int]:
+    return None if w is None else w.data_ptr()
+
+
 def _knots_ptr(knots) -> Tuple[Optional[np.ndarray], Optional[C.POINTER(C.c_double)]]:
     if knots is None:
         return None, None
@@ -71,15 +90,19 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
                n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
                out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                initial_normal=None, tile_config: int = -1, normals: bool = True,
+               path_weights=None, prof_weights=None,
                out: Optional[Tuple[torch.Tensor, Optional[torch.Tensor]]] = None,
                workspace: Optional[torch.Tensor] = None, stream=None):
-    """Positions (3, n_u, n_v) and normals (or None) of one sweep."""
+    """Positions (3, n_u, n_v) and normals (or None) of one sweep; with
+    weights (device float64, one per control point) a curve is rational."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
     qc = _check_ctrl(prof_ctrl, "prof_ctrl")
+    pw = _weights(path_weights, pc.shape[0], "path_weights")
+    qw = _weights(prof_weights, qc.shape[0], "prof_weights")
     pk, pkp = _knots_ptr(path_knots)
     qk, qkp = _knots_ptr(prof_knots)
-    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp)
-    prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp)
+    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
+    prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
@@ -106,15 +129,18 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
 def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tensor, prof_degree: int,
                    n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
                    out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
-                   initial_normal=None, normals: bool = True, stream=None):
+                   initial_normal=None, normals: bool = True, path_weights=None, prof_weights=None,
+                   stream=None):
     """Times every surface configuration on this sweep and records the
     fastest for its shape class; returns (best_config, best_ms, pos, nrm)."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
     qc = _check_ctrl(prof_ctrl, "prof_ctrl")
+    pw = _weights(path_weights, pc.shape[0], "path_weights")
+    qw = _weights(prof_weights, qc.shape[0], "prof_weights")
     pk, pkp = _knots_ptr(path_knots)
     qk, qkp = _knots_ptr(prof_knots)
-    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp)
-    prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp)
+    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
+    prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
@@ -138,11 +164,13 @@ def surface_config_for(n_u: int, n_v: int, out_dtype=torch.float32) -> int:
 
 def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
                  out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
-                 initial_normal=None, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                 initial_normal=None, path_weights=None, workspace: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
     """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
+    pw = _weights(path_weights, pc.shape[0], "path_weights")
     pk, pkp = _knots_ptr(path_knots)
-    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp)
+    path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
     ws_bytes = L.sweep_frames_workspace_size(path, int(n_u), opt)
     if ws_bytes == 0:
@@ -157,8 +185,8 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
 
 def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree: int, n_u: int, n_v: int, *,
                         prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
-    path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None)
-    prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None)
+    path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None, None)
+    prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None, None)
     return L.sweep_eval_workspace_size(path, prof, n_u, n_v, make_options(out_dtype, frame_dtype))
 
 
@@ -175,7 +203,7 @@ class Batch:
 
     def __init__(self, path_ctrl: Sequence, path_degree: Sequence[int], prof_ctrl: Sequence,
                  prof_degree: Sequence[int], n_u: Sequence[int], n_v: Sequence[int], *, prof_closed=None,
-                 path_knots=None, prof_knots=None, device="cuda"):
+                 path_knots=None, prof_knots=None, path_weights=None, prof_weights=None, device="cuda"):
         n = len(path_ctrl)
         self.n_sweeps = n
         as_np = lambda a: np.ascontiguousarray(a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else a,
@@ -203,6 +231,9 @@ class Batch:
             self.prof_knots = np.ascontiguousarray(np.concatenate(ks)) if ks else None
         self.path_ctrl = torch.as_tensor(np.concatenate(P)).to(device)
         self.prof_ctrl = torch.as_tensor(np.concatenate(Q)).to(device)
+        # Weights: for every path (profile) or for none; packed like the control points.
+        self.path_weights = self._pack_weights(path_weights, P, "path_weights", device)
+        self.prof_weights = self._pack_weights(prof_weights, Q, "prof_weights", device)
         sizes = self.n_u.astype(np.int64) * self.n_v.astype(np.int64)
         a = self.PLANE_ALIGN
         self.plane = (sizes + a - 1) // a * a
@@ -212,17 +243,36 @@ class Batch:
         self.path_offsets = np.concatenate([[0], np.cumsum(self.path_n)[:-1]]).astype(np.int64)
         self.prof_offsets = np.concatenate([[0], np.cumsum(self.prof_n)[:-1]]).astype(np.int64)
 
+    @staticmethod
+    def _pack_weights(ws, ctrl, what, device):
+        if ws is None:
+            return None
+        if any(w is None for w in ws):
+            raise ValueError(f"{what} must give weights for every curve (or be None)")
+        flat = []
+        for w, c in zip(ws, ctrl):
+            w = np.asarray(w.detach().cpu().numpy() if isinstance(w, torch.Tensor) else w, np.float64).reshape(-1)
+            if w.shape[0] != c.shape[0]:
+                raise ValueError(f"{what}: one weight per control point")
+            flat.append(w)
+        return torch.as_tensor(np.concatenate(flat)).to(device)
+
     @classmethod
     def from_specs(cls, specs, device="cuda") -> "Batch":
-        """From objects with path/profile (ctrl, degree, closed, knots), n_u, n_v."""
+        """From objects with path/profile (ctrl, degree, closed, knots,
+        weights), n_u, n_v."""
         pk = [s.path.knots for s in specs]
         qk = [s.profile.knots for s in specs]
+        pw = [getattr(s.path, "weights", None) for s in specs]
+        qw = [getattr(s.profile, "weights", None) for s in specs]
         return cls([s.path.ctrl for s in specs], [s.path.degree for s in specs],
                    [s.profile.ctrl for s in specs], [s.profile.degree for s in specs],
                    [s.n_u for s in specs], [s.n_v for s in specs],
                    prof_closed=[int(s.profile.closed) for s in specs],
                    path_knots=None if all(k is None for k in pk) else pk,
-                   prof_knots=None if all(k is None for k in qk) else qk, device=device)
+                   prof_knots=None if all(k is None for k in qk) else qk,
+                   path_weights=None if all(w is None for w in pw) else pw,
+                   prof_weights=None if all(w is None for w in qw) else qw, device=device)
 
     def c_struct(self) -> L.SweepBatch:
         ip = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
@@ -230,7 +280,8 @@ class Batch:
         return L.SweepBatch(self.n_sweeps, 0, ip(self.path_n), ip(self.path_degree), ip(self.prof_n),
                             ip(self.prof_degree), ip(self.prof_closed), ip(self.n_u), ip(self.n_v),
                             dp(self.path_knots), dp(self.prof_knots),
-                            self.path_ctrl.data_ptr(), self.prof_ctrl.data_ptr())
+                            self.path_ctrl.data_ptr(), self.prof_ctrl.data_ptr(),
+                            _wptr(self.path_weights), _wptr(self.prof_weights))
 
     def view(self, flat: torch.Tensor, k: int) -> torch.Tensor:
         """Sweep k's (3, n_u, n_v) block of a flat batched output (a view with

@@ -149,7 +149,10 @@ __device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, dou
     }
 }
 
-// Basis of sample i of ns (any degree up to kMaxDeg): span and values.
+// Basis of sample i of ns (any degree up to kMaxDeg): span and values.  For
+// a rational curve the values are those of the rational basis
+// R_k = w_k N_k / W and R_k' = w_k (N_k' W - N_k W') / W^2 (W = sum w_k N_k),
+// the derivatives of C and C' with respect to control point k.
 __device__ __forceinline__ int sample_basis(const DCurve& c, int i, int ns, double* N, double* dN)
 {
     const double u = sample_param(c, i, ns);
@@ -162,6 +165,20 @@ __device__ __forceinline__ int sample_basis(const DCurve& c, int i, int ns, doub
     case 5: basis_vals<5>(c, u, s, N, dN); break;
     case 6: basis_vals<6>(c, u, s, N, dN); break;
     default: basis_vals<7>(c, u, s, N, dN); break;
+    }
+    if (c.w) {
+        double W = 0.0, W1 = 0.0;
+        for (int j = 0; j <= c.p; ++j) {
+            const double wk = weight_at(c, s - c.p + j);
+            W += wk * N[j];
+            W1 += wk * dN[j];
+        }
+        for (int j = 0; j <= c.p; ++j) {
+            const double wk = weight_at(c, s - c.p + j);
+            const double Rj = wk * N[j] / W;
+            dN[j] = wk * (dN[j] * W - N[j] * W1) / (W * W);
+            N[j] = Rj;
+        }
     }
     return s;
 }
@@ -259,6 +276,8 @@ __device__ V3<double> block_suffix_sum(V3<double> v, double (*lds)[3], V3<double
 __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restrict__ descs,
                                                       const double* __restrict__ path_ctrl,
                                                       const double* __restrict__ prof_ctrl,
+                                                      const double* __restrict__ path_w,
+                                                      const double* __restrict__ prof_w,
                                                       const double* __restrict__ knots, InitialNormal n0,
                                                       const double* __restrict__ rows, const double* rowpart,
                                                       const double* colpart, double* rowacc, double* colacc,
@@ -269,9 +288,10 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
     __shared__ double lpart[kBlock][3];
     const BatchDesc d = descs[blockIdx.x];
     const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
-                      d.n_path, d.p_path, 0, d.n_path};
+                      d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
     const DCurve prof{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
-                      d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof};
+                      d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
+                      prof_w ? prof_w + d.prof_ctrl_off : nullptr};
     const int n_u = d.n_u, n_v = d.n_v;
     const double* rows_k = rows + 16 * d.row_off;
     double* racc = rowacc + 12 * d.row_off;

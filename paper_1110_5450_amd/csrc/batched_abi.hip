@@ -145,6 +145,8 @@ struct NodeArgs {
     const int2* tiles;
     const double* path_ctrl;
     const double* prof_ctrl;
+    const double* path_w;
+    const double* prof_w;
     const double* knots;
     InitialNormal n0;
     int reorth;
@@ -171,8 +173,8 @@ static int node_args(GNode& n)
     NodeArgs& A = n.a;
     void** q = n.ptrs;
     switch (n.kind) {
-    case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 5; }
-    case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.knots, &A.n0, &A.reorth, &A.rows}; std::memcpy(q, v, sizeof v); return 7; }
+    case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.prof_w, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 6; }
+    case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.path_w, &A.knots, &A.n0, &A.reorth, &A.rows}; std::memcpy(q, v, sizeof v); return 8; }
     default: { void* v[] = {&A.descs, &A.tiles, &A.rows, &A.ptab, &A.pos, &A.nrm}; std::memcpy(q, v, sizeof v); return 6; }
     }
 }
@@ -391,6 +393,8 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     std::memcpy(&A, &P->a, sizeof A);
     A.path_ctrl = batch->path_ctrl;
     A.prof_ctrl = batch->prof_ctrl;
+    A.path_w = batch->path_weights;
+    A.prof_w = batch->prof_weights;
     A.rows = ws + L.rows;
     A.ptab = ws + L.ptab;
     A.pos = pos;
@@ -464,6 +468,8 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         std::memcpy(&n.a, &P->a, sizeof n.a);
         n.a.path_ctrl = batch->path_ctrl;
         n.a.prof_ctrl = batch->prof_ctrl;
+        n.a.path_w = batch->path_weights;
+        n.a.prof_w = batch->prof_weights;
         n.a.reorth = 1;
         n.a.rows = ws + B.rows;
         n.a.ptab = ws + B.ptab;
@@ -497,6 +503,8 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         const BatchDesc* descs = P->d_descs;
         const double* pc = batch->path_ctrl;
         const double* qc = batch->prof_ctrl;
+        const double* pw = batch->path_weights;
+        const double* qw = batch->prof_weights;
         const double* kn = P->d_knots;
         InitialNormal n0 = P->a.n0;
         const void* rows = ws + B.rows;
@@ -511,8 +519,8 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         void* spans_v = ws + B.spans_v;
         double* gp = grad_path_ctrl;
         double* gq = grad_prof_ctrl;
-        void* args[17] = {&descs, &pc, &qc, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc, &rho,
-                          &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq};
+        void* args[19] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
+                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq};
         if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward adjoint");
     }

@@ -25,15 +25,18 @@
 
 namespace sweep {
 
-__device__ __forceinline__ DCurve path_of(const BatchDesc& d, const double* path_ctrl, const double* knots)
+__device__ __forceinline__ DCurve path_of(const BatchDesc& d, const double* path_ctrl, const double* path_w,
+                                          const double* knots)
 {
     return DCurve{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
-                  d.n_path, d.p_path, 0, d.n_path};
+                  d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
 }
-__device__ __forceinline__ DCurve prof_of(const BatchDesc& d, const double* prof_ctrl, const double* knots)
+__device__ __forceinline__ DCurve prof_of(const BatchDesc& d, const double* prof_ctrl, const double* prof_w,
+                                          const double* knots)
 {
     return DCurve{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
-                  d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof};
+                  d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
+                  prof_w ? prof_w + d.prof_ctrl_off : nullptr};
 }
 
 struct ChunkLds {
@@ -102,12 +105,13 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void kb_profile(const BatchDesc* __restrict__ descs,
                                                      const int2* __restrict__ vchunks,
                                                      const double* __restrict__ prof_ctrl,
+                                                     const double* __restrict__ prof_w,
                                                      const double* __restrict__ knots, T* __restrict__ ptab)
 {
     const int2 vc = vchunks[blockIdx.x];
     const BatchDesc d = descs[vc.x];
     const int j = vc.y * kBlock + threadIdx.x;
-    if (j < d.n_v) write_profile<T>(prof_of(d, prof_ctrl, knots), j, d.n_v, ptab + 8 * d.ptab_off);
+    if (j < d.n_v) write_profile<T>(prof_of(d, prof_ctrl, prof_w, knots), j, d.n_v, ptab + 8 * d.ptab_off);
 }
 
 // Row records of the sweeps whose path has degree P: one block per sweep.
@@ -115,13 +119,14 @@ template <int P, class F, class T>
 __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
                                                    const int* __restrict__ sweeps,
                                                    const double* __restrict__ path_ctrl,
+                                                   const double* __restrict__ path_w,
                                                    const double* __restrict__ knots, InitialNormal n0, int reorth,
                                                    T* __restrict__ rows)
 {
     __shared__ ChunkLds L;
     __shared__ M3<F> lds_m[kWaves];
     const BatchDesc d = descs[sweeps[blockIdx.x]];
-    const DCurve path = path_of(d, path_ctrl, knots);
+    const DCurve path = path_of(d, path_ctrl, path_w, knots);
     const V3<double> fb = first_leg(path);
     const int n_u = d.n_u;
     T* rows_k = rows + 16 * (size_t)d.row_off;

@@ -68,6 +68,7 @@ struct DCurve {
     int p;       // degree
     int closed;  // periodic uniform
     int nb;      // basis functions: n (open) or n + p (closed)
+    const double* __restrict__ w;      // n weights (rational curve), or nullptr
 };
 
 __device__ __forceinline__ V3<double> ctrl_pt(const DCurve& c, int k)
@@ -75,6 +76,11 @@ __device__ __forceinline__ V3<double> ctrl_pt(const DCurve& c, int k)
     const int kk = (c.closed && k >= c.n) ? k - c.n : k;
     const double* q = c.ctrl + 3 * (size_t)kk;
     return {q[0], q[1], q[2]};
+}
+
+__device__ __forceinline__ double weight_at(const DCurve& c, int k)
+{
+    return c.w[(c.closed && k >= c.n) ? k - c.n : k];
 }
 
 // Knot k: the given vector, else periodic U_k = k, else clamped uniform
@@ -126,7 +132,61 @@ __device__ __forceinline__ int sample_span(const DCurve& c, int i, int ns, doubl
     return lo;
 }
 
-// C and derivatives up to order ND at u (in span s) for a degree-P B-spline.
+// Rational curve (NURBS Book ch. 4): the homogeneous curve (w P, w) has the
+// same basis and derivative nets, giving A, A', A'' and W, W', W''; then
+// C = A / W, C' = (A' - W' C) / W, C'' = (A'' - 2 W' C' - W'' C) / W.
+// Uk, B, D1, D2 as in curve_derivs; Pt the P+1 control points of span s.
+template <int P, int ND>
+__device__ __forceinline__ void rational_derivs(const DCurve& c, int s, const double* Uk, const double* B,
+                                                const double* D1, const double* D2, const V3<double>* Pt,
+                                                V3<double>* out)
+{
+    V3<double> Hw[P + 1];
+    double wt[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        wt[j] = weight_at(c, s - P + j);
+        Hw[j] = wt[j] * Pt[j];
+    }
+    V3<double> A0 = mk(0.0, 0.0, 0.0);
+    double W0 = 0.0;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) { A0 = A0 + B[j] * Hw[j]; W0 = W0 + B[j] * wt[j]; }
+    const V3<double> C0 = divs(A0, W0);
+    out[0] = C0;
+    if (ND >= 1) {
+        V3<double> Q1[P > 0 ? P : 1];
+        double q1[P > 0 ? P : 1];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const double f = (double)P / (Uk[P + j] - Uk[j]);
+            Q1[j] = f * (Hw[j + 1] - Hw[j]);
+            q1[j] = f * (wt[j + 1] - wt[j]);
+        }
+        V3<double> A1 = mk(0.0, 0.0, 0.0);
+        double W1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) { A1 = A1 + D1[j] * Q1[j]; W1 = W1 + D1[j] * q1[j]; }
+        const V3<double> C1 = divs(A1 - W1 * C0, W0);
+        out[1] = C1;
+        if (ND >= 2) {
+            V3<double> A2 = mk(0.0, 0.0, 0.0);
+            double W2 = 0.0;
+            if (P >= 2) {
+#pragma unroll
+                for (int j = 0; j + 1 < P; ++j) {
+                    const double f = (double)(P - 1) / (Uk[P + j] - Uk[j + 1]);
+                    A2 = A2 + D2[j] * (f * (Q1[j + 1] - Q1[j]));
+                    W2 = W2 + D2[j] * (f * (q1[j + 1] - q1[j]));
+                }
+            }
+            out[2] = divs(A2 - (2.0 * W1) * C1 - W2 * C0, W0);
+        }
+    }
+}
+
+// C and derivatives up to order ND at u (in span s) for a degree-P B-spline
+// (rational when c.w is set).
 // Basis values of degrees P, P-1, P-2 come from one triangular sweep of the
 // Cox-de Boor recursion (one division per knot interval and degree);
 // derivatives use the derivative control nets
@@ -173,6 +233,10 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V
     V3<double> Pt[P + 1];
 #pragma unroll
     for (int j = 0; j <= P; ++j) Pt[j] = ctrl_pt(c, s - P + j);
+    if (c.w) {
+        rational_derivs<P, ND>(c, s, Uk, B, D1, D2, Pt, out);
+        return;
+    }
     V3<double> C0 = mk(0.0, 0.0, 0.0);
 #pragma unroll
     for (int j = 0; j <= P; ++j) C0 = C0 + B[j] * Pt[j];

@@ -310,8 +310,8 @@ static sweep_status run_frames(const sweep_curve* path, int n_u, const sweep_opt
     sweep_status s = upload_knots(path->knots, path->n_ctrl, path->degree, Up, st);
     if (s != SWEEP_OK) return s;
     DCurve dp{path->ctrl, path->knots ? Up : nullptr, path->n_ctrl, path->degree, 0,
-              nbasis(path->n_ctrl, path->degree, 0)};
-    DCurve dq{nullptr, nullptr, 1, 1, 0, 1};
+              nbasis(path->n_ctrl, path->degree, 0), path->weights};
+    DCurve dq{nullptr, nullptr, 1, 1, 0, 1, nullptr};
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
@@ -338,9 +338,9 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
     if (s != SWEEP_OK) return s;
     trace_mark(0, st);
     DCurve dp{path->ctrl, path->knots ? Up : nullptr, path->n_ctrl, path->degree, 0,
-              nbasis(path->n_ctrl, path->degree, 0)};
+              nbasis(path->n_ctrl, path->degree, 0), path->weights};
     DCurve dq{prof->ctrl, prof->knots ? Uq : nullptr, prof->n_ctrl, prof->degree, prof->closed,
-              nbasis(prof->n_ctrl, prof->degree, prof->closed)};
+              nbasis(prof->n_ctrl, prof->degree, prof->closed), prof->weights};
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);

@@ -31,10 +31,16 @@ def dev_ctrl(a) -> torch.Tensor:
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def _dev_w(w):
+    return None if w is None else dev_ctrl(w)
+
+
 def gpu_sweep(spec, out_dtype=torch.float32, frame_dtype=torch.float64, **kw):
     p, q = spec.path, spec.profile
     return api.sweep_eval(dev_ctrl(p.ctrl), p.degree, dev_ctrl(q.ctrl), q.degree, spec.n_u, spec.n_v,
                           prof_closed=q.closed, path_knots=p.knots, prof_knots=q.knots,
+                          path_weights=_dev_w(getattr(p, "weights", None)),
+                          prof_weights=_dev_w(getattr(q, "weights", None)),
                           out_dtype=out_dtype, frame_dtype=frame_dtype, **kw)
 
 

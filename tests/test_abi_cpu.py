@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert L.sweep_version() == 100
+    assert L.sweep_version() == 101
     o = L.default_options()
     assert (o.out_precision, o.frame_precision, o.reorthonormalize, o.has_initial_normal, o.tile_config) == (0, 1, 1, 0, -1)
     assert L.sweep_tile_config_count() >= 8
