@@ -67,6 +67,12 @@ def _dev_spec(spec, dev):
     return torch.as_tensor(spec.path.ctrl).to(dev), torch.as_tensor(spec.profile.ctrl).to(dev)
 
 
+def _dev_weights(curve, dev):
+    import torch
+    w = getattr(curve, "weights", None)
+    return None if w is None else torch.as_tensor(w).to(dev)
+
+
 def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
     """Wall time of `steps` sweep_eval calls, the per-call (frame, surface)
     stage times from the library's HIP events, and optionally the outputs."""
@@ -82,9 +88,11 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
                                              spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype),
                      dtype=torch.uint8, device=dev)
 
+    Pw, Qw = _dev_weights(spec.path, dev), _dev_weights(spec.profile, dev)
+
     def step():
         api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v, out_dtype=out_dtype,
-                       frame_dtype=frame_dtype, out=(pos, nrm), workspace=ws)
+                       frame_dtype=frame_dtype, path_weights=Pw, prof_weights=Qw, out=(pos, nrm), workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -143,6 +151,26 @@ def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 1000):
         "sample": (f"the full {spec.n_u}x{spec.n_v} grid (frame scan, FP64 positions and normals) "
                    f"run {reps} times, {total:.1f} s in all"),
     }
+
+
+def rational_variant(steps: int):
+    """The large sweep with rational (NURBS) path and profile: throughput,
+    stage times and sampled parity against the oracle."""
+    import numpy as np
+    import torch
+    import synth
+
+    spec = synth.c2_rational()
+    N = spec.n_u * spec.n_v
+    el, surf, frame, res = time_single(spec, steps, 1, torch.float32, keep=True)
+    rng = np.random.default_rng(8)
+    rows = np.unique(np.concatenate([[0, spec.n_u - 1], rng.integers(0, spec.n_u, 6)]))
+    err = sampled_error(spec, res[0], res[1], rows, 1e-5)
+    del res
+    torch.cuda.empty_cache()
+    return {"workload": "the large sweep with weights U(0.5, 2) on path and profile control points",
+            "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
+            "frame_ms": sum(frame) / len(frame), "surface_ms": sum(surf) / len(surf), "error_vs_oracle": err}
 
 
 def batched_variants(steps: int):
@@ -373,6 +401,8 @@ def main():
             "plain_fp64_out": {"vertices_per_s": N * steps64 / el64, "ms_per_step": 1e3 * el64 / steps64,
                                "surface_ms": s64, "surface_GBps": 48.0 * N / (s64 * 1e-3) / 1e9},
         }
+        log("[bench] rational ...")
+        out["variants"]["rational_fp32_out"] = rational_variant(steps64)
         log("[bench] batched ...")
         out["variants"]["batched"] = batched_variants(max(3, args.steps // 4))
         log("[bench] adjoint ...")

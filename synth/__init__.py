@@ -14,6 +14,7 @@ measured on):
   are perturbed uniformly by +-10 %; grid 256 x 64; FP64 output.
 * ``c2`` large single sweep: 1024 path / 64 profile control points, grid
   65536 x 1024 (67,108,864 vertices); FP32 output with FP64 frame scan.
+* ``c2_rational`` the same curves with weights U(0.5, 2) (NURBS).
 * ``c3`` precision study: the ``c1`` path and profile at 1,048,576 x 32.
 * ``c4`` batched: 4096 sweeps; path counts uniform in [8, 512], profile counts
   uniform in [4, 64], path and profile degree each uniform in {2, 3}, n_u
@@ -36,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "CurveSpec", "SweepSpec", "random_walk", "perturbed_circle", "single",
-    "config", "c1", "c2", "c3", "c4", "c5", "loss_weights",
+    "config", "c1", "c2", "c2_rational", "c3", "c4", "c5", "loss_weights",
 ]
 
 
@@ -103,6 +104,16 @@ def c1() -> SweepSpec:
 
 def c2(n_u: int = 65536, n_v: int = 1024) -> SweepSpec:
     return single(2, 1024, 64, n_u, n_v)
+
+
+def c2_rational(n_u: int = 65536, n_v: int = 1024, seed: int = 22) -> SweepSpec:
+    """The large sweep's curves made rational: weights U(0.5, 2) per control
+    point (path first, then profile)."""
+    s = c2(n_u, n_v)
+    rng = np.random.default_rng(seed)
+    s.path.weights = rng.uniform(0.5, 2.0, s.path.n)
+    s.profile.weights = rng.uniform(0.5, 2.0, s.profile.n)
+    return s
 
 
 def c3(n_u: int = 1048576, n_v: int = 32) -> SweepSpec:
