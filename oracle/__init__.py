@@ -65,6 +65,12 @@ def lib():
                                  _dp, _dp, C.c_double, _dp, _dp]
         L.or_loss.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, _dp]
         L.or_max_threads.restype = C.c_int
+        L.or_sweep_ex.restype = C.c_int
+        L.or_sweep_ex.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, C.c_int, C.c_int,
+                                  C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.or_curve_samples3.restype = None
+        L.or_frenet.restype = None
+        L.or_surface_rows_ex.restype = None
         _lib = L
     return _lib
 
@@ -218,6 +224,80 @@ def sweep(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True,
     if nf < 0:
         raise ValueError("oracle: bad sweep input")
     return SweepResult(pos, nrm, kap, R.reshape(n_u, 3, 3).transpose(0, 2, 1).copy(), nf, (r0, r1))
+
+
+FRAME_MODES = {"rmf": 0, "frenet": 1}
+
+def frenet(t, d1, d2, d3):
+    """Sample-level Frenet frame from tangents t and the first, second and
+    third derivatives (each (n, 3)): (R (n, 3, 3) with columns r = n, s = b,
+    t; omega (n,))."""
+    t, d1, d2, d3 = (_f64(a).reshape(-1, 3) for a in (t, d1, d2, d3))
+    n = t.shape[0]
+    R = np.zeros((n, 9))
+    R[:, 6:9] = t
+    om = np.empty(n)
+    lib().or_frenet(C.c_int(n), _ptr(d1), _ptr(d2), _ptr(d3), _ptr(R), _ptr(om))
+    return R.reshape(n, 3, 3).transpose(0, 2, 1).copy(), om
+
+
+def surface_ex_from_samples(x, d1, d2, R, omega, law, S, dS):
+    """Sample-level surface with a general frame: R (n_u, 3, 3) columns
+    r, s, t; omega (n_u,) or None; law (n_u, 4) = (sigma, theta, dsigma/du,
+    dtheta/du) or None.  Returns (pos, nrm, kappa)."""
+    x, d1, d2, S, dS = (_f64(a) for a in (x, d1, d2, S, dS))
+    nu, nv = x.shape[0], S.shape[0]
+    Rr = _f64(np.asarray(R).transpose(0, 2, 1).reshape(nu, 9))
+    om = None if omega is None else _f64(omega)
+    lw = None if law is None else _f64(law)
+    pos = np.empty((3, nu, nv))
+    nrm = np.empty((3, nu, nv))
+    kap = np.empty((nu, nv))
+    lib().or_surface_rows_ex(C.c_int(nu), C.c_int(nv), C.c_int(0), C.c_int(nu), _ptr(x), _ptr(d1), _ptr(d2),
+                             _ptr(Rr), _ptr(om), _ptr(lw), _ptr(S), _ptr(dS), _ptr(pos), _ptr(nrm), _ptr(kap))
+    return pos, nrm, kap
+
+
+
+def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mode: str = "rmf", law=None,
+             rows: Optional[Tuple[int, int]] = None, want_kappa=True):
+    """Whole sweep with a frame mode ("rmf" or "frenet") and an optional law
+    curve (open curve whose control points hold (scale, twist angle, -)).
+    Returns (SweepResult, omega (n_u,))."""
+    P, Q = Curve.of(path), Curve.of(profile)
+    Lw = None if law is None else Curve.of(law)
+    r0, r1 = (0, n_u) if rows is None else rows
+    pos = np.empty((3, n_u, n_v))
+    nrm = np.empty((3, n_u, n_v))
+    kap = np.empty((n_u, n_v)) if want_kappa else None
+    R = np.empty((n_u, 9))
+    om = np.empty(n_u)
+    n0a = None if n0 is None else _f64(n0)
+    nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), int(reorth), FRAME_MODES[mode],
+                           None if Lw is None else C.cast(Lw.ref, C.c_void_p), r0, r1, _ptr(pos), _ptr(nrm),
+                           _ptr(kap), _ptr(R), _ptr(om))
+    if nf < 0:
+        raise ValueError("oracle: bad sweep input")
+    return SweepResult(pos, nrm, kap, R.reshape(n_u, 3, 3).transpose(0, 2, 1).copy(), nf, (r0, r1)), om
+
+
+def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = "rmf", law=None):
+    """sweep_ex on the listed rows only: (pos (3, len(rows), n_v), nrm,
+    kappa (len(rows), n_v))."""
+    rows = np.asarray(rows, dtype=np.int64)
+    P, Q = Curve.of(path), Curve.of(profile)
+    Lw = None if law is None else Curve.of(law)
+    pos = np.empty((3, n_u, n_v))
+    nrm = np.empty((3, n_u, n_v))
+    kap = np.empty((n_u, n_v))
+    n0a = None if n0 is None else _f64(n0)
+    for i in rows:
+        nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), 1, FRAME_MODES[mode],
+                               None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(i), int(i) + 1,
+                               _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
+        if nf < 0:
+            raise ValueError("oracle: bad sweep input")
+    return pos[:, rows], nrm[:, rows], kap[rows]
 
 
 def sweep_rows(path, profile, n_u: int, n_v: int, rows, n0=None, reorth: bool = True):

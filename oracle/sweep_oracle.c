@@ -111,7 +111,7 @@ int or_span(const double *U, int nb, int p, double u)
  * out[d*(p+1) + j] = D^d N_{span-p+j, p}(u), d = 0..nd, j = 0..p. */
 void or_basis(const double *U, int p, int span, double u, int nd, double *out)
 {
-    double T[3][OR_MAXP + 1][OR_MAXP + 2];
+    double T[4][OR_MAXP + 1][OR_MAXP + 2];
     int lo = span - p;
     memset(T, 0, sizeof T);
     for (int j = 0; j <= p + 1; ++j) T[0][0][j] = (lo + j == span) ? 1.0 : 0.0;
@@ -153,10 +153,10 @@ static double weight_of(const or_curve *c, int k)
  * A(u) = sum_k N_{k,p}(u) w_k P_k and W(u) = sum_k N_{k,p}(u) w_k are
  * polynomial B-splines, C = A / W, and the derivatives follow from
  * A^{(d)} = sum_{i=0}^{d} binom(d, i) W^{(i)} C^{(d-i)} (Leibniz rule on
- * A = W C), solved for C^{(d)} in the order d = 0, 1, 2. */
+ * A = W C), solved for C^{(d)} in the order d = 0, 1, 2, 3. */
 static void rational_eval(const or_curve *c, const double *B, int span, int nd, double *out)
 {
-    double A[3][3], W[3];
+    double A[4][3], W[4];
     for (int d = 0; d <= nd; ++d) {
         double a[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
         for (int j = 0; j <= c->p; ++j) {
@@ -172,7 +172,7 @@ static void rational_eval(const or_curve *c, const double *B, int span, int nd, 
         for (int e = 0; e < 3; ++e) A[d][e] = a[e];
         W[d] = wsum;
     }
-    static const double binom[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 2, 1}};
+    static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
     for (int d = 0; d <= nd; ++d)
         for (int e = 0; e < 3; ++e) {
             double v = A[d][e];
@@ -182,11 +182,11 @@ static void rational_eval(const or_curve *c, const double *B, int span, int nd, 
         }
 }
 
-/* C^{(d)}(u) = sum_k D^d N_{k,p}(u) P~_k for d = 0..nd; out[d*3 + c]
- * (rational curves: see rational_eval). */
+/* C^{(d)}(u) = sum_k D^d N_{k,p}(u) P~_k for d = 0..nd (nd <= 3);
+ * out[d*3 + c] (rational curves: see rational_eval). */
 void or_curve_eval(const or_curve *c, const double *U, double u, int nd, double *out)
 {
-    double B[3 * (OR_MAXP + 1)];
+    double B[4 * (OR_MAXP + 1)];
     int nb = or_nbasis(c->n, c->p, c->closed);
     int span = or_span(U, nb, c->p, u);
     or_basis(U, c->p, span, u, nd, B);
@@ -209,23 +209,40 @@ void or_curve_eval(const or_curve *c, const double *U, double u, int nd, double 
     }
 }
 
-/* Samples of a curve: pts/d1/d2 are ns x 3 (d1, d2 may be NULL). */
-void or_curve_samples(const or_curve *c, int ns, double *pts, double *d1, double *d2)
+/* Samples of a curve: pts/d1/d2/d3 are ns x 3 (d1, d2, d3 may be NULL). */
+void or_curve_samples3(const or_curve *c, int ns, double *pts, double *d1, double *d2, double *d3)
 {
     int nk = or_nknots(c->n, c->p, c->closed);
     double *U = (double *)malloc(sizeof(double) * (size_t)nk);
     or_knots(c->n, c->p, c->closed, c->knots, U);
-    int nd = d2 ? 2 : (d1 ? 1 : 0);
+    int nd = d3 ? 3 : (d2 ? 2 : (d1 ? 1 : 0));
     for (int i = 0; i < ns; ++i) {
         double u = or_param(c->n, c->p, c->closed, U, i, ns);
-        double o[9];
+        double o[12];
         or_curve_eval(c, U, u, nd, o);
         for (int e = 0; e < 3; ++e) {
             pts[3 * i + e] = o[e];
             if (d1) d1[3 * i + e] = o[3 + e];
             if (d2) d2[3 * i + e] = o[6 + e];
+            if (d3) d3[3 * i + e] = o[9 + e];
         }
     }
+    free(U);
+}
+
+void or_curve_samples(const or_curve *c, int ns, double *pts, double *d1, double *d2)
+{
+    or_curve_samples3(c, ns, pts, d1, d2, NULL);
+}
+
+/* Parameter domain [U_p, U_nb] of a curve. */
+static void domain_of(const or_curve *c, double *a, double *b)
+{
+    int nk = or_nknots(c->n, c->p, c->closed);
+    double *U = (double *)malloc(sizeof(double) * (size_t)nk);
+    or_knots(c->n, c->p, c->closed, c->knots, U);
+    *a = U[c->p];
+    *b = U[or_nbasis(c->n, c->p, c->closed)];
     free(U);
 }
 
@@ -444,6 +461,147 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
     }
 }
 
+/* ------------------------------------- F2 Frenet frame and sweep laws */
+
+/* Relative size below which C'' has no component normal to t: the Frenet
+ * normal is then undefined (straight pieces, inflections). */
+#define OR_FRENET_EPS 1e-8
+
+/*
+ * Frenet frame (pointwise): t as in O5 (tangents computed by or_frame's O5
+ * and passed in R's third column); the principal normal
+ *   n = normalize(C'' - (C''.t) t)   when |C'' - (C''.t) t| > 1e-8 |C''|,
+ * else the axis-rule vector of t (O6).  r = n, s = t x n (the binormal).
+ * omega_out[i] (may be NULL) = |C'| tau, the rate at which the Frenet frame
+ * turns about t relative to a rotation-minimizing one, with the torsion
+ *   tau = det(C', C'', C3) / |C' x C''|^2   (C3 the third derivative),
+ * and 0 where the normal fell back to the axis rule.
+ */
+void or_frenet(int nu, const double *d1, const double *d2, const double *d3, double *R, double *omega_out)
+{
+    for (int i = 0; i < nu; ++i) {
+        double *r = R + 9 * (size_t)i, *sv = r + 3;
+        const double *t = r + 6;
+        const double *C1 = d1 + 3 * i, *C2 = d2 + 3 * i, *C3 = d3 + 3 * i;
+        double ct = dot3(C2, t);
+        double q[3] = {C2[0] - ct * t[0], C2[1] - ct * t[1], C2[2] - ct * t[2]};
+        double nq = norm3(q);
+        double omega = 0.0;
+        if (nq > OR_FRENET_EPS * norm3(C2)) {
+            scale_div3(q, nq, r);
+            double k[3];
+            cross3(C1, C2, k);
+            double kk = dot3(k, k);
+            if (kk > 0.0) omega = norm3(C1) * (dot3(k, C3) / kk) * (MUT(17) ? 2.0 : 1.0);
+        } else {
+            double e_a[3] = {0.0, 0.0, 0.0};
+            e_a[axis_rule(t)] = 1.0;
+            project_out(e_a, t, r);
+        }
+        cross3(t, r, sv);
+        if (omega_out) omega_out[i] = omega;
+    }
+}
+
+/*
+ * Sweep laws along u.  A law curve L(l) (open B-spline whose control points
+ * hold (sigma, theta, unused)) gives at u-sample i the scale sigma and the
+ * twist angle theta (radians) of the profile: the profile point S becomes
+ *   p = sigma (cos th S_x - sin th S_y, sin th S_x + cos th S_y, S_z),
+ * i.e. the cross-section is rotated about t by theta and scaled by sigma.
+ * The law is sampled like the path (sample i of n_u on its own domain), so
+ * dl/du = (law domain length) / (path domain length).
+ *
+ * Rows [row0, row1) of the surface for a general frame R (nu x 9, rows r, s,
+ * t) whose derivatives are taken as
+ *   t' = (C'' - (C''.t) t) / |C'|,
+ *   r' = -(r.t') t + omega s,   s' = -(s.t') t - omega r,
+ * (omega = 0: rotation-minimizing; omega = |C'| tau: Frenet), and
+ *   X   = x + p_r r + p_s s + p_t t,
+ *   X_u = C' + p_r r' + p_s s' + p_t t' + p'_r r + p'_s s + p'_t t,
+ *   X_v = the scaled and rotated S'(v) in the frame,
+ *   N   = (X_v x X_u)/|X_v x X_u| (0 when 0 or not finite),
+ * all in world coordinates.  law (nu x 4: sigma, theta, dsigma/du,
+ * dtheta/du) and omega (nu) may be NULL (sigma = 1, theta = 0; omega = 0).
+ * kappa = |X_v| (|C'| + |p_r||r'| + |p_s||s'| + |p_t||t'| + |p'|_1) /
+ * |X_v x X_u|.
+ */
+void or_surface_rows_ex(int nu, int nv, int row0, int row1,
+                        const double *x, const double *d1, const double *d2, const double *R,
+                        const double *omega, const double *law, const double *S, const double *dS,
+                        double *pos, double *nrm, double *kappa)
+{
+    size_t N = (size_t)nu * (size_t)nv;
+    for (int i = row0; i < row1; ++i) {
+        const double *r = R + 9 * (size_t)i, *s = r + 3, *t = r + 6;
+        const double *xi = x + 3 * i, *C1 = d1 + 3 * i, *C2 = d2 + 3 * i;
+        double L = norm3(C1);
+        double tp[3] = {0.0, 0.0, 0.0}, rp[3], sp[3];
+        if (L > 0.0) {
+            double ct = dot3(C2, t);
+            for (int e = 0; e < 3; ++e) tp[e] = (C2[e] - ct * t[e]) / L;
+        }
+        double om = omega ? omega[i] : 0.0;
+        double rt = dot3(r, tp), st = dot3(s, tp);
+        for (int e = 0; e < 3; ++e) {
+            rp[e] = -rt * t[e] + (MUT(15) ? -om : om) * s[e];
+            sp[e] = -st * t[e] - om * r[e];
+        }
+        double sg = 1.0, th = 0.0, dsg = 0.0, dth = 0.0;
+        if (law) { sg = law[4 * i]; th = law[4 * i + 1]; dsg = law[4 * i + 2]; dth = law[4 * i + 3]; }
+        double c = cos(th), sn = sin(th);
+        double nrp = norm3(rp), nsp = norm3(sp), ntp = norm3(tp);
+        for (int j = 0; j < nv; ++j) {
+            const double *Sj = S + 3 * j, *dSj = dS + 3 * j;
+            double u0 = c * Sj[0] - sn * Sj[1], u1 = sn * Sj[0] + c * Sj[1];
+            double pr = sg * u0, ps = sg * u1, pt = sg * Sj[2];
+            /* d/du of sigma Rot(theta) S = sigma' Rot S + sigma theta' Rot J S, J = [[0,-1],[1,0]] */
+            double dpr = dsg * u0 - sg * dth * u1;
+            double dps = dsg * u1 + (MUT(16) ? -sg : sg) * dth * u0;
+            double dpt = dsg * Sj[2];
+            double qr = sg * (c * dSj[0] - sn * dSj[1]), qs = sg * (sn * dSj[0] + c * dSj[1]), qt = sg * dSj[2];
+            double X[3], Xu[3], Xv[3], cr[3];
+            for (int e = 0; e < 3; ++e) {
+                X[e] = xi[e] + pr * r[e] + ps * s[e] + pt * t[e];
+                Xv[e] = qr * r[e] + qs * s[e] + qt * t[e];
+                Xu[e] = C1[e] + pr * rp[e] + ps * sp[e] + pt * tp[e] + dpr * r[e] + dps * s[e] + dpt * t[e];
+            }
+            cross3(Xv, Xu, cr);
+            double nn = norm3(cr);
+            size_t v = (size_t)i * (size_t)nv + (size_t)j;
+            if (pos)
+                for (int e = 0; e < 3; ++e) pos[e * N + v] = X[e];
+            if (nrm) {
+                int ok = nn > 0.0 && isfinite(nn);
+                for (int e = 0; e < 3; ++e) nrm[e * N + v] = ok ? cr[e] / nn : 0.0;
+            }
+            if (kappa) {
+                double num = norm3(Xv) * (L + fabs(pr) * nrp + fabs(ps) * nsp + fabs(pt) * ntp +
+                                          fabs(dpr) + fabs(dps) + fabs(dpt));
+                kappa[v] = nn > 0.0 ? num / nn : INFINITY;
+            }
+        }
+    }
+}
+
+/* Law values at the nu u-samples: (sigma, theta, dsigma/du, dtheta/du). */
+static void law_samples(const or_curve *law, const or_curve *path, int nu, double *out)
+{
+    double *v = (double *)malloc(sizeof(double) * 6 * (size_t)nu);
+    or_curve_samples(law, nu, v, v + 3 * (size_t)nu, NULL);
+    double la, lb, pa, pb;
+    domain_of(law, &la, &lb);
+    domain_of(path, &pa, &pb);
+    double f = (lb - la) / (pb - pa);
+    for (int i = 0; i < nu; ++i) {
+        out[4 * i] = v[3 * i];
+        out[4 * i + 1] = v[3 * i + 1];
+        out[4 * i + 2] = v[3 * (size_t)nu + 3 * i] * f;
+        out[4 * i + 3] = v[3 * (size_t)nu + 3 * i + 1] * f;
+    }
+    free(v);
+}
+
 /* ---------------------------------------------------- O1-O8 a whole sweep */
 
 /* Unit direction of the first nonzero leg P_{k+1} - P_k, else e_z. */
@@ -483,6 +641,44 @@ int or_sweep(const or_curve *path, const or_curve *prof, int nu, int nv,
     for (int i = row0; i < row1; ++i)
         or_surface_rows(nu, nv, i, i + 1, x, d1, d2, R, S, dS, pos, nrm, kappa, NULL, NULL);
     free(S);
+    if (!frame_out) free(R);
+    free(x);
+    return nf;
+}
+
+/*
+ * Whole sweep with a frame mode (0 rotation-minimizing, 1 Frenet) and an
+ * optional law curve (NULL: none).  Same outputs as or_sweep (omega_out,
+ * nu values, may be NULL); with mode 0 and no law the result equals
+ * or_sweep's up to rounding (the surface derivative is then assembled in
+ * world instead of frame coordinates).
+ */
+int or_sweep_ex(const or_curve *path, const or_curve *prof, int nu, int nv,
+                const double *n0, int reorth, int mode, const or_curve *law, int row0, int row1,
+                double *pos, double *nrm, double *kappa, double *frame_out, double *omega_out)
+{
+    if (nu < 2 || nv < 1 || path->closed || (law && law->closed)) return -1;
+    double *x = (double *)malloc(sizeof(double) * 12 * (size_t)nu);
+    double *d1 = x + 3 * (size_t)nu, *d2 = x + 6 * (size_t)nu, *d3 = x + 9 * (size_t)nu;
+    double *R = frame_out ? frame_out : (double *)malloc(sizeof(double) * 9 * (size_t)nu);
+    double *om = omega_out ? omega_out : (double *)malloc(sizeof(double) * (size_t)nu);
+    double *lw = law ? (double *)malloc(sizeof(double) * 4 * (size_t)nu) : NULL;
+    double *S = (double *)malloc(sizeof(double) * 6 * (size_t)nv);
+    double *dS = S + 3 * (size_t)nv;
+    or_curve_samples3(path, nu, x, d1, d2, d3);
+    or_curve_samples(prof, nv, S, dS, NULL);
+    double ft[3];
+    first_leg(path, ft);
+    int nf = or_frame(nu, x, d1, ft, n0, reorth, R);   /* tangents (and the RMF) */
+    if (mode == 1) or_frenet(nu, d1, d2, d3, R, om);
+    else for (int i = 0; i < nu; ++i) om[i] = 0.0;
+    if (lw) law_samples(law, path, nu, lw);
+    #pragma omp parallel for schedule(static)
+    for (int i = row0; i < row1; ++i)
+        or_surface_rows_ex(nu, nv, i, i + 1, x, d1, d2, R, om, lw, S, dS, pos, nrm, kappa);
+    free(S);
+    if (lw) free(lw);
+    if (!omega_out) free(om);
     if (!frame_out) free(R);
     free(x);
     return nf;

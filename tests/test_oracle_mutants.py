@@ -20,6 +20,9 @@ harness on the unmodified source must pass.  Mistakes planted:
  12  clamped knots k/(n-p+1)
  13  frame: s = r x t (left-handed)
  14  finite differences divided by h instead of 2h
+ 15  frame derivative: sign of the omega term in r'
+ 16  twist law: sign of sigma theta' in the derivative of the profile point
+ 17  Frenet torsion rate doubled
 """
 
 from __future__ import annotations
@@ -35,8 +38,8 @@ from oracle import build as obuild
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_bspline.py", "tests/test_oracle_frame.py", "tests/test_oracle_grad.py",
-             "tests/test_oracle_rational.py"]
-MUTANTS = list(range(1, 15))
+             "tests/test_oracle_rational.py", "tests/test_oracle_frenet_laws.py"]
+MUTANTS = list(range(1, 18))
 
 
 def _run_pins(lib_path: str) -> subprocess.CompletedProcess:
