@@ -76,7 +76,7 @@
 extern "C" {
 #endif
 
-#define SWEEP_VERSION 101  /* major*100 + minor */
+#define SWEEP_VERSION 102  /* major*100 + minor */
 #define SWEEP_MAX_DEGREE 7
 
 typedef enum {
@@ -95,8 +95,30 @@ typedef enum {
 
 typedef enum { SWEEP_F32 = 0, SWEEP_F64 = 1 } sweep_precision;
 
+/*
+ * Frame modes.  SWEEP_FRAME_RMF: the rotation-minimizing frame above.
+ * SWEEP_FRAME_FRENET: the Frenet frame of the path, pointwise: r = the
+ * principal normal normalize(C'' - (C''.t) t), s = t x r (the binormal);
+ * where |C'' - (C''.t) t| <= 1e-8 |C''| (straight pieces, inflections) r is
+ * the axis-rule vector of t.  The surface normal then uses the Frenet frame's
+ * derivative: the frame turns about t at the rate omega = |C'| tau relative
+ * to a rotation-minimizing frame, with the torsion
+ * tau = det(C', C'', C3)/|C' x C''|^2 (C3 the third derivative; omega = 0
+ * where the axis rule was used).
+ *
+ * Sweep law (sweep_options.law): an open B-spline L(l) whose control points
+ * hold (sigma, theta, unused), sampled like the path (sample i of n_u on its
+ * own domain).  At u-sample i the profile point S becomes
+ *     sigma (cos th S_x - sin th S_y, sin th S_x + cos th S_y, S_z),
+ * i.e. the cross-section is scaled by sigma and turned about t by theta
+ * (radians); the surface normal includes d(sigma)/du and d(theta)/du.
+ * Frame modes and laws are supported by sweep_eval (and sweep_autotune);
+ * the other entry points return SWEEP_ERR_UNSUPPORTED for them.
+ */
+typedef enum { SWEEP_FRAME_RMF = 0, SWEEP_FRAME_FRENET = 1 } sweep_frame_mode;
+
 /* A B-spline curve. */
-typedef struct {
+typedef struct sweep_curve_s {
     int32_t n_ctrl;      /* control points (for a closed curve: the m distinct ones) */
     int32_t degree;      /* 1..SWEEP_MAX_DEGREE */
     int32_t closed;      /* 0 open, 1 closed periodic uniform (profiles only) */
@@ -122,7 +144,8 @@ typedef struct {
     double initial_normal[3];
     int32_t tile_config;      /* -1 (default): tuned/automatic; >= 0 a fixed
                                  surface-kernel configuration (sweep_tile_config_count) */
-    int32_t reserved;
+    int32_t frame_mode;       /* SWEEP_FRAME_RMF (default) or SWEEP_FRAME_FRENET, see above */
+    const struct sweep_curve_s *law; /* NULL (default) or a sweep law, see above */
 } sweep_options;
 
 /* A batch of independent sweeps.  Per-sweep arrays are HOST memory with

@@ -20,6 +20,7 @@ STATUS = {
     -7: "SWEEP_ERR_WORKSPACE", -8: "SWEEP_ERR_UNSUPPORTED", -9: "SWEEP_ERR_HIP", -10: "SWEEP_ERR_BAD_OPTION",
 }
 SWEEP_F32, SWEEP_F64 = 0, 1
+SWEEP_FRAME_RMF, SWEEP_FRAME_FRENET = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -33,7 +34,8 @@ class SweepCurve(C.Structure):
 class SweepOptions(C.Structure):
     _fields_ = [("out_precision", C.c_int32), ("frame_precision", C.c_int32),
                 ("reorthonormalize", C.c_int32), ("has_initial_normal", C.c_int32),
-                ("initial_normal", C.c_double * 3), ("tile_config", C.c_int32), ("reserved", C.c_int32)]
+                ("initial_normal", C.c_double * 3), ("tile_config", C.c_int32), ("frame_mode", C.c_int32),
+                ("law", C.c_void_p)]
 
 
 class SweepBatch(C.Structure):

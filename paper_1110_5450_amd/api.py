@@ -54,8 +54,25 @@ def _knots_ptr(knots) -> Tuple[Optional[np.ndarray], Optional[C.POINTER(C.c_doub
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+_FRAME_MODES = {"rmf": L.SWEEP_FRAME_RMF, "frenet": L.SWEEP_FRAME_FRENET}
+
+
+class Law:
+    """A sweep law: an open B-spline whose control points (device float64,
+    (n, 3)) hold (scale, twist angle in radians, unused) along the path;
+    degree, optional knot vector (host) and weights."""
+
+    def __init__(self, ctrl: torch.Tensor, degree: int, knots=None, weights=None):
+        self.ctrl = _check_ctrl(ctrl, "law ctrl")
+        self.degree = int(degree)
+        self._knots, kp = _knots_ptr(knots)
+        self.weights = _weights(weights, self.ctrl.shape[0], "law weights")
+        self.c = L.SweepCurve(self.ctrl.shape[0], self.degree, 0, 0, self.ctrl.data_ptr(), kp, _wptr(self.weights))
+
+
 def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
-                 initial_normal=None, tile_config: int = -1) -> L.SweepOptions:
+                 initial_normal=None, tile_config: int = -1, frame_mode: str = "rmf",
+                 law: Optional[Law] = None) -> L.SweepOptions:
     o = L.default_options()
     o.out_precision = _DT[out_dtype]
     o.frame_precision = _DT[frame_dtype]
@@ -65,6 +82,12 @@ def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonorm
         for k in range(3):
             o.initial_normal[k] = float(initial_normal[k])
     o.tile_config = int(tile_config)
+    if frame_mode not in _FRAME_MODES:
+        raise ValueError(f"frame_mode must be one of {sorted(_FRAME_MODES)}")
+    o.frame_mode = _FRAME_MODES[frame_mode]
+    if law is not None:
+        o.law = C.cast(C.pointer(law.c), C.c_void_p)
+        o._law_ref = law          # keeps the curve struct and its buffers alive
     return o
 
 
@@ -90,7 +113,7 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
                n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
                out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                initial_normal=None, tile_config: int = -1, normals: bool = True,
-               path_weights=None, prof_weights=None,
+               path_weights=None, prof_weights=None, frame_mode: str = "rmf", law: Optional[Law] = None,
                out: Optional[Tuple[torch.Tensor, Optional[torch.Tensor]]] = None,
                workspace: Optional[torch.Tensor] = None, stream=None):
     """Positions (3, n_u, n_v) and normals (or None) of one sweep; with
@@ -103,7 +126,7 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
     qk, qkp = _knots_ptr(prof_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         # invalid metadata: let the call report the reason
@@ -130,7 +153,7 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
                    n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
                    out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                    initial_normal=None, normals: bool = True, path_weights=None, prof_weights=None,
-                   stream=None):
+                   frame_mode: str = "rmf", law: Optional[Law] = None, stream=None):
     """Times every surface configuration on this sweep and records the
     fastest for its shape class; returns (best_config, best_ms, pos, nrm)."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
@@ -141,7 +164,7 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
     qk, qkp = _knots_ptr(prof_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode, law=law)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         L.check(L.sweep_eval(path, prof, int(n_u), int(n_v), opt, 0, 0, 0, 0, 0))
@@ -164,14 +187,15 @@ def surface_config_for(n_u: int, n_v: int, out_dtype=torch.float32) -> int:
 
 def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
                  out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
-                 initial_normal=None, path_weights=None, workspace: Optional[torch.Tensor] = None,
-                 stream=None) -> torch.Tensor:
-    """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame."""
+                 initial_normal=None, path_weights=None, frame_mode: str = "rmf",
+                 workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame
+    (rotation-minimizing; other frame modes are sweep_eval only)."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
     pw = _weights(path_weights, pc.shape[0], "path_weights")
     pk, pkp = _knots_ptr(path_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode)
     ws_bytes = L.sweep_frames_workspace_size(path, int(n_u), opt)
     if ws_bytes == 0:
         L.check(L.sweep_frames(path, int(n_u), opt, 0, 0, 0, 0))
@@ -184,10 +208,12 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
 
 
 def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree: int, n_u: int, n_v: int, *,
-                        prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
+                        prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64,
+                        frame_mode: str = "rmf", law: Optional[Law] = None) -> int:
     path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None, None)
     prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None, None)
-    return L.sweep_eval_workspace_size(path, prof, n_u, n_v, make_options(out_dtype, frame_dtype))
+    return L.sweep_eval_workspace_size(path, prof, n_u, n_v,
+                                       make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law))
 
 
 class Batch:
@@ -306,10 +332,13 @@ class Batch:
 
 def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
                        reorthonormalize: bool = True, initial_normal=None, tile_config: int = -1,
-                       normals: bool = True, out=None, workspace: Optional[torch.Tensor] = None, stream=None):
-    """Flat positions (3 * total vertices) and normals (or None) of a batch."""
+                       normals: bool = True, frame_mode: str = "rmf", out=None,
+                       workspace: Optional[torch.Tensor] = None, stream=None):
+    """Flat positions and normals (or None) of a batch in the padded batched
+    layout (rotation-minimizing frames; other frame modes are sweep_eval
+    only)."""
     b = batch.c_struct()
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode)
     ws_bytes = L.sweep_batched_workspace_size(b, opt)
     if ws_bytes == 0:
         L.check(L.sweep_eval_batched(b, opt, 0, 0, 0, 0, 0))

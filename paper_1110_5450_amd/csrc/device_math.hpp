@@ -134,12 +134,13 @@ __device__ __forceinline__ int sample_span(const DCurve& c, int i, int ns, doubl
 
 // Rational curve (NURBS Book ch. 4): the homogeneous curve (w P, w) has the
 // same basis and derivative nets, giving A, A', A'' and W, W', W''; then
-// C = A / W, C' = (A' - W' C) / W, C'' = (A'' - 2 W' C' - W'' C) / W.
+// C = A / W, C' = (A' - W' C) / W, C'' = (A'' - 2 W' C' - W'' C) / W, and
+// the third derivative C3 = (A3 - 3 W' C'' - 3 W'' C' - W3 C) / W.
 // Uk, B, D1, D2 as in curve_derivs; Pt the P+1 control points of span s.
 template <int P, int ND>
 __device__ __forceinline__ void rational_derivs(const DCurve& c, int s, const double* Uk, const double* B,
-                                                const double* D1, const double* D2, const V3<double>* Pt,
-                                                V3<double>* out)
+                                                const double* D1, const double* D2, const double* D3,
+                                                const V3<double>* Pt, V3<double>* out)
 {
     V3<double> Hw[P + 1];
     double wt[P + 1];
@@ -172,15 +173,33 @@ __device__ __forceinline__ void rational_derivs(const DCurve& c, int s, const do
         if (ND >= 2) {
             V3<double> A2 = mk(0.0, 0.0, 0.0);
             double W2 = 0.0;
+            V3<double> Q2[P > 1 ? P - 1 : 1];
+            double q2[P > 1 ? P - 1 : 1];
             if (P >= 2) {
 #pragma unroll
                 for (int j = 0; j + 1 < P; ++j) {
                     const double f = (double)(P - 1) / (Uk[P + j] - Uk[j + 1]);
-                    A2 = A2 + D2[j] * (f * (Q1[j + 1] - Q1[j]));
-                    W2 = W2 + D2[j] * (f * (q1[j + 1] - q1[j]));
+                    Q2[j] = f * (Q1[j + 1] - Q1[j]);
+                    q2[j] = f * (q1[j + 1] - q1[j]);
+                    A2 = A2 + D2[j] * Q2[j];
+                    W2 = W2 + D2[j] * q2[j];
                 }
             }
-            out[2] = divs(A2 - (2.0 * W1) * C1 - W2 * C0, W0);
+            const V3<double> C2 = divs(A2 - (2.0 * W1) * C1 - W2 * C0, W0);
+            out[2] = C2;
+            if (ND >= 3) {
+                V3<double> A3 = mk(0.0, 0.0, 0.0);
+                double W3 = 0.0;
+                if (P >= 3) {
+#pragma unroll
+                    for (int j = 0; j + 2 < P; ++j) {
+                        const double f = (double)(P - 2) / (Uk[P + j] - Uk[j + 2]);
+                        A3 = A3 + D3[j] * (f * (Q2[j + 1] - Q2[j]));
+                        W3 = W3 + D3[j] * (f * (q2[j + 1] - q2[j]));
+                    }
+                }
+                out[3] = divs(A3 - (3.0 * W1) * C2 - (3.0 * W2) * C1 - W3 * C0, W0);
+            }
         }
     }
 }
@@ -203,9 +222,11 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V
     double B[P + 1];
     double D1[P > 0 ? P : 1];
     double D2[P > 1 ? P - 1 : 1];
+    double D3[P > 2 ? P - 2 : 1];
     B[0] = 1.0;
     if (P - 1 == 0) D1[0] = 1.0;
     if (P - 2 == 0) D2[0] = 1.0;
+    if (ND >= 3 && P - 3 == 0) D3[0] = 1.0;
 #pragma unroll
     for (int q = 1; q <= P; ++q) {
         // B holds N_{s-q+1+j, q-1}, j = 0..q-1; build N_{s-q+j, q}, j = 0..q.
@@ -229,12 +250,16 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V
 #pragma unroll
             for (int j = 0; j <= q; ++j) D2[j] = B[j];
         }
+        if (ND >= 3 && q == P - 3) {
+#pragma unroll
+            for (int j = 0; j <= q; ++j) D3[j] = B[j];
+        }
     }
     V3<double> Pt[P + 1];
 #pragma unroll
     for (int j = 0; j <= P; ++j) Pt[j] = ctrl_pt(c, s - P + j);
     if (c.w) {
-        rational_derivs<P, ND>(c, s, Uk, B, D1, D2, Pt, out);
+        rational_derivs<P, ND>(c, s, Uk, B, D1, D2, D3, Pt, out);
         return;
     }
     V3<double> C0 = mk(0.0, 0.0, 0.0);
@@ -251,14 +276,28 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V
         out[1] = C1;
         if (ND >= 2) {
             V3<double> C2 = mk(0.0, 0.0, 0.0);
+            V3<double> R2[P > 1 ? P - 1 : 1];
             if (P >= 2) {
 #pragma unroll
                 for (int j = 0; j + 1 < P; ++j) {
                     const V3<double> R = ((double)(P - 1) / (Uk[P + j] - Uk[j + 1])) * (Q1[j + 1] - Q1[j]);
                     C2 = C2 + D2[j] * R;
+                    R2[j] = R;
                 }
             }
             out[2] = C2;
+            if (ND >= 3) {
+                // third derivative net (P-2)(R_{k+1} - R_k)/(U_{k+P+1} - U_{k+3})
+                V3<double> C3 = mk(0.0, 0.0, 0.0);
+                if (P >= 3) {
+#pragma unroll
+                    for (int j = 0; j + 2 < P; ++j) {
+                        const V3<double> T3 = ((double)(P - 2) / (Uk[P + j] - Uk[j + 2])) * (R2[j + 1] - R2[j]);
+                        C3 = C3 + D3[j] * T3;
+                    }
+                }
+                out[3] = C3;
+            }
         }
     }
 #undef UK

@@ -125,6 +125,91 @@ __device__ __forceinline__ void write_row(const StepInputs& s, const M3<F>& ex, 
     q[12] = (T)L; q[13] = (T)a; q[14] = (T)b; q[15] = T(0);
 }
 
+// ------------------------------------------------ frame modes and laws
+
+// Extended row record (kRowExt values), used with the Frenet frame mode or a
+// sweep law: x (3), r (3), s (3), t (3), |C'|, a, b, omega, A (2x2 row-major),
+// A' (2x2), sigma, sigma', 0 x 6.  omega is the rate (per unit u) at which
+// the frame turns about t relative to a rotation-minimizing one (0 for the
+// rotation-minimizing frame, |C'| tau for Frenet); A = sigma Rot(theta) maps
+// the profile's (x, y) into the (r, s) plane, A' = dA/du; sigma scales the
+// profile's z.  (kRowExt is declared with the launchers.)
+
+// Relative size below which C'' has no component normal to t (no Frenet
+// normal: the axis rule is used and omega = 0).
+constexpr double kFrenetEps = 1e-8;
+
+// Law value at a u-sample: scale, twist angle and their u-derivatives.
+struct LawSample {
+    double sg, th, dsg, dth;
+};
+
+template <class F, class T>
+__device__ __forceinline__ void write_row_ext(const StepInputs& s, const M3<F>& ex, const F* rb, V3<double> C1,
+                                              V3<double> C2, V3<double> C3, int frenet, LawSample lw, int reorth,
+                                              T* __restrict__ q)
+{
+    const V3<F> t = cvt<F>(s.t0);
+    V3<F> r;
+    double omega = 0.0;
+    if (frenet) {
+        // principal normal from C'' (pointwise, FP64), torsion rate from C'''
+        const double ct = dot(C2, s.t0);
+        const V3<double> qv = C2 - ct * s.t0;
+        const double nq = sqrt(dot(qv, qv));
+        V3<double> rd;
+        if (nq > kFrenetEps * sqrt(dot(C2, C2))) {
+            rd = divs(qv, nq);
+            const V3<double> k = cross(C1, C2);
+            const double kk = dot(k, k);
+            if (kk > 0.0) omega = sqrt(dot(C1, C1)) * (dot(k, C3) / kk);
+        } else {
+            rd = axis_normal<double>(s.t0);
+        }
+        r = cvt<F>(rd);
+    } else {
+        r = apply(ex, mk(rb[0], rb[1], rb[2]));
+        if (reorth) {
+            const V3<F> w = r - dot(r, t) * t;
+            r = divs(w, (F)sqrt(dot(w, w)));
+        }
+    }
+    const V3<F> sv = cross(t, r);
+    const double L = sqrt(dot(C1, C1));
+    F a = F(0), b = F(0);
+    if (L > 0.0) {
+        const V3<F> c2 = cvt<F>(C2);
+        a = dot(r, c2) / (F)L;
+        b = dot(sv, c2) / (F)L;
+    }
+    const double c = cos(lw.th), sn = sin(lw.th);
+    q[0] = (T)s.x0.x; q[1] = (T)s.x0.y; q[2] = (T)s.x0.z;
+    q[3] = (T)r.x; q[4] = (T)r.y; q[5] = (T)r.z;
+    q[6] = (T)sv.x; q[7] = (T)sv.y; q[8] = (T)sv.z;
+    q[9] = (T)t.x; q[10] = (T)t.y; q[11] = (T)t.z;
+    q[12] = (T)L; q[13] = (T)a; q[14] = (T)b; q[15] = (T)omega;
+    q[16] = (T)(lw.sg * c); q[17] = (T)(-lw.sg * sn); q[18] = (T)(lw.sg * sn); q[19] = (T)(lw.sg * c);
+    const double gc = lw.dsg * c - lw.sg * lw.dth * sn, gs = lw.dsg * sn + lw.sg * lw.dth * c;
+    q[20] = (T)gc; q[21] = (T)(-gs); q[22] = (T)gs; q[23] = (T)gc;
+    q[24] = (T)lw.sg; q[25] = (T)lw.dsg;
+#pragma unroll
+    for (int e = 26; e < kRowExt; ++e) q[e] = T(0);
+}
+
+// Law at u-sample i of n_u: the law curve holds (sigma, theta, -) and is
+// sampled like the path; dl/du = du_scale.  No law: sigma = 1, theta = 0.
+__device__ __forceinline__ LawSample law_at(const DCurve* law, int i, int n_u, double du_scale)
+{
+    LawSample lw{1.0, 0.0, 0.0, 0.0};
+    if (law) {
+        V3<double> o[2];
+        sample_derivs_any<1>(*law, i, n_u, o);
+        lw.sg = o[0].x; lw.th = o[0].y;
+        lw.dsg = o[1].x * du_scale; lw.dth = o[1].y * du_scale;
+    }
+    return lw;
+}
+
 // Profile record of sample j: S (3), S' (3), 0, 0.
 template <class T>
 __device__ __forceinline__ void write_profile(const DCurve& prof, int j, int n_v, T* __restrict__ tab)

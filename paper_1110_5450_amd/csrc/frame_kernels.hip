@@ -188,6 +188,37 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply(const double* __restrict
                     rows + 16 * (size_t)i);
 }
 
+// Extended row records (Frenet frame mode and/or a sweep law): the same
+// block scan for the rotation-minimizing frame; the Frenet mode replaces r by
+// the principal normal and needs the third derivative of the path, which is
+// evaluated here (the samples hold x, C', C'' only).
+template <class F, class T>
+__global__ __launch_bounds__(kBlock) void k_frame_apply_ext(const double* __restrict__ smp, int n_u,
+                                                            const int* __restrict__ chunk_lv,
+                                                            const double* __restrict__ fallback_t,
+                                                            const F* __restrict__ r_in, int reorth, DCurve path,
+                                                            int frenet, DCurve law, int has_law, double du_scale,
+                                                            T* __restrict__ rows)
+{
+    __shared__ int lds_i[kWaves];
+    __shared__ M3<F> lds_m[kWaves];
+    const size_t nu = (size_t)n_u;
+    const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, blockIdx.x);
+    M3<F> total;
+    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m, total);
+    const int i = blockIdx.x * kChunk + threadIdx.x;
+    if (i >= n_u) return;
+    V3<double> C3 = mk(0.0, 0.0, 0.0);
+    if (frenet) {
+        V3<double> o[4];
+        sample_derivs_any<3>(path, i, n_u, o);
+        C3 = o[3];
+    }
+    const LawSample lw = law_at(has_law ? &law : nullptr, i, n_u, du_scale);
+    write_row_ext<F, T>(s, ex, r_in + 3 * (size_t)blockIdx.x, smp_get(smp, nu, 1, i), smp_get(smp, nu, 2, i), C3,
+                        frenet, lw, reorth, rows + kRowExt * (size_t)i);
+}
+
 // ------------------------------------------------------------- launchers
 
 int frame_chunk_size() { return kChunk; }
@@ -213,20 +244,24 @@ hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v,
 template <class F, class T>
 hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const int* chunk_fix,
                         const double* fallback_t, InitialNormal n0, int reorth, F* agg, F* r_in, T* rows,
-                        hipStream_t st)
+                        hipStream_t st, const FrameExt* ext)
 {
     const int nc = (n_u + kChunk - 1) / kChunk;
     hipLaunchKernelGGL(k_frame_carry<F>, dim3(1), dim3(kBlock), 0, st, agg, nc, smp, n_u, chunk_lv, chunk_fix,
                        fallback_t, n0, r_in);
-    hipLaunchKernelGGL((k_frame_apply<F, T>), dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t, r_in,
-                       reorth, rows);
+    if (ext)
+        hipLaunchKernelGGL((k_frame_apply_ext<F, T>), dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t,
+                           r_in, reorth, ext->path, ext->frenet, ext->law, ext->has_law, ext->du_scale, rows);
+    else
+        hipLaunchKernelGGL((k_frame_apply<F, T>), dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, fallback_t,
+                           r_in, reorth, rows);
     return hipGetLastError();
 }
 #define SWEEP_INST(F, T)                                                                                          \
     template hipError_t launch_prep<F, T>(const DCurve&, int, const DCurve&, int, double*, int*, int*, double*, F*, \
                                           T*, hipStream_t);                                                        \
     template hipError_t launch_frame<F, T>(const double*, int, const int*, const int*, const double*, InitialNormal, \
-                                           int, F*, F*, T*, hipStream_t);
+                                           int, F*, F*, T*, hipStream_t, const FrameExt*);
 SWEEP_INST(double, float)
 SWEEP_INST(double, double)
 SWEEP_INST(float, float)

@@ -22,11 +22,24 @@ int frame_chunk_size();
 template <class F, class T>
 hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
                        int* chunk_fix, double* fallback_t, F* agg, T* ptab, hipStream_t st);
-// Carry scan and row table (16 values per u-row).
+// Values per extended row record (frame modes, sweep laws).
+constexpr int kRowExt = 32;
+
+// Frenet frame mode and sweep law of a single sweep (extended row records).
+struct FrameExt {
+    DCurve path;       // the path (its third derivative, Frenet mode)
+    int frenet;        // 1: Frenet frame
+    DCurve law;        // law curve (sigma, theta, -), valid when has_law
+    int has_law;
+    double du_scale;   // d(law parameter)/du
+};
+
+// Carry scan and row table: 16 values per u-row, or 32 (extended records)
+// when ext is given.
 template <class F, class T>
 hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const int* chunk_fix,
                         const double* fallback_t, InitialNormal n0, int reorth, F* agg, F* r_in, T* rows,
-                        hipStream_t st);
+                        hipStream_t st, const FrameExt* ext = nullptr);
 
 // Surface write of one sweep from its row table (16 values per u-row) and
 // profile table (8 values per v-sample).
@@ -37,9 +50,10 @@ struct SurfaceConfig {
     int nontemporal;    // nontemporal stores
 };
 
+// ext: row records of 32 values (frame modes, laws) instead of 16.
 template <class T>
 hipError_t launch_surface(const T* rows, const T* prof, int n_u, int n_v, T* pos, T* nrm,
-                          const SurfaceConfig& cfg, hipStream_t st);
+                          const SurfaceConfig& cfg, hipStream_t st, bool ext = false);
 
 
 // ----------------------------------------------------------------- batched

@@ -46,6 +46,49 @@ __device__ __forceinline__ void vertex(const T* row, T Sx, T Sy, T Sz, T Dx, T D
     Nn[2] = nx * r2 + ny * s2 + nz * t2;
 }
 
+// One vertex from an extended row record (32 values: x r s t L a b omega
+// A A' sigma sigma') and a profile record (S S'): the profile point in the
+// frame is p = (A (S_x, S_y), sigma S_z), its u-derivative
+// p' = (A' (S_x, S_y), sigma' S_z), and in frame coordinates
+//   X_v = (A (S'_x, S'_y), sigma S'_z),
+//   X_u = (p'_r + p_t a - omega p_s, p'_s + p_t b + omega p_r,
+//          L - p_r a - p_s b + p'_t).
+template <class T>
+__device__ __forceinline__ void vertex_ext(const T* row, T Sx, T Sy, T Sz, T Dx, T Dy, T Dz, T* X, T* Nn)
+{
+    const T x0 = row[0], x1 = row[1], x2 = row[2];
+    const T r0 = row[3], r1 = row[4], r2 = row[5];
+    const T s0 = row[6], s1 = row[7], s2 = row[8];
+    const T t0 = row[9], t1 = row[10], t2 = row[11];
+    const T L = row[12], a = row[13], b = row[14], om = row[15];
+    const T A00 = row[16], A01 = row[17], A10 = row[18], A11 = row[19];
+    const T G00 = row[20], G01 = row[21], G10 = row[22], G11 = row[23];
+    const T sg = row[24], dsg = row[25];
+    const T pr = A00 * Sx + A01 * Sy, ps = A10 * Sx + A11 * Sy, pt = sg * Sz;
+    const T dpr = G00 * Sx + G01 * Sy, dps = G10 * Sx + G11 * Sy, dpt = dsg * Sz;
+    X[0] = x0 + pr * r0 + ps * s0 + pt * t0;
+    X[1] = x1 + pr * r1 + ps * s1 + pt * t1;
+    X[2] = x2 + pr * r2 + ps * s2 + pt * t2;
+    const T qx = A00 * Dx + A01 * Dy, qy = A10 * Dx + A11 * Dy, qz = sg * Dz;
+    const T ux = dpr + pt * a - om * ps, uy = dps + pt * b + om * pr, uz = L - pr * a - ps * b + dpt;
+    T nx = qy * uz - qz * uy;
+    T ny = qz * ux - qx * uz;
+    T nz = qx * uy - qy * ux;
+    const T inv = inv_norm<T>(nx * nx + ny * ny + nz * nz);
+    nx *= inv; ny *= inv; nz *= inv;
+    Nn[0] = nx * r0 + ny * s0 + nz * t0;
+    Nn[1] = nx * r1 + ny * s1 + nz * t1;
+    Nn[2] = nx * r2 + ny * s2 + nz * t2;
+}
+
+// Row record length RL (16 or 32) selects the vertex formula.
+template <int RL, class T>
+__device__ __forceinline__ void vertex_rl(const T* row, T Sx, T Sy, T Sz, T Dx, T Dy, T Dz, T* X, T* Nn)
+{
+    if (RL == 16) vertex<T>(row, Sx, Sy, Sz, Dx, Dy, Dz, X, Nn);
+    else vertex_ext<T>(row, Sx, Sy, Sz, Dx, Dy, Dz, X, Nn);
+}
+
 template <bool NT, class T>
 __device__ __forceinline__ void store6(T* __restrict__ pos, T* __restrict__ nrm, size_t N, size_t v,
                                        const T* X, const T* Nn, bool wn)

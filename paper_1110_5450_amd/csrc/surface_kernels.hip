@@ -24,7 +24,7 @@
 
 namespace sweep {
 
-template <class T, bool NRM, bool NT>
+template <class T, bool NRM, bool NT, int RL>
 __global__ __launch_bounds__(kBlock) void k_surface_tiles(const T* __restrict__ rows, const T* __restrict__ prof,
                                                           int n_u, int n_v, int R, int n_col_tiles,
                                                           T* __restrict__ pos, T* __restrict__ nrm)
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_surface_tiles(const T* __restrict__ 
     const size_t N = (size_t)n_u * (size_t)n_v;
     for (int i = i0; i < i1; ++i) {
         T X[3], Nn[3];
-        vertex<T>(rows + 16 * (size_t)i, Sx, Sy, Sz, Dx, Dy, Dz, X, Nn);
+        vertex_rl<RL, T>(rows + RL * (size_t)i, Sx, Sy, Sz, Dx, Dy, Dz, X, Nn);
         store6<NT>(pos, nrm, N, (size_t)i * (size_t)n_v + (size_t)j, X, Nn, NRM);
     }
 }
@@ -63,12 +63,12 @@ void fastdiv_constants(int d, unsigned long long* m, int* shift)
     *shift = f.shift;
 }
 
-template <class T, bool NRM, bool NT, int K>
+template <class T, bool NRM, bool NT, int K, int RL>
 __global__ __launch_bounds__(kBlock) void k_surface_linear(const T* __restrict__ rows, const T* __restrict__ prof,
                                                            int n_u, int n_v, FastDiv dv,
                                                            T* __restrict__ pos, T* __restrict__ nrm)
 {
-    __shared__ T lrow[kMaxLdsRows * 16];
+    __shared__ T lrow[kMaxLdsRows * RL];
     const long long N = (long long)n_u * (long long)n_v;
     const long long v0 = (long long)blockIdx.x * (kBlock * K);
     const long long vlast = min(N, v0 + kBlock * K) - 1;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_surface_linear(const T* __restrict__
     const int nrow = fdiv((unsigned)vlast, dv) - ilo + 1;
     const bool staged = nrow <= kMaxLdsRows;
     if (staged)
-        for (int e = threadIdx.x; e < nrow * 16; e += kBlock) lrow[e] = rows[16 * (size_t)ilo + e];
+        for (int e = threadIdx.x; e < nrow * RL; e += kBlock) lrow[e] = rows[RL * (size_t)ilo + e];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -86,14 +86,14 @@ __global__ __launch_bounds__(kBlock) void k_surface_linear(const T* __restrict__
             const int j = (int)v - i * n_v;
             const T* q = prof + 8 * (size_t)j;
             T X[3], Nn[3];
-            const T* row = staged ? lrow + 16 * (i - ilo) : rows + 16 * (size_t)i;
-            vertex<T>(row, q[0], q[1], q[2], q[3], q[4], q[5], X, Nn);
+            const T* row = staged ? lrow + RL * (i - ilo) : rows + RL * (size_t)i;
+            vertex_rl<RL, T>(row, q[0], q[1], q[2], q[3], q[4], q[5], X, Nn);
             store6<NT>(pos, nrm, (size_t)N, (size_t)v, X, Nn, NRM);
         }
     }
 }
 
-template <class T, bool NRM, bool NT>
+template <class T, bool NRM, bool NT, int RL>
 static void launch_surface_t(const T* rows, const T* prof, int n_u, int n_v, T* pos, T* nrm,
                              const SurfaceConfig& cfg, hipStream_t st)
 {
@@ -101,7 +101,7 @@ static void launch_surface_t(const T* rows, const T* prof, int n_u, int n_v, T* 
         const int n_col_tiles = (n_v + kBlock - 1) / kBlock;
         const int R = cfg.rows_per_block > 0 ? cfg.rows_per_block : 1;
         const long long grid = (long long)n_col_tiles * ((n_u + R - 1) / R);
-        hipLaunchKernelGGL((k_surface_tiles<T, NRM, NT>), dim3((unsigned)grid), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_surface_tiles<T, NRM, NT, RL>), dim3((unsigned)grid), dim3(kBlock), 0, st,
                            rows, prof, n_u, n_v, R, n_col_tiles, pos, nrm);
     } else {
         const long long N = (long long)n_u * n_v;
@@ -109,31 +109,39 @@ static void launch_surface_t(const T* rows, const T* prof, int n_u, int n_v, T* 
         const int K = cfg.tile_vertices / kBlock;
         const unsigned grid = (unsigned)((N + cfg.tile_vertices - 1) / cfg.tile_vertices);
         switch (K) {
-        case 1: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 1>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
-        case 2: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 2>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
-        case 4: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 4>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
-        default: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 8>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
+        case 1: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 1, RL>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
+        case 2: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 2, RL>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
+        case 4: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 4, RL>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
+        default: hipLaunchKernelGGL((k_surface_linear<T, NRM, NT, 8, RL>), dim3(grid), dim3(kBlock), 0, st, rows, prof, n_u, n_v, dv, pos, nrm); break;
         }
+    }
+}
+
+template <class T, int RL>
+static void launch_surface_rl(const T* rows, const T* prof, int n_u, int n_v, T* pos, T* nrm,
+                              const SurfaceConfig& cfg, hipStream_t st)
+{
+    const bool wn = nrm != nullptr;
+    if (cfg.nontemporal) {
+        if (wn) launch_surface_t<T, true, true, RL>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
+        else launch_surface_t<T, false, true, RL>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
+    } else {
+        if (wn) launch_surface_t<T, true, false, RL>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
+        else launch_surface_t<T, false, false, RL>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
     }
 }
 
 template <class T>
 hipError_t launch_surface(const T* rows, const T* prof, int n_u, int n_v, T* pos, T* nrm,
-                          const SurfaceConfig& cfg, hipStream_t st)
+                          const SurfaceConfig& cfg, hipStream_t st, bool ext)
 {
-    const bool wn = nrm != nullptr;
-    if (cfg.nontemporal) {
-        if (wn) launch_surface_t<T, true, true>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
-        else launch_surface_t<T, false, true>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
-    } else {
-        if (wn) launch_surface_t<T, true, false>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
-        else launch_surface_t<T, false, false>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
-    }
+    if (ext) launch_surface_rl<T, kRowExt>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
+    else launch_surface_rl<T, 16>(rows, prof, n_u, n_v, pos, nrm, cfg, st);
     return hipGetLastError();
 }
 template hipError_t launch_surface<float>(const float*, const float*, int, int, float*, float*,
-                                          const SurfaceConfig&, hipStream_t);
+                                          const SurfaceConfig&, hipStream_t, bool);
 template hipError_t launch_surface<double>(const double*, const double*, int, int, double*, double*,
-                                           const SurfaceConfig&, hipStream_t);
+                                           const SurfaceConfig&, hipStream_t, bool);
 
 }  // namespace sweep

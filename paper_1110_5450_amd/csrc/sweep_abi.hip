@@ -118,7 +118,24 @@ sweep_status check_options(const sweep_options* o)
             if (!std::isfinite(o->initial_normal[k])) return fail(SWEEP_ERR_BAD_OPTION, "initial_normal not finite");
     if (o->tile_config < -1 || o->tile_config >= tile_config_count())
         return fail(SWEEP_ERR_BAD_OPTION, "tile_config %d outside -1..%d", o->tile_config, tile_config_count() - 1);
+    if (o->frame_mode != SWEEP_FRAME_RMF && o->frame_mode != SWEEP_FRAME_FRENET)
+        return fail(SWEEP_ERR_BAD_OPTION, "frame_mode %d is not RMF (0) or FRENET (1)", o->frame_mode);
+    if (o->law) {
+        if (o->law->closed) return fail(SWEEP_ERR_UNSUPPORTED, "law: the law curve must be open");
+        sweep_status st = check_curve(o->law, "law", true);
+        if (st != SWEEP_OK) return st;
+    }
     return SWEEP_OK;
+}
+
+// Options that need the extended row records (Frenet frame or a law).
+bool options_ext(const sweep_options* o) { return o->frame_mode != SWEEP_FRAME_RMF || o->law != nullptr; }
+
+// Parameter domain [U_p, U_n] of an open curve (given knots or [0, 1]).
+static double domain_length(const sweep_curve* c)
+{
+    if (!c->knots) return 1.0;
+    return c->knots[c->n_ctrl] - c->knots[c->degree];
 }
 
 sweep_status check_grid(int n_u, int n_v)
@@ -261,10 +278,13 @@ SurfaceConfig auto_surface_config(int n_u, int n_v, int t64)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, total;
+    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, knots_law, total;
 };
 
-static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz)
+// rl: values per row record (16, or kRowExt with a frame mode or law);
+// nlk: knots of the law curve (0 without a law or with its default knots).
+static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz,
+                                  int rl = 16, int nlk = 0)
 {
     SingleLayout L{};
     const int nc = (n_u + frame_chunk_size() - 1) / frame_chunk_size();
@@ -277,8 +297,9 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
     L.fallback = off;   off = align_up(off + sizeof(double) * 3);
     L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
     L.r_in = off;       off = align_up(off + fsz * 3 * (size_t)nc);
-    L.rows = off;       off = align_up(off + tsz * 16 * (size_t)n_u);
+    L.rows = off;       off = align_up(off + tsz * (size_t)rl * (size_t)n_u);
     L.prof_tab = off;   off = align_up(off + tsz * 8 * (size_t)n_v);
+    L.knots_law = off;  off = align_up(off + sizeof(double) * (size_t)nlk);
     L.total = off;
     return L;
 }
@@ -288,7 +309,9 @@ static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof,
 {
     const size_t fsz = o->frame_precision == SWEEP_F64 ? 8 : 4;
     const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
-    return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz);
+    const int nlk = (o->law && o->law->knots) ? nknots(o->law->n_ctrl, o->law->degree, 0) : 0;
+    return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz,
+                         options_ext(o) ? kRowExt : 16, nlk);
 }
 
 // Copies given knots to the device (a blocking copy from pageable memory);
@@ -350,13 +373,28 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
     hipError_t e = launch_prep<F, T>(dp, n_u, dq, n_v, smp, clv, cfx, fb, (F*)(ws + L.agg), ptab, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
+    const bool ext = options_ext(o);
+    FrameExt fx{};
+    if (ext) {
+        fx.path = dp;
+        fx.frenet = o->frame_mode == SWEEP_FRAME_FRENET;
+        if (o->law) {
+            const sweep_curve* lc = o->law;
+            double* Ul = (double*)(ws + L.knots_law);
+            if ((s = upload_knots(lc->knots, lc->n_ctrl, lc->degree, Ul, st)) != SWEEP_OK) return s;
+            fx.law = DCurve{lc->ctrl, lc->knots ? Ul : nullptr, lc->n_ctrl, lc->degree, 0,
+                            nbasis(lc->n_ctrl, lc->degree, 0), lc->weights};
+            fx.has_law = 1;
+            fx.du_scale = domain_length(lc) / domain_length(path);
+        }
+    }
     e = launch_frame<F, T>(smp, n_u, clv, cfx, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
-                           rows, st);
+                           rows, st, ext ? &fx : nullptr);
     if (e != hipSuccess) return hip_fail(e, "frame");
     trace_mark(1, st);
     const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config)
                                                    : auto_surface_config(n_u, n_v, o->out_precision == SWEEP_F64);
-    e = launch_surface<T>(rows, ptab, n_u, n_v, (T*)pos, (T*)nrm, cfg, st);
+    e = launch_surface<T>(rows, ptab, n_u, n_v, (T*)pos, (T*)nrm, cfg, st, ext);
     if (e != hipSuccess) return hip_fail(e, "surface");
     trace_mark(2, st);
     return SWEEP_OK;
@@ -466,6 +504,7 @@ sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_opti
     sweep_status s = check_options(opt);
     if (s != SWEEP_OK) return s;
     if ((s = check_curve(path, "path", true)) != SWEEP_OK) return s;
+    if (options_ext(opt)) return fail(SWEEP_ERR_UNSUPPORTED, "sweep_frames: frame modes and laws are sweep_eval only");
     if (n_u < 2 || n_u >= (1 << 30)) return fail(SWEEP_ERR_BAD_GRID, "n_u %d outside 2..2^30-1", n_u);
     if (!frames) return fail(SWEEP_ERR_NULL_ARG, "frames is NULL");
     const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
@@ -506,9 +545,9 @@ sweep_status sweep_autotune(const sweep_curve* path, const sweep_curve* profile,
         const SurfaceConfig& cfg = tile_config(c);
         auto run = [&]() -> hipError_t {
             return t64 ? launch_surface<double>((const double*)(ws + L.rows), (const double*)(ws + L.prof_tab), n_u,
-                                                n_v, (double*)pos, (double*)nrm, cfg, st)
+                                                n_v, (double*)pos, (double*)nrm, cfg, st, options_ext(&o))
                        : launch_surface<float>((const float*)(ws + L.rows), (const float*)(ws + L.prof_tab), n_u, n_v,
-                                               (float*)pos, (float*)nrm, cfg, st);
+                                               (float*)pos, (float*)nrm, cfg, st, options_ext(&o));
         };
         if ((e = run()) != hipSuccess) break;   // warm-up
         if ((e = hipEventRecord(ev0, st)) != hipSuccess) break;

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert L.sweep_version() == 101
+    assert L.sweep_version() == 102
     o = L.default_options()
     assert (o.out_precision, o.frame_precision, o.reorthonormalize, o.has_initial_normal, o.tile_config) == (0, 1, 1, 0, -1)
     assert L.sweep_tile_config_count() >= 8
@@ -139,3 +139,30 @@ def test_workspace_checks():
     _expect(_call(a, b, ws_bytes=need - 1), "SWEEP_ERR_WORKSPACE", str(need))
     _expect(_call(a, b, ws=0), "SWEEP_ERR_WORKSPACE")
     _expect(_call(a, b, ws=FAKE + 8), "SWEEP_ERR_WORKSPACE", "aligned")
+
+
+def test_frame_mode_and_law_options():
+    a, b = _curves()
+    o = L.default_options()
+    assert o.frame_mode == 0 and not o.law
+    o.frame_mode = 2
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_BAD_OPTION")
+    # a law is validated like an open curve
+    law = L.SweepCurve(3, 5, 0, 0, FAKE, None)
+    o = L.default_options()
+    o.law = C.cast(C.pointer(law), C.c_void_p)
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_BAD_COUNT")
+    law = L.SweepCurve(4, 1, 1, 0, FAKE, None)
+    o.law = C.cast(C.pointer(law), C.c_void_p)
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_UNSUPPORTED")
+    # extended rows need a larger workspace
+    law = L.SweepCurve(4, 1, 0, 0, FAKE, None)
+    o.law = C.cast(C.pointer(law), C.c_void_p)
+    base = L.sweep_eval_workspace_size(a, b, 256, 64, L.default_options())
+    assert L.sweep_eval_workspace_size(a, b, 256, 64, o) > base
+    o2 = L.default_options()
+    o2.frame_mode = 1
+    assert L.sweep_eval_workspace_size(a, b, 256, 64, o2) > base
+    # frames-only entry point and batches do not take frame modes or laws
+    st = L.sweep_frames(a, 256, o2, FAKE, FAKE, 1 << 40, 0)
+    assert L.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
