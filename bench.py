@@ -73,7 +73,7 @@ def _dev_weights(curve, dev):
     return None if w is None else torch.as_tensor(w).to(dev)
 
 
-def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
+def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, frame_mode="rmf", law=None):
     """Wall time of `steps` sweep_eval calls, the per-call (frame, surface)
     stage times from the library's HIP events, and optionally the outputs."""
     import torch
@@ -84,15 +84,18 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
     P, Q = _dev_spec(spec, dev)
     pos = torch.empty((3, spec.n_u, spec.n_v), dtype=out_dtype, device=dev)
     nrm = torch.empty_like(pos)
+    glaw = None if law is None else api.Law(torch.as_tensor(law.ctrl).to(dev), law.degree, law.knots)
     ws = torch.empty(api.eval_workspace_size(P.shape[0], spec.path.degree, Q.shape[0], spec.profile.degree,
-                                             spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype),
+                                             spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype,
+                                             frame_mode=frame_mode, law=glaw),
                      dtype=torch.uint8, device=dev)
 
     Pw, Qw = _dev_weights(spec.path, dev), _dev_weights(spec.profile, dev)
 
     def step():
         api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v, out_dtype=out_dtype,
-                       frame_dtype=frame_dtype, path_weights=Pw, prof_weights=Qw, out=(pos, nrm), workspace=ws)
+                       frame_dtype=frame_dtype, path_weights=Pw, prof_weights=Qw, frame_mode=frame_mode, law=glaw,
+                       out=(pos, nrm), workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -114,7 +117,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False):
     return t1 - t0, surf, frame, out
 
 
-def sampled_error(spec, pos, nrm, rows, tol):
+def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None):
     """Parity figures of a GPU result on sampled rows against the oracle."""
     import numpy as np
     import torch
@@ -124,7 +127,11 @@ def sampled_error(spec, pos, nrm, rows, tol):
     gp = pos.index_select(1, idx).double().cpu().numpy()
     gn = nrm.index_select(1, idx).double().cpu().numpy()
     x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
-    rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
+    if frame_mode == "rmf" and law is None:
+        rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
+    else:
+        rp, rn, rk = oracle.sweep_rows_ex(spec.path, spec.profile, spec.n_u, spec.n_v, rows, mode=frame_mode,
+                                          law=law)
     diag = float(np.linalg.norm(x.max(0) - x.min(0)))
     r = oracle.compare(rp, rn, rk, gp, gn, diag, 1e6)
     r["rows"] = len(rows)
@@ -171,6 +178,29 @@ def rational_variant(steps: int):
     return {"workload": "the large sweep with weights U(0.5, 2) on path and profile control points",
             "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
             "frame_ms": sum(frame) / len(frame), "surface_ms": sum(surf) / len(surf), "error_vs_oracle": err}
+
+
+def frenet_law_variant(steps: int):
+    """The large sweep with the Frenet frame and a scale/twist law (extended
+    row records): throughput, stage times and sampled parity."""
+    import numpy as np
+    import torch
+    import synth
+
+    spec = synth.c2()
+    law = synth.sweep_law()
+    N = spec.n_u * spec.n_v
+    el, surf, frame, res = time_single(spec, steps, 1, torch.float32, keep=True, frame_mode="frenet", law=law)
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([[0, spec.n_u - 1], rng.integers(0, spec.n_u, 6)]))
+    err = sampled_error(spec, res[0], res[1], rows, 1e-5, frame_mode="frenet", law=law)
+    del res
+    torch.cuda.empty_cache()
+    s_ms = sum(surf) / len(surf)
+    return {"workload": "the large sweep, Frenet frame, scale/twist law (16 control points, cubic)",
+            "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
+            "frame_ms": sum(frame) / len(frame), "surface_ms": s_ms,
+            "surface_GBps": 24.0 * N / (s_ms * 1e-3) / 1e9, "error_vs_oracle": err}
 
 
 def batched_variants(steps: int):
@@ -403,6 +433,8 @@ def main():
         }
         log("[bench] rational ...")
         out["variants"]["rational_fp32_out"] = rational_variant(steps64)
+        log("[bench] frenet + law ...")
+        out["variants"]["frenet_law_fp32_out"] = frenet_law_variant(steps64)
         log("[bench] batched ...")
         out["variants"]["batched"] = batched_variants(max(3, args.steps // 4))
         log("[bench] adjoint ...")

@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "CurveSpec", "SweepSpec", "random_walk", "perturbed_circle", "single",
-    "config", "c1", "c2", "c2_rational", "c3", "c4", "c5", "loss_weights",
+    "config", "c1", "c2", "c2_rational", "sweep_law", "c3", "c4", "c5", "loss_weights",
 ]
 
 
@@ -114,6 +114,17 @@ def c2_rational(n_u: int = 65536, n_v: int = 1024, seed: int = 22) -> SweepSpec:
     s.path.weights = rng.uniform(0.5, 2.0, s.path.n)
     s.profile.weights = rng.uniform(0.5, 2.0, s.profile.n)
     return s
+
+
+def sweep_law(n: int = 16, degree: int = 3, seed: int = 23) -> CurveSpec:
+    """A sweep law along the path: control points (sigma, theta, 0) with
+    scale sigma ~ U(0.8, 1.2) and twist angle theta a random walk with
+    U(-0.5, 0.5) radian steps."""
+    rng = np.random.default_rng(seed)
+    ctrl = np.zeros((n, 3))
+    ctrl[:, 0] = rng.uniform(0.8, 1.2, n)
+    ctrl[:, 1] = np.cumsum(rng.uniform(-0.5, 0.5, n))
+    return CurveSpec(ctrl, degree)
 
 
 def c3(n_u: int = 1048576, n_v: int = 32) -> SweepSpec:
