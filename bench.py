@@ -418,7 +418,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
-                     "kernel": "k_surface_tiles<float> (surface write)", "alg_bytes_per_launch": bytes_alg,
+                     "kernel": "k_surface_tiles<float, true, true, 16> (surface write)", "alg_bytes_per_launch": bytes_alg,
                      "avg_launch_ms": surf_ms},
         "stages_ms": {"frame": sum(frame) / len(frame), "surface": surf_ms},
         "error_vs_oracle": err,

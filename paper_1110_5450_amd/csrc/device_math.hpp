@@ -394,12 +394,61 @@ __device__ __forceinline__ int step_matrix(V3<F> v1, V3<F> ti, V3<F> tn, M3<F>& 
 
 // --------------------------------------------------------- wave/block scans
 
-template <class F>
-__device__ __forceinline__ M3<F> shfl_up_m3(const M3<F>& a, int d)
+// Cross-lane moves by DPP (data-parallel primitives of the GFX9 ISA: VALU
+// moves, no LDS traffic).  Controls: row_shr:n = 0x110 + n (within rows of
+// 16 lanes), row_bcast:15 = 0x142 (lane 15 of each row to the next row),
+// row_bcast:31 = 0x143 (lane 31 to rows 2 and 3), wave_shr:1 = 0x138.  A lane
+// without a source lane receives 0 (callers discard those values).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_val(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffLL));
+    const int hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_val(float v)
+{
+    return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL, class F>
+__device__ __forceinline__ M3<F> dpp_m3(const M3<F>& a)
 {
     M3<F> r;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) r.m[k] = __shfl_up(a.m[k], d, 64);
+    for (int k = 0; k < 9; ++k) r.m[k] = dpp_val<CTRL>(a.m[k]);
+    return r;
+}
+
+// Inclusive ordered product over the wave (lane 0 earliest, later factors on
+// the left): products within rows of 16 lanes (shifts 1, 2, 4, 8), then row
+// totals carried to rows 1 and 3, then lane 31 to the upper half.
+template <class F>
+__device__ __forceinline__ M3<F> wave_inclusive_product(M3<F> x)
+{
+    const int lane = threadIdx.x & 63, rl = lane & 15;
+    M3<F> inc = x;
+    { const M3<F> o = dpp_m3<0x111>(inc); if (rl >= 1) inc = mul(inc, o); }
+    { const M3<F> o = dpp_m3<0x112>(inc); if (rl >= 2) inc = mul(inc, o); }
+    { const M3<F> o = dpp_m3<0x114>(inc); if (rl >= 4) inc = mul(inc, o); }
+    { const M3<F> o = dpp_m3<0x118>(inc); if (rl >= 8) inc = mul(inc, o); }
+    { const M3<F> o = dpp_m3<0x142>(inc); if (lane & 16) inc = mul(inc, o); }
+    { const M3<F> o = dpp_m3<0x143>(inc); if (lane >= 32) inc = mul(inc, o); }
+    return inc;
+}
+
+// The previous lane's value (lane 0: identity).
+template <class F>
+__device__ __forceinline__ M3<F> wave_shift_up1(const M3<F>& a)
+{
+    M3<F> r = dpp_m3<0x138>(a);
+    if ((threadIdx.x & 63) == 0) r = ident<F>();
     return r;
 }
 
@@ -411,12 +460,7 @@ template <class F>
 __device__ M3<F> block_exclusive_product(M3<F> x, M3<F>* lds, M3<F>& total)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    M3<F> inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const M3<F> o = shfl_up_m3(inc, d);
-        if (lane >= d) inc = mul(inc, o);
-    }
+    M3<F> inc = wave_inclusive_product<F>(x);
     if (lane == 63) lds[w] = inc;
     __syncthreads();
     M3<F> wave_prefix = ident<F>();
@@ -424,11 +468,44 @@ __device__ M3<F> block_exclusive_product(M3<F> x, M3<F>* lds, M3<F>& total)
     M3<F> tot = ident<F>();
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) tot = mul(lds[k], tot);
-    M3<F> exc = shfl_up_m3(inc, 1);
-    if (lane == 0) exc = ident<F>();
+    const M3<F> exc = wave_shift_up1<F>(inc);
     total = tot;
     __syncthreads();
     return mul(exc, wave_prefix);
+}
+
+// Same exclusive product without the block total (fewer products per thread).
+template <class F>
+__device__ M3<F> block_exclusive_product(M3<F> x, M3<F>* lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    M3<F> inc = wave_inclusive_product<F>(x);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    M3<F> wave_prefix = ident<F>();
+    for (int k = 0; k < w; ++k) wave_prefix = mul(lds[k], wave_prefix);
+    const M3<F> exc = wave_shift_up1<F>(inc);
+    __syncthreads();
+    return mul(exc, wave_prefix);
+}
+
+// Ordered product x_{255} ... x_0 of the block (later factors on the left),
+// with the same combination order as block_exclusive_product's total; the
+// result is valid in wave 0 only (the other waves skip the final combine).
+template <class F>
+__device__ M3<F> block_product(M3<F> x, M3<F>* lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    M3<F> inc = wave_inclusive_product<F>(x);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    M3<F> tot = ident<F>();
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) tot = mul(lds[k], tot);
+    }
+    __syncthreads();
+    return tot;
 }
 
 // Exclusive max-scan of ints over the block (identity -1); block max in `total`.

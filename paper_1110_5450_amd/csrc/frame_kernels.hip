@@ -132,8 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(DCurve path, int n_u, DCurve pr
     V3<double> d_lv = d0;
     if (!valid0 && lv >= 0) d_lv = mk(sd[0][lv - base], sd[1][lv - base], sd[2][lv - base]);
     const StepInputs s = resolve_step(x0, d0, valid0, x1, d1, valid1, has_step, lv, d_lv, fb);
-    M3<F> prod;
-    block_exclusive_product<F>(step_of<F>(s), lds_m, prod);
+    const M3<F> prod = block_product<F>(step_of<F>(s), lds_m);
     if (threadIdx.x < 9) agg[9 * (size_t)b + threadIdx.x] = prod.m[threadIdx.x];
 }
 
@@ -149,7 +148,12 @@ __global__ __launch_bounds__(kBlock) void k_frame_carry(F* __restrict__ agg, int
 {
     __shared__ int lds_i[kWaves];
     __shared__ M3<F> lds_m[kWaves];
-    for (int base = 0; base < n_chunks; base += kBlock) {
+    // any flagged chunk at all?  one strided pass and one block reduction
+    int any = -1;
+    for (int c = threadIdx.x; c < n_chunks; c += kBlock) any = chunk_fix[c] ? c : any;
+    int last_flagged;
+    block_exclusive_max(any, lds_i, last_flagged);
+    for (int base = 0; base <= last_flagged; base += kBlock) {   // uniform; skipped when none
         const int c = base + threadIdx.x;
         int total;
         block_exclusive_max(c < n_chunks && chunk_fix[c] ? c : -1, lds_i, total);
@@ -157,8 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_carry(F* __restrict__ agg, int
         for (int b = base; b < min(n_chunks, base + kBlock); ++b) {
             if (!chunk_fix[b]) continue;
             const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, b);
-            M3<F> prod;
-            block_exclusive_product<F>(step_of<F>(s), lds_m, prod);
+            const M3<F> prod = block_product<F>(step_of<F>(s), lds_m);
             if (threadIdx.x < 9) agg[9 * (size_t)b + threadIdx.x] = prod.m[threadIdx.x];
             __threadfence_block();
             __syncthreads();
@@ -180,8 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply(const double* __restrict
     __shared__ M3<F> lds_m[kWaves];
     const size_t nu = (size_t)n_u;
     const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, blockIdx.x);
-    M3<F> total;
-    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m, total);
+    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m);
     const int i = blockIdx.x * kChunk + threadIdx.x;
     if (i >= n_u) return;
     write_row<F, T>(s, ex, r_in + 3 * (size_t)blockIdx.x, smp_get(smp, nu, 1, i), smp_get(smp, nu, 2, i), reorth,
@@ -204,8 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply_ext(const double* __rest
     __shared__ M3<F> lds_m[kWaves];
     const size_t nu = (size_t)n_u;
     const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, blockIdx.x);
-    M3<F> total;
-    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m, total);
+    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m);
     const int i = blockIdx.x * kChunk + threadIdx.x;
     if (i >= n_u) return;
     V3<double> C3 = mk(0.0, 0.0, 0.0);
