@@ -136,6 +136,38 @@ def test_precision_study_grid_sampled_rows():
     _sampled(spec, rows, torch.float32, frame_dtype=torch.float32, tol=1e-3)
 
 
+@pytest.mark.parametrize("tile_config", [-1, 14])
+def test_maximum_grid_sampled_rows(tile_config):
+    """The largest grid the boundary accepts: n_u * n_v just under 2^31
+    (1,048,575 x 2048 = 2,147,481,600 vertices, 51.5 GB of FP32 output), so
+    every vertex index is near the top of the 32-bit range; the default
+    column-tile kernel and the linear kernel (64-bit-multiply division by
+    n_v) are both checked on sampled rows, including the last one."""
+    spec = synth.c2(n_u=1048575, n_v=2048)
+    assert spec.n_u * spec.n_v < 2 ** 31 and spec.n_u * (spec.n_v + 1) >= 2 ** 31
+    rows = np.unique(np.concatenate([[0, 255, 256, 524288, spec.n_u - 2, spec.n_u - 1],
+                                     rng.integers(0, spec.n_u, 6)]))
+    say(f"[case] maximum grid tile_config={tile_config}")
+    pos, nrm = gpu_sweep(spec, torch.float32, tile_config=tile_config)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(rows, device=pos.device)
+    gp = pos.index_select(1, idx).cpu().numpy()
+    gn = nrm.index_select(1, idx).cpu().numpy()
+    del pos, nrm
+    torch.cuda.empty_cache()
+    x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
+    rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
+    ok, r = parity(rp, rn, rk, gp, gn, TOL[torch.float32], diag=float(np.linalg.norm(x.max(0) - x.min(0))))
+    say("   ", r)
+    assert ok, r
+
+
+def test_grid_limit_is_rejected():
+    spec = synth.c2(n_u=1048576, n_v=2048)      # exactly 2^31 vertices
+    with pytest.raises(Exception, match="BAD_GRID"):
+        gpu_sweep(spec, torch.float32)
+
+
 @pytest.mark.parametrize("name,n_u", [("c1", 256), ("c1", 5000), ("c3", 1048576), ("c2", 65536)])
 def test_frames_match_oracle(name, n_u):
     """The whole frame (every u-sample) against the oracle's sequential FP64
