@@ -24,12 +24,13 @@
 namespace sweep {
 
 // One wave per unit (sweep, group of G rows, segment of 64 columns); every
-// wave of the block reaches the barriers.  The wave stages its G x 64 tile
-// of w (three planes) in LDS with coalesced loads, then
-//   lane = column j:            h_j += R_i^T w_ij over the G rows,
-//   lane = (component c, row r): the 12 row sums over the 64 columns,
-// each a sequential sum in a fixed order.  Rows are padded to 65 elements so
-// that both passes read LDS without bank conflicts.
+// wave of the block reaches the barriers.  Lane = column j loads its G x 3
+// values of w (coalesced) and keeps them in registers for the column sums
+//   h_j += R_i^T w_ij over the G rows;
+// the values also go to an LDS tile (rows padded to 65 elements: no bank
+// conflicts) from which lane = (component c, row r, half h) forms the row
+// sums over 32 of the 64 columns; the two halves are added in a fixed order
+// (h = 0 first).  Small tiles keep five blocks per CU resident.
 template <class T>
 __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
                                                      const int4* __restrict__ units, int n_units,
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
     const int nr = live ? min(G, n_u - i0) : 0;
     const int j = seg * 64 + lane;
     const bool vj = live && j < n_v;
+    T w[3][G];
     {
         double S0 = 0.0, S1 = 0.0, S2 = 0.0;
         if (vj) {
@@ -64,17 +66,19 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         const T* w0 = grad + d.out_off;
 #pragma unroll
         for (int r = 0; r < G; ++r) {
-            T a = T(0), b = T(0), c = T(0);
+            w[0][r] = w[1][r] = w[2][r] = T(0);
             if (vj && r < nr) {
                 const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
-                a = __builtin_nontemporal_load(w0 + v);
-                b = __builtin_nontemporal_load(w0 + P + v);
-                c = __builtin_nontemporal_load(w0 + 2 * P + v);
+                w[0][r] = __builtin_nontemporal_load(w0 + v);
+                w[1][r] = __builtin_nontemporal_load(w0 + P + v);
+                w[2][r] = __builtin_nontemporal_load(w0 + 2 * P + v);
             }
-            lw[wave][0][r][lane] = a; lw[wave][1][r][lane] = b; lw[wave][2][r][lane] = c;
+        }
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            lw[wave][0][r][lane] = w[0][r]; lw[wave][1][r][lane] = w[1][r]; lw[wave][2][r][lane] = w[2][r];
         }
     }
-    __syncthreads();
     if (vj) {
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         const double* R0 = rows + 16 * (d.row_off + i0);
@@ -82,29 +86,37 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         for (int r = 0; r < G; ++r) {
             if (r < nr) {
                 const double* R = R0 + 16 * r;
-                const double w[3] = {(double)lw[wave][0][r][lane], (double)lw[wave][1][r][lane],
-                                     (double)lw[wave][2][r][lane]};
-                h0 += R[3] * w[0] + R[4] * w[1] + R[5] * w[2];
-                h1 += R[6] * w[0] + R[7] * w[1] + R[8] * w[2];
-                h2 += R[9] * w[0] + R[10] * w[1] + R[11] * w[2];
+                const double a = (double)w[0][r], b = (double)w[1][r], c = (double)w[2][r];
+                h0 += R[3] * a + R[4] * b + R[5] * c;
+                h1 += R[6] * a + R[7] * b + R[8] * c;
+                h2 += R[9] * a + R[10] * b + R[11] * c;
             }
         }
         double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
         q[0] = h0; q[1] = h1; q[2] = h2;
     }
-    const int r = lane % G, c = lane / G;
-    if (live && c < 3 && r < nr) {
+    __syncthreads();
+    // lane = ((c * G + r) << 1) | h
+    const int h = lane & 1, cr = lane >> 1, r = cr % G, c = cr / G;
+    const bool act = live && c < 3 && r < nr;
+    double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    if (act) {
         const int ncol = min(64, n_v - seg * 64);
-        double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-        for (int jj = 0; jj < ncol; ++jj) {
-            const double w = (double)lw[wave][c][r][jj];
-            a0 += w;
-            ax += ls[wave][0][jj] * w;
-            ay += ls[wave][1][jj] * w;
-            az += ls[wave][2][jj] * w;
+        const int j0 = h * 32, j1 = min(ncol, j0 + 32);
+        for (int jj = j0; jj < j1; ++jj) {
+            const double v = (double)lw[wave][c][r][jj];
+            a0 += v;
+            ax += ls[wave][0][jj] * v;
+            ay += ls[wave][1][jj] * v;
+            az += ls[wave][2][jj] * v;
         }
+    }
+    // the second half's sums from the neighbouring lane (every lane takes part)
+    const double b0 = __shfl_xor(a0, 1, 64), bx = __shfl_xor(ax, 1, 64);
+    const double by = __shfl_xor(ay, 1, 64), bz = __shfl_xor(az, 1, 64);
+    if (act && h == 0) {
         double* q = rowpart + 12 * (d.rowpart_off + (size_t)seg * n_u + i0 + r);
-        q[c] = a0; q[3 + c] = ax; q[6 + c] = ay; q[9 + c] = az;
+        q[c] = a0 + b0; q[3 + c] = ax + bx; q[6 + c] = ay + by; q[9 + c] = az + bz;
     }
 }
 

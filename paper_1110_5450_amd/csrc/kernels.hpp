@@ -84,8 +84,8 @@ constexpr int kPlaneAlign = 64;
 // Rows per reduction group in the adjoint's streaming read of dL/dX (the
 // LDS tile of a wave holds G x 65 values per plane).
 template <class T>
-constexpr int bw_row_group() { return sizeof(T) == 8 ? 8 : 16; }
-inline int bw_row_group_for(bool t64) { return t64 ? 8 : 16; }
+constexpr int bw_row_group() { return sizeof(T) == 8 ? 4 : 8; }
+inline int bw_row_group_for(bool t64) { return t64 ? 4 : 8; }
 
 struct BackwardKernels {
     const void* reduce;
