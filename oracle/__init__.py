@@ -67,7 +67,12 @@ def lib():
         L.or_max_threads.restype = C.c_int
         L.or_sweep_ex.restype = C.c_int
         L.or_sweep_ex.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, C.c_int, C.c_int,
-                                  C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+                                  C.c_void_p, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.or_arclength_params.restype = C.c_double
+        L.or_arclength_params.argtypes = [C.POINTER(_Curve), C.c_int, _dp]
+        L.or_curve_samples_at.restype = None
+        L.or_triangles.restype = C.c_longlong
+        L.or_triangles.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p]
         L.or_curve_samples3.restype = None
         L.or_frenet.restype = None
         L.or_surface_rows_ex.restype = None
@@ -260,7 +265,7 @@ def surface_ex_from_samples(x, d1, d2, R, omega, law, S, dS):
 
 
 def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mode: str = "rmf", law=None,
-             rows: Optional[Tuple[int, int]] = None, want_kappa=True):
+             rows: Optional[Tuple[int, int]] = None, want_kappa=True, arclength: bool = False):
     """Whole sweep with a frame mode ("rmf" or "frenet") and an optional law
     curve (open curve whose control points hold (scale, twist angle, -)).
     Returns (SweepResult, omega (n_u,))."""
@@ -274,14 +279,15 @@ def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mo
     om = np.empty(n_u)
     n0a = None if n0 is None else _f64(n0)
     nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), int(reorth), FRAME_MODES[mode],
-                           None if Lw is None else C.cast(Lw.ref, C.c_void_p), r0, r1, _ptr(pos), _ptr(nrm),
-                           _ptr(kap), _ptr(R), _ptr(om))
+                           None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), r0, r1,
+                           _ptr(pos), _ptr(nrm), _ptr(kap), _ptr(R), _ptr(om))
     if nf < 0:
         raise ValueError("oracle: bad sweep input")
     return SweepResult(pos, nrm, kap, R.reshape(n_u, 3, 3).transpose(0, 2, 1).copy(), nf, (r0, r1)), om
 
 
-def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = "rmf", law=None):
+def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = "rmf", law=None,
+                  arclength: bool = False):
     """sweep_ex on the listed rows only: (pos (3, len(rows), n_v), nrm,
     kappa (len(rows), n_v))."""
     rows = np.asarray(rows, dtype=np.int64)
@@ -293,11 +299,40 @@ def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = 
     n0a = None if n0 is None else _f64(n0)
     for i in rows:
         nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), 1, FRAME_MODES[mode],
-                               None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(i), int(i) + 1,
-                               _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
+                               None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), int(i),
+                               int(i) + 1, _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
         if nf < 0:
             raise ValueError("oracle: bad sweep input")
     return pos[:, rows], nrm[:, rows], kap[rows]
+
+
+def arclength_params(curve, ns: int):
+    """(u (ns,), total length) of the arc-length samples of an open curve."""
+    c = Curve.of(curve)
+    u = np.empty(ns)
+    total = lib().or_arclength_params(c.ref, int(ns), _ptr(u))
+    if total < 0:
+        raise ValueError("arc-length sampling needs an open curve")
+    return u, total
+
+
+def curve_at(curve, u, nd: int = 2):
+    """Points and derivatives (nd+1 arrays (n, 3)) at the given parameters."""
+    c = Curve.of(curve)
+    u = _f64(u)
+    n = u.shape[0]
+    outs = [np.empty((n, 3)) for _ in range(4)]
+    ptrs = [_ptr(outs[0])] + [_ptr(outs[d]) if d <= nd else None for d in (1, 2, 3)]
+    lib().or_curve_samples_at(c.ref, C.c_int(n), _ptr(u), *ptrs)
+    return outs[: nd + 1]
+
+
+def triangles(n_u: int, n_v: int, closed_v: bool) -> np.ndarray:
+    """(T, 3) int32 triangle list of the grid (see or_triangles)."""
+    t = lib().or_triangles(int(n_u), int(n_v), int(bool(closed_v)), None)
+    tri = np.empty((t, 3), np.int32)
+    lib().or_triangles(int(n_u), int(n_v), int(bool(closed_v)), tri.ctypes.data_as(C.c_void_p))
+    return tri
 
 
 def sweep_rows(path, profile, n_u: int, n_v: int, rows, n0=None, reorth: bool = True):

@@ -27,6 +27,7 @@
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fopenmp -fPIC -shared.
  * FP contraction is off so every product and sum is rounded where written.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -461,6 +462,172 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
     }
 }
 
+/* ------------------------------------------ F4 arc-length sampling */
+
+/* Gauss-Legendre rule with 8 nodes on [-1, 1]: nodes as the roots of the
+ * Legendre polynomial P_8 (Newton's method on the three-term recurrence from
+ * the Chebyshev guesses cos(pi (k - 1/4)/(8 + 1/2))), weights
+ * 2 / ((1 - x^2) P_8'(x)^2). */
+static void gauss_legendre8(double *x, double *w)
+{
+    const int n = 8;
+    for (int k = 0; k < n; ++k) {
+        double z = cos(M_PI * (k + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        {   /* derivative at the converged root */
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[k] = z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+#define OR_ARC_SUB 32   /* equal sub-intervals per knot span, 8 Gauss nodes each */
+
+/* Integral of |C'| over [a, b] by the 8-point Gauss-Legendre rule. */
+static double speed_gl8(const or_curve *c, const double *U, double a, double b, const double *gx, const double *gw)
+{
+    double mid = 0.5 * (a + b), half = 0.5 * (b - a), part = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double o[6];
+        or_curve_eval(c, U, mid + half * gx[k], 1, o);
+        part += gw[k] * norm3(o + 3);
+    }
+    return half * part;
+}
+
+/*
+ * Arc-length sampling of an open curve: u_i with s(u_i) = (i/(ns-1)) s(b),
+ * s(u) = integral of |C'| from the domain start a to u; u_0 = a,
+ * u_{ns-1} = b.  Every non-empty knot span [U_k, U_{k+1}] is cut into
+ * OR_ARC_SUB equal pieces (boundaries U_k + (U_{k+1} - U_k)(m/OR_ARC_SUB),
+ * the last one U_{k+1}), each integrated by 8-point Gauss-Legendre, and the
+ * piece lengths are summed in order into a cumulative table.  A target's
+ * piece is the last one (in order) whose cumulative start is <= the target;
+ * inside it Newton's method on s(u) - target (derivative |C'(u)|) from the
+ * linear guess, kept inside the bracket (a bisection step replaces a Newton
+ * step that leaves it or meets |C'| = 0), until s(u) hits the target
+ * exactly, |du| <= 4 eps max(1, |u|), or 40 steps.
+ * u_out: ns values; returns the total length, or -1 for a closed curve.
+ */
+double or_arclength_params(const or_curve *c, int ns, double *u_out)
+{
+    if (c->closed) return -1.0;
+    double gx[8], gw[8];
+    gauss_legendre8(gx, gw);
+    int nk = or_nknots(c->n, c->p, 0), nb = c->n;
+    double *U = (double *)malloc(sizeof(double) * (size_t)nk);
+    or_knots(c->n, c->p, 0, c->knots, U);
+    int npc = (nb - c->p) * OR_ARC_SUB;                 /* pieces (empty spans give empty pieces) */
+    double *lo = (double *)malloc(sizeof(double) * (size_t)npc);
+    double *hi = (double *)malloc(sizeof(double) * (size_t)npc);
+    double *cum = (double *)malloc(sizeof(double) * (size_t)(npc + 1));
+    cum[0] = 0.0;
+    for (int k = c->p, q = 0; k < nb; ++k)
+        for (int m = 0; m < OR_ARC_SUB; ++m, ++q) {
+            double w = U[k + 1] - U[k];
+            lo[q] = U[k] + w * ((double)m / OR_ARC_SUB);
+            hi[q] = m + 1 < OR_ARC_SUB ? U[k] + w * ((double)(m + 1) / OR_ARC_SUB) : U[k + 1];
+            cum[q + 1] = cum[q] + (w > 0.0 ? speed_gl8(c, U, lo[q], hi[q], gx, gw) : 0.0);
+        }
+    double total = cum[npc];
+    for (int i = 0; i < ns; ++i) {
+        if (i == 0) { u_out[i] = U[c->p]; continue; }
+        if (i == ns - 1) { u_out[i] = U[nb]; continue; }
+        double target = ((double)i / (double)(MUT(18) ? ns : ns - 1)) * total;
+        int q = 0;
+        for (int r = 0; r < npc; ++r)
+            if (hi[r] > lo[r] && cum[r] <= target) q = r;
+        double len = cum[q + 1] - cum[q];
+        double u = len > 0.0 ? lo[q] + (target - cum[q]) / len * (hi[q] - lo[q]) : lo[q];
+        double blo = lo[q], bhi = hi[q];
+        for (int it = 0; it < 40; ++it) {
+            double f = cum[q] + speed_gl8(c, U, lo[q], u, gx, gw) - target;
+            if (f == 0.0) break;
+            if (f > 0.0) bhi = u; else blo = u;
+            double o[6];
+            or_curve_eval(c, U, u, 1, o);
+            double sp = norm3(o + 3), un;
+            if (sp > 0.0) un = u - f / sp;
+            else un = 0.5 * (blo + bhi);
+            if (!(un >= blo && un <= bhi)) un = 0.5 * (blo + bhi);
+            double du = fabs(un - u);
+            u = un;
+            if (du <= 4.0 * 2.220446049250313e-16 * (fabs(u) > 1.0 ? fabs(u) : 1.0)) break;
+        }
+        u_out[i] = u;
+    }
+    free(cum);
+    free(hi);
+    free(lo);
+    free(U);
+    return total;
+}
+
+/* Curve samples at given parameters (pts/d1/d2/d3 ns x 3, d1..d3 may be NULL). */
+void or_curve_samples_at(const or_curve *c, int ns, const double *u, double *pts, double *d1, double *d2,
+                         double *d3)
+{
+    int nk = or_nknots(c->n, c->p, c->closed);
+    double *U = (double *)malloc(sizeof(double) * (size_t)nk);
+    or_knots(c->n, c->p, c->closed, c->knots, U);
+    int nd = d3 ? 3 : (d2 ? 2 : (d1 ? 1 : 0));
+    for (int i = 0; i < ns; ++i) {
+        double o[12];
+        or_curve_eval(c, U, u[i], nd, o);
+        for (int e = 0; e < 3; ++e) {
+            pts[3 * i + e] = o[e];
+            if (d1) d1[3 * i + e] = o[3 + e];
+            if (d2) d2[3 * i + e] = o[6 + e];
+            if (d3) d3[3 * i + e] = o[9 + e];
+        }
+    }
+    free(U);
+}
+
+/*
+ * Triangle list of the n_u x n_v grid (vertex (i, j) has index i n_v + j):
+ * each quad (i, j), (i+1, j), (i, j+1), (i+1, j+1), j + 1 taken modulo n_v
+ * when the profile is closed, gives the triangles
+ *   (i, j) (i, j+1) (i+1, j)   and   (i+1, j) (i, j+1) (i+1, j+1),
+ * counter-clockwise seen from the side the normal X_v x X_u points to.
+ * Quads in row-major order (i, then j); returns the triangle count.
+ */
+long long or_triangles(int nu, int nv, int closed_v, int *tri)
+{
+    int nq = closed_v ? nv : nv - 1;
+    long long t = 0;
+    for (int i = 0; i + 1 < nu; ++i)
+        for (int j = 0; j < nq; ++j) {
+            int j1 = (j + 1) % nv;
+            int a = i * nv + j, b = i * nv + j1, c = (i + 1) * nv + j, d = (i + 1) * nv + j1;
+            if (tri) {
+                int *q = tri + 3 * t;
+                q[0] = a; q[1] = MUT(19) ? c : b; q[2] = MUT(19) ? b : c;
+                q[3] = c; q[4] = b; q[5] = d;
+            }
+            t += 2;
+        }
+    return t;
+}
+
 /* ------------------------------------- F2 Frenet frame and sweep laws */
 
 /* Relative size below which C'' has no component normal to t: the Frenet
@@ -647,17 +814,18 @@ int or_sweep(const or_curve *path, const or_curve *prof, int nu, int nv,
 }
 
 /*
- * Whole sweep with a frame mode (0 rotation-minimizing, 1 Frenet) and an
- * optional law curve (NULL: none).  Same outputs as or_sweep (omega_out,
+ * Whole sweep with a frame mode (0 rotation-minimizing, 1 Frenet), an
+ * optional law curve (NULL: none) and the path sampled uniformly in its
+ * parameter (arclength = 0) or in arc length (1; not with a law).  Same outputs as or_sweep (omega_out,
  * nu values, may be NULL); with mode 0 and no law the result equals
  * or_sweep's up to rounding (the surface derivative is then assembled in
  * world instead of frame coordinates).
  */
 int or_sweep_ex(const or_curve *path, const or_curve *prof, int nu, int nv,
-                const double *n0, int reorth, int mode, const or_curve *law, int row0, int row1,
+                const double *n0, int reorth, int mode, const or_curve *law, int arclength, int row0, int row1,
                 double *pos, double *nrm, double *kappa, double *frame_out, double *omega_out)
 {
-    if (nu < 2 || nv < 1 || path->closed || (law && law->closed)) return -1;
+    if (nu < 2 || nv < 1 || path->closed || (law && law->closed) || (law && arclength)) return -1;
     double *x = (double *)malloc(sizeof(double) * 12 * (size_t)nu);
     double *d1 = x + 3 * (size_t)nu, *d2 = x + 6 * (size_t)nu, *d3 = x + 9 * (size_t)nu;
     double *R = frame_out ? frame_out : (double *)malloc(sizeof(double) * 9 * (size_t)nu);
@@ -665,7 +833,14 @@ int or_sweep_ex(const or_curve *path, const or_curve *prof, int nu, int nv,
     double *lw = law ? (double *)malloc(sizeof(double) * 4 * (size_t)nu) : NULL;
     double *S = (double *)malloc(sizeof(double) * 6 * (size_t)nv);
     double *dS = S + 3 * (size_t)nv;
-    or_curve_samples3(path, nu, x, d1, d2, d3);
+    if (arclength) {
+        double *u = (double *)malloc(sizeof(double) * (size_t)nu);
+        or_arclength_params(path, nu, u);
+        or_curve_samples_at(path, nu, u, x, d1, d2, d3);
+        free(u);
+    } else {
+        or_curve_samples3(path, nu, x, d1, d2, d3);
+    }
     or_curve_samples(prof, nv, S, dS, NULL);
     double ft[3];
     first_leg(path, ft);

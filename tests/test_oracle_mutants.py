@@ -23,6 +23,8 @@ harness on the unmodified source must pass.  Mistakes planted:
  15  frame derivative: sign of the omega term in r'
  16  twist law: sign of sigma theta' in the derivative of the profile point
  17  Frenet torsion rate doubled
+ 18  arc-length targets i/n_s instead of i/(n_s - 1)
+ 19  first triangle of each quad wound clockwise
 """
 
 from __future__ import annotations
@@ -38,8 +40,9 @@ from oracle import build as obuild
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_bspline.py", "tests/test_oracle_frame.py", "tests/test_oracle_grad.py",
-             "tests/test_oracle_rational.py", "tests/test_oracle_frenet_laws.py"]
-MUTANTS = list(range(1, 18))
+             "tests/test_oracle_rational.py", "tests/test_oracle_frenet_laws.py",
+             "tests/test_oracle_arclength_mesh.py"]
+MUTANTS = list(range(1, 20))
 
 
 def _run_pins(lib_path: str) -> subprocess.CompletedProcess:
