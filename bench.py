@@ -73,7 +73,8 @@ def _dev_weights(curve, dev):
     return None if w is None else torch.as_tensor(w).to(dev)
 
 
-def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, frame_mode="rmf", law=None):
+def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, frame_mode="rmf", law=None,
+                u_sampling="parameter"):
     """Wall time of `steps` sweep_eval calls, the per-call (frame, surface)
     stage times from the library's HIP events, and optionally the outputs."""
     import torch
@@ -87,7 +88,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     glaw = None if law is None else api.Law(torch.as_tensor(law.ctrl).to(dev), law.degree, law.knots)
     ws = torch.empty(api.eval_workspace_size(P.shape[0], spec.path.degree, Q.shape[0], spec.profile.degree,
                                              spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype,
-                                             frame_mode=frame_mode, law=glaw),
+                                             frame_mode=frame_mode, law=glaw, u_sampling=u_sampling),
                      dtype=torch.uint8, device=dev)
 
     Pw, Qw = _dev_weights(spec.path, dev), _dev_weights(spec.profile, dev)
@@ -95,7 +96,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     def step():
         api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v, out_dtype=out_dtype,
                        frame_dtype=frame_dtype, path_weights=Pw, prof_weights=Qw, frame_mode=frame_mode, law=glaw,
-                       out=(pos, nrm), workspace=ws)
+                       u_sampling=u_sampling, out=(pos, nrm), workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -117,7 +118,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     return t1 - t0, surf, frame, out
 
 
-def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None):
+def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None, arclength=False):
     """Parity figures of a GPU result on sampled rows against the oracle."""
     import numpy as np
     import torch
@@ -127,11 +128,11 @@ def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None):
     gp = pos.index_select(1, idx).double().cpu().numpy()
     gn = nrm.index_select(1, idx).double().cpu().numpy()
     x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
-    if frame_mode == "rmf" and law is None:
+    if frame_mode == "rmf" and law is None and not arclength:
         rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
     else:
         rp, rn, rk = oracle.sweep_rows_ex(spec.path, spec.profile, spec.n_u, spec.n_v, rows, mode=frame_mode,
-                                          law=law)
+                                          law=law, arclength=arclength)
     diag = float(np.linalg.norm(x.max(0) - x.min(0)))
     r = oracle.compare(rp, rn, rk, gp, gn, diag, 1e6)
     r["rows"] = len(rows)
@@ -201,6 +202,52 @@ def frenet_law_variant(steps: int):
             "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
             "frame_ms": sum(frame) / len(frame), "surface_ms": s_ms,
             "surface_GBps": 24.0 * N / (s_ms * 1e-3) / 1e9, "error_vs_oracle": err}
+
+
+def arclength_variant(steps: int):
+    """The large sweep with its path sampled at equal arc length (length
+    table, Newton inversion, then the same frame and surface): throughput,
+    stage times and sampled parity."""
+    import numpy as np
+    import torch
+    import synth
+
+    spec = synth.c2()
+    N = spec.n_u * spec.n_v
+    el, surf, frame, res = time_single(spec, steps, 1, torch.float32, keep=True, u_sampling="arclength")
+    rng = np.random.default_rng(10)
+    rows = np.unique(np.concatenate([[0, spec.n_u - 1], rng.integers(0, spec.n_u, 6)]))
+    err = sampled_error(spec, res[0], res[1], rows, 1e-5, arclength=True)
+    del res
+    torch.cuda.empty_cache()
+    return {"workload": "the large sweep, path samples at equal arc length",
+            "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
+            "frame_ms": sum(frame) / len(frame), "surface_ms": sum(surf) / len(surf), "error_vs_oracle": err}
+
+
+def triangles_variant(steps: int):
+    """The triangle list of the large sweep's grid (closed profile):
+    2 (n_u-1) n_v triangles of 3 int32, write-only."""
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+
+    spec = synth.c2()
+    nt = api.triangle_count(spec.n_u, spec.n_v, True)
+    tri = torch.empty((nt, 3), dtype=torch.int32, device="cuda")
+    api.triangles(spec.n_u, spec.n_v, True, out=tri)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        api.triangles(spec.n_u, spec.n_v, True, out=tri)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del tri
+    torch.cuda.empty_cache()
+    return {"workload": f"triangle list of the {spec.n_u}x{spec.n_v} grid, closed profile", "triangles": nt,
+            "ms": ms, "GBps": 12.0 * nt / (ms * 1e-3) / 1e9}
 
 
 def batched_variants(steps: int):
@@ -359,6 +406,8 @@ def main():
     ap.add_argument("--precision-study", action="store_true")
     ap.add_argument("--variants-only", action="store_true",
                     help="run only the batched (4096 sweeps) and adjoint (256 sweeps) variants and print them")
+    ap.add_argument("--variant", choices=["rational", "frenet_law", "arclength", "triangles", "batched", "adjoint"],
+                    help="run only this variant and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (3 launches) whose counter readings scale "
                          "the surface kernel's HBM traffic counters")
@@ -381,6 +430,13 @@ def main():
         log("[bench] adjoint ...")
         v["adjoint"] = adjoint_variant(args.steps)
         print(json.dumps(v), flush=True)
+        return
+
+    if args.variant:
+        fn = {"rational": rational_variant, "frenet_law": frenet_law_variant, "arclength": arclength_variant,
+              "triangles": triangles_variant, "batched": batched_variants, "adjoint": adjoint_variant}[args.variant]
+        log(f"[bench] {args.variant} ...")
+        print(json.dumps({args.variant: fn(args.steps)}), flush=True)
         return
 
     if args.copy_calibration:
@@ -435,6 +491,10 @@ def main():
         out["variants"]["rational_fp32_out"] = rational_variant(steps64)
         log("[bench] frenet + law ...")
         out["variants"]["frenet_law_fp32_out"] = frenet_law_variant(steps64)
+        log("[bench] arc length ...")
+        out["variants"]["arclength_fp32_out"] = arclength_variant(steps64)
+        log("[bench] triangles ...")
+        out["variants"]["triangles"] = triangles_variant(steps64)
         log("[bench] batched ...")
         out["variants"]["batched"] = batched_variants(max(3, args.steps // 4))
         log("[bench] adjoint ...")

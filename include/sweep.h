@@ -76,7 +76,7 @@
 extern "C" {
 #endif
 
-#define SWEEP_VERSION 102  /* major*100 + minor */
+#define SWEEP_VERSION 103  /* major*100 + minor */
 #define SWEEP_MAX_DEGREE 7
 
 typedef enum {
@@ -117,6 +117,19 @@ typedef enum { SWEEP_F32 = 0, SWEEP_F64 = 1 } sweep_precision;
  */
 typedef enum { SWEEP_FRAME_RMF = 0, SWEEP_FRAME_FRENET = 1 } sweep_frame_mode;
 
+/*
+ * Path sampling.  SWEEP_U_PARAMETER: the uniform parameter samples above.
+ * SWEEP_U_ARCLENGTH: u_i with s(u_i) = (i/(n_u-1)) s(U_n), s(u) the arc
+ * length from the start of the domain (u_0 and u_{n_u-1} the domain ends).
+ * Every non-empty knot span is cut into 32 equal pieces integrated by
+ * 8-point Gauss-Legendre (a cumulative table); inside the piece holding a
+ * target, Newton's method on s(u) - target kept in a bisection bracket, to
+ * |du| <= 4 eps max(1, |u|).  Supported by sweep_eval (not with a law) and
+ * sweep_frames; the batched and adjoint entry points return
+ * SWEEP_ERR_UNSUPPORTED.
+ */
+typedef enum { SWEEP_U_PARAMETER = 0, SWEEP_U_ARCLENGTH = 1 } sweep_u_sampling;
+
 /* A B-spline curve. */
 typedef struct sweep_curve_s {
     int32_t n_ctrl;      /* control points (for a closed curve: the m distinct ones) */
@@ -146,6 +159,8 @@ typedef struct {
                                  surface-kernel configuration (sweep_tile_config_count) */
     int32_t frame_mode;       /* SWEEP_FRAME_RMF (default) or SWEEP_FRAME_FRENET, see above */
     const struct sweep_curve_s *law; /* NULL (default) or a sweep law, see above */
+    int32_t u_sampling;       /* SWEEP_U_PARAMETER (default) or SWEEP_U_ARCLENGTH, see above */
+    int32_t reserved;
 } sweep_options;
 
 /* A batch of independent sweeps.  Per-sweep arrays are HOST memory with
@@ -268,6 +283,20 @@ sweep_status sweep_autotune(const sweep_curve *path, const sweep_curve *profile,
 /* The surface configuration tile_config = -1 selects for this shape and
  * output precision (the tuned one if recorded, else the built-in rule). */
 int32_t sweep_surface_config_for(int32_t n_u, int32_t n_v, int32_t out_precision);
+
+/*
+ * Triangle list of an n_u x n_v grid (vertex (i, j) has index i*n_v + j, the
+ * single-sweep layout): every quad (i, j), (i+1, j), (i, j+1), (i+1, j+1),
+ * j+1 taken modulo n_v when closed_v (a closed profile), gives the triangles
+ *     (i,j) (i,j+1) (i+1,j)   and   (i+1,j) (i,j+1) (i+1,j+1),
+ * counter-clockwise seen from the side the normal X_v x X_u points to.
+ * tri: DEVICE, 3 int32 per triangle, quads in row-major order; n_tri (HOST,
+ * may be NULL) receives 2 (n_u-1) (closed_v ? n_v : n_v-1).  max_tri is the
+ * capacity of tri in triangles; a smaller capacity is an error
+ * (SWEEP_ERR_WORKSPACE) and nothing is written.
+ */
+sweep_status sweep_triangles(int32_t n_u, int32_t n_v, int32_t closed_v, int32_t *tri, int64_t max_tri,
+                             int64_t *n_tri, void *stream);
 
 /* Number of fixed surface-kernel configurations accepted in tile_config. */
 int32_t sweep_tile_config_count(void);

@@ -21,6 +21,7 @@ STATUS = {
 }
 SWEEP_F32, SWEEP_F64 = 0, 1
 SWEEP_FRAME_RMF, SWEEP_FRAME_FRENET = 0, 1
+SWEEP_U_PARAMETER, SWEEP_U_ARCLENGTH = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -35,7 +36,7 @@ class SweepOptions(C.Structure):
     _fields_ = [("out_precision", C.c_int32), ("frame_precision", C.c_int32),
                 ("reorthonormalize", C.c_int32), ("has_initial_normal", C.c_int32),
                 ("initial_normal", C.c_double * 3), ("tile_config", C.c_int32), ("frame_mode", C.c_int32),
-                ("law", C.c_void_p)]
+                ("law", C.c_void_p), ("u_sampling", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SweepBatch(C.Structure):
@@ -95,6 +96,8 @@ def lib():
         L.sweep_autotune.restype = C.c_int32
         L.sweep_surface_config_for.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.sweep_surface_config_for.restype = C.c_int32
+        L.sweep_triangles.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64), vp]
+        L.sweep_triangles.restype = C.c_int32
         L.sweep_tile_config_count.argtypes = []
         L.sweep_tile_config_count.restype = C.c_int32
         L.sweep_last_error.argtypes = []
@@ -168,6 +171,13 @@ def sweep_batched_output_elems(batch: SweepBatch) -> int:
 
 def sweep_backward_workspace_size(batch: SweepBatch, opt: SweepOptions) -> int:
     return lib().sweep_backward_workspace_size(C.byref(batch), C.byref(opt))
+
+
+def sweep_triangles(n_u: int, n_v: int, closed_v: int, tri: int, max_tri: int, stream: int):
+    """(status, n_tri)."""
+    n = C.c_int64(0)
+    st = lib().sweep_triangles(n_u, n_v, closed_v, tri, max_tri, C.byref(n), stream)
+    return st, n.value
 
 
 def sweep_trace_enable(max_calls: int) -> int:

@@ -70,9 +70,12 @@ class Law:
         self.c = L.SweepCurve(self.ctrl.shape[0], self.degree, 0, 0, self.ctrl.data_ptr(), kp, _wptr(self.weights))
 
 
+_U_SAMPLING = {"parameter": L.SWEEP_U_PARAMETER, "arclength": L.SWEEP_U_ARCLENGTH}
+
+
 def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                  initial_normal=None, tile_config: int = -1, frame_mode: str = "rmf",
-                 law: Optional[Law] = None) -> L.SweepOptions:
+                 law: Optional[Law] = None, u_sampling: str = "parameter") -> L.SweepOptions:
     o = L.default_options()
     o.out_precision = _DT[out_dtype]
     o.frame_precision = _DT[frame_dtype]
@@ -85,6 +88,9 @@ def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonorm
     if frame_mode not in _FRAME_MODES:
         raise ValueError(f"frame_mode must be one of {sorted(_FRAME_MODES)}")
     o.frame_mode = _FRAME_MODES[frame_mode]
+    if u_sampling not in _U_SAMPLING:
+        raise ValueError(f"u_sampling must be one of {sorted(_U_SAMPLING)}")
+    o.u_sampling = _U_SAMPLING[u_sampling]
     if law is not None:
         o.law = C.cast(C.pointer(law.c), C.c_void_p)
         o._law_ref = law          # keeps the curve struct and its buffers alive
@@ -114,10 +120,12 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
                out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                initial_normal=None, tile_config: int = -1, normals: bool = True,
                path_weights=None, prof_weights=None, frame_mode: str = "rmf", law: Optional[Law] = None,
+               u_sampling: str = "parameter",
                out: Optional[Tuple[torch.Tensor, Optional[torch.Tensor]]] = None,
                workspace: Optional[torch.Tensor] = None, stream=None):
     """Positions (3, n_u, n_v) and normals (or None) of one sweep; with
-    weights (device float64, one per control point) a curve is rational."""
+    weights (device float64, one per control point) a curve is rational;
+    u_sampling="arclength" places the path samples at equal arc length."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
     qc = _check_ctrl(prof_ctrl, "prof_ctrl")
     pw = _weights(path_weights, pc.shape[0], "path_weights")
@@ -126,7 +134,8 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
     qk, qkp = _knots_ptr(prof_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law,
+                       u_sampling)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         # invalid metadata: let the call report the reason
@@ -153,7 +162,8 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
                    n_u: int, n_v: int, *, prof_closed: bool = True, path_knots=None, prof_knots=None,
                    out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                    initial_normal=None, normals: bool = True, path_weights=None, prof_weights=None,
-                   frame_mode: str = "rmf", law: Optional[Law] = None, stream=None):
+                   frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter",
+                   stream=None):
     """Times every surface configuration on this sweep and records the
     fastest for its shape class; returns (best_config, best_ms, pos, nrm)."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
@@ -164,7 +174,8 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
     qk, qkp = _knots_ptr(prof_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode, law=law)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode, law=law,
+                       u_sampling=u_sampling)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         L.check(L.sweep_eval(path, prof, int(n_u), int(n_v), opt, 0, 0, 0, 0, 0))
@@ -188,6 +199,7 @@ def surface_config_for(n_u: int, n_v: int, out_dtype=torch.float32) -> int:
 def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
                  out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
                  initial_normal=None, path_weights=None, frame_mode: str = "rmf",
+                 u_sampling: str = "parameter",
                  workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame
     (rotation-minimizing; other frame modes are sweep_eval only)."""
@@ -195,7 +207,8 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
     pw = _weights(path_weights, pc.shape[0], "path_weights")
     pk, pkp = _knots_ptr(path_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode,
+                       u_sampling=u_sampling)
     ws_bytes = L.sweep_frames_workspace_size(path, int(n_u), opt)
     if ws_bytes == 0:
         L.check(L.sweep_frames(path, int(n_u), opt, 0, 0, 0, 0))
@@ -209,11 +222,32 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
 
 def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree: int, n_u: int, n_v: int, *,
                         prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64,
-                        frame_mode: str = "rmf", law: Optional[Law] = None) -> int:
+                        frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter") -> int:
     path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None, None)
     prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None, None)
     return L.sweep_eval_workspace_size(path, prof, n_u, n_v,
-                                       make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law))
+                                       make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law,
+                                                    u_sampling=u_sampling))
+
+
+def triangle_count(n_u: int, n_v: int, closed_v: bool = True) -> int:
+    return 2 * (int(n_u) - 1) * (int(n_v) if closed_v else int(n_v) - 1)
+
+
+def triangles(n_u: int, n_v: int, closed_v: bool = True, *, out: Optional[torch.Tensor] = None,
+              device="cuda", stream=None) -> torch.Tensor:
+    """Triangle list (n_tri, 3) int32 of the n_u x n_v grid of a sweep
+    (vertex (i, j) = i*n_v + j), counter-clockwise about X_v x X_u."""
+    nt = triangle_count(n_u, n_v, closed_v)
+    if out is None:
+        out = torch.empty((max(nt, 0), 3), dtype=torch.int32, device=device)
+    else:
+        _check_out(out, 3 * nt, torch.int32, "out")
+    st, n = L.sweep_triangles(int(n_u), int(n_v), int(bool(closed_v)), out.data_ptr() if out.numel() else 0,
+                              out.numel() // 3, _stream_handle(stream))
+    L.check(st)
+    assert n == nt
+    return out
 
 
 class Batch:

@@ -19,6 +19,7 @@ int tile_config_count();
 const SurfaceConfig& tile_config(int k);
 SurfaceConfig auto_surface_config(int n_u, int n_v, int t64);
 bool options_ext(const sweep_options* o);
+bool options_single_only(const sweep_options* o);
 sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, hipStream_t st);
 
 }  // namespace sweep

@@ -66,7 +66,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     if (!o) return fail(SWEEP_ERR_NULL_ARG, "options are NULL");
     sweep_status st = check_options(o);
     if (st != SWEEP_OK) return st;
-    if (options_ext(o)) return fail(SWEEP_ERR_UNSUPPORTED, "frame modes and laws are sweep_eval only");
+    if (options_single_only(o))
+        return fail(SWEEP_ERR_UNSUPPORTED, "frame modes, laws and arc-length sampling are sweep_eval only");
     if (b->n_sweeps < 1) return fail(SWEEP_ERR_BAD_COUNT, "n_sweeps %d < 1", b->n_sweeps);
     if (!b->path_n || !b->path_degree || !b->prof_n || !b->prof_degree || !b->n_u || !b->n_v)
         return fail(SWEEP_ERR_NULL_ARG, "a per-sweep array is NULL");

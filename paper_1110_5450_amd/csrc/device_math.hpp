@@ -69,6 +69,8 @@ struct DCurve {
     int closed;  // periodic uniform
     int nb;      // basis functions: n (open) or n + p (closed)
     const double* __restrict__ w;      // n weights (rational curve), or nullptr
+    const double* __restrict__ su;     // sample parameters (arc-length sampling), or nullptr
+    const int* __restrict__ ss;        // their spans
 };
 
 __device__ __forceinline__ V3<double> ctrl_pt(const DCurve& c, int k)
@@ -307,6 +309,10 @@ __device__ __forceinline__ void curve_derivs(const DCurve& c, double u, int s, V
 template <int P, int ND>
 __device__ __forceinline__ void sample_derivs(const DCurve& c, int i, int ns, V3<double>* out)
 {
+    if (c.su) {   // tabulated sample parameters (arc-length sampling)
+        curve_derivs<P, ND>(c, c.su[i], c.ss[i], out);
+        return;
+    }
     const double u = sample_param(c, i, ns);
     curve_derivs<P, ND>(c, u, sample_span(c, i, ns, u), out);
 }

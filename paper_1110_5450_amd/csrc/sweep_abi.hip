@@ -120,6 +120,10 @@ sweep_status check_options(const sweep_options* o)
         return fail(SWEEP_ERR_BAD_OPTION, "tile_config %d outside -1..%d", o->tile_config, tile_config_count() - 1);
     if (o->frame_mode != SWEEP_FRAME_RMF && o->frame_mode != SWEEP_FRAME_FRENET)
         return fail(SWEEP_ERR_BAD_OPTION, "frame_mode %d is not RMF (0) or FRENET (1)", o->frame_mode);
+    if (o->u_sampling != SWEEP_U_PARAMETER && o->u_sampling != SWEEP_U_ARCLENGTH)
+        return fail(SWEEP_ERR_BAD_OPTION, "u_sampling %d is not PARAMETER (0) or ARCLENGTH (1)", o->u_sampling);
+    if (o->u_sampling == SWEEP_U_ARCLENGTH && o->law)
+        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length sampling with a sweep law");
     if (o->law) {
         if (o->law->closed) return fail(SWEEP_ERR_UNSUPPORTED, "law: the law curve must be open");
         sweep_status st = check_curve(o->law, "law", true);
@@ -130,6 +134,9 @@ sweep_status check_options(const sweep_options* o)
 
 // Options that need the extended row records (Frenet frame or a law).
 bool options_ext(const sweep_options* o) { return o->frame_mode != SWEEP_FRAME_RMF || o->law != nullptr; }
+
+// Options supported by sweep_eval only.
+bool options_single_only(const sweep_options* o) { return options_ext(o) || o->u_sampling != SWEEP_U_PARAMETER; }
 
 // Parameter domain [U_p, U_n] of an open curve (given knots or [0, 1]).
 static double domain_length(const sweep_curve* c)
@@ -278,13 +285,14 @@ SurfaceConfig auto_surface_config(int n_u, int n_v, int t64)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, knots_law, total;
+    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, knots_law;
+    size_t arc_len, arc_cum, arc_u, arc_span, total;
 };
 
 // rl: values per row record (16, or kRowExt with a frame mode or law);
 // nlk: knots of the law curve (0 without a law or with its default knots).
 static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, int n_u, int n_v, size_t fsz, size_t tsz,
-                                  int rl = 16, int nlk = 0)
+                                  int rl = 16, int nlk = 0, bool arclength = false)
 {
     SingleLayout L{};
     const int nc = (n_u + frame_chunk_size() - 1) / frame_chunk_size();
@@ -300,6 +308,11 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
     L.rows = off;       off = align_up(off + tsz * (size_t)rl * (size_t)n_u);
     L.prof_tab = off;   off = align_up(off + tsz * 8 * (size_t)n_v);
     L.knots_law = off;  off = align_up(off + sizeof(double) * (size_t)nlk);
+    const size_t npc = arclength ? (size_t)(np - pp) * 32 : 0;   // pieces of the arc-length table
+    L.arc_len = off;    off = align_up(off + sizeof(double) * npc);
+    L.arc_cum = off;    off = align_up(off + sizeof(double) * (arclength ? npc + 1 : 0));
+    L.arc_u = off;      off = align_up(off + sizeof(double) * (arclength ? (size_t)n_u : 0));
+    L.arc_span = off;   off = align_up(off + sizeof(int) * (arclength ? (size_t)n_u : 0));
     L.total = off;
     return L;
 }
@@ -311,7 +324,7 @@ static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof,
     const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
     const int nlk = (o->law && o->law->knots) ? nknots(o->law->n_ctrl, o->law->degree, 0) : 0;
     return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz,
-                         options_ext(o) ? kRowExt : 16, nlk);
+                         options_ext(o) ? kRowExt : 16, nlk, o->u_sampling == SWEEP_U_ARCLENGTH);
 }
 
 // Copies given knots to the device (a blocking copy from pageable memory);
@@ -321,6 +334,21 @@ sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, h
     if (!host_knots) return SWEEP_OK;
     hipError_t e = hipMemcpyAsync(dst, host_knots, sizeof(double) * nknots(n, p, 0), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "knots");
+    return SWEEP_OK;
+}
+
+// Arc-length sampling: tabulates the path's sample parameters and spans in
+// the workspace and points the curve at them.
+static sweep_status setup_arclength(DCurve& dp, int n_u, const sweep_options* o, char* ws, const SingleLayout& L,
+                                    hipStream_t st)
+{
+    if (o->u_sampling != SWEEP_U_ARCLENGTH) return SWEEP_OK;
+    double* su = (double*)(ws + L.arc_u);
+    int* ss = (int*)(ws + L.arc_span);
+    hipError_t e = launch_arclength(dp, n_u, (double*)(ws + L.arc_len), (double*)(ws + L.arc_cum), su, ss, st);
+    if (e != hipSuccess) return hip_fail(e, "arc-length sampling");
+    dp.su = su;
+    dp.ss = ss;
     return SWEEP_OK;
 }
 
@@ -335,6 +363,7 @@ static sweep_status run_frames(const sweep_curve* path, int n_u, const sweep_opt
     DCurve dp{path->ctrl, path->knots ? Up : nullptr, path->n_ctrl, path->degree, 0,
               nbasis(path->n_ctrl, path->degree, 0), path->weights};
     DCurve dq{nullptr, nullptr, 1, 1, 0, 1, nullptr};
+    if ((s = setup_arclength(dp, n_u, o, ws, L, st)) != SWEEP_OK) return s;
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
@@ -364,6 +393,7 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
               nbasis(path->n_ctrl, path->degree, 0), path->weights};
     DCurve dq{prof->ctrl, prof->knots ? Uq : nullptr, prof->n_ctrl, prof->degree, prof->closed,
               nbasis(prof->n_ctrl, prof->degree, prof->closed), prof->weights};
+    if ((s = setup_arclength(dp, n_u, o, ws, L, st)) != SWEEP_OK) return s;
     double* smp = (double*)(ws + L.smp);
     int* clv = (int*)(ws + L.chunk_lv);
     double* fb = (double*)(ws + L.fallback);
@@ -493,7 +523,8 @@ size_t sweep_frames_workspace_size(const sweep_curve* path, int32_t n_u, const s
     if (check_curve_meta(path->n_ctrl, path->degree, path->closed, path->knots, "path", true) != SWEEP_OK) return 0;
     if (n_u < 2 || check_options(opt) != SWEEP_OK) return 0;
     const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
-    return single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0).total;
+    return single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0, 16, 0,
+                         opt->u_sampling == SWEEP_U_ARCLENGTH).total;
 }
 
 sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_options* opt, void* frames,
@@ -505,10 +536,11 @@ sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_opti
     if (s != SWEEP_OK) return s;
     if ((s = check_curve(path, "path", true)) != SWEEP_OK) return s;
     if (options_ext(opt)) return fail(SWEEP_ERR_UNSUPPORTED, "sweep_frames: frame modes and laws are sweep_eval only");
+    const bool arc = opt->u_sampling == SWEEP_U_ARCLENGTH;
     if (n_u < 2 || n_u >= (1 << 30)) return fail(SWEEP_ERR_BAD_GRID, "n_u %d outside 2..2^30-1", n_u);
     if (!frames) return fail(SWEEP_ERR_NULL_ARG, "frames is NULL");
     const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
-    const SingleLayout L = single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0);
+    const SingleLayout L = single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0, 16, 0, arc);
     if (!workspace || ws_bytes < L.total)
         return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, L.total);
     if (((uintptr_t)workspace) % 256 != 0) return fail(SWEEP_ERR_WORKSPACE, "workspace is not 256-byte aligned");
@@ -583,6 +615,21 @@ int32_t sweep_surface_config_for(int32_t n_u, int32_t n_v, int32_t out_precision
             return k;
     }
     return -1;
+}
+
+sweep_status sweep_triangles(int32_t n_u, int32_t n_v, int32_t closed_v, int32_t* tri, int64_t max_tri,
+                             int64_t* n_tri, void* stream)
+{
+    if (closed_v != 0 && closed_v != 1) return fail(SWEEP_ERR_BAD_OPTION, "closed_v %d is not 0/1", closed_v);
+    sweep_status s = check_grid(n_u, n_v);
+    if (s != SWEEP_OK) return s;
+    const long long nt = 2LL * (n_u - 1) * (closed_v ? n_v : n_v - 1);
+    if (n_tri) *n_tri = nt;
+    if (!tri) return fail(SWEEP_ERR_NULL_ARG, "tri is NULL");
+    if (max_tri < nt) return fail(SWEEP_ERR_WORKSPACE, "tri holds %lld triangles, %lld needed", (long long)max_tri, nt);
+    const hipError_t e = launch_triangles(n_u, n_v, closed_v, tri, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "triangles");
+    return SWEEP_OK;
 }
 
 int32_t sweep_tile_config_count(void) { return tile_config_count(); }

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert L.sweep_version() == 102
+    assert L.sweep_version() == 103
     o = L.default_options()
     assert (o.out_precision, o.frame_precision, o.reorthonormalize, o.has_initial_normal, o.tile_config) == (0, 1, 1, 0, -1)
     assert L.sweep_tile_config_count() >= 8
@@ -166,3 +166,34 @@ def test_frame_mode_and_law_options():
     # frames-only entry point and batches do not take frame modes or laws
     st = L.sweep_frames(a, 256, o2, FAKE, FAKE, 1 << 40, 0)
     assert L.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
+
+
+def test_u_sampling_options():
+    a, b = _curves()
+    o = L.default_options()
+    assert o.u_sampling == 0
+    o.u_sampling = 2
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_BAD_OPTION", "u_sampling")
+    # arc-length sampling needs room for the length table and sample parameters
+    o = L.default_options()
+    o.u_sampling = 1
+    base = L.sweep_eval_workspace_size(a, b, 256, 64, L.default_options())
+    arc = L.sweep_eval_workspace_size(a, b, 256, 64, o)
+    assert arc >= base + 8 * (16 - 3) * 32 + 8 * 256
+    assert L.sweep_frames_workspace_size(a, 256, o) > L.sweep_frames_workspace_size(a, 256, L.default_options())
+    # not together with a law
+    law = L.SweepCurve(4, 1, 0, 0, FAKE, None)
+    o.law = C.cast(C.pointer(law), C.c_void_p)
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_UNSUPPORTED", "arc-length")
+
+
+def test_triangles_validation():
+    n = C.c_int64(-1)
+    lib = L.lib()
+    # the count is reported before the buffer is looked at
+    st = lib.sweep_triangles(5, 7, 1, None, 0, C.byref(n), None)
+    assert L.STATUS[st] == "SWEEP_ERR_NULL_ARG" and n.value == 2 * 4 * 7
+    st = lib.sweep_triangles(5, 7, 0, FAKE, 2 * 4 * 6 - 1, C.byref(n), None)
+    assert L.STATUS[st] == "SWEEP_ERR_WORKSPACE" and n.value == 2 * 4 * 6
+    assert L.STATUS[lib.sweep_triangles(5, 7, 2, FAKE, 1 << 40, None, None)] == "SWEEP_ERR_BAD_OPTION"
+    assert L.STATUS[lib.sweep_triangles(1, 7, 1, FAKE, 1 << 40, None, None)] == "SWEEP_ERR_BAD_GRID"

@@ -1,0 +1,195 @@
+"""Arc-length sampling of the path and the triangle list on the GPU (next-row
+f4): parity with the oracle's arc-length sweep (polynomial, given knots with
+repeated interior knots, rational; FP64 and FP32 output; several frame chunks
+and a ragged tail; sampled rows at the 65,536 x 1,024 size), the closed forms
+(an unevenly parametrised line sampled at equal steps, a NURBS circle at equal
+angles) computed on the device, and the triangle list bit-exact against the
+oracle's, consistent with the GPU normals."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1110_5450_amd import _lib, api
+from tests.gpu_util import TOL, dev_ctrl, gpu_sweep, parity, say
+from tests.test_oracle_rational import nurbs_circle
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+
+
+def _check(spec, out_dtype, tol=None, n0=None):
+    say(f"[case] arclength n_u={spec.n_u} n_v={spec.n_v} p={spec.path.degree} knots={spec.path.knots is not None} "
+        f"rational={getattr(spec.path, 'weights', None) is not None} out={out_dtype}")
+    ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, spec.n_v, n0=n0, arclength=True)
+    pos, nrm = gpu_sweep(spec, out_dtype, u_sampling="arclength", initial_normal=n0)
+    torch.cuda.synchronize()
+    ok, r = parity(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(),
+                   TOL[out_dtype] if tol is None else tol)
+    say("   ", r)
+    assert ok, r
+    return r
+
+
+@pytest.mark.parametrize("out_dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("p", [1, 3, 5, 7])
+def test_arclength_sweep_matches_oracle(out_dtype, p):
+    spec = synth.single(120 + p, 13, 9, 1000, 67, p_path=p)
+    _check(spec, out_dtype)
+
+
+@pytest.mark.parametrize("rational", [False, True])
+def test_arclength_with_repeated_knots_and_rational_path(rational):
+    rng = np.random.default_rng(12)
+    P = synth.random_walk(rng, 10)
+    U = np.array([0, 0, 0, 0, .1, .3, .3, .6, .75, .9, 1.7, 1.7, 1.7, 1.7])   # a double interior knot
+    spec = synth.SweepSpec(synth.CurveSpec(P, 3, knots=U), synth.CurveSpec(synth.perturbed_circle(rng, 8), 3, True),
+                           777, 40)
+    if rational:
+        spec.path.weights = rng.uniform(0.5, 2.0, 10)
+    _check(spec, torch.float64)
+
+
+def test_arclength_through_a_cusp():
+    # A triple interior knot makes the cubic path only C0: here it turns by
+    # 177 degrees between two samples 6e-4 apart in u.  The short chord
+    # across the cusp carries the rounding of the sample positions into the
+    # rotation of every frame after it: the oracle itself moves its normals
+    # by 1.2e-12 when its sample parameters are perturbed by 1e-16
+    # (relative), so the normals are held to 1e-11 here.
+    rng = np.random.default_rng(12)
+    P = synth.random_walk(rng, 10)
+    U = np.array([0, 0, 0, 0, .1, .3, .3, .3, .6, .9, 1.7, 1.7, 1.7, 1.7])
+    spec = synth.SweepSpec(synth.CurveSpec(P, 3, knots=U), synth.CurveSpec(synth.perturbed_circle(rng, 8), 3, True),
+                           777, 40)
+    _check(spec, torch.float64, tol=1e-11)
+
+
+def test_arclength_samples_on_a_line_and_a_circle():
+    # an unevenly parametrised straight line: equal steps along it
+    P = np.array([[0, 0, 0], [0.1, 0.2, 0.3], [0.15, 0.3, 0.45], [1, 2, 3], [2, 4, 6.0]])
+    n_u = 1001
+    rows = api.sweep_frames(dev_ctrl(P), 3, n_u, u_sampling="arclength").cpu().numpy()
+    x = rows[:, 0:3]
+    total = np.linalg.norm(P[-1] - P[0])
+    d = np.linalg.norm(np.diff(x, axis=0), axis=1)
+    say(f"   line: max step error {np.abs(d - total / (n_u - 1)).max():.3e}")
+    assert np.abs(d - total / (n_u - 1)).max() <= 256 * EPS * total
+    # the parameter rule is far from it
+    xu = api.sweep_frames(dev_ctrl(P), 3, n_u).cpu().numpy()[:, 0:3]
+    assert np.ptp(np.linalg.norm(np.diff(xu, axis=0), axis=1)) > 1e-3
+    # a NURBS circle: equal angles
+    r = 0.7
+    ctrl, w, U = nurbs_circle(r)
+    rows = api.sweep_frames(dev_ctrl(ctrl), 2, 361, path_knots=U, path_weights=dev_ctrl(w),
+                            u_sampling="arclength").cpu().numpy()
+    ang = np.unwrap(np.arctan2(rows[:, 1], rows[:, 0]))
+    err = np.abs(ang - 2 * np.pi * np.arange(361) / 360).max()
+    say(f"   circle: max angle error {err:.3e}")
+    assert err <= 256 * EPS
+
+
+def test_arclength_frames_match_oracle():
+    spec = synth.single(131, 40, 8, 3000, 8)
+    rows = api.sweep_frames(dev_ctrl(spec.path.ctrl), 3, spec.n_u, u_sampling="arclength").cpu().numpy()
+    ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, 3, arclength=True, want_kappa=False)
+    u, _ = oracle.arclength_params(spec.path, spec.n_u)
+    x, = oracle.curve_at(spec.path, u, nd=0)
+    scale = np.abs(x).max()
+    assert np.abs(rows[:, 0:3] - x).max() <= 1e-13 * scale
+    # frame columns r, s, t against the oracle's frame
+    R = ref.frame
+    for c, off in enumerate((3, 6, 9)):
+        assert np.abs(rows[:, off:off + 3] - R[:, :, c]).max() <= 1e-11
+
+
+def test_arclength_large_sweep_sampled_rows():
+    spec = synth.c2()
+    say(f"[case] arclength sampled rows n_u={spec.n_u} n_v={spec.n_v}")
+    pos, nrm = gpu_sweep(spec, torch.float32, u_sampling="arclength")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    rows = np.unique(np.concatenate([[0, 1, 255, 256, 4096, spec.n_u - 2, spec.n_u - 1],
+                                     rng.integers(0, spec.n_u, 5)]))
+    idx = torch.as_tensor(rows, device=pos.device)
+    gp = pos.index_select(1, idx).cpu().numpy()
+    gn = nrm.index_select(1, idx).cpu().numpy()
+    del pos, nrm
+    torch.cuda.empty_cache()
+    u, _ = oracle.arclength_params(spec.path, spec.n_u)
+    x, = oracle.curve_at(spec.path, u, nd=0)
+    rp, rn, rk = oracle.sweep_rows_ex(spec.path, spec.profile, spec.n_u, spec.n_v, rows, arclength=True)
+    ok, r = parity(rp, rn, rk, gp, gn, TOL[torch.float32], diag=float(np.linalg.norm(x.max(0) - x.min(0))))
+    say("   ", r)
+    assert ok, r
+
+
+def test_arclength_rejected_where_unsupported():
+    spec = synth.single(140, 8, 8, 64, 16)
+    law = api.Law(dev_ctrl(np.array([[1, 0, 0], [1.2, 0.3, 0], [0.9, 0.5, 0.0]])), 2)
+    with pytest.raises(_lib.SweepError, match="UNSUPPORTED"):
+        gpu_sweep(spec, u_sampling="arclength", law=law)
+    b = api.Batch.from_specs([spec])
+    opt = api.make_options(u_sampling="arclength")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    pos = torch.empty(b.out_elems, device="cuda")
+    st = _lib.sweep_eval_batched(b.c_struct(), opt, pos.data_ptr(), 0, ws.data_ptr(), ws.numel(), 0)
+    assert _lib.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("n_u,n_v,closed", [(2, 3, True), (2, 3, False), (17, 64, True), (300, 257, False),
+                                             (4096, 1024, True), (1025, 31, False)])
+def test_triangles_bit_exact(n_u, n_v, closed):
+    say(f"[case] triangles {n_u}x{n_v} closed={closed}")
+    tri = api.triangles(n_u, n_v, closed)
+    torch.cuda.synchronize()
+    ref = oracle.triangles(n_u, n_v, closed)
+    assert tri.shape == ref.shape == (api.triangle_count(n_u, n_v, closed), 3)
+    assert np.array_equal(tri.cpu().numpy(), ref)
+
+
+def test_triangles_into_a_given_buffer_and_short_buffer():
+    n_u, n_v = 50, 40
+    nt = api.triangle_count(n_u, n_v, True)
+    buf = torch.full((nt + 10, 3), -7, dtype=torch.int32, device="cuda")
+    api.triangles(n_u, n_v, True, out=buf)
+    torch.cuda.synchronize()
+    assert np.array_equal(buf[:nt].cpu().numpy(), oracle.triangles(n_u, n_v, True))
+    assert torch.all(buf[nt:] == -7)
+    with pytest.raises(ValueError, match="elements"):
+        api.triangles(n_u, n_v, True, out=torch.empty((nt - 1, 3), dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("n_u,n_v,closed", [(3, 3, False), (33, 17, True), (700, 129, False)])
+def test_triangles_unaligned_buffer(n_u, n_v, closed):
+    # a buffer 4 bytes past a 16-byte boundary takes the one-int-per-thread kernel
+    nt = api.triangle_count(n_u, n_v, closed)
+    base = torch.full((3 * nt + 2,), -7, dtype=torch.int32, device="cuda")
+    view = base[1:1 + 3 * nt]
+    assert view.data_ptr() % 16 == 4
+    api.triangles(n_u, n_v, closed, out=view)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy().reshape(-1, 3), oracle.triangles(n_u, n_v, closed))
+    assert int(base[0]) == -7 and int(base[-1]) == -7
+
+
+@pytest.mark.parametrize("u_sampling", ["parameter", "arclength"])
+def test_triangles_face_the_gpu_normals(u_sampling):
+    # smooth path, closed profile: every face normal points along the
+    # vertex normals (counter-clockwise about X_v x X_u)
+    path = np.array([[0, 0, 0], [1, 0.2, 0], [2, 0, 0.3], [3, -0.3, 0.5], [4, 0, 0.4]])
+    rng = np.random.default_rng(8)
+    spec = synth.SweepSpec(synth.CurveSpec(path, 3), synth.CurveSpec(synth.perturbed_circle(rng, 9), 3, True), 200, 96)
+    pos, nrm = gpu_sweep(spec, torch.float64, u_sampling=u_sampling)
+    tri = api.triangles(spec.n_u, spec.n_v, True).long()
+    X = pos.reshape(3, -1).T
+    N = nrm.reshape(3, -1).T
+    a, b, c = X[tri[:, 0]], X[tri[:, 1]], X[tri[:, 2]]
+    fn = torch.cross(b - a, c - a, dim=1)
+    vn = N[tri[:, 0]] + N[tri[:, 1]] + N[tri[:, 2]]
+    assert bool(((fn * vn).sum(1) > 0).all())
