@@ -62,8 +62,8 @@ def lib():
         L.or_loss.restype = C.c_double
         L.or_fd_grad.restype = None
         L.or_fd_grad.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int,
-                                 _dp, _dp, C.c_double, _dp, _dp]
-        L.or_loss.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, _dp]
+                                 _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.or_loss.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, _dp, _dp]
         L.or_max_threads.restype = C.c_int
         L.or_sweep_ex.restype = C.c_int
         L.or_sweep_ex.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, C.c_int, C.c_int,
@@ -194,7 +194,7 @@ def surface_from_samples(x, d1, d2, R, S, dS, want_kappa: bool = True):
     nrm = np.empty((3, nu, nv))
     kap = np.empty((nu, nv)) if want_kappa else None
     lib().or_surface_rows(C.c_int(nu), C.c_int(nv), C.c_int(0), C.c_int(nu), _ptr(x), _ptr(d1), _ptr(d2),
-                          _ptr(Rr), _ptr(S), _ptr(dS), _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
+                          _ptr(Rr), _ptr(S), _ptr(dS), _ptr(pos), _ptr(nrm), _ptr(kap), None, None, None)
     return pos, nrm, kap
 
 
@@ -361,26 +361,33 @@ def profile_samples(profile, n_v: int):
     return Curve.of(profile).samples(n_v, nd=1)
 
 
-def loss(path, profile, n_u: int, n_v: int, w, n0=None) -> float:
-    """L = sum w . X, w shaped (3, n_u, n_v)."""
+def _grid_weights(a, n_u: int, n_v: int):
+    if a is None:
+        return None
+    a = _f64(a)
+    assert a.shape == (3, n_u, n_v)
+    return a
+
+
+def loss(path, profile, n_u: int, n_v: int, w, n0=None, g=None) -> float:
+    """L = sum w . X + sum g . N, w and g shaped (3, n_u, n_v) (either may
+    be None: that term is left out)."""
     P, Q = Curve.of(path), Curve.of(profile)
-    w = _f64(w)
-    assert w.shape == (3, n_u, n_v)
+    w, g = _grid_weights(w, n_u, n_v), _grid_weights(g, n_u, n_v)
     n0a = None if n0 is None else _f64(n0)
-    return lib().or_loss(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w))
+    return lib().or_loss(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w), _ptr(g))
 
 
 def fd_grad(path, profile, n_u: int, n_v: int, w, h: float = 1e-6, n0=None,
-            want_path=True, want_profile=True):
-    """Central-difference gradient of L = sum w . X with respect to the path
-    and profile control points: (gP (n_path, 3), gQ (n_prof, 3))."""
+            want_path=True, want_profile=True, g=None):
+    """Central-difference gradient of L = sum w . X + sum g . N with respect
+    to the path and profile control points: (gP (n_path, 3), gQ (n_prof, 3))."""
     P, Q = Curve.of(path), Curve.of(profile)
-    w = _f64(w)
-    assert w.shape == (3, n_u, n_v)
+    w, g = _grid_weights(w, n_u, n_v), _grid_weights(g, n_u, n_v)
     gP = np.zeros((P.n, 3)) if want_path else None
     gQ = np.zeros((Q.n, 3)) if want_profile else None
     n0a = None if n0 is None else _f64(n0)
-    lib().or_fd_grad(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w), float(h), _ptr(gP), _ptr(gQ))
+    lib().or_fd_grad(P.ref, Q.ref, n_u, n_v, _ptr(n0a), _ptr(w), _ptr(g), float(h), _ptr(gP), _ptr(gQ))
     return gP, gQ
 
 

@@ -20,7 +20,7 @@
  *          frames", ACM TOG 27(1), 2008.
  *   O8     Surface X = C(u) + [r s t] S(v) and its normal from the partial
  *          derivatives, with the derivative of the continuous RMF.
- *   O10    Central finite differences of L = sum w . X.
+ *   O10    Central finite differences of L = sum w . X + sum g . N.
  * Where a published method leaves a choice open (degenerate tangents, the
  * initial normal, sampling, orientation) the choice is stated at the step.
  *
@@ -414,7 +414,7 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
                      const double *x, const double *d1, const double *d2, const double *R,
                      const double *S, const double *dS,
                      double *pos, double *nrm, double *kappa,
-                     const double *w, double *wsum)
+                     const double *w, const double *g, double *wsum)
 {
     size_t N = (size_t)nu * (size_t)nv;
     for (int i = row0; i < row1; ++i) {
@@ -446,10 +446,9 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
             size_t v = (size_t)i * (size_t)nv + (size_t)j;
             if (pos)
                 for (int e = 0; e < 3; ++e) pos[e * N + v] = X[e];
-            if (nrm) {
-                int ok = nn > 0.0 && isfinite(nn);
+            int ok = nn > 0.0 && isfinite(nn);
+            if (nrm)
                 for (int e = 0; e < 3; ++e) nrm[e * N + v] = ok ? cr[e] / nn : 0.0;
-            }
             if (kappa) {
                 double num = norm3(Xv) * (L + fabs(Sj[0] * a) + fabs(Sj[1] * b) +
                                           fabs(Sj[2]) * (fabs(a) + fabs(b)));
@@ -457,6 +456,8 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
             }
             if (w)
                 for (int e = 0; e < 3; ++e) acc += w[e * N + v] * X[e];
+            if (g && ok)
+                for (int e = 0; e < 3; ++e) acc += g[e * N + v] * (MUT(20) ? cr[e] : cr[e] / nn);
         }
         if (wsum) wsum[i - row0] = acc;
     }
@@ -806,7 +807,7 @@ int or_sweep(const or_curve *path, const or_curve *prof, int nu, int nv,
     int nf = or_frame(nu, x, d1, ft, n0, reorth, R);
     #pragma omp parallel for schedule(static)
     for (int i = row0; i < row1; ++i)
-        or_surface_rows(nu, nv, i, i + 1, x, d1, d2, R, S, dS, pos, nrm, kappa, NULL, NULL);
+        or_surface_rows(nu, nv, i, i + 1, x, d1, d2, R, S, dS, pos, nrm, kappa, NULL, NULL, NULL);
     free(S);
     if (!frame_out) free(R);
     free(x);
@@ -869,9 +870,11 @@ void or_path_samples(const or_curve *path, int nu, double *x, double *d1, double
 
 /* ------------------------------------------------- O10 loss and gradient */
 
-/* L = sum_{c,i,j} w[c,i,j] X[c,i,j] (X over the full grid), sequential. */
+/* L = sum_{c,i,j} (w[c,i,j] X[c,i,j] + g[c,i,j] N[c,i,j]) over the full
+ * grid, sequential; w or g may be NULL (that term is left out).  N is the
+ * unit normal, 0 where it is undefined. */
 double or_loss(const or_curve *path, const or_curve *prof, int nu, int nv,
-               const double *n0, const double *w)
+               const double *n0, const double *w, const double *g)
 {
     double *x = (double *)malloc(sizeof(double) * (9 * (size_t)nu + 9 * (size_t)nu + 6 * (size_t)nv + (size_t)nu));
     double *d1 = x + 3 * (size_t)nu, *d2 = x + 6 * (size_t)nu;
@@ -883,7 +886,7 @@ double or_loss(const or_curve *path, const or_curve *prof, int nu, int nv,
     double ft[3];
     first_leg(path, ft);
     or_frame(nu, x, d1, ft, n0, 1, R);
-    or_surface_rows(nu, nv, 0, nu, x, d1, d2, R, S, dS, NULL, NULL, NULL, w, rs);
+    or_surface_rows(nu, nv, 0, nu, x, d1, d2, R, S, dS, NULL, NULL, NULL, w, g, rs);
     double L = 0.0;
     for (int i = 0; i < nu; ++i) L += rs[i];
     free(x);
@@ -897,7 +900,7 @@ double or_loss(const or_curve *path, const or_curve *prof, int nu, int nv,
  * skip those coordinates.  OpenMP over coordinates.
  */
 void or_fd_grad(const or_curve *path, const or_curve *prof, int nu, int nv,
-                const double *n0, const double *w, double h, double *gP, double *gQ)
+                const double *n0, const double *w, const double *g, double h, double *gP, double *gQ)
 {
     int nP = 3 * path->n, nQ = 3 * prof->n;
     int total = (gP ? nP : 0) + (gQ ? nQ : 0);
@@ -913,9 +916,9 @@ void or_fd_grad(const or_curve *path, const or_curve *prof, int nu, int nv,
         c.ctrl = cp;
         double th = cp[k];
         cp[k] = th + h;
-        double Lp = onP ? or_loss(&c, prof, nu, nv, n0, w) : or_loss(path, &c, nu, nv, n0, w);
+        double Lp = onP ? or_loss(&c, prof, nu, nv, n0, w, g) : or_loss(path, &c, nu, nv, n0, w, g);
         cp[k] = th - h;
-        double Lm = onP ? or_loss(&c, prof, nu, nv, n0, w) : or_loss(path, &c, nu, nv, n0, w);
+        double Lm = onP ? or_loss(&c, prof, nu, nv, n0, w, g) : or_loss(path, &c, nu, nv, n0, w, g);
         double g = (Lp - Lm) / (MUT(14) ? h : 2.0 * h);
         if (onP) gP[k] = g; else gQ[k] = g;
         free(cp);

@@ -61,3 +61,58 @@ def test_loss_is_weighted_sum_of_positions():
     path, prof, nu, nv, w = _small(seed=4)
     r = oracle.sweep(path, prof, nu, nv, want_nrm=False, want_kappa=False)
     assert abs(oracle.loss(path, prof, nu, nv, w) - float(np.sum(w * r.pos))) < 1e-10
+
+
+# ------------------------------------------------ the normal term of the loss
+# L_N = sum g . N (N the unit normal).  Normals are unchanged when the whole
+# sweep is translated or scaled about the origin (the frame depends on
+# directions only), which fixes two combinations of the gradient; on an exact
+# cylinder the normals are the radial directions whatever the radius.
+
+def test_normal_loss_is_weighted_sum_of_normals():
+    path, prof, nu, nv, _ = _small(seed=5)
+    g = np.random.default_rng(50).standard_normal((3, nu, nv))
+    r = oracle.sweep(path, prof, nu, nv, want_kappa=False)
+    assert abs(oracle.loss(path, prof, nu, nv, None, g=g) - float(np.sum(g * r.nrm))) < 1e-10
+    w = np.random.default_rng(51).standard_normal((3, nu, nv))
+    both = oracle.loss(path, prof, nu, nv, w, g=g)
+    assert abs(both - float(np.sum(w * r.pos) + np.sum(g * r.nrm))) < 1e-10
+
+
+def test_normal_loss_on_an_exact_cylinder():
+    from tests.test_oracle_rational import nurbs_circle
+    rho, nu, nv = 0.4, 17, 40
+    ctrl, wts, U = nurbs_circle(rho)
+    path = synth.CurveSpec(np.array([[0, 0, -1.0], [0, 0, 0.0], [0, 0, 1.5], [0, 0, 3.0]]), 3)
+    prof = synth.CurveSpec(ctrl, 2, False, U, wts)
+    r = oracle.sweep(path, prof, nu, nv, want_kappa=False)
+    d = np.hypot(r.pos[0], r.pos[1])
+    radial = np.stack([r.pos[0] / d, r.pos[1] / d, np.zeros_like(d)])
+    sign = np.sign(np.sum(radial[:, 0, 0] * r.nrm[:, 0, 0]))
+    # g = the radial direction: every vertex contributes +-1
+    assert abs(oracle.loss(path, prof, nu, nv, None, g=radial) - sign * nu * nv) <= 1e-11 * nu * nv
+    # the normals do not depend on the radius: scaling the profile control
+    # points leaves L_N unchanged
+    g = np.random.default_rng(52).standard_normal((3, nu, nv))
+    _, gQ = oracle.fd_grad(path, prof, nu, nv, None, g=g, want_path=False)
+    assert abs(np.sum(prof.ctrl * gQ)) <= 1e-7 * np.abs(gQ).max() * ctrl.shape[0]
+    assert np.abs(gQ).max() > 1e-3
+
+
+def test_normal_gradient_translation_and_scaling_invariants():
+    path, prof, nu, nv, _ = _small(seed=11)
+    # a profile off its plane (S_z != 0): with S_z = 0 the normal is the
+    # direction of (R S') x t and each curve's scaling alone leaves it as is
+    prof.ctrl[:, 2] = 0.15 * np.random.default_rng(54).standard_normal(prof.ctrl.shape[0])
+    g = np.random.default_rng(53).standard_normal((3, nu, nv))
+    gP, gQ = oracle.fd_grad(path, prof, nu, nv, None, g=g)
+    scale = max(np.abs(gP).max(), np.abs(gQ).max())
+    assert scale > 1e-2
+    # translating the path translates the surface
+    assert np.abs(gP.sum(axis=0)).max() <= 1e-7 * scale * path.ctrl.shape[0]
+    # scaling path and profile together scales the surface
+    total = np.sum(path.ctrl * gP) + np.sum(prof.ctrl * gQ)
+    assert abs(total) <= 1e-7 * scale * (np.abs(path.ctrl).sum() + np.abs(prof.ctrl).sum())
+    # neither holds for one curve alone
+    assert abs(np.sum(path.ctrl * gP)) > 1e-3 * scale
+    assert abs(np.sum(prof.ctrl * gQ)) > 1e-3 * scale

@@ -25,6 +25,7 @@ harness on the unmodified source must pass.  Mistakes planted:
  17  Frenet torsion rate doubled
  18  arc-length targets i/n_s instead of i/(n_s - 1)
  19  first triangle of each quad wound clockwise
+ 20  normal term of the loss: the cross product not normalised
 """
 
 from __future__ import annotations
@@ -42,7 +43,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_bspline.py", "tests/test_oracle_frame.py", "tests/test_oracle_grad.py",
              "tests/test_oracle_rational.py", "tests/test_oracle_frenet_laws.py",
              "tests/test_oracle_arclength_mesh.py"]
-MUTANTS = list(range(1, 20))
+MUTANTS = list(range(1, 21))
 
 
 def _run_pins(lib_path: str) -> subprocess.CompletedProcess:
