@@ -36,6 +36,10 @@ sys.path.insert(0, ROOT)
 METRIC = "swept-surface vertices/s (pos+normal) and % HBM peak; batched/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 COPY_CAL_BYTES = 512 << 20
+# Untimed replays of a batched graph before timing: on this HIP runtime one
+# of the first ten launches of a graph (the ninth, in the runs we looked at)
+# stalls the host for 35-40 ms once; steady-state replays take ~0.1 ms.
+GRAPH_WARMUP = 12
 COUNTERS = os.path.join(ROOT, "profiles", "surface_c2_counters.json")
 SURFACE_SRC = os.path.join(ROOT, "paper_1110_5450_amd", "csrc", "surface_kernels.hip")
 
@@ -263,7 +267,7 @@ def batched_variants(steps: int):
     ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
     pos = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pos)
-    for _ in range(2):
+    for _ in range(GRAPH_WARMUP):
         api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -332,10 +336,20 @@ def adjoint_variant(steps: int):
         api.sweep_backward(b, g, workspace=ws)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # positions and normals: the reduction reads both gradients
+    gn = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(6))
+    for _ in range(2):
+        api.sweep_backward(b, g, grad_nrm=gn, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.sweep_backward(b, g, grad_nrm=gn, workspace=ws)
+    torch.cuda.synchronize()
+    el_n = time.perf_counter() - t0
     fw = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     fn = torch.empty_like(fw)
     wsf = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
-    for _ in range(2):
+    for _ in range(GRAPH_WARMUP):
         api.sweep_eval_batched(b, out=(fw, fn), workspace=wsf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -345,7 +359,9 @@ def adjoint_variant(steps: int):
     elf = time.perf_counter() - t0
     return {"workload": "256 sweeps, 64/16 cps, 1024x64, FP32", "vertices": N,
             "forward_ms": 1e3 * elf / steps, "backward_ms": 1e3 * el / steps,
-            "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9}
+            "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9,
+            "backward_with_normals_ms": 1e3 * el_n / steps,
+            "backward_with_normals_grad_read_GBps": 24.0 * N / (el_n / steps) / 1e9}
 
 
 def precision_study(steps: int = 5):

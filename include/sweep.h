@@ -76,7 +76,7 @@
 extern "C" {
 #endif
 
-#define SWEEP_VERSION 103  /* major*100 + minor */
+#define SWEEP_VERSION 104  /* major*100 + minor */
 #define SWEEP_MAX_DEGREE 7
 
 typedef enum {
@@ -241,15 +241,29 @@ int64_t sweep_batched_output_elems(const sweep_batch *batch);
  * grad_path_ctrl (DEVICE, sum(path_n) x 3 FP64) and grad_prof_ctrl (DEVICE,
  * sum(prof_n) x 3 FP64), the gradients of L with respect to the control
  * points.  The frame is recomputed in FP64; reductions accumulate in FP64 in
- * a fixed order (deterministic).  Gradients through normals, and with
- * respect to weights (rational curves: weights are held fixed), are not
- * provided.
+ * a fixed order (deterministic).  Gradients with respect to weights
+ * (rational curves: weights are held fixed) and knots are not provided.
  * At tangent reversals the step rotation is treated as locally constant.
+ * sweep_backward(..., grad_pos, ...) is sweep_backward_ex with
+ * grad_nrm = NULL.
+ *
+ * sweep_backward_ex also takes grad_nrm = dL/dnrm (DEVICE, same layout and
+ * precision as the batched nrm output, or NULL); grad_pos may be NULL when
+ * grad_nrm is not (both NULL is SWEEP_ERR_NULL_ARG).  The normal is
+ * N = (X_v x X_u)/|X_v x X_u| with X_u from the continuous frame's derivative
+ * (its dependence on C'' through the frame's rate of turn is included);
+ * where the cross product is 0 or not finite the normal is the constant 0
+ * and passes no gradient.  Samples with C' = 0 pass none through a, b, |C'|.
+ * The workspace size covers both entry points.
  */
 sweep_status sweep_backward(const sweep_batch *batch, const sweep_options *opt,
                             const void *grad_pos, double *grad_path_ctrl,
                             double *grad_prof_ctrl, void *workspace, size_t ws_bytes,
                             void *stream);
+sweep_status sweep_backward_ex(const sweep_batch *batch, const sweep_options *opt,
+                               const void *grad_pos, const void *grad_nrm,
+                               double *grad_path_ctrl, double *grad_prof_ctrl,
+                               void *workspace, size_t ws_bytes, void *stream);
 size_t sweep_backward_workspace_size(const sweep_batch *batch, const sweep_options *opt);
 
 /*

@@ -85,6 +85,8 @@ def lib():
         L.sweep_batched_output_elems.restype = C.c_int64
         L.sweep_backward.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp, sz, vp]
         L.sweep_backward.restype = C.c_int32
+        L.sweep_backward_ex.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp, vp, sz, vp]
+        L.sweep_backward_ex.restype = C.c_int32
         L.sweep_backward_workspace_size.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions)]
         L.sweep_backward_workspace_size.restype = sz
         L.sweep_trace_enable.argtypes = [C.c_int32]
@@ -163,6 +165,12 @@ def sweep_backward(batch: SweepBatch, opt: SweepOptions, grad_pos: int, grad_pat
                    grad_prof_ctrl: int, workspace: int, ws_bytes: int, stream: int) -> int:
     return lib().sweep_backward(C.byref(batch), C.byref(opt), grad_pos, grad_path_ctrl, grad_prof_ctrl,
                                 workspace, ws_bytes, stream)
+
+
+def sweep_backward_ex(batch: SweepBatch, opt: SweepOptions, grad_pos: int, grad_nrm: int, grad_path_ctrl: int,
+                      grad_prof_ctrl: int, workspace: int, ws_bytes: int, stream: int) -> int:
+    return lib().sweep_backward_ex(C.byref(batch), C.byref(opt), grad_pos, grad_nrm, grad_path_ctrl,
+                                   grad_prof_ctrl, workspace, ws_bytes, stream)
 
 
 def sweep_batched_output_elems(batch: SweepBatch) -> int:

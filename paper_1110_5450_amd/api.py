@@ -396,28 +396,36 @@ def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=to
     return L.sweep_batched_workspace_size(batch.c_struct(), make_options(out_dtype, frame_dtype))
 
 
-def sweep_backward(batch: Batch, grad_pos: torch.Tensor, *, initial_normal=None, workspace=None, stream=None):
-    """Gradients of L with dL/dpos = grad_pos (flat, like the batched output;
-    its dtype is the output precision) with respect to the packed path and
-    profile control points: (g_path (sum path_n, 3), g_prof (sum prof_n, 3)),
-    float64."""
+def sweep_backward(batch: Batch, grad_pos: Optional[torch.Tensor], *, grad_nrm: Optional[torch.Tensor] = None,
+                   initial_normal=None, workspace=None, stream=None):
+    """Gradients of L with dL/dpos = grad_pos and dL/dnrm = grad_nrm (flat,
+    like the batched outputs; their dtype is the output precision; either may
+    be None, not both) with respect to the packed path and profile control
+    points: (g_path (sum path_n, 3), g_prof (sum prof_n, 3)), float64."""
     b = batch.c_struct()
-    if grad_pos.dtype not in _DT:
-        raise TypeError("grad_pos must be float32 or float64")
-    g = grad_pos.contiguous()
-    if g.numel() != batch.out_elems:
-        raise ValueError("grad_pos has the wrong size")
-    opt = make_options(g.dtype, torch.float64, True, initial_normal)
+    given = [t for t in (grad_pos, grad_nrm) if t is not None]
+    if not given:
+        raise ValueError("grad_pos and grad_nrm are both None")
+    dt = given[0].dtype
+    if dt not in _DT or any(t.dtype != dt for t in given):
+        raise TypeError("grad_pos / grad_nrm must both be float32 or both float64")
+    g = grad_pos.contiguous() if grad_pos is not None else None
+    gn = grad_nrm.contiguous() if grad_nrm is not None else None
+    for t, what in ((g, "grad_pos"), (gn, "grad_nrm")):
+        if t is not None and t.numel() != batch.out_elems:
+            raise ValueError(f"{what} has the wrong size")
+    opt = make_options(dt, torch.float64, True, initial_normal)
     ws_bytes = L.sweep_backward_workspace_size(b, opt)
     if ws_bytes == 0:
-        L.check(L.sweep_backward(b, opt, 0, 0, 0, 0, 0, 0))
+        L.check(L.sweep_backward_ex(b, opt, 0, 0, 0, 0, 0, 0, 0))
     dev = batch.path_ctrl.device
     gP = torch.empty((int(batch.path_n.sum()), 3), dtype=torch.float64, device=dev)
     gQ = torch.empty((int(batch.prof_n.sum()), 3), dtype=torch.float64, device=dev)
     if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    L.check(L.sweep_backward(b, opt, g.data_ptr(), gP.data_ptr(), gQ.data_ptr(), workspace.data_ptr(),
-                             _nbytes(workspace), _stream_handle(stream)))
+    L.check(L.sweep_backward_ex(b, opt, g.data_ptr() if g is not None else 0, gn.data_ptr() if gn is not None else 0,
+                                gP.data_ptr(), gQ.data_ptr(), workspace.data_ptr(), _nbytes(workspace),
+                                _stream_handle(stream)))
     return gP, gQ
 
 

@@ -1,9 +1,9 @@
 """Differentiable sweep: torch.autograd.Function over the C ABI.
 
 forward  -> sweep_eval_batched (positions and normals),
-backward -> sweep_backward (hand-written adjoint kernels), giving dL/d(path
-control points) and dL/d(profile control points) in float64.  Normals are
-outputs only: a loss that depends on them raises in backward.
+backward -> sweep_backward_ex (hand-written adjoint kernels) with the
+incoming gradients of positions and normals, giving dL/d(path control
+points) and dL/d(profile control points) in float64.
 """
 
 from __future__ import annotations
@@ -24,16 +24,13 @@ class SweepFunction(torch.autograd.Function):
         pos, nrm = api.sweep_eval_batched(batch, out_dtype=out_dtype, initial_normal=initial_normal)
         ctx.batch = batch
         ctx.initial_normal = initial_normal
-        ctx.mark_non_differentiable(nrm)
         return pos, nrm
 
     @staticmethod
     def backward(ctx, grad_pos: Optional[torch.Tensor], grad_nrm: Optional[torch.Tensor]):
-        if grad_nrm is not None and bool((grad_nrm != 0).any()):
-            raise RuntimeError("gradients through the normals are not provided")
-        if grad_pos is None:
+        if grad_pos is None and grad_nrm is None:
             return None, None, None, None, None
-        gP, gQ = api.sweep_backward(ctx.batch, grad_pos, initial_normal=ctx.initial_normal)
+        gP, gQ = api.sweep_backward(ctx.batch, grad_pos, grad_nrm=grad_nrm, initial_normal=ctx.initial_normal)
         return gP, gQ, None, None, None
 
 

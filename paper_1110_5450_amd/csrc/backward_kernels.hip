@@ -1,5 +1,5 @@
-// backward_kernels.hip -- adjoint of the positions with respect to the path
-// and profile control points, for a batch.  With w = dL/dX and
+// backward_kernels.hip -- adjoint of the positions and normals with respect
+// to the path and profile control points, for a batch.  With w = dL/dX and
 // X_ij = x_i + S_x r_i + S_y s_i + S_z t_i:
 //   dL/dx_i (direct)    = sum_j w_ij
 //   dL/dr_i, ds_i, dt_i = sum_j S_{x,y,z}(v_j) w_ij
@@ -12,6 +12,17 @@
 // normalisation, r_0 through the initial-normal rule, and x, C' to the
 // control points through the basis functions.  Every sum runs in FP64 in a
 // fixed order: the result does not depend on scheduling.
+//
+// Normals (g = dL/dN, optional): N_ij = R_i n_ij with n = m/|m|,
+// m = q_j x u_ij in frame coordinates, q = S' and
+// u = (S_z a, S_z b, L - S_x a - S_y b), a = r.C''/L, b = s.C''/L, L = |C'|.
+// With gh = R^T g, mb = (gh - (gh.n) n)/|m|, qb = u x mb, ub = mb x q:
+//   dL/dr_i, ds_i, dt_i += sum_j n_{x,y,z} g_ij
+//   dL/da_i = sum_j (ub_x S_z - ub_z S_x),  dL/db_i = sum_j (ub_y S_z - ub_z S_y),
+//   dL/dL_i = sum_j ub_z
+//   dL/dS_j += sum_i (-ub_z a, -ub_z b, ub_x a + ub_y b),  dL/dS'_j = sum_i qb
+// and a, b, L pass on to r, s, C'' and C'.  Where |m| is 0 or not finite the
+// normal is the constant 0 and passes nothing.
 //
 // kbw_reduce   one wave per (sweep, group of G rows, 64 columns): streaming
 //              read of w through an LDS tile, per-row partials over the 64
@@ -31,14 +42,20 @@ namespace sweep {
 // conflicts) from which lane = (component c, row r, half h) forms the row
 // sums over 32 of the 64 columns; the two halves are added in a fixed order
 // (h = 0 first).  Small tiles keep five blocks per CU resident.
-template <class T>
+// With NRM the lane also loads g for its G rows and forms the normal terms:
+// column sums in registers, row sums by DPP scans over the wave.  grad may
+// be null (no position term).
+template <class T, bool NRM>
 __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
                                                      const int4* __restrict__ units, int n_units,
-                                                     const T* __restrict__ grad, const double* __restrict__ rows,
+                                                     const T* __restrict__ grad, const T* __restrict__ gnrm,
+                                                     const double* __restrict__ rows,
                                                      const double* __restrict__ ptab, double* __restrict__ rowpart,
                                                      double* __restrict__ colpart)
 {
     constexpr int G = bw_row_group<T>();
+    constexpr int RP = NRM ? kRowPartNrm : kRowPart;
+    constexpr int CP = NRM ? kColPartNrm : kColPart;
     __shared__ T lw[kWaves][3][G][65];
     __shared__ double ls[kWaves][3][64];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -63,11 +80,11 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         }
         ls[wave][0][lane] = S0; ls[wave][1][lane] = S1; ls[wave][2][lane] = S2;
         const size_t P = (size_t)d.plane;   // plane stride of the batched layout
-        const T* w0 = grad + d.out_off;
+        const T* w0 = grad ? grad + d.out_off : nullptr;
 #pragma unroll
         for (int r = 0; r < G; ++r) {
             w[0][r] = w[1][r] = w[2][r] = T(0);
-            if (vj && r < nr) {
+            if (w0 && vj && r < nr) {
                 const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
                 w[0][r] = __builtin_nontemporal_load(w0 + v);
                 w[1][r] = __builtin_nontemporal_load(w0 + P + v);
@@ -79,9 +96,9 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
             lw[wave][0][r][lane] = w[0][r]; lw[wave][1][r][lane] = w[1][r]; lw[wave][2][r][lane] = w[2][r];
         }
     }
+    const double* R0 = rows + 16 * (d.row_off + i0);
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
     if (vj) {
-        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-        const double* R0 = rows + 16 * (d.row_off + i0);
 #pragma unroll
         for (int r = 0; r < G; ++r) {
             if (r < nr) {
@@ -92,7 +109,65 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
                 h2 += R[9] * a + R[10] * b + R[11] * c;
             }
         }
-        double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
+    }
+    if (NRM) {
+        V3<double> S = mk(0.0, 0.0, 0.0), q = S;
+        if (vj) {
+            const double* pq = ptab + 8 * (d.ptab_off + j);
+            S = mk(pq[0], pq[1], pq[2]);
+            q = mk(pq[3], pq[4], pq[5]);
+        }
+        const size_t P = (size_t)d.plane;
+        const T* g0 = gnrm + d.out_off;
+        V3<double> hD = mk(0.0, 0.0, 0.0);
+        for (int r = 0; r < nr; ++r) {   // wave-uniform bound: every lane reaches the butterflies
+            const double* R = R0 + 16 * r;
+            double c[12];
+#pragma unroll
+            for (int e = 0; e < 12; ++e) c[e] = 0.0;
+            if (vj) {
+                const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
+                const V3<double> gv = mk((double)__builtin_nontemporal_load(g0 + v),
+                                         (double)__builtin_nontemporal_load(g0 + P + v),
+                                         (double)__builtin_nontemporal_load(g0 + 2 * P + v));
+                const V3<double> rr = mk(R[3], R[4], R[5]), ss = mk(R[6], R[7], R[8]), tt = mk(R[9], R[10], R[11]);
+                const double L = R[12], a = R[13], b = R[14];
+                const V3<double> u = mk(S.z * a, S.z * b, L - S.x * a - S.y * b);
+                const V3<double> m = cross(q, u);
+                const double mm = dot(m, m);
+                if (mm > 0.0 && mm < INFINITY) {
+                    const double inv = 1.0 / sqrt(mm);
+                    const V3<double> n = inv * m;
+                    const V3<double> gh = mk(dot(rr, gv), dot(ss, gv), dot(tt, gv));
+                    const V3<double> mb = inv * (gh - dot(gh, n) * n);
+                    const V3<double> qb = cross(u, mb), ub = cross(mb, q);
+                    c[0] = n.x * gv.x; c[1] = n.x * gv.y; c[2] = n.x * gv.z;
+                    c[3] = n.y * gv.x; c[4] = n.y * gv.y; c[5] = n.y * gv.z;
+                    c[6] = n.z * gv.x; c[7] = n.z * gv.y; c[8] = n.z * gv.z;
+                    c[9] = ub.x * S.z - ub.z * S.x;
+                    c[10] = ub.y * S.z - ub.z * S.y;
+                    c[11] = ub.z;
+                    h0 -= ub.z * a;
+                    h1 -= ub.z * b;
+                    h2 += ub.x * a + ub.y * b;
+                    hD = hD + qb;
+                }
+            }
+            double mine = 0.0;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                const double tot = wave_total(c[e]);
+                mine = lane == e ? tot : mine;
+            }
+            if (lane < 12) rowpart[RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r) + kRowPart + lane] = mine;
+        }
+        if (vj) {
+            double* qd = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
+            qd[3] = hD.x; qd[4] = hD.y; qd[5] = hD.z;
+        }
+    }
+    if (vj) {
+        double* q = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
         q[0] = h0; q[1] = h1; q[2] = h2;
     }
     __syncthreads();
@@ -115,22 +190,25 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
     const double b0 = __shfl_xor(a0, 1, 64), bx = __shfl_xor(ax, 1, 64);
     const double by = __shfl_xor(ay, 1, 64), bz = __shfl_xor(az, 1, 64);
     if (act && h == 0) {
-        double* q = rowpart + 12 * (d.rowpart_off + (size_t)seg * n_u + i0 + r);
+        double* q = rowpart + RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r);
         q[c] = a0 + b0; q[3 + c] = ax + bx; q[6 + c] = ay + by; q[9 + c] = az + bz;
     }
 }
 
-// Basis values N_{s-P+j,P}(u) and first derivatives, j = 0..P.
+// Basis values N_{s-P+j,P}(u) and first derivatives, j = 0..P, and (d2N
+// not null) second derivatives.
 template <int P>
-__device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, double* N, double* dN)
+__device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, double* N, double* dN, double* d2N)
 {
     double Uk[2 * P + 1];
 #pragma unroll
     for (int m = 0; m < 2 * P; ++m) Uk[m] = knot(c, s - P + 1 + m);
     double B[P + 1];
     double D1[P > 0 ? P : 1];
+    double D2[P > 1 ? P - 1 : 1];
     B[0] = 1.0;
     if (P - 1 == 0) D1[0] = 1.0;
+    if (P - 2 == 0) D2[0] = 1.0;
 #pragma unroll
     for (int q = 1; q <= P; ++q) {
         double nb_[P + 1];
@@ -149,6 +227,10 @@ __device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, dou
 #pragma unroll
             for (int j = 0; j <= q; ++j) D1[j] = B[j];
         }
+        if (q == P - 2) {
+#pragma unroll
+            for (int j = 0; j <= q; ++j) D2[j] = B[j];
+        }
     }
     // C' = sum_j D1[j] Q_j with Q_j = P (P_{j+1} - P_j) / (U_{s+j+1} - U_{s-P+j+1})
 #pragma unroll
@@ -159,35 +241,63 @@ __device__ __forceinline__ void basis_vals(const DCurve& c, double u, int s, dou
         N[j] = B[j];
         dN[j] = (double)P * v;
     }
+    if (d2N) {
+        // first derivatives of the degree P-1 functions N_{s-P+1+j,P-1}
+        // from the degree P-2 values, then the same difference rule again
+        double E1[P > 0 ? P : 1];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            double v = 0.0;
+            if (P >= 2) {
+                if (j >= 1) v += D2[j - 1] / (Uk[P - 1 + j] - Uk[j]);
+                if (j <= P - 2) v -= D2[j] / (Uk[P + j] - Uk[j + 1]);
+            }
+            E1[j] = (double)(P - 1) * v;
+        }
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            double v = 0.0;
+            if (j >= 1) v += E1[j - 1] / (Uk[P + j - 1] - Uk[j - 1]);
+            if (j < P) v -= E1[j] / (Uk[P + j] - Uk[j]);
+            d2N[j] = (double)P * v;
+        }
+    }
 }
 
-// Basis of sample i of ns (any degree up to kMaxDeg): span and values.  For
-// a rational curve the values are those of the rational basis
-// R_k = w_k N_k / W and R_k' = w_k (N_k' W - N_k W') / W^2 (W = sum w_k N_k),
-// the derivatives of C and C' with respect to control point k.
-__device__ __forceinline__ int sample_basis(const DCurve& c, int i, int ns, double* N, double* dN)
+// Basis of sample i of ns (any degree up to kMaxDeg): span and values, and
+// (d2N not null) second derivatives.  For a rational curve the values are
+// those of the rational basis R_k = w_k N_k / W, R_k' = w_k (N_k' W - N_k W')
+// / W^2 and R_k'' = w_k (N_k''/W - 2 N_k' W'/W^2 - N_k W''/W^2
+// + 2 N_k W'^2/W^3) (W = sum w_k N_k): the derivatives of C, C' and C'' with
+// respect to control point k.
+__device__ __forceinline__ int sample_basis(const DCurve& c, int i, int ns, double* N, double* dN,
+                                            double* d2N = nullptr)
 {
     const double u = sample_param(c, i, ns);
     const int s = sample_span(c, i, ns, u);
     switch (c.p) {
-    case 1: basis_vals<1>(c, u, s, N, dN); break;
-    case 2: basis_vals<2>(c, u, s, N, dN); break;
-    case 3: basis_vals<3>(c, u, s, N, dN); break;
-    case 4: basis_vals<4>(c, u, s, N, dN); break;
-    case 5: basis_vals<5>(c, u, s, N, dN); break;
-    case 6: basis_vals<6>(c, u, s, N, dN); break;
-    default: basis_vals<7>(c, u, s, N, dN); break;
+    case 1: basis_vals<1>(c, u, s, N, dN, d2N); break;
+    case 2: basis_vals<2>(c, u, s, N, dN, d2N); break;
+    case 3: basis_vals<3>(c, u, s, N, dN, d2N); break;
+    case 4: basis_vals<4>(c, u, s, N, dN, d2N); break;
+    case 5: basis_vals<5>(c, u, s, N, dN, d2N); break;
+    case 6: basis_vals<6>(c, u, s, N, dN, d2N); break;
+    default: basis_vals<7>(c, u, s, N, dN, d2N); break;
     }
     if (c.w) {
-        double W = 0.0, W1 = 0.0;
+        double W = 0.0, W1 = 0.0, W2 = 0.0;
         for (int j = 0; j <= c.p; ++j) {
             const double wk = weight_at(c, s - c.p + j);
             W += wk * N[j];
             W1 += wk * dN[j];
+            if (d2N) W2 += wk * d2N[j];
         }
         for (int j = 0; j <= c.p; ++j) {
             const double wk = weight_at(c, s - c.p + j);
             const double Rj = wk * N[j] / W;
+            if (d2N)
+                d2N[j] = wk * (d2N[j] / W - 2.0 * dN[j] * W1 / (W * W) - N[j] * W2 / (W * W) +
+                               2.0 * N[j] * W1 * W1 / (W * W * W));
             dN[j] = wk * (dN[j] * W - N[j] * W1) / (W * W);
             N[j] = Rj;
         }
@@ -285,6 +395,35 @@ __device__ V3<double> block_suffix_sum(V3<double> v, double (*lds)[3], V3<double
     return v + later;
 }
 
+// Row records of the partial sums: kRowPart = 12 values for the positions
+// (sum w, dL/dr, dL/ds, dL/dt), kRowPartNrm = 24 with the normal terms
+// (then sum n_x g, sum n_y g, sum n_z g, dL/da, dL/db, dL/dL); column records
+// hold dL/dS (kColPart = 3), and dL/dS' after it with the normal terms
+// (kColPartNrm = 6).
+
+// The normal terms' share of dL/dr_i, dL/ds_i and dL/dt_i: sum_j n_{x,y,z} g_ij
+// and, through a = r.C''/L and b = s.C''/L, (dL/da) C''/L and (dL/db) C''/L
+// (C'' from the second-derivative basis).  Written over the record's
+// direct terms (values 3..11), which then hold the totals.
+__device__ __forceinline__ void fold_normal_frame_terms(const DCurve& path, int i, int n_u, const RowRec& R,
+                                                        double* a)
+{
+    V3<double> Gr = mk(a[3], a[4], a[5]) + mk(a[12], a[13], a[14]);
+    V3<double> Gs = mk(a[6], a[7], a[8]) + mk(a[15], a[16], a[17]);
+    const V3<double> Gt = mk(a[9], a[10], a[11]) + mk(a[18], a[19], a[20]);
+    if (R.L > 0.0) {
+        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1], d2N[kMaxDeg + 1];
+        const int s = sample_basis(path, i, n_u, Nv, dN, d2N);
+        V3<double> C2 = mk(0.0, 0.0, 0.0);
+        for (int j = 0; j <= path.p; ++j) C2 = C2 + d2N[j] * ctrl_pt(path, s - path.p + j);
+        Gr = Gr + (a[21] / R.L) * C2;
+        Gs = Gs + (a[22] / R.L) * C2;
+    }
+    a[3] = Gr.x; a[4] = Gr.y; a[5] = Gr.z;
+    a[6] = Gs.x; a[7] = Gs.y; a[8] = Gs.z;
+    a[9] = Gt.x; a[10] = Gt.y; a[11] = Gt.z;
+}
+
 __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restrict__ descs,
                                                       const double* __restrict__ path_ctrl,
                                                       const double* __restrict__ prof_ctrl,
@@ -294,10 +433,12 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
                                                       const double* __restrict__ rows, const double* rowpart,
                                                       const double* colpart, double* rowacc, double* colacc,
                                                       double* rho, double* sgrad, int* spans_u, double* qgrad,
-                                                      int* spans_v, double* __restrict__ gP, double* __restrict__ gQ)
+                                                      int* spans_v, double* __restrict__ gP, double* __restrict__ gQ,
+                                                      int nrm)
 {
+    const int rp = nrm ? kRowPartNrm : kRowPart, cp = nrm ? kColPartNrm : kColPart;
     __shared__ double lds3[kWaves][3];
-    __shared__ double lpart[kBlock][3];
+    __shared__ double lpart[kBlock][kColPartNrm];
     const BatchDesc d = descs[blockIdx.x];
     const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
                       d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
@@ -306,8 +447,8 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
                       prof_w ? prof_w + d.prof_ctrl_off : nullptr};
     const int n_u = d.n_u, n_v = d.n_v;
     const double* rows_k = rows + 16 * d.row_off;
-    double* racc = rowacc + 12 * d.row_off;
-    double* cacc = colacc + 3 * d.ptab_off;
+    double* racc = rowacc + (size_t)rp * d.row_off;
+    double* cacc = colacc + (size_t)cp * d.ptab_off;
     double* rho_k = rho + 3 * d.row_off;
     double* sg = sgrad + 24 * d.row_off;
     int* su = spans_u + d.row_off;
@@ -316,16 +457,18 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
 
     // 1. finish the partial sums (fixed order over segments / groups)
     for (int i = threadIdx.x; i < n_u; i += kBlock) {
-        double a[12];
+        double a[kRowPartNrm];
 #pragma unroll
-        for (int e = 0; e < 12; ++e) a[e] = 0.0;
+        for (int e = 0; e < kRowPartNrm; ++e) a[e] = 0.0;
         for (int sgi = 0; sgi < d.nseg; ++sgi) {
-            const double* q = rowpart + 12 * (d.rowpart_off + (size_t)sgi * n_u + i);
+            const double* q = rowpart + rp * (d.rowpart_off + (size_t)sgi * n_u + i);
 #pragma unroll
-            for (int e = 0; e < 12; ++e) a[e] += q[e];
+            for (int e = 0; e < kRowPartNrm; ++e)
+                if (e < rp) a[e] += q[e];
         }
 #pragma unroll
-        for (int e = 0; e < 12; ++e) racc[12 * (size_t)i + e] = a[e];
+        for (int e = 0; e < kRowPartNrm; ++e)
+            if (e < rp) racc[rp * (size_t)i + e] = a[e];
     }
     {
         // column sums over the row groups: `parts` threads per column, each
@@ -335,24 +478,36 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
             const int j = t / parts, part = t % parts;
             const int g0 = (int)((long long)d.ngroup * part / parts);
             const int g1 = (int)((long long)d.ngroup * (part + 1) / parts);
-            double h[3] = {0.0, 0.0, 0.0};
+            double h[kColPartNrm];
+#pragma unroll
+            for (int e = 0; e < kColPartNrm; ++e) h[e] = 0.0;
             for (int g = g0; g < g1; ++g) {
-                const double* q = colpart + 3 * (d.colpart_off + (size_t)g * n_v + j);
-                h[0] += q[0]; h[1] += q[1]; h[2] += q[2];
+                const double* q = colpart + cp * (d.colpart_off + (size_t)g * n_v + j);
+#pragma unroll
+                for (int e = 0; e < kColPartNrm; ++e)
+                    if (e < cp) h[e] += q[e];
             }
             if (parts == 1) {
-                cacc[3 * (size_t)j] = h[0]; cacc[3 * (size_t)j + 1] = h[1]; cacc[3 * (size_t)j + 2] = h[2];
+#pragma unroll
+                for (int e = 0; e < kColPartNrm; ++e)
+                    if (e < cp) cacc[cp * (size_t)j + e] = h[e];
             } else {
-                lpart[t][0] = h[0]; lpart[t][1] = h[1]; lpart[t][2] = h[2];
+#pragma unroll
+                for (int e = 0; e < kColPartNrm; ++e) lpart[t][e] = h[e];
             }
         }
         __syncthreads();
         if (parts > 1)
             for (int j = threadIdx.x; j < n_v; j += kBlock) {
-                V3<double> h = mk(0.0, 0.0, 0.0);
+                double h[kColPartNrm];
+#pragma unroll
+                for (int e = 0; e < kColPartNrm; ++e) h[e] = 0.0;
                 for (int part = 0; part < parts; ++part)
-                    h = h + mk(lpart[j * parts + part][0], lpart[j * parts + part][1], lpart[j * parts + part][2]);
-                cacc[3 * (size_t)j] = h.x; cacc[3 * (size_t)j + 1] = h.y; cacc[3 * (size_t)j + 2] = h.z;
+#pragma unroll
+                    for (int e = 0; e < kColPartNrm; ++e) h[e] += lpart[j * parts + part][e];
+#pragma unroll
+                for (int e = 0; e < kColPartNrm; ++e)
+                    if (e < cp) cacc[cp * (size_t)j + e] = h[e];
             }
     }
     __threadfence_block();
@@ -366,7 +521,8 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         V3<double> di = mk(0.0, 0.0, 0.0);
         if (i < n_u) {
             const RowRec R = row_at(rows_k + 16 * (size_t)i);
-            const double* a = racc + 12 * (size_t)i;
+            double* a = racc + rp * (size_t)i;
+            if (nrm) fold_normal_frame_terms(path, i, n_u, R, a);
             const V3<double> Gr = mk(a[3], a[4], a[5]), Gs = mk(a[6], a[7], a[8]);
             const V3<double> rb = Gr + cross(Gs, R.t);
             di = mk(dot(R.r, rb), dot(R.s, rb), dot(R.t, rb));
@@ -382,8 +538,20 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
     // 3. per-sample adjoint of x_i and C'_i, and their basis contributions
     for (int i = threadIdx.x; i < n_u; i += kBlock) {
         const RowRec R = row_at(rows_k + 16 * (size_t)i);
-        const double* a = racc + 12 * (size_t)i;
+        // (with the normal terms, values 3..11 hold the totals: step 2)
+        const double* a = racc + rp * (size_t)i;
         const V3<double> g = mk(a[0], a[1], a[2]), Gs = mk(a[6], a[7], a[8]), Gt = mk(a[9], a[10], a[11]);
+        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1], d2N[kMaxDeg + 1];
+        const int s = sample_basis(path, i, n_u, Nv, dN, nrm ? d2N : nullptr);
+        V3<double> C2b = mk(0.0, 0.0, 0.0);   // dL/dC'' (normal terms)
+        double Lb = 0.0;                       // dL/dL, L = |C'| (normal terms)
+        if (nrm) {
+            if (R.L > 0.0) {
+                const double* rr = rows_k + 16 * (size_t)i;
+                C2b = divs(a[21] * R.r + a[22] * R.s, R.L);
+                Lb = a[23] - (a[21] * rr[13] + a[22] * rr[14]) / R.L;
+            }
+        }
         V3<double> xb = g;
         V3<double> tb = Gt + cross(R.r, Gs);
         const V3<double> rh = mk(rho_k[3 * (size_t)i], rho_k[3 * (size_t)i + 1], rho_k[3 * (size_t)i + 2]);
@@ -427,12 +595,11 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         }
         // t = C'/|C'|; samples with C' = 0 carry a tangent and pass no gradient
         V3<double> cb = mk(0.0, 0.0, 0.0);
-        if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L);
-        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1];
-        const int s = sample_basis(path, i, n_u, Nv, dN);
+        if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L) + Lb * R.t;
         su[i] = s;
         for (int j = 0; j <= path.p; ++j) {
-            const V3<double> c = Nv[j] * xb + dN[j] * cb;
+            V3<double> c = Nv[j] * xb + dN[j] * cb;
+            if (nrm) c = c + d2N[j] * C2b;
             double* q = sg + 24 * (size_t)i + 3 * j;
             q[0] = c.x; q[1] = c.y; q[2] = c.z;
         }
@@ -442,10 +609,13 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         double Nv[kMaxDeg + 1], dN[kMaxDeg + 1];
         const int s = sample_basis(prof, j, n_v, Nv, dN);
         sv[j] = s;
-        const V3<double> h = mk(cacc[3 * (size_t)j], cacc[3 * (size_t)j + 1], cacc[3 * (size_t)j + 2]);
+        const double* ca = cacc + cp * (size_t)j;
+        const V3<double> h = mk(ca[0], ca[1], ca[2]);
+        const V3<double> hd = nrm ? mk(ca[3], ca[4], ca[5]) : mk(0.0, 0.0, 0.0);
         for (int l = 0; l <= prof.p; ++l) {
+            const V3<double> c = Nv[l] * h + dN[l] * hd;
             double* q = qg + 24 * (size_t)j + 3 * l;
-            q[0] = Nv[l] * h.x; q[1] = Nv[l] * h.y; q[2] = Nv[l] * h.z;
+            q[0] = c.x; q[1] = c.y; q[2] = c.z;
         }
     }
     __threadfence_block();
@@ -523,10 +693,11 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
     }
 }
 
-BackwardKernels backward_kernels(bool t64)
+BackwardKernels backward_kernels(bool t64, bool nrm)
 {
     BackwardKernels k;
-    k.reduce = t64 ? (const void*)&kbw_reduce<double> : (const void*)&kbw_reduce<float>;
+    if (nrm) k.reduce = t64 ? (const void*)&kbw_reduce<double, true> : (const void*)&kbw_reduce<float, true>;
+    else k.reduce = t64 ? (const void*)&kbw_reduce<double, false> : (const void*)&kbw_reduce<float, false>;
     k.adjoint = (const void*)&kbw_adjoint;
     return k;
 }

@@ -46,10 +46,11 @@ static BackwardLayout backward_layout(const BatchLayout& L)
     auto seg = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
     B.rows = seg(8 * 16 * (size_t)L.n_rows);
     B.ptab = seg(8 * 8 * (size_t)L.n_vs);
-    B.rowpart = seg(8 * 12 * (size_t)L.n_rowpart);
-    B.colpart = seg(8 * 3 * (size_t)L.n_colpart);
-    B.rowacc = seg(8 * 12 * (size_t)L.n_rows);
-    B.colacc = seg(8 * 3 * (size_t)L.n_vs);
+    // sized for the normal terms (the longer partial records)
+    B.rowpart = seg(8 * kRowPartNrm * (size_t)L.n_rowpart);
+    B.colpart = seg(8 * kColPartNrm * (size_t)L.n_colpart);
+    B.rowacc = seg(8 * kRowPartNrm * (size_t)L.n_rows);
+    B.colacc = seg(8 * kColPartNrm * (size_t)L.n_vs);
     B.rho = seg(8 * 3 * (size_t)L.n_rows);
     B.sgrad = seg(8 * 24 * (size_t)L.n_rows);
     B.spans_u = seg(4 * (size_t)L.n_rows);
@@ -428,13 +429,24 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
                             double* grad_path_ctrl, double* grad_prof_ctrl, void* workspace, size_t ws_bytes,
                             void* stream)
 {
+    if (!grad_pos) return fail(SWEEP_ERR_NULL_ARG, "grad_pos is NULL");
+    return sweep_backward_ex(batch, opt, grad_pos, nullptr, grad_path_ctrl, grad_prof_ctrl, workspace, ws_bytes,
+                             stream);
+}
+
+sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* opt, const void* grad_pos,
+                               const void* grad_nrm, double* grad_path_ctrl, double* grad_prof_ctrl,
+                               void* workspace, size_t ws_bytes, void* stream)
+{
     sweep_options def;
     if (!opt) { sweep_default_options(&def); opt = &def; }
     BatchKey key;
     BatchLayout L;
     sweep_status st = check_batch(batch, opt, &key, &L, nullptr, nullptr);
     if (st != SWEEP_OK) return st;
-    if (!grad_pos || !grad_path_ctrl || !grad_prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "a gradient buffer is NULL");
+    if (!grad_pos && !grad_nrm) return fail(SWEEP_ERR_NULL_ARG, "grad_pos and grad_nrm are both NULL");
+    if (!grad_path_ctrl || !grad_prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "a gradient buffer is NULL");
+    const int nrm = grad_nrm != nullptr;
     const BackwardLayout B = backward_layout(L);
     if (!workspace || ws_bytes < B.total)
         return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, B.total);
@@ -463,7 +475,7 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
     hipStream_t sm = (hipStream_t)stream;
     char* ws = (char*)workspace;
     const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock);
-    const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64);
+    const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64, nrm);
     {
         // FP64 frame recomputation with re-orthonormalisation: profile tables, frames
         GNode n;
@@ -492,11 +504,12 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         const int4* units = P->d_units;
         int n_units = P->n_units;
         const void* g = grad_pos;
+        const void* gn = grad_nrm;
         const void* rows = ws + B.rows;
         const void* ptab = ws + B.ptab;
         void* rowpart = ws + B.rowpart;
         void* colpart = ws + B.colpart;
-        void* args[8] = {&descs, &units, &n_units, &g, &rows, &ptab, &rowpart, &colpart};
+        void* args[9] = {&descs, &units, &n_units, &g, &gn, &rows, &ptab, &rowpart, &colpart};
         const unsigned grid = (unsigned)((n_units + kWaves - 1) / kWaves);
         if ((e = hipLaunchKernel(BK.reduce, dim3(grid), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward reduce");
@@ -521,8 +534,9 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
         void* spans_v = ws + B.spans_v;
         double* gp = grad_path_ctrl;
         double* gq = grad_prof_ctrl;
-        void* args[19] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
-                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq};
+        int nrm_arg = nrm;
+        void* args[20] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
+                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq, &nrm_arg};
         if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward adjoint");
     }

@@ -99,7 +99,12 @@ struct BackwardKernels {
     const void* reduce;
     const void* adjoint;
 };
-BackwardKernels backward_kernels(bool t64);
+// nrm: the reduction also takes dL/dN (normal terms, longer partial records).
+BackwardKernels backward_kernels(bool t64, bool nrm);
+
+// Partial-sum record lengths of the adjoint (doubles per row / per column).
+constexpr int kRowPart = 12, kRowPartNrm = 24;
+constexpr int kColPart = 3, kColPartNrm = 6;
 
 // Fast division constants for 0 <= v < 2^31.
 void fastdiv_constants(int d, unsigned long long* m, int* shift);

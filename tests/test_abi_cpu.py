@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert L.sweep_version() == 103
+    assert L.sweep_version() == 104
     o = L.default_options()
     assert (o.out_precision, o.frame_precision, o.reorthonormalize, o.has_initial_normal, o.tile_config) == (0, 1, 1, 0, -1)
     assert L.sweep_tile_config_count() >= 8
@@ -197,3 +197,17 @@ def test_triangles_validation():
     assert L.STATUS[st] == "SWEEP_ERR_WORKSPACE" and n.value == 2 * 4 * 6
     assert L.STATUS[lib.sweep_triangles(5, 7, 2, FAKE, 1 << 40, None, None)] == "SWEEP_ERR_BAD_OPTION"
     assert L.STATUS[lib.sweep_triangles(1, 7, 1, FAKE, 1 << 40, None, None)] == "SWEEP_ERR_BAD_GRID"
+
+
+def test_backward_ex_requires_a_gradient():
+    import synth
+    from paper_1110_5450_amd import api
+    # host tensors stand in for device buffers: nothing below is dereferenced
+    spec = synth.single(3, 8, 6, 32, 16)
+    b = api.Batch.from_specs([spec], device="cpu")
+    o = L.default_options()
+    st = L.sweep_backward_ex(b.c_struct(), o, 0, 0, FAKE, FAKE, FAKE, 1 << 40, 0)
+    assert L.STATUS[st] == "SWEEP_ERR_NULL_ARG" and "both NULL" in L.last_error()
+    st = L.sweep_backward(b.c_struct(), o, 0, FAKE, FAKE, FAKE, 1 << 40, 0)
+    assert L.STATUS[st] == "SWEEP_ERR_NULL_ARG" and "grad_pos" in L.last_error()
+    assert L.sweep_backward_workspace_size(b.c_struct(), o) > 0

@@ -84,6 +84,6 @@ def test_autograd_function_and_gradcheck():
     f = lambda a, c: dsweep(a, c, b, out_dtype=torch.float64)[0]
     assert torch.autograd.gradcheck(f, (Pt.detach().requires_grad_(True), Qt.detach().requires_grad_(True)),
                                     eps=1e-6, atol=1e-6, rtol=1e-5, nondet_tol=0.0)
-    # normals are not differentiable
+    # normals are differentiable too (their gradients: test_adjoint_normals_gpu)
     pos, nrm = dsweep(Pt, Qt, b, out_dtype=torch.float64)
-    assert not nrm.requires_grad
+    assert nrm.requires_grad
