@@ -391,6 +391,36 @@ def fd_grad(path, profile, n_u: int, n_v: int, w, h: float = 1e-6, n0=None,
     return gP, gQ
 
 
+def fd_param_grad(path, profile, n_u: int, n_v: int, w, which: str, g=None, h: float = 1e-6, n0=None,
+                  entries=None, groups=None):
+    """Central-difference gradient of L = sum w . X + sum g . N with respect to
+    the knot vector or the weights of one curve: which is "path_knots",
+    "prof_knots" (open curves with given knots), "path_weights" or
+    "prof_weights" (rational curves).  entries: the indices to perturb
+    (default all); groups: lists of indices moved together by the same h
+    (the result has one value per group).  Returns a float64 array."""
+    curve_name, part = which.split("_")
+    base = path if curve_name == "path" else profile
+    vec = _f64(base.knots if part == "knots" else base.weights).copy()
+    if groups is None:
+        idx = range(vec.shape[0]) if entries is None else entries
+        groups = [[k] for k in idx]
+
+    def L_at(v):
+        c = Curve(base.ctrl, base.degree, base.closed, v if part == "knots" else base.knots,
+                  v if part == "weights" else getattr(base, "weights", None))
+        return loss(c if curve_name == "path" else path, c if curve_name == "prof" else profile, n_u, n_v, w,
+                    n0=n0, g=g)
+
+    out = np.empty(len(groups))
+    for q, grp in enumerate(groups):
+        vp, vm = vec.copy(), vec.copy()
+        vp[list(grp)] += h
+        vm[list(grp)] -= h
+        out[q] = (L_at(vp) - L_at(vm)) / (2.0 * h)
+    return out
+
+
 def max_threads() -> int:
     return lib().or_max_threads()
 

@@ -116,3 +116,79 @@ def test_normal_gradient_translation_and_scaling_invariants():
     # neither holds for one curve alone
     assert abs(np.sum(path.ctrl * gP)) > 1e-3 * scale
     assert abs(np.sum(prof.ctrl * gQ)) > 1e-3 * scale
+
+
+# ------------------------------------- knot and weight gradients (FD helper)
+# The curve is unchanged when every knot is shifted or scaled together (the
+# samples follow the domain) or when every weight is scaled: the gradient of
+# any loss satisfies sum_m dL/dU_m = 0, sum_m U_m dL/dU_m = 0 and
+# sum_k w_k dL/dw_k = 0.  The first and last knots of a clamped vector do not
+# enter the curve at all.
+
+def _knotted(seed, rational=False, nu=48, nv=12):
+    rng = np.random.default_rng(seed)
+    n, p = 9, 3
+    P = synth.random_walk(rng, n)
+    inner = np.sort(rng.uniform(0.1, 0.9, n - p - 1))
+    U = np.concatenate([np.full(p + 1, 0.2), 0.2 + 1.3 * inner, np.full(p + 1, 1.5)])
+    Q = synth.perturbed_circle(rng, 7)
+    Q[:, 2] = 0.1 * rng.standard_normal(7)
+    path = synth.CurveSpec(P, p, knots=U)
+    prof = synth.CurveSpec(Q, 3, True)
+    if rational:
+        path.weights = rng.uniform(0.5, 2.0, n)
+        prof.weights = rng.uniform(0.5, 2.0, 7)
+    w = rng.standard_normal((3, nu, nv))
+    g = rng.standard_normal((3, nu, nv))
+    return path, prof, nu, nv, w, g
+
+
+def test_knot_gradient_invariants():
+    path, prof, nu, nv, w, g = _knotted(31)
+    U = path.knots
+    p = path.degree
+    # interior knots one by one; the clamped end runs moved as a whole
+    start, end = list(range(0, p + 1)), list(range(len(U) - p - 1, len(U)))
+    groups = [start] + [[k] for k in range(p + 1, len(U) - p - 1)] + [end]
+    d = oracle.fd_param_grad(path, prof, nu, nv, w, "path_knots", g=g, groups=groups)
+    scale = np.abs(d).max()
+    assert scale > 1e-2
+    assert abs(d.sum()) <= 1e-6 * scale * len(d)
+    vals = np.array([U[grp[0]] for grp in groups])
+    assert abs(np.sum(vals * d)) <= 1e-6 * scale * np.abs(vals).sum()
+    # the outermost knots do not enter
+    ends = oracle.fd_param_grad(path, prof, nu, nv, w, "path_knots", g=g, entries=[0, len(U) - 1])
+    assert np.all(ends == 0.0)
+
+
+def test_weight_gradient_invariant():
+    path, prof, nu, nv, w, g = _knotted(32, rational=True)
+    for which, c in (("path_weights", path), ("prof_weights", prof)):
+        d = oracle.fd_param_grad(path, prof, nu, nv, w, which, g=g)
+        scale = np.abs(d).max()
+        assert scale > 1e-2
+        assert abs(np.sum(c.weights * d)) <= 1e-6 * scale * np.abs(c.weights).sum()
+
+
+def test_profile_weight_gradient_closed_form():
+    # positions only: X is linear in the profile point S, and a rational
+    # point moves with its weight as dS/dw_k = N_k (Q_k - S) / W
+    # (W = sum_l w_l N_l), so dL/dw_k = sum_j h_j . N_k(v_j) (Q_k - S_j) / W_j
+    # with h_j = sum_i R_i^T w_ij.
+    path, prof, nu, nv, w, _ = _knotted(33, rational=True)
+    d = oracle.fd_param_grad(path, prof, nu, nv, w, "prof_weights")
+    r = oracle.sweep(path, prof, nu, nv, want_nrm=False, want_kappa=False)
+    h = np.einsum("iab,aij->jb", r.frame, w)
+    c = oracle.Curve.of(prof)
+    U, q, m = c.knot_vector(), c.degree, c.n
+    S, _ = oracle.profile_samples(prof, nv)
+    ref = np.zeros(m)
+    for j in range(nv):
+        v = c.param(j, nv)
+        sp = c.span(v)
+        N = oracle.basis(U, q, sp, v, nd=0)[0]
+        ks = [(sp - q + l) % m for l in range(q + 1)]
+        W = sum(prof.weights[k] * N[l] for l, k in enumerate(ks))
+        for l, k in enumerate(ks):
+            ref[k] += N[l] * (h[j] @ (prof.ctrl[k] - S[j])) / W
+    assert np.abs(d - ref).max() <= 1e-7 * np.abs(ref).max()
