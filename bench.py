@@ -36,9 +36,10 @@ sys.path.insert(0, ROOT)
 METRIC = "swept-surface vertices/s (pos+normal) and % HBM peak; batched/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 COPY_CAL_BYTES = 512 << 20
-# Untimed replays of a batched graph before timing: on this HIP runtime one
-# of the first ten launches of a graph (the ninth, in the runs we looked at)
-# stalls the host for 35-40 ms once; steady-state replays take ~0.1 ms.
+# Untimed calls before timing a batched entry point: on this HIP runtime one
+# of the first ten launches of a graph (the ninth, in the runs we looked at),
+# and one of the first backward calls that request knot and weight gradients,
+# stall the host once for 35-70 ms; steady-state calls take 0.1-1 ms.
 GRAPH_WARMUP = 12
 COUNTERS = os.path.join(ROOT, "profiles", "surface_c2_counters.json")
 SURFACE_SRC = os.path.join(ROOT, "paper_1110_5450_amd", "csrc", "surface_kernels.hip")
@@ -328,7 +329,7 @@ def adjoint_variant(steps: int):
     N = b.n_vertices
     g = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
     ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
-    for _ in range(2):
+    for _ in range(GRAPH_WARMUP):
         api.sweep_backward(b, g, workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -338,7 +339,7 @@ def adjoint_variant(steps: int):
     el = time.perf_counter() - t0
     # positions and normals: the reduction reads both gradients
     gn = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(6))
-    for _ in range(2):
+    for _ in range(GRAPH_WARMUP):
         api.sweep_backward(b, g, grad_nrm=gn, workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -346,6 +347,26 @@ def adjoint_variant(steps: int):
         api.sweep_backward(b, g, grad_nrm=gn, workspace=ws)
     torch.cuda.synchronize()
     el_n = time.perf_counter() - t0
+    # knot and weight gradients as well: the same sweeps with their clamped
+    # uniform knot vectors given explicitly and unit weights (rational form)
+    import numpy as np
+    for s in specs:
+        n, p = s.path.n, s.path.degree
+        s.path.knots = np.concatenate([np.zeros(p), np.arange(n - p + 1) / (n - p), np.ones(p)])
+        s.path.weights = np.ones(n)
+        s.profile.weights = np.ones(s.profile.n)
+    bp = api.Batch.from_specs(specs)
+    names = ["path_knots", "path_weights", "prof_weights"]
+    wsp = torch.empty(api.backward_workspace_size(bp), dtype=torch.uint8, device="cuda")
+    for _ in range(GRAPH_WARMUP):
+        api.sweep_backward(bp, g, grad_nrm=gn, params=names, workspace=wsp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.sweep_backward(bp, g, grad_nrm=gn, params=names, workspace=wsp)
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    del wsp
     fw = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     fn = torch.empty_like(fw)
     wsf = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
@@ -361,7 +382,8 @@ def adjoint_variant(steps: int):
             "forward_ms": 1e3 * elf / steps, "backward_ms": 1e3 * el / steps,
             "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9,
             "backward_with_normals_ms": 1e3 * el_n / steps,
-            "backward_with_normals_grad_read_GBps": 24.0 * N / (el_n / steps) / 1e9}
+            "backward_with_normals_grad_read_GBps": 24.0 * N / (el_n / steps) / 1e9,
+            "backward_with_normals_knots_weights_ms": 1e3 * el_p / steps}
 
 
 def precision_study(steps: int = 5):

@@ -241,15 +241,16 @@ int64_t sweep_batched_output_elems(const sweep_batch *batch);
  * grad_path_ctrl (DEVICE, sum(path_n) x 3 FP64) and grad_prof_ctrl (DEVICE,
  * sum(prof_n) x 3 FP64), the gradients of L with respect to the control
  * points.  The frame is recomputed in FP64; reductions accumulate in FP64 in
- * a fixed order (deterministic).  Gradients with respect to weights
- * (rational curves: weights are held fixed) and knots are not provided.
+ * a fixed order (deterministic).  Knots and weights are held fixed here;
+ * sweep_backward_ex also gives their gradients.
  * At tangent reversals the step rotation is treated as locally constant.
  * sweep_backward(..., grad_pos, ...) is sweep_backward_ex with
  * grad_nrm = NULL.
  *
  * sweep_backward_ex also takes grad_nrm = dL/dnrm (DEVICE, same layout and
  * precision as the batched nrm output, or NULL); grad_pos may be NULL when
- * grad_nrm is not (both NULL is SWEEP_ERR_NULL_ARG).  The normal is
+ * grad_nrm is not (both NULL is SWEEP_ERR_NULL_ARG), and params (or NULL)
+ * asks for gradients with respect to knots and weights, see below.  The normal is
  * N = (X_v x X_u)/|X_v x X_u| with X_u from the continuous frame's derivative
  * (its dependence on C'' through the frame's rate of turn is included);
  * where the cross product is 0 or not finite the normal is the constant 0
@@ -260,9 +261,32 @@ sweep_status sweep_backward(const sweep_batch *batch, const sweep_options *opt,
                             const void *grad_pos, double *grad_path_ctrl,
                             double *grad_prof_ctrl, void *workspace, size_t ws_bytes,
                             void *stream);
+
+/*
+ * Knot and weight gradients of sweep_backward_ex (each pointer NULL to skip).
+ * path_knots: DEVICE, packed like batch->path_knots (which must be given),
+ * dL/dU_m for every entry; prof_knots: the same for the open profiles' given
+ * knots (closed profiles have none).  The sample parameters follow the
+ * domain ends U_p and U_n, so those two entries also carry the samples'
+ * motion.  An entry inside a run of equal knots gets the partial derivative
+ * of the evaluation formula with the run's other entries held; the sum over
+ * the run is the derivative for moving the run as a whole (the first and last
+ * knots of a vector never enter the curve: 0).  path_weights / prof_weights:
+ * DEVICE, packed like batch->path_weights / prof_weights (which must be
+ * given), dL/dw_k.  A request without the matching batch field is
+ * SWEEP_ERR_BAD_OPTION.
+ */
+typedef struct {
+    double *path_knots;
+    double *prof_knots;
+    double *path_weights;
+    double *prof_weights;
+} sweep_param_grads;
+
 sweep_status sweep_backward_ex(const sweep_batch *batch, const sweep_options *opt,
                                const void *grad_pos, const void *grad_nrm,
                                double *grad_path_ctrl, double *grad_prof_ctrl,
+                               const sweep_param_grads *params,
                                void *workspace, size_t ws_bytes, void *stream);
 size_t sweep_backward_workspace_size(const sweep_batch *batch, const sweep_options *opt);
 

@@ -39,6 +39,11 @@ class SweepOptions(C.Structure):
                 ("law", C.c_void_p), ("u_sampling", C.c_int32), ("reserved", C.c_int32)]
 
 
+class SweepParamGrads(C.Structure):
+    _fields_ = [("path_knots", C.c_void_p), ("prof_knots", C.c_void_p), ("path_weights", C.c_void_p),
+                ("prof_weights", C.c_void_p)]
+
+
 class SweepBatch(C.Structure):
     _fields_ = [("n_sweeps", C.c_int32), ("reserved", C.c_int32),
                 ("path_n", _ip), ("path_degree", _ip), ("prof_n", _ip), ("prof_degree", _ip),
@@ -85,7 +90,8 @@ def lib():
         L.sweep_batched_output_elems.restype = C.c_int64
         L.sweep_backward.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp, sz, vp]
         L.sweep_backward.restype = C.c_int32
-        L.sweep_backward_ex.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp, vp, sz, vp]
+        L.sweep_backward_ex.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, vp,
+                                        C.POINTER(SweepParamGrads), vp, sz, vp]
         L.sweep_backward_ex.restype = C.c_int32
         L.sweep_backward_workspace_size.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions)]
         L.sweep_backward_workspace_size.restype = sz
@@ -168,9 +174,11 @@ def sweep_backward(batch: SweepBatch, opt: SweepOptions, grad_pos: int, grad_pat
 
 
 def sweep_backward_ex(batch: SweepBatch, opt: SweepOptions, grad_pos: int, grad_nrm: int, grad_path_ctrl: int,
-                      grad_prof_ctrl: int, workspace: int, ws_bytes: int, stream: int) -> int:
+                      grad_prof_ctrl: int, params, workspace: int, ws_bytes: int, stream: int) -> int:
+    """params: a SweepParamGrads or None."""
     return lib().sweep_backward_ex(C.byref(batch), C.byref(opt), grad_pos, grad_nrm, grad_path_ctrl,
-                                   grad_prof_ctrl, workspace, ws_bytes, stream)
+                                   grad_prof_ctrl, C.byref(params) if params is not None else None, workspace,
+                                   ws_bytes, stream)
 
 
 def sweep_batched_output_elems(batch: SweepBatch) -> int:

@@ -302,6 +302,14 @@ class Batch:
         self.n_vertices = int(sizes.sum())
         self.path_offsets = np.concatenate([[0], np.cumsum(self.path_n)[:-1]]).astype(np.int64)
         self.prof_offsets = np.concatenate([[0], np.cumsum(self.prof_n)[:-1]]).astype(np.int64)
+        # offsets of each sweep's knots in the packed knot arrays (-1: none)
+        closed = self.prof_closed if self.prof_closed is not None else np.ones(n, np.int32)
+        pk_len = (self.path_n + self.path_degree + 1).astype(np.int64)
+        qk_len = np.where(closed == 0, self.prof_n + self.prof_degree + 1, 0).astype(np.int64)
+        self.path_knot_offsets = (np.concatenate([[0], np.cumsum(pk_len)[:-1]]) if self.path_knots is not None
+                                  else np.full(n, -1)).astype(np.int64)
+        self.prof_knot_offsets = (np.where(closed == 0, np.concatenate([[0], np.cumsum(qk_len)[:-1]]), -1)
+                                  if self.prof_knots is not None else np.full(n, -1)).astype(np.int64)
 
     @staticmethod
     def _pack_weights(ws, ctrl, what, device):
@@ -357,6 +365,14 @@ class Batch:
             self.view(flat, k).copy_(torch.as_tensor(blk))
         return flat
 
+    def path_knot_slice(self, k: int) -> slice:
+        o = int(self.path_knot_offsets[k])
+        return slice(o, o + int(self.path_n[k] + self.path_degree[k] + 1))
+
+    def prof_knot_slice(self, k: int) -> slice:
+        o = int(self.prof_knot_offsets[k])
+        return slice(o, o + int(self.prof_n[k] + self.prof_degree[k] + 1))
+
     def path_slice(self, k: int) -> slice:
         return slice(int(self.path_offsets[k]), int(self.path_offsets[k] + self.path_n[k]))
 
@@ -396,12 +412,18 @@ def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=to
     return L.sweep_batched_workspace_size(batch.c_struct(), make_options(out_dtype, frame_dtype))
 
 
+_PARAM_GRADS = ("path_knots", "prof_knots", "path_weights", "prof_weights")
+
+
 def sweep_backward(batch: Batch, grad_pos: Optional[torch.Tensor], *, grad_nrm: Optional[torch.Tensor] = None,
-                   initial_normal=None, workspace=None, stream=None):
+                   params: Sequence[str] = (), initial_normal=None, workspace=None, stream=None):
     """Gradients of L with dL/dpos = grad_pos and dL/dnrm = grad_nrm (flat,
     like the batched outputs; their dtype is the output precision; either may
     be None, not both) with respect to the packed path and profile control
-    points: (g_path (sum path_n, 3), g_prof (sum prof_n, 3)), float64."""
+    points: (g_path (sum path_n, 3), g_prof (sum prof_n, 3)), float64.  With
+    params (names among path_knots, prof_knots, path_weights, prof_weights)
+    a third item maps each name to its float64 gradient, packed like the
+    batch's knot or weight array."""
     b = batch.c_struct()
     given = [t for t in (grad_pos, grad_nrm) if t is not None]
     if not given:
@@ -417,16 +439,30 @@ def sweep_backward(batch: Batch, grad_pos: Optional[torch.Tensor], *, grad_nrm: 
     opt = make_options(dt, torch.float64, True, initial_normal)
     ws_bytes = L.sweep_backward_workspace_size(b, opt)
     if ws_bytes == 0:
-        L.check(L.sweep_backward_ex(b, opt, 0, 0, 0, 0, 0, 0, 0))
+        L.check(L.sweep_backward_ex(b, opt, 0, 0, 0, 0, None, 0, 0, 0))
     dev = batch.path_ctrl.device
     gP = torch.empty((int(batch.path_n.sum()), 3), dtype=torch.float64, device=dev)
     gQ = torch.empty((int(batch.prof_n.sum()), 3), dtype=torch.float64, device=dev)
     if workspace is None or _nbytes(workspace) < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    extra, pg = {}, None
+    if params:
+        pg = L.SweepParamGrads()
+        sizes = {"path_knots": None if batch.path_knots is None else batch.path_knots.shape[0],
+                 "prof_knots": None if batch.prof_knots is None else batch.prof_knots.shape[0],
+                 "path_weights": None if batch.path_weights is None else batch.path_weights.numel(),
+                 "prof_weights": None if batch.prof_weights is None else batch.prof_weights.numel()}
+        for name in params:
+            if name not in _PARAM_GRADS:
+                raise ValueError(f"unknown parameter gradient {name!r}")
+            if not sizes[name]:
+                raise ValueError(f"{name} gradients need the batch's {name}")
+            extra[name] = torch.zeros(sizes[name], dtype=torch.float64, device=dev)
+            setattr(pg, name, extra[name].data_ptr())
     L.check(L.sweep_backward_ex(b, opt, g.data_ptr() if g is not None else 0, gn.data_ptr() if gn is not None else 0,
-                                gP.data_ptr(), gQ.data_ptr(), workspace.data_ptr(), _nbytes(workspace),
+                                gP.data_ptr(), gQ.data_ptr(), pg, workspace.data_ptr(), _nbytes(workspace),
                                 _stream_handle(stream)))
-    return gP, gQ
+    return (gP, gQ, extra) if params else (gP, gQ)
 
 
 def backward_workspace_size(batch: Batch, out_dtype=torch.float32) -> int:

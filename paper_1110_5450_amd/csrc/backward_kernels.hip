@@ -30,6 +30,7 @@
 // kbw_adjoint  one block per sweep: finishes the partial sums, runs the
 //              suffix sum, the per-sample adjoint and the per-control-point
 //              gathers.
+#include "basis_ders.hpp"
 #include "frame_common.hpp"
 
 namespace sweep {
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
                                                       const double* colpart, double* rowacc, double* colacc,
                                                       double* rho, double* sgrad, int* spans_u, double* qgrad,
                                                       int* spans_v, double* __restrict__ gP, double* __restrict__ gQ,
-                                                      int nrm)
+                                                      int nrm, double* xstash)
 {
     const int rp = nrm ? kRowPartNrm : kRowPart, cp = nrm ? kColPartNrm : kColPart;
     __shared__ double lds3[kWaves][3];
@@ -597,6 +598,13 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
         V3<double> cb = mk(0.0, 0.0, 0.0);
         if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L) + Lb * R.t;
         su[i] = s;
+        if (xstash) {
+            // dL/dC, dL/dC', dL/dC'' of the sample, for the knot and weight gradients
+            double* q = xstash + 9 * (d.row_off + (size_t)i);
+            q[0] = xb.x; q[1] = xb.y; q[2] = xb.z;
+            q[3] = cb.x; q[4] = cb.y; q[5] = cb.z;
+            q[6] = C2b.x; q[7] = C2b.y; q[8] = C2b.z;
+        }
         for (int j = 0; j <= path.p; ++j) {
             V3<double> c = Nv[j] * xb + dN[j] * cb;
             if (nrm) c = c + d2N[j] * C2b;
@@ -693,12 +701,208 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
     }
 }
 
+// ------------------------------------------------ knot and weight gradients
+
+// Per-sample records of the parameter gradients (kParamRec doubles): the
+// 2p local knot contributions, then the p+1 local weight contributions, and
+// dL/du (the sample's parameter) in the last slot.
+constexpr int kParamRec = 24;
+
+// Contributions of one sample on span s at parameter u, given dL/dC, dL/dC'
+// and dL/dC'' there: kc[m] = dL/dU_{s-P+1+m} at fixed u (m < 2P), wc[l] =
+// dL/dw_{s-P+l} (rational curves), and the return value dL/du.  Dual-number
+// passes of the basis and curve derivatives, one per local knot or weight.
+template <int P>
+__device__ __noinline__ double param_contrib(const DCurve& c, double u, int s, V3<double> xb, V3<double> cb,
+                                             V3<double> c2b, bool want_k, bool want_w, double* kc, double* wc)
+{
+    double Pl[P + 1][3];
+    Dual Ud[2 * P], wd[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        const V3<double> q = ctrl_pt(c, s - P + j);
+        Pl[j][0] = q.x; Pl[j][1] = q.y; Pl[j][2] = q.z;
+        wd[j] = dual(c.w ? weight_at(c, s - P + j) : 1.0);
+    }
+#pragma unroll
+    for (int m = 0; m < 2 * P; ++m) Ud[m] = dual(knot(c, s - P + 1 + m));
+    const Dual* wp = c.w ? wd : nullptr;
+    const Dual ud = dual(u);
+    // dL/du: C', C'', C''' at fixed knots and weights
+    double eu;
+    {
+        Dual D[4][P + 1], C[4][3];
+        basis_ders<P, 3, Dual>(Ud, ud, D);
+        curve_ders<P, 3, Dual>(D, Pl, wp, C);
+        eu = xb.x * C[1][0].v + xb.y * C[1][1].v + xb.z * C[1][2].v + cb.x * C[2][0].v + cb.y * C[2][1].v +
+             cb.z * C[2][2].v + c2b.x * C[3][0].v + c2b.y * C[3][1].v + c2b.z * C[3][2].v;
+    }
+    auto contract = [&](const Dual (&C)[3][3]) {
+        return xb.x * C[0][0].d + xb.y * C[0][1].d + xb.z * C[0][2].d + cb.x * C[1][0].d + cb.y * C[1][1].d +
+               cb.z * C[1][2].d + c2b.x * C[2][0].d + c2b.y * C[2][1].d + c2b.z * C[2][2].d;
+    };
+    if (want_k) {
+        for (int m = 0; m < 2 * P; ++m) {
+            Ud[m].d = 1.0;
+            Dual D[3][P + 1], C[3][3];
+            basis_ders<P, 2, Dual>(Ud, ud, D);
+            curve_ders<P, 2, Dual>(D, Pl, wp, C);
+            kc[m] = contract(C);
+            Ud[m].d = 0.0;
+        }
+    }
+    if (want_w && c.w) {
+        Dual D[3][P + 1];
+        basis_ders<P, 2, Dual>(Ud, ud, D);
+        for (int l = 0; l <= P; ++l) {
+            wd[l].d = 1.0;
+            Dual C[3][3];
+            curve_ders<P, 2, Dual>(D, Pl, wd, C);
+            wc[l] = contract(C);
+            wd[l].d = 0.0;
+        }
+    }
+    return eu;
+}
+
+__device__ __forceinline__ double param_contrib_any(const DCurve& c, double u, int s, V3<double> xb, V3<double> cb,
+                                                    V3<double> c2b, bool want_k, bool want_w, double* kc,
+                                                    double* wc)
+{
+    switch (c.p) {
+    case 1: return param_contrib<1>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    case 2: return param_contrib<2>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    case 3: return param_contrib<3>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    case 4: return param_contrib<4>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    case 5: return param_contrib<5>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    case 6: return param_contrib<6>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    default: return param_contrib<7>(c, u, s, xb, cb, c2b, want_k, want_w, kc, wc);
+    }
+}
+
+// Sum over the block of (a, b) pairs, thread order fixed.
+__device__ __forceinline__ void block_pair_total(double a, double b, double (*lds)[3], double& ta, double& tb)
+{
+    V3<double> tot;
+    block_suffix_sum(mk(a, b, 0.0), lds, tot);
+    ta = tot.x;
+    tb = tot.y;
+}
+
+// One curve's knot and weight gradients from its per-sample adjoints:
+// records per sample, the domain-end terms of the sample parameters
+// (u = U_p + (U_n - U_p) i/(ns-1) on an open curve), then one thread per
+// knot / weight gathers the samples whose span reaches it.
+// adj(i, xb, cb, c2b) gives the sample's dL/dC, dL/dC', dL/dC''.
+template <class Adj>
+__device__ void curve_param_grads(const DCurve& c, int ns, const int* spans, double* rec, bool want_k, bool want_w,
+                                  double* gk, double* gw, double (*lds)[3], Adj adj)
+{
+    const int p = c.p;
+    for (int i = threadIdx.x; i < ns; i += kBlock) {
+        V3<double> xb, cb, c2b;
+        adj(i, xb, cb, c2b);
+        double* r = rec + kParamRec * (size_t)i;
+        const double u = sample_param(c, i, ns);
+        r[kParamRec - 1] = param_contrib_any(c, u, spans[i], xb, cb, c2b, want_k, want_w, r, r + 2 * p);
+    }
+    __syncthreads();
+    double e0 = 0.0, e1 = 0.0;   // dL/dU_p and dL/dU_n through the sample parameters
+    if (want_k) {
+        for (int b0 = 0; b0 < ns; b0 += kBlock) {
+            const int i = b0 + threadIdx.x;
+            double a = 0.0, b = 0.0;
+            if (i < ns) {
+                const double eu = rec[kParamRec * (size_t)i + kParamRec - 1];
+                const double f = (double)i / (double)(ns - 1);
+                a = eu * (1.0 - f);
+                b = eu * f;
+            }
+            double ta, tb;
+            block_pair_total(a, b, lds, ta, tb);
+            e0 += ta;
+            e1 += tb;
+        }
+        // knots 0 .. n+p: samples with span in [m-p, m+p-1] reach knot m
+        for (int m = threadIdx.x; m <= c.n + p; m += kBlock) {
+            const int lo = lower_bound_int(spans, ns, m - p), hi = lower_bound_int(spans, ns, m + p);
+            double acc = 0.0;
+            for (int i = lo; i < hi; ++i) acc += rec[kParamRec * (size_t)i + (m - (spans[i] - p + 1))];
+            if (m == p) acc += e0;
+            if (m == c.n) acc += e1;
+            gk[m] = acc;
+        }
+    }
+    if (want_w && c.w) {
+        // weight l: basis indices l (and l + n on a closed curve), reached by
+        // the samples with span in [k, k+p]
+        for (int l = threadIdx.x; l < c.n; l += kBlock) {
+            double acc = 0.0;
+            for (int kk = l; kk < c.nb; kk += c.n) {
+                const int lo = lower_bound_int(spans, ns, kk), hi = lower_bound_int(spans, ns, kk + p + 1);
+                for (int i = lo; i < hi; ++i) acc += rec[kParamRec * (size_t)i + 2 * p + (kk - (spans[i] - p))];
+                if (!c.closed) break;
+            }
+            gw[l] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// One block per sweep, after kbw_adjoint: xstash holds dL/dC, dL/dC',
+// dL/dC'' per path sample (9 doubles), colacc dL/dS (and dL/dS') per
+// profile sample, spans_u / spans_v the samples' spans.
+__global__ __launch_bounds__(kBlock) void kbw_params(const BatchDesc* __restrict__ descs,
+                                                     const double* __restrict__ path_ctrl,
+                                                     const double* __restrict__ prof_ctrl,
+                                                     const double* __restrict__ path_w,
+                                                     const double* __restrict__ prof_w,
+                                                     const double* __restrict__ knots, const double* xstash,
+                                                     const double* colacc, const int* spans_u, const int* spans_v,
+                                                     double* recu, double* recv, int nrm, double* gPk, double* gQk,
+                                                     double* gPw, double* gQw)
+{
+    __shared__ double lds3[kWaves][3];
+    const BatchDesc d = descs[blockIdx.x];
+    const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
+                      d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
+    const DCurve prof{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
+                      d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
+                      prof_w ? prof_w + d.prof_ctrl_off : nullptr};
+    const int cp = nrm ? kColPartNrm : kColPart;
+    const bool pk = gPk && d.path_kuser_off >= 0, qk = gQk && d.prof_kuser_off >= 0;
+    const bool pw = gPw != nullptr, qw = gQw != nullptr;
+    if (pk || pw) {
+        const double* xs = xstash + 9 * d.row_off;
+        curve_param_grads(path, d.n_u, spans_u + d.row_off, recu + kParamRec * d.row_off, pk, pw,
+                          pk ? gPk + d.path_kuser_off : nullptr, pw ? gPw + d.path_ctrl_off : nullptr, lds3,
+                          [&](int i, V3<double>& xb, V3<double>& cb, V3<double>& c2b) {
+                              const double* q = xs + 9 * (size_t)i;
+                              xb = mk(q[0], q[1], q[2]);
+                              cb = mk(q[3], q[4], q[5]);
+                              c2b = mk(q[6], q[7], q[8]);
+                          });
+    }
+    if (qk || qw) {
+        const double* ca = colacc + (size_t)cp * d.ptab_off;
+        curve_param_grads(prof, d.n_v, spans_v + d.ptab_off, recv + kParamRec * d.ptab_off, qk, qw,
+                          qk ? gQk + d.prof_kuser_off : nullptr, qw ? gQw + d.prof_ctrl_off : nullptr, lds3,
+                          [&](int j, V3<double>& xb, V3<double>& cb, V3<double>& c2b) {
+                              const double* q = ca + (size_t)cp * j;
+                              xb = mk(q[0], q[1], q[2]);
+                              cb = nrm ? mk(q[3], q[4], q[5]) : mk(0.0, 0.0, 0.0);
+                              c2b = mk(0.0, 0.0, 0.0);
+                          });
+    }
+}
+
 BackwardKernels backward_kernels(bool t64, bool nrm)
 {
     BackwardKernels k;
     if (nrm) k.reduce = t64 ? (const void*)&kbw_reduce<double, true> : (const void*)&kbw_reduce<float, true>;
     else k.reduce = t64 ? (const void*)&kbw_reduce<double, false> : (const void*)&kbw_reduce<float, false>;
     k.adjoint = (const void*)&kbw_adjoint;
+    k.params = (const void*)&kbw_params;
     return k;
 }
 

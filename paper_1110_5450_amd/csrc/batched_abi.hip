@@ -36,7 +36,8 @@ struct BatchLayout {
 
 // Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
 struct BackwardLayout {
-    size_t rows, ptab, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v, total;
+    size_t rows, ptab, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v;
+    size_t xstash, recu, recv, total;
 };
 
 static BackwardLayout backward_layout(const BatchLayout& L)
@@ -56,6 +57,10 @@ static BackwardLayout backward_layout(const BatchLayout& L)
     B.spans_u = seg(4 * (size_t)L.n_rows);
     B.qgrad = seg(8 * 24 * (size_t)L.n_vs);
     B.spans_v = seg(4 * (size_t)L.n_vs);
+    // knot and weight gradients: per-sample adjoints and records
+    B.xstash = seg(8 * 9 * (size_t)L.n_rows);
+    B.recu = seg(8 * 24 * (size_t)L.n_rows);
+    B.recv = seg(8 * 24 * (size_t)L.n_vs);
     B.total = off;
     return B;
 }
@@ -107,6 +112,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             d.plane = plane_stride((long long)nu * nv);
             d.row_off = L.n_rows; d.ptab_off = L.n_vs;
             d.rowpart_off = L.n_rowpart; d.colpart_off = L.n_colpart; d.nseg = nseg; d.ngroup = ngroup;
+            d.path_kuser_off = pk ? pk_off : -1;
+            d.prof_kuser_off = qk ? qk_off : -1;
             descs->push_back(d);
         }
         if (key) {
@@ -430,13 +437,13 @@ sweep_status sweep_backward(const sweep_batch* batch, const sweep_options* opt, 
                             void* stream)
 {
     if (!grad_pos) return fail(SWEEP_ERR_NULL_ARG, "grad_pos is NULL");
-    return sweep_backward_ex(batch, opt, grad_pos, nullptr, grad_path_ctrl, grad_prof_ctrl, workspace, ws_bytes,
-                             stream);
+    return sweep_backward_ex(batch, opt, grad_pos, nullptr, grad_path_ctrl, grad_prof_ctrl, nullptr, workspace,
+                             ws_bytes, stream);
 }
 
 sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* opt, const void* grad_pos,
                                const void* grad_nrm, double* grad_path_ctrl, double* grad_prof_ctrl,
-                               void* workspace, size_t ws_bytes, void* stream)
+                               const sweep_param_grads* params, void* workspace, size_t ws_bytes, void* stream)
 {
     sweep_options def;
     if (!opt) { sweep_default_options(&def); opt = &def; }
@@ -447,6 +454,13 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
     if (!grad_pos && !grad_nrm) return fail(SWEEP_ERR_NULL_ARG, "grad_pos and grad_nrm are both NULL");
     if (!grad_path_ctrl || !grad_prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "a gradient buffer is NULL");
     const int nrm = grad_nrm != nullptr;
+    sweep_param_grads pg{};
+    if (params) pg = *params;
+    if (pg.path_knots && !batch->path_knots) return fail(SWEEP_ERR_BAD_OPTION, "path knot gradients need given path knots");
+    if (pg.prof_knots && !batch->prof_knots) return fail(SWEEP_ERR_BAD_OPTION, "profile knot gradients need given profile knots");
+    if (pg.path_weights && !batch->path_weights) return fail(SWEEP_ERR_BAD_OPTION, "path weight gradients need path weights");
+    if (pg.prof_weights && !batch->prof_weights) return fail(SWEEP_ERR_BAD_OPTION, "profile weight gradients need profile weights");
+    const bool want_params = pg.path_knots || pg.prof_knots || pg.path_weights || pg.prof_weights;
     const BackwardLayout B = backward_layout(L);
     if (!workspace || ws_bytes < B.total)
         return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, B.total);
@@ -535,10 +549,27 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         double* gp = grad_path_ctrl;
         double* gq = grad_prof_ctrl;
         int nrm_arg = nrm;
-        void* args[20] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
-                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq, &nrm_arg};
+        void* xstash = want_params ? ws + B.xstash : nullptr;
+        void* args[21] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
+                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq, &nrm_arg, &xstash};
         if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward adjoint");
+        if (want_params) {
+            const void* xs = xstash;
+            const void* ca = colacc;
+            const void* su = spans_u;
+            const void* sv = spans_v;
+            void* recu = ws + B.recu;
+            void* recv = ws + B.recv;
+            double* gpk = pg.path_knots;
+            double* gqk = pg.prof_knots;
+            double* gpw = pg.path_weights;
+            double* gqw = pg.prof_weights;
+            void* pargs[17] = {&descs, &pc, &qc, &pw, &qw, &kn, &xs, &ca, &su, &sv, &recu, &recv, &nrm_arg,
+                               &gpk, &gqk, &gpw, &gqw};
+            if ((e = hipLaunchKernel(BK.params, dim3(batch->n_sweeps), dim3(kBlock), pargs, 0, sm)) != hipSuccess)
+                return hip_fail(e, "backward knot and weight gradients");
+        }
     }
     return SWEEP_OK;
 }

@@ -82,6 +82,8 @@ struct BatchDesc {
     long long rowpart_off;         // adjoint: first per-segment row partial (12 doubles each)
     long long colpart_off;         // adjoint: first per-group column partial (3 doubles each)
     int nseg, ngroup;              // adjoint: 64-column segments, row groups
+    long long path_kuser_off;      // adjoint: offset of the path's knots in the caller's packing, -1 = none
+    long long prof_kuser_off;      // adjoint: the same for an open profile's knots
 };
 
 // Batched output planes start on multiples of this many elements (256 B in
@@ -98,6 +100,7 @@ inline int bw_row_group_for(bool t64) { return t64 ? 4 : 8; }
 struct BackwardKernels {
     const void* reduce;
     const void* adjoint;
+    const void* params;    // knot and weight gradients
 };
 // nrm: the reduction also takes dL/dN (normal terms, longer partial records).
 BackwardKernels backward_kernels(bool t64, bool nrm);

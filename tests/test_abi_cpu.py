@@ -206,8 +206,14 @@ def test_backward_ex_requires_a_gradient():
     spec = synth.single(3, 8, 6, 32, 16)
     b = api.Batch.from_specs([spec], device="cpu")
     o = L.default_options()
-    st = L.sweep_backward_ex(b.c_struct(), o, 0, 0, FAKE, FAKE, FAKE, 1 << 40, 0)
+    st = L.sweep_backward_ex(b.c_struct(), o, 0, 0, FAKE, FAKE, None, FAKE, 1 << 40, 0)
     assert L.STATUS[st] == "SWEEP_ERR_NULL_ARG" and "both NULL" in L.last_error()
+    # knot and weight gradients need the matching batch fields
+    for name in ("path_knots", "prof_knots", "path_weights", "prof_weights"):
+        pg = L.SweepParamGrads()
+        setattr(pg, name, FAKE)
+        st = L.sweep_backward_ex(b.c_struct(), o, FAKE, 0, FAKE, FAKE, pg, FAKE, 1 << 40, 0)
+        assert L.STATUS[st] == "SWEEP_ERR_BAD_OPTION", name
     st = L.sweep_backward(b.c_struct(), o, 0, FAKE, FAKE, FAKE, 1 << 40, 0)
     assert L.STATUS[st] == "SWEEP_ERR_NULL_ARG" and "grad_pos" in L.last_error()
     assert L.sweep_backward_workspace_size(b.c_struct(), o) > 0
