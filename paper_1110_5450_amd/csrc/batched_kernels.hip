@@ -179,23 +179,48 @@ __global__ __launch_bounds__(kBlock) void kb_surface(const BatchDesc* __restrict
     const T* ptab_k = ptab + 8 * d.ptab_off;
     T* pos_k = pos + d.out_off;
     T* nrm_k = NRM ? nrm + d.out_off : nrm;
-    // the sweep's last tile also covers the plane padding [N, plane), which
-    // is zeroed (plane <= N rounded up to the tile size)
+    // The profile records of all K vertices are loaded before the first
+    // store: on this ISA the vector-memory counter also counts stores, so a
+    // load issued after a store would wait for it.  Row records come from
+    // LDS (or, for a tile of more than kMaxLdsRows rows, from global memory).
+    T qv[K][6];
+    int vi[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const long long v = v0 + threadIdx.x + k * kBlock;
+        vi[k] = 0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) qv[k][e] = T(0);
         if (v < N) {
             const int i = fdiv((unsigned)v, dv);
             const int j = (int)v - i * d.n_v;
+            vi[k] = i;
             const T* q = ptab_k + 8 * (size_t)j;
-            const T* row = staged ? lrow + 16 * (i - ilo) : rows_k + 16 * (size_t)i;
-            T X[3], Nn[3];
-            vertex<T>(row, q[0], q[1], q[2], q[3], q[4], q[5], X, Nn);
-            store6<NT>(pos_k, nrm_k, (size_t)d.plane, (size_t)v, X, Nn, NRM);
-        } else if (v < d.plane) {
-            const T z[3] = {T(0), T(0), T(0)};
-            store6<NT>(pos_k, nrm_k, (size_t)d.plane, (size_t)v, z, z, NRM);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) qv[k][e] = q[e];
         }
+    }
+    // the sweep's last tile also covers the plane padding [N, plane), which
+    // is zeroed (plane <= N rounded up to the tile size).  Two copies of the
+    // row reads (block-uniform choice), so that the staged one reads LDS only.
+    // All K vertices are formed before the first store, for the same reason.
+    T X[K][3], Nn[K][3];
+    auto form = [&](const T* base, int row0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) X[k][c] = Nn[k][c] = T(0);
+            if (v0 + threadIdx.x + k * kBlock < N)
+                vertex<T>(base + 16 * (size_t)(vi[k] - row0), qv[k][0], qv[k][1], qv[k][2], qv[k][3], qv[k][4],
+                          qv[k][5], X[k], Nn[k]);
+        }
+    };
+    if (staged) form(lrow, ilo);
+    else form(rows_k, 0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const long long v = v0 + threadIdx.x + k * kBlock;
+        if (v < d.plane) store6<NT>(pos_k, nrm_k, (size_t)d.plane, (size_t)v, X[k], Nn[k], NRM);
     }
 }
 
