@@ -67,9 +67,11 @@ def lib():
         L.or_max_threads.restype = C.c_int
         L.or_sweep_ex.restype = C.c_int
         L.or_sweep_ex.argtypes = [C.POINTER(_Curve), C.POINTER(_Curve), C.c_int, C.c_int, _dp, C.c_int, C.c_int,
-                                  C.c_void_p, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+                                  C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_arclength_params.restype = C.c_double
         L.or_arclength_params.argtypes = [C.POINTER(_Curve), C.c_int, _dp]
+        L.or_monitor_params.restype = C.c_double
+        L.or_monitor_params.argtypes = [C.POINTER(_Curve), C.c_int, C.c_double, _dp]
         L.or_curve_samples_at.restype = None
         L.or_triangles.restype = C.c_longlong
         L.or_triangles.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p]
@@ -265,7 +267,7 @@ def surface_ex_from_samples(x, d1, d2, R, omega, law, S, dS):
 
 
 def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mode: str = "rmf", law=None,
-             rows: Optional[Tuple[int, int]] = None, want_kappa=True, arclength: bool = False):
+             rows: Optional[Tuple[int, int]] = None, want_kappa=True, arclength: bool = False, lam: float = 0.0):
     """Whole sweep with a frame mode ("rmf" or "frenet") and an optional law
     curve (open curve whose control points hold (scale, twist angle, -)).
     Returns (SweepResult, omega (n_u,))."""
@@ -279,7 +281,7 @@ def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mo
     om = np.empty(n_u)
     n0a = None if n0 is None else _f64(n0)
     nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), int(reorth), FRAME_MODES[mode],
-                           None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), r0, r1,
+                           None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), float(lam), r0, r1,
                            _ptr(pos), _ptr(nrm), _ptr(kap), _ptr(R), _ptr(om))
     if nf < 0:
         raise ValueError("oracle: bad sweep input")
@@ -287,7 +289,7 @@ def sweep_ex(path, profile, n_u: int, n_v: int, n0=None, reorth: bool = True, mo
 
 
 def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = "rmf", law=None,
-                  arclength: bool = False):
+                  arclength: bool = False, lam: float = 0.0):
     """sweep_ex on the listed rows only: (pos (3, len(rows), n_v), nrm,
     kappa (len(rows), n_v))."""
     rows = np.asarray(rows, dtype=np.int64)
@@ -299,18 +301,22 @@ def sweep_rows_ex(path, profile, n_u: int, n_v: int, rows, n0=None, mode: str = 
     n0a = None if n0 is None else _f64(n0)
     for i in rows:
         nf = lib().or_sweep_ex(P.ref, Q.ref, n_u, n_v, _ptr(n0a), 1, FRAME_MODES[mode],
-                               None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), int(i),
+                               None if Lw is None else C.cast(Lw.ref, C.c_void_p), int(bool(arclength)), float(lam),
+                               int(i),
                                int(i) + 1, _ptr(pos), _ptr(nrm), _ptr(kap), None, None)
         if nf < 0:
             raise ValueError("oracle: bad sweep input")
     return pos[:, rows], nrm[:, rows], kap[rows]
 
 
-def arclength_params(curve, ns: int):
-    """(u (ns,), total length) of the arc-length samples of an open curve."""
+def arclength_params(curve, ns: int, lam: float = 0.0):
+    """(u (ns,), total) of the arc-length samples of an open curve, or with
+    lam > 0 of the curvature-adaptive samples (total = arc length + lam x
+    turning angle)."""
     c = Curve.of(curve)
     u = np.empty(ns)
-    total = lib().or_arclength_params(c.ref, int(ns), _ptr(u))
+    total = (lib().or_arclength_params(c.ref, int(ns), _ptr(u)) if lam == 0.0
+             else lib().or_monitor_params(c.ref, int(ns), float(lam), _ptr(u)))
     if total < 0:
         raise ValueError("arc-length sampling needs an open curve")
     return u, total

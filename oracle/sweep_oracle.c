@@ -502,15 +502,26 @@ static void gauss_legendre8(double *x, double *w)
 
 #define OR_ARC_SUB 32   /* equal sub-intervals per knot span, 8 Gauss nodes each */
 
-/* Integral of |C'| over [a, b] by the 8-point Gauss-Legendre rule. */
-static double speed_gl8(const or_curve *c, const double *U, double a, double b, const double *gx, const double *gw)
+/* Sampling density at u: |C'| (arc length), plus lam |C'| kappa =
+ * lam |C' x C''| / |C'|^2 (lam times the rate of turn of the tangent), so
+ * that its integral is arc length + lam x turning angle. */
+static double density(const or_curve *c, const double *U, double u, double lam)
+{
+    double o[9];
+    or_curve_eval(c, U, u, lam != 0.0 ? 2 : 1, o);
+    double sp = norm3(o + 3);
+    if (lam == 0.0) return sp;
+    double cr[3];
+    cross3(o + 3, o + 6, cr);
+    return sp + (sp > 0.0 ? lam * norm3(cr) / (MUT(21) ? sp * sp * sp : sp * sp) : 0.0);
+}
+
+/* Integral of the density over [a, b] by the 8-point Gauss-Legendre rule. */
+static double speed_gl8(const or_curve *c, const double *U, double a, double b, double lam, const double *gx,
+                        const double *gw)
 {
     double mid = 0.5 * (a + b), half = 0.5 * (b - a), part = 0.0;
-    for (int k = 0; k < 8; ++k) {
-        double o[6];
-        or_curve_eval(c, U, mid + half * gx[k], 1, o);
-        part += gw[k] * norm3(o + 3);
-    }
+    for (int k = 0; k < 8; ++k) part += gw[k] * density(c, U, mid + half * gx[k], lam);
     return half * part;
 }
 
@@ -527,8 +538,11 @@ static double speed_gl8(const or_curve *c, const double *U, double a, double b, 
  * step that leaves it or meets |C'| = 0), until s(u) hits the target
  * exactly, |du| <= 4 eps max(1, |u|), or 40 steps.
  * u_out: ns values; returns the total length, or -1 for a closed curve.
+ * With lam > 0 the same with the density |C'| (1 + lam kappa) in place of
+ * |C'| (curvature-adaptive sampling: equal steps of arc length plus lam
+ * times the turning angle; lam = 0 is arc length).
  */
-double or_arclength_params(const or_curve *c, int ns, double *u_out)
+double or_monitor_params(const or_curve *c, int ns, double lam, double *u_out)
 {
     if (c->closed) return -1.0;
     double gx[8], gw[8];
@@ -546,7 +560,7 @@ double or_arclength_params(const or_curve *c, int ns, double *u_out)
             double w = U[k + 1] - U[k];
             lo[q] = U[k] + w * ((double)m / OR_ARC_SUB);
             hi[q] = m + 1 < OR_ARC_SUB ? U[k] + w * ((double)(m + 1) / OR_ARC_SUB) : U[k + 1];
-            cum[q + 1] = cum[q] + (w > 0.0 ? speed_gl8(c, U, lo[q], hi[q], gx, gw) : 0.0);
+            cum[q + 1] = cum[q] + (w > 0.0 ? speed_gl8(c, U, lo[q], hi[q], lam, gx, gw) : 0.0);
         }
     double total = cum[npc];
     for (int i = 0; i < ns; ++i) {
@@ -560,12 +574,10 @@ double or_arclength_params(const or_curve *c, int ns, double *u_out)
         double u = len > 0.0 ? lo[q] + (target - cum[q]) / len * (hi[q] - lo[q]) : lo[q];
         double blo = lo[q], bhi = hi[q];
         for (int it = 0; it < 40; ++it) {
-            double f = cum[q] + speed_gl8(c, U, lo[q], u, gx, gw) - target;
+            double f = cum[q] + speed_gl8(c, U, lo[q], u, lam, gx, gw) - target;
             if (f == 0.0) break;
             if (f > 0.0) bhi = u; else blo = u;
-            double o[6];
-            or_curve_eval(c, U, u, 1, o);
-            double sp = norm3(o + 3), un;
+            double sp = density(c, U, u, lam), un;
             if (sp > 0.0) un = u - f / sp;
             else un = 0.5 * (blo + bhi);
             if (!(un >= blo && un <= bhi)) un = 0.5 * (blo + bhi);
@@ -581,6 +593,8 @@ double or_arclength_params(const or_curve *c, int ns, double *u_out)
     free(U);
     return total;
 }
+
+double or_arclength_params(const or_curve *c, int ns, double *u_out) { return or_monitor_params(c, ns, 0.0, u_out); }
 
 /* Curve samples at given parameters (pts/d1/d2/d3 ns x 3, d1..d3 may be NULL). */
 void or_curve_samples_at(const or_curve *c, int ns, const double *u, double *pts, double *d1, double *d2,
@@ -817,14 +831,15 @@ int or_sweep(const or_curve *path, const or_curve *prof, int nu, int nv,
 /*
  * Whole sweep with a frame mode (0 rotation-minimizing, 1 Frenet), an
  * optional law curve (NULL: none) and the path sampled uniformly in its
- * parameter (arclength = 0) or in arc length (1; not with a law).  Same outputs as or_sweep (omega_out,
+ * parameter (arclength = 0) or in arc length (1; not with a law), with
+ * lam > 0 curvature-adaptively (see or_monitor_params).  Same outputs as or_sweep (omega_out,
  * nu values, may be NULL); with mode 0 and no law the result equals
  * or_sweep's up to rounding (the surface derivative is then assembled in
  * world instead of frame coordinates).
  */
 int or_sweep_ex(const or_curve *path, const or_curve *prof, int nu, int nv,
-                const double *n0, int reorth, int mode, const or_curve *law, int arclength, int row0, int row1,
-                double *pos, double *nrm, double *kappa, double *frame_out, double *omega_out)
+                const double *n0, int reorth, int mode, const or_curve *law, int arclength, double lam, int row0,
+                int row1, double *pos, double *nrm, double *kappa, double *frame_out, double *omega_out)
 {
     if (nu < 2 || nv < 1 || path->closed || (law && law->closed) || (law && arclength)) return -1;
     double *x = (double *)malloc(sizeof(double) * 12 * (size_t)nu);
@@ -836,7 +851,7 @@ int or_sweep_ex(const or_curve *path, const or_curve *prof, int nu, int nv,
     double *dS = S + 3 * (size_t)nv;
     if (arclength) {
         double *u = (double *)malloc(sizeof(double) * (size_t)nu);
-        or_arclength_params(path, nu, u);
+        or_monitor_params(path, nu, lam, u);
         or_curve_samples_at(path, nu, u, x, d1, d2, d3);
         free(u);
     } else {

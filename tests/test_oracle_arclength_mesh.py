@@ -109,3 +109,42 @@ def test_triangles_count_wrap_and_orientation(closed):
     fn = np.cross(b - a, c - a)
     vn = N[tri[:, 0]] + N[tri[:, 1]] + N[tri[:, 2]]
     assert np.all((fn * vn).sum(1) > 0)
+
+
+# ------------------------------------------ curvature-adaptive sampling
+# density |C'| (1 + lam kappa): equal steps of arc length + lam x turning angle
+
+def test_adaptive_with_lam_zero_is_arc_length():
+    spec = synth.c1().path
+    a, ta = oracle.arclength_params(spec, 300)
+    b, tb = oracle.arclength_params(spec, 300, lam=0.0)
+    assert np.array_equal(a, b) and ta == tb
+
+
+@pytest.mark.parametrize("r,lam", [(1.0, 0.7), (0.3, 2.0)])
+def test_adaptive_on_a_circle_is_arc_length(r, lam):
+    # constant curvature: the density is a constant multiple of |C'|
+    ctrl, w, U = nurbs_circle(r)
+    spec = synth.CurveSpec(ctrl, 2, False, U, w)
+    ua, _ = oracle.arclength_params(spec, 97)
+    ub, total = oracle.arclength_params(spec, 97, lam=lam)
+    assert abs(total - 2 * np.pi * (r + lam)) <= 64 * EPS * (r + lam)
+    assert np.abs(ua - ub).max() <= 1e-13
+
+
+@pytest.mark.parametrize("lam", [0.25, 1.5])
+def test_adaptive_on_a_parabola(lam):
+    # y = x^2 on [0, 1] as a quadratic Bezier curve with x(u) = u: arc length
+    # s(x) = x sqrt(1 + 4x^2)/2 + asinh(2x)/4, turning angle atan(2x)
+    P = np.array([[0, 0, 0], [0.5, 0, 0], [1, 1, 0.0]])
+    spec = synth.CurveSpec(P, 2)
+    ns = 65
+    u, total = oracle.arclength_params(spec, ns, lam=lam)
+    m = lambda x: x * np.sqrt(1 + 4 * x * x) / 2 + np.arcsinh(2 * x) / 4 + lam * np.arctan(2 * x)
+    assert abs(total - m(1.0)) <= 1e-13 * m(1.0)
+    x, = oracle.curve_at(spec, u, nd=0)
+    assert np.abs(x[:, 0] - u).max() <= 4 * EPS
+    assert np.abs(m(x[:, 0]) - total * np.arange(ns) / (ns - 1)).max() <= 1e-13 * total
+    # denser where the curve turns (near x = 0, where kappa = 2)
+    a, _ = oracle.arclength_params(spec, ns)
+    assert u[1] < a[1]

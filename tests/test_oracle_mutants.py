@@ -26,6 +26,7 @@ harness on the unmodified source must pass.  Mistakes planted:
  18  arc-length targets i/n_s instead of i/(n_s - 1)
  19  first triangle of each quad wound clockwise
  20  normal term of the loss: the cross product not normalised
+ 21  adaptive sampling density: lam |C' x C''| / |C'|^3 (kappa without |C'|)
 """
 
 from __future__ import annotations
@@ -43,7 +44,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_bspline.py", "tests/test_oracle_frame.py", "tests/test_oracle_grad.py",
              "tests/test_oracle_rational.py", "tests/test_oracle_frenet_laws.py",
              "tests/test_oracle_arclength_mesh.py"]
-MUTANTS = list(range(1, 21))
+MUTANTS = list(range(1, 22))
 
 
 def _run_pins(lib_path: str) -> subprocess.CompletedProcess:
