@@ -79,7 +79,7 @@ def _dev_weights(curve, dev):
 
 
 def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, frame_mode="rmf", law=None,
-                u_sampling="parameter"):
+                u_sampling="parameter", u_lambda=0.0):
     """Wall time of `steps` sweep_eval calls, the per-call (frame, surface)
     stage times from the library's HIP events, and optionally the outputs."""
     import torch
@@ -93,7 +93,8 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     glaw = None if law is None else api.Law(torch.as_tensor(law.ctrl).to(dev), law.degree, law.knots)
     ws = torch.empty(api.eval_workspace_size(P.shape[0], spec.path.degree, Q.shape[0], spec.profile.degree,
                                              spec.n_u, spec.n_v, out_dtype=out_dtype, frame_dtype=frame_dtype,
-                                             frame_mode=frame_mode, law=glaw, u_sampling=u_sampling),
+                                             frame_mode=frame_mode, law=glaw, u_sampling=u_sampling,
+                                             u_lambda=u_lambda),
                      dtype=torch.uint8, device=dev)
 
     Pw, Qw = _dev_weights(spec.path, dev), _dev_weights(spec.profile, dev)
@@ -101,7 +102,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     def step():
         api.sweep_eval(P, spec.path.degree, Q, spec.profile.degree, spec.n_u, spec.n_v, out_dtype=out_dtype,
                        frame_dtype=frame_dtype, path_weights=Pw, prof_weights=Qw, frame_mode=frame_mode, law=glaw,
-                       u_sampling=u_sampling, out=(pos, nrm), workspace=ws)
+                       u_sampling=u_sampling, u_lambda=u_lambda, out=(pos, nrm), workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -123,7 +124,7 @@ def time_single(spec, steps, warmup, out_dtype, frame_dtype=None, keep=False, fr
     return t1 - t0, surf, frame, out
 
 
-def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None, arclength=False):
+def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None, arclength=False, lam=0.0):
     """Parity figures of a GPU result on sampled rows against the oracle."""
     import numpy as np
     import torch
@@ -137,7 +138,7 @@ def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None, arcleng
         rp, rn, rk, _ = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
     else:
         rp, rn, rk = oracle.sweep_rows_ex(spec.path, spec.profile, spec.n_u, spec.n_v, rows, mode=frame_mode,
-                                          law=law, arclength=arclength)
+                                          law=law, arclength=arclength, lam=lam)
     diag = float(np.linalg.norm(x.max(0) - x.min(0)))
     r = oracle.compare(rp, rn, rk, gp, gn, diag, 1e6)
     r["rows"] = len(rows)
@@ -225,9 +226,17 @@ def arclength_variant(steps: int):
     err = sampled_error(spec, res[0], res[1], rows, 1e-5, arclength=True)
     del res
     torch.cuda.empty_cache()
+    # curvature-adaptive: equal steps of arc length + 0.5 x turning angle
+    ela, surfa, framea, resa = time_single(spec, steps, 1, torch.float32, keep=True, u_sampling="adaptive",
+                                           u_lambda=0.5)
+    erra = sampled_error(spec, resa[0], resa[1], rows, 1e-5, arclength=True, lam=0.5)
+    del resa
+    torch.cuda.empty_cache()
     return {"workload": "the large sweep, path samples at equal arc length",
             "vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
-            "frame_ms": sum(frame) / len(frame), "surface_ms": sum(surf) / len(surf), "error_vs_oracle": err}
+            "frame_ms": sum(frame) / len(frame), "surface_ms": sum(surf) / len(surf), "error_vs_oracle": err,
+            "adaptive_lambda_0.5": {"vertices_per_s": N * steps / ela, "ms_per_step": 1e3 * ela / steps,
+                                    "frame_ms": sum(framea) / len(framea), "error_vs_oracle": erra}}
 
 
 def triangles_variant(steps: int):

@@ -76,7 +76,7 @@
 extern "C" {
 #endif
 
-#define SWEEP_VERSION 104  /* major*100 + minor */
+#define SWEEP_VERSION 105  /* major*100 + minor */
 #define SWEEP_MAX_DEGREE 7
 
 typedef enum {
@@ -124,11 +124,14 @@ typedef enum { SWEEP_FRAME_RMF = 0, SWEEP_FRAME_FRENET = 1 } sweep_frame_mode;
  * Every non-empty knot span is cut into 32 equal pieces integrated by
  * 8-point Gauss-Legendre (a cumulative table); inside the piece holding a
  * target, Newton's method on s(u) - target kept in a bisection bracket, to
- * |du| <= 4 eps max(1, |u|).  Supported by sweep_eval (not with a law) and
- * sweep_frames; the batched and adjoint entry points return
- * SWEEP_ERR_UNSUPPORTED.
+ * |du| <= 4 eps max(1, |u|).  SWEEP_U_ADAPTIVE: the same with the density
+ * |C'| (1 + u_lambda kappa) in place of |C'| (kappa the path's curvature):
+ * equal steps of arc length plus u_lambda times the tangent's turning angle,
+ * so samples crowd where the path bends (u_lambda = 0 is arc length).
+ * Supported by sweep_eval (not with a law) and sweep_frames; the batched and
+ * adjoint entry points return SWEEP_ERR_UNSUPPORTED.
  */
-typedef enum { SWEEP_U_PARAMETER = 0, SWEEP_U_ARCLENGTH = 1 } sweep_u_sampling;
+typedef enum { SWEEP_U_PARAMETER = 0, SWEEP_U_ARCLENGTH = 1, SWEEP_U_ADAPTIVE = 2 } sweep_u_sampling;
 
 /* A B-spline curve. */
 typedef struct sweep_curve_s {
@@ -159,8 +162,10 @@ typedef struct {
                                  surface-kernel configuration (sweep_tile_config_count) */
     int32_t frame_mode;       /* SWEEP_FRAME_RMF (default) or SWEEP_FRAME_FRENET, see above */
     const struct sweep_curve_s *law; /* NULL (default) or a sweep law, see above */
-    int32_t u_sampling;       /* SWEEP_U_PARAMETER (default) or SWEEP_U_ARCLENGTH, see above */
+    int32_t u_sampling;       /* SWEEP_U_PARAMETER (default), SWEEP_U_ARCLENGTH or
+                                 SWEEP_U_ADAPTIVE, see above */
     int32_t reserved;
+    double u_lambda;          /* SWEEP_U_ADAPTIVE: length weight of the turning angle (>= 0, finite) */
 } sweep_options;
 
 /* A batch of independent sweeps.  Per-sweep arrays are HOST memory with

@@ -21,7 +21,7 @@ STATUS = {
 }
 SWEEP_F32, SWEEP_F64 = 0, 1
 SWEEP_FRAME_RMF, SWEEP_FRAME_FRENET = 0, 1
-SWEEP_U_PARAMETER, SWEEP_U_ARCLENGTH = 0, 1
+SWEEP_U_PARAMETER, SWEEP_U_ARCLENGTH, SWEEP_U_ADAPTIVE = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -36,7 +36,8 @@ class SweepOptions(C.Structure):
     _fields_ = [("out_precision", C.c_int32), ("frame_precision", C.c_int32),
                 ("reorthonormalize", C.c_int32), ("has_initial_normal", C.c_int32),
                 ("initial_normal", C.c_double * 3), ("tile_config", C.c_int32), ("frame_mode", C.c_int32),
-                ("law", C.c_void_p), ("u_sampling", C.c_int32), ("reserved", C.c_int32)]
+                ("law", C.c_void_p), ("u_sampling", C.c_int32), ("reserved", C.c_int32),
+                ("u_lambda", C.c_double)]
 
 
 class SweepParamGrads(C.Structure):

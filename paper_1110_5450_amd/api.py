@@ -70,12 +70,13 @@ class Law:
         self.c = L.SweepCurve(self.ctrl.shape[0], self.degree, 0, 0, self.ctrl.data_ptr(), kp, _wptr(self.weights))
 
 
-_U_SAMPLING = {"parameter": L.SWEEP_U_PARAMETER, "arclength": L.SWEEP_U_ARCLENGTH}
+_U_SAMPLING = {"parameter": L.SWEEP_U_PARAMETER, "arclength": L.SWEEP_U_ARCLENGTH,
+               "adaptive": L.SWEEP_U_ADAPTIVE}
 
 
 def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                  initial_normal=None, tile_config: int = -1, frame_mode: str = "rmf",
-                 law: Optional[Law] = None, u_sampling: str = "parameter") -> L.SweepOptions:
+                 law: Optional[Law] = None, u_sampling: str = "parameter", u_lambda: float = 0.0) -> L.SweepOptions:
     o = L.default_options()
     o.out_precision = _DT[out_dtype]
     o.frame_precision = _DT[frame_dtype]
@@ -91,6 +92,7 @@ def make_options(out_dtype=torch.float32, frame_dtype=torch.float64, reorthonorm
     if u_sampling not in _U_SAMPLING:
         raise ValueError(f"u_sampling must be one of {sorted(_U_SAMPLING)}")
     o.u_sampling = _U_SAMPLING[u_sampling]
+    o.u_lambda = float(u_lambda)
     if law is not None:
         o.law = C.cast(C.pointer(law.c), C.c_void_p)
         o._law_ref = law          # keeps the curve struct and its buffers alive
@@ -120,12 +122,13 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
                out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                initial_normal=None, tile_config: int = -1, normals: bool = True,
                path_weights=None, prof_weights=None, frame_mode: str = "rmf", law: Optional[Law] = None,
-               u_sampling: str = "parameter",
+               u_sampling: str = "parameter", u_lambda: float = 0.0,
                out: Optional[Tuple[torch.Tensor, Optional[torch.Tensor]]] = None,
                workspace: Optional[torch.Tensor] = None, stream=None):
     """Positions (3, n_u, n_v) and normals (or None) of one sweep; with
     weights (device float64, one per control point) a curve is rational;
-    u_sampling="arclength" places the path samples at equal arc length."""
+    u_sampling="arclength" places the path samples at equal arc length,
+    "adaptive" at equal steps of arc length + u_lambda x turning angle."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
     qc = _check_ctrl(prof_ctrl, "prof_ctrl")
     pw = _weights(path_weights, pc.shape[0], "path_weights")
@@ -135,7 +138,7 @@ def sweep_eval(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.Tenso
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law,
-                       u_sampling)
+                       u_sampling, u_lambda)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         # invalid metadata: let the call report the reason
@@ -163,7 +166,7 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
                    out_dtype=torch.float32, frame_dtype=torch.float64, reorthonormalize: bool = True,
                    initial_normal=None, normals: bool = True, path_weights=None, prof_weights=None,
                    frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter",
-                   stream=None):
+                   u_lambda: float = 0.0, stream=None):
     """Times every surface configuration on this sweep and records the
     fastest for its shape class; returns (best_config, best_ms, pos, nrm)."""
     pc = _check_ctrl(path_ctrl, "path_ctrl")
@@ -175,7 +178,7 @@ def sweep_autotune(path_ctrl: torch.Tensor, path_degree: int, prof_ctrl: torch.T
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     prof = L.SweepCurve(qc.shape[0], int(prof_degree), int(bool(prof_closed)), 0, qc.data_ptr(), qkp, _wptr(qw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode, law=law,
-                       u_sampling=u_sampling)
+                       u_sampling=u_sampling, u_lambda=u_lambda)
     ws_bytes = L.sweep_eval_workspace_size(path, prof, int(n_u), int(n_v), opt)
     if ws_bytes == 0:
         L.check(L.sweep_eval(path, prof, int(n_u), int(n_v), opt, 0, 0, 0, 0, 0))
@@ -199,7 +202,7 @@ def surface_config_for(n_u: int, n_v: int, out_dtype=torch.float32) -> int:
 def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_knots=None,
                  out_dtype=torch.float64, frame_dtype=torch.float64, reorthonormalize: bool = True,
                  initial_normal=None, path_weights=None, frame_mode: str = "rmf",
-                 u_sampling: str = "parameter",
+                 u_sampling: str = "parameter", u_lambda: float = 0.0,
                  workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Row records (n_u, 16): x, r, s, t, |C'|, a, b, 0 of the moving frame
     (rotation-minimizing; other frame modes are sweep_eval only)."""
@@ -208,7 +211,7 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
     pk, pkp = _knots_ptr(path_knots)
     path = L.SweepCurve(pc.shape[0], int(path_degree), 0, 0, pc.data_ptr(), pkp, _wptr(pw))
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, frame_mode=frame_mode,
-                       u_sampling=u_sampling)
+                       u_sampling=u_sampling, u_lambda=u_lambda)
     ws_bytes = L.sweep_frames_workspace_size(path, int(n_u), opt)
     if ws_bytes == 0:
         L.check(L.sweep_frames(path, int(n_u), opt, 0, 0, 0, 0))
@@ -222,12 +225,13 @@ def sweep_frames(path_ctrl: torch.Tensor, path_degree: int, n_u: int, *, path_kn
 
 def eval_workspace_size(n_path: int, path_degree: int, n_prof: int, prof_degree: int, n_u: int, n_v: int, *,
                         prof_closed: bool = True, out_dtype=torch.float32, frame_dtype=torch.float64,
-                        frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter") -> int:
+                        frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter",
+                        u_lambda: float = 0.0) -> int:
     path = L.SweepCurve(n_path, path_degree, 0, 0, 1, None, None)
     prof = L.SweepCurve(n_prof, prof_degree, int(prof_closed), 0, 1, None, None)
     return L.sweep_eval_workspace_size(path, prof, n_u, n_v,
                                        make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law,
-                                                    u_sampling=u_sampling))
+                                                    u_sampling=u_sampling, u_lambda=u_lambda))
 
 
 def triangle_count(n_u: int, n_v: int, closed_v: bool = True) -> int:

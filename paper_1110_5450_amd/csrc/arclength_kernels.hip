@@ -29,12 +29,18 @@ __device__ const double kGlW[8] = {0.10122853629037669, 0.22238103445337434, 0.3
                                    0.36268378337836177, 0.36268378337836177, 0.31370664587788705,
                                    0.22238103445337434, 0.10122853629037669};
 
-template <int P>
-__device__ double speed_at(const DCurve& c, int s, double u)
+// Sampling density at u on span s: |C'| (arc length), and with ADAPT
+// |C'| + lam |C' x C''| / |C'|^2 = |C'| (1 + lam kappa), whose integral is
+// arc length plus lam times the turning angle (curvature-adaptive sampling).
+template <int P, bool ADAPT>
+__device__ double speed_at(const DCurve& c, int s, double u, double lam)
 {
-    V3<double> o[2];
-    curve_derivs<P, 1>(c, u, s, o);
-    return sqrt(dot(o[1], o[1]));
+    V3<double> o[3];
+    curve_derivs<P, ADAPT ? 2 : 1>(c, u, s, o);
+    const double sp = sqrt(dot(o[1], o[1]));
+    if (!ADAPT) return sp;
+    const V3<double> cr = cross(o[1], o[2]);
+    return sp + (sp > 0.0 ? lam * sqrt(dot(cr, cr)) / (sp * sp) : 0.0);
 }
 
 // Piece q = (k - p) * kArcSub + m of span k: its bounds.
@@ -49,8 +55,8 @@ __device__ __forceinline__ void piece_bounds(const DCurve& c, int q, int& k, dou
 
 // Eight lanes per piece, one Gauss-Legendre node each; the weighted speeds
 // are summed by a butterfly over the eight lanes.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_arc_pieces(DCurve c, int npc, double* __restrict__ len)
+template <int P, bool ADAPT>
+__global__ __launch_bounds__(kBlock) void k_arc_pieces(DCurve c, int npc, double lam, double* __restrict__ len)
 {
     const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 3;
     const int l = threadIdx.x & 7;
@@ -64,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_arc_pieces(DCurve c, int npc, double
         return;
     }
     const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
-    double part = kGlW[l] * speed_at<P>(c, k, mid + half * kGlX[l]);
+    double part = kGlW[l] * speed_at<P, ADAPT>(c, k, mid + half * kGlX[l], lam);
     part += __shfl_xor(part, 1, 8);
     part += __shfl_xor(part, 2, 8);
     part += __shfl_xor(part, 4, 8);
@@ -179,8 +185,8 @@ static int arc_coarse_stride(int npc)
     return cs;
 }
 
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc, int cstride,
+template <int P, bool ADAPT>
+__global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc, int cstride, double lam,
                                                        const double* __restrict__ cum, double* __restrict__ su,
                                                        int* __restrict__ ss)
 {
@@ -229,8 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc
         for (int it = 0; it < 40; ++it) {
             const double mid = 0.5 * (plo + u), half = 0.5 * (u - plo);
             double e = 0.0;
-            if (l < 8) e = wl * speed_at<P>(c, k, mid + half * xl);
-            else if (l == 8) e = speed_at<P>(c, k, u);
+            if (l < 8) e = wl * speed_at<P, ADAPT>(c, k, mid + half * xl, lam);
+            else if (l == 8) e = speed_at<P, ADAPT>(c, k, u, lam);
             const double sp = __shfl(e, 8, kArcLanes);
             double part = l < 8 ? e : 0.0;
             part += __shfl_xor(part, 1, kArcLanes);
@@ -255,16 +261,18 @@ __global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc
 
 int arc_pieces(const DCurve& c) { return (c.n - c.p) * kArcSub; }
 
-hipError_t launch_arclength(const DCurve& c, int ns, double* len, double* cum, double* su, int* ss, hipStream_t st)
+template <bool ADAPT>
+static hipError_t launch_arclength_t(const DCurve& c, int ns, double lam, double* len, double* cum, double* su,
+                                     int* ss, hipStream_t st)
 {
     const int npc = arc_pieces(c), cs = arc_coarse_stride(npc);
     const dim3 gp((unsigned)(((long long)npc * 8 + kBlock - 1) / kBlock));
     const dim3 gs((unsigned)(((long long)ns * kArcLanes + kBlock - 1) / kBlock));
-#define SWEEP_CASE(P)                                                                                        \
-    case P:                                                                                                  \
-        hipLaunchKernelGGL(k_arc_pieces<P>, gp, dim3(kBlock), 0, st, c, npc, len);                          \
-        hipLaunchKernelGGL(k_arc_cumsum, dim3(1), dim3(kScanThreads), 0, st, len, npc, cum);                \
-        hipLaunchKernelGGL(k_arc_params<P>, gs, dim3(kBlock), 0, st, c, ns, npc, cs, cum, su, ss);          \
+#define SWEEP_CASE(P)                                                                                           \
+    case P:                                                                                                     \
+        hipLaunchKernelGGL((k_arc_pieces<P, ADAPT>), gp, dim3(kBlock), 0, st, c, npc, lam, len);                \
+        hipLaunchKernelGGL(k_arc_cumsum, dim3(1), dim3(kScanThreads), 0, st, len, npc, cum);                   \
+        hipLaunchKernelGGL((k_arc_params<P, ADAPT>), gs, dim3(kBlock), 0, st, c, ns, npc, cs, lam, cum, su, ss); \
         break;
     switch (c.p) {
         SWEEP_CASE(1) SWEEP_CASE(2) SWEEP_CASE(3) SWEEP_CASE(4) SWEEP_CASE(5) SWEEP_CASE(6) SWEEP_CASE(7)
@@ -272,6 +280,13 @@ hipError_t launch_arclength(const DCurve& c, int ns, double* len, double* cum, d
     }
 #undef SWEEP_CASE
     return hipGetLastError();
+}
+
+hipError_t launch_arclength(const DCurve& c, int ns, double lam, double* len, double* cum, double* su, int* ss,
+                            hipStream_t st)
+{
+    return lam != 0.0 ? launch_arclength_t<true>(c, ns, lam, len, cum, su, ss, st)
+                      : launch_arclength_t<false>(c, ns, lam, len, cum, su, ss, st);
 }
 
 // ------------------------------------------------------------ triangles

@@ -22,11 +22,13 @@ int frame_chunk_size();
 template <class F, class T>
 hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
                        int* chunk_fix, double* fallback_t, F* agg, T* ptab, hipStream_t st);
-// Arc-length sampling of an open curve: piece lengths (len, arc_pieces(c)
-// values), their cumulative table (cum, one more), sample parameters su and
-// spans ss (ns each).
+// Arc-length sampling of an open curve (lam = 0), or curvature-adaptive
+// sampling with density |C'| (1 + lam kappa): piece integrals (len,
+// arc_pieces(c) values), their cumulative table (cum, one more), sample
+// parameters su and spans ss (ns each).
 int arc_pieces(const DCurve& c);
-hipError_t launch_arclength(const DCurve& c, int ns, double* len, double* cum, double* su, int* ss, hipStream_t st);
+hipError_t launch_arclength(const DCurve& c, int ns, double lam, double* len, double* cum, double* su, int* ss,
+                            hipStream_t st);
 // Triangle list of the n_u x n_v grid (6 ints per quad).
 hipError_t launch_triangles(int n_u, int n_v, int closed_v, int* tri, hipStream_t st);
 

@@ -120,10 +120,13 @@ sweep_status check_options(const sweep_options* o)
         return fail(SWEEP_ERR_BAD_OPTION, "tile_config %d outside -1..%d", o->tile_config, tile_config_count() - 1);
     if (o->frame_mode != SWEEP_FRAME_RMF && o->frame_mode != SWEEP_FRAME_FRENET)
         return fail(SWEEP_ERR_BAD_OPTION, "frame_mode %d is not RMF (0) or FRENET (1)", o->frame_mode);
-    if (o->u_sampling != SWEEP_U_PARAMETER && o->u_sampling != SWEEP_U_ARCLENGTH)
-        return fail(SWEEP_ERR_BAD_OPTION, "u_sampling %d is not PARAMETER (0) or ARCLENGTH (1)", o->u_sampling);
-    if (o->u_sampling == SWEEP_U_ARCLENGTH && o->law)
-        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length sampling with a sweep law");
+    if (o->u_sampling != SWEEP_U_PARAMETER && o->u_sampling != SWEEP_U_ARCLENGTH && o->u_sampling != SWEEP_U_ADAPTIVE)
+        return fail(SWEEP_ERR_BAD_OPTION, "u_sampling %d is not PARAMETER (0), ARCLENGTH (1) or ADAPTIVE (2)",
+                    o->u_sampling);
+    if (o->u_sampling == SWEEP_U_ADAPTIVE && !(std::isfinite(o->u_lambda) && o->u_lambda >= 0.0))
+        return fail(SWEEP_ERR_BAD_OPTION, "u_lambda %g is not a finite value >= 0", o->u_lambda);
+    if (o->u_sampling != SWEEP_U_PARAMETER && o->law)
+        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length or adaptive sampling with a sweep law");
     if (o->law) {
         if (o->law->closed) return fail(SWEEP_ERR_UNSUPPORTED, "law: the law curve must be open");
         sweep_status st = check_curve(o->law, "law", true);
@@ -135,7 +138,8 @@ sweep_status check_options(const sweep_options* o)
 // Options that need the extended row records (Frenet frame or a law).
 bool options_ext(const sweep_options* o) { return o->frame_mode != SWEEP_FRAME_RMF || o->law != nullptr; }
 
-// Options supported by sweep_eval only.
+// Options supported by sweep_eval (and, without frame modes and laws,
+// sweep_frames) only.
 bool options_single_only(const sweep_options* o) { return options_ext(o) || o->u_sampling != SWEEP_U_PARAMETER; }
 
 // Parameter domain [U_p, U_n] of an open curve (given knots or [0, 1]).
@@ -324,7 +328,7 @@ static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof,
     const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
     const int nlk = (o->law && o->law->knots) ? nknots(o->law->n_ctrl, o->law->degree, 0) : 0;
     return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz,
-                         options_ext(o) ? kRowExt : 16, nlk, o->u_sampling == SWEEP_U_ARCLENGTH);
+                         options_ext(o) ? kRowExt : 16, nlk, o->u_sampling != SWEEP_U_PARAMETER);
 }
 
 // Copies given knots to the device (a blocking copy from pageable memory);
@@ -342,10 +346,11 @@ sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, h
 static sweep_status setup_arclength(DCurve& dp, int n_u, const sweep_options* o, char* ws, const SingleLayout& L,
                                     hipStream_t st)
 {
-    if (o->u_sampling != SWEEP_U_ARCLENGTH) return SWEEP_OK;
+    if (o->u_sampling == SWEEP_U_PARAMETER) return SWEEP_OK;
     double* su = (double*)(ws + L.arc_u);
     int* ss = (int*)(ws + L.arc_span);
-    hipError_t e = launch_arclength(dp, n_u, (double*)(ws + L.arc_len), (double*)(ws + L.arc_cum), su, ss, st);
+    const double lam = o->u_sampling == SWEEP_U_ADAPTIVE ? o->u_lambda : 0.0;
+    hipError_t e = launch_arclength(dp, n_u, lam, (double*)(ws + L.arc_len), (double*)(ws + L.arc_cum), su, ss, st);
     if (e != hipSuccess) return hip_fail(e, "arc-length sampling");
     dp.su = su;
     dp.ss = ss;
@@ -524,7 +529,7 @@ size_t sweep_frames_workspace_size(const sweep_curve* path, int32_t n_u, const s
     if (n_u < 2 || check_options(opt) != SWEEP_OK) return 0;
     const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;
     return single_layout(path->n_ctrl, path->degree, 4, 3, 1, n_u, 0, fsz, 0, 16, 0,
-                         opt->u_sampling == SWEEP_U_ARCLENGTH).total;
+                         opt->u_sampling != SWEEP_U_PARAMETER).total;
 }
 
 sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_options* opt, void* frames,
@@ -536,7 +541,7 @@ sweep_status sweep_frames(const sweep_curve* path, int32_t n_u, const sweep_opti
     if (s != SWEEP_OK) return s;
     if ((s = check_curve(path, "path", true)) != SWEEP_OK) return s;
     if (options_ext(opt)) return fail(SWEEP_ERR_UNSUPPORTED, "sweep_frames: frame modes and laws are sweep_eval only");
-    const bool arc = opt->u_sampling == SWEEP_U_ARCLENGTH;
+    const bool arc = opt->u_sampling != SWEEP_U_PARAMETER;
     if (n_u < 2 || n_u >= (1 << 30)) return fail(SWEEP_ERR_BAD_GRID, "n_u %d outside 2..2^30-1", n_u);
     if (!frames) return fail(SWEEP_ERR_NULL_ARG, "frames is NULL");
     const size_t fsz = opt->frame_precision == SWEEP_F64 ? 8 : 4;

@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert L.sweep_version() == 104
+    assert L.sweep_version() == 105
     o = L.default_options()
     assert (o.out_precision, o.frame_precision, o.reorthonormalize, o.has_initial_normal, o.tile_config) == (0, 1, 1, 0, -1)
     assert L.sweep_tile_config_count() >= 8
@@ -172,8 +172,19 @@ def test_u_sampling_options():
     a, b = _curves()
     o = L.default_options()
     assert o.u_sampling == 0
-    o.u_sampling = 2
+    o.u_sampling = 3
     _expect(_call(a, b, opt=o), "SWEEP_ERR_BAD_OPTION", "u_sampling")
+    # adaptive sampling: a finite weight >= 0
+    for lam in (-1.0, math.inf, math.nan):
+        o = L.default_options()
+        o.u_sampling = 2
+        o.u_lambda = lam
+        _expect(_call(a, b, opt=o), "SWEEP_ERR_BAD_OPTION", "u_lambda")
+    o = L.default_options()
+    o.u_sampling = 2
+    o.u_lambda = 0.5
+    assert L.sweep_eval_workspace_size(a, b, 256, 64, o) > L.sweep_eval_workspace_size(a, b, 256, 64,
+                                                                                       L.default_options())
     # arc-length sampling needs room for the length table and sample parameters
     o = L.default_options()
     o.u_sampling = 1
@@ -184,7 +195,7 @@ def test_u_sampling_options():
     # not together with a law
     law = L.SweepCurve(4, 1, 0, 0, FAKE, None)
     o.law = C.cast(C.pointer(law), C.c_void_p)
-    _expect(_call(a, b, opt=o), "SWEEP_ERR_UNSUPPORTED", "arc-length")
+    _expect(_call(a, b, opt=o), "SWEEP_ERR_UNSUPPORTED", "arc-length or adaptive")
 
 
 def test_triangles_validation():

@@ -23,11 +23,12 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
 
 
-def _check(spec, out_dtype, tol=None, n0=None):
+def _check(spec, out_dtype, tol=None, n0=None, lam=0.0):
     say(f"[case] arclength n_u={spec.n_u} n_v={spec.n_v} p={spec.path.degree} knots={spec.path.knots is not None} "
-        f"rational={getattr(spec.path, 'weights', None) is not None} out={out_dtype}")
-    ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, spec.n_v, n0=n0, arclength=True)
-    pos, nrm = gpu_sweep(spec, out_dtype, u_sampling="arclength", initial_normal=n0)
+        f"rational={getattr(spec.path, 'weights', None) is not None} out={out_dtype} lam={lam}")
+    ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, spec.n_v, n0=n0, arclength=True, lam=lam)
+    kw = dict(u_sampling="adaptive", u_lambda=lam) if lam else dict(u_sampling="arclength")
+    pos, nrm = gpu_sweep(spec, out_dtype, initial_normal=n0, **kw)
     torch.cuda.synchronize()
     ok, r = parity(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(),
                    TOL[out_dtype] if tol is None else tol)
@@ -41,6 +42,34 @@ def _check(spec, out_dtype, tol=None, n0=None):
 def test_arclength_sweep_matches_oracle(out_dtype, p):
     spec = synth.single(120 + p, 13, 9, 1000, 67, p_path=p)
     _check(spec, out_dtype)
+
+
+@pytest.mark.parametrize("out_dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("p,lam", [(2, 0.5), (3, 0.1), (3, 2.0), (5, 0.7)])
+def test_adaptive_sweep_matches_oracle(out_dtype, p, lam):
+    spec = synth.single(150 + p, 13, 9, 1000, 67, p_path=p)
+    _check(spec, out_dtype, lam=lam)
+
+
+def test_adaptive_rational_path():
+    spec = synth.single(160, 10, 8, 777, 40)
+    spec.path.weights = np.random.default_rng(16).uniform(0.5, 2.0, 10)
+    _check(spec, torch.float64, lam=0.4)
+
+
+@pytest.mark.parametrize("lam", [0.25, 1.5])
+def test_adaptive_samples_on_a_parabola(lam):
+    # y = x^2, x in [0, 1], as a quadratic Bezier curve (x(u) = u): equal
+    # steps of arc length s(x) = x sqrt(1 + 4x^2)/2 + asinh(2x)/4 plus
+    # lam x the turning angle atan(2x)
+    P = np.array([[0, 0, 0], [0.5, 0, 0], [1, 1, 0.0]])
+    n_u = 2049
+    rows = api.sweep_frames(dev_ctrl(P), 2, n_u, u_sampling="adaptive", u_lambda=lam).cpu().numpy()
+    x = rows[:, 0]
+    m = lambda x: x * np.sqrt(1 + 4 * x * x) / 2 + np.arcsinh(2 * x) / 4 + lam * np.arctan(2 * x)
+    err = np.abs(m(x) - m(1.0) * np.arange(n_u) / (n_u - 1)).max()
+    say(f"   parabola lam={lam}: max monitor error {err:.3e}")
+    assert err <= 1e-13 * m(1.0)
 
 
 @pytest.mark.parametrize("rational", [False, True])
