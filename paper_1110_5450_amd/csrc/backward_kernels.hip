@@ -44,8 +44,8 @@ namespace sweep {
 // sums over 32 of the 64 columns; the two halves are added in a fixed order
 // (h = 0 first).  Small tiles keep five blocks per CU resident.
 // With NRM the lane also loads g for its G rows and forms the normal terms:
-// column sums in registers, row sums by DPP scans over the wave.  grad may
-// be null (no position term).
+// column sums in registers, row sums through the LDS tile.  grad may be null
+// (no position term).
 template <class T, bool NRM>
 __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
                                                      const int4* __restrict__ units, int n_units,
@@ -111,66 +111,6 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
             }
         }
     }
-    if (NRM) {
-        V3<double> S = mk(0.0, 0.0, 0.0), q = S;
-        if (vj) {
-            const double* pq = ptab + 8 * (d.ptab_off + j);
-            S = mk(pq[0], pq[1], pq[2]);
-            q = mk(pq[3], pq[4], pq[5]);
-        }
-        const size_t P = (size_t)d.plane;
-        const T* g0 = gnrm + d.out_off;
-        V3<double> hD = mk(0.0, 0.0, 0.0);
-        for (int r = 0; r < nr; ++r) {   // wave-uniform bound: every lane reaches the butterflies
-            const double* R = R0 + 16 * r;
-            double c[12];
-#pragma unroll
-            for (int e = 0; e < 12; ++e) c[e] = 0.0;
-            if (vj) {
-                const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
-                const V3<double> gv = mk((double)__builtin_nontemporal_load(g0 + v),
-                                         (double)__builtin_nontemporal_load(g0 + P + v),
-                                         (double)__builtin_nontemporal_load(g0 + 2 * P + v));
-                const V3<double> rr = mk(R[3], R[4], R[5]), ss = mk(R[6], R[7], R[8]), tt = mk(R[9], R[10], R[11]);
-                const double L = R[12], a = R[13], b = R[14];
-                const V3<double> u = mk(S.z * a, S.z * b, L - S.x * a - S.y * b);
-                const V3<double> m = cross(q, u);
-                const double mm = dot(m, m);
-                if (mm > 0.0 && mm < INFINITY) {
-                    const double inv = 1.0 / sqrt(mm);
-                    const V3<double> n = inv * m;
-                    const V3<double> gh = mk(dot(rr, gv), dot(ss, gv), dot(tt, gv));
-                    const V3<double> mb = inv * (gh - dot(gh, n) * n);
-                    const V3<double> qb = cross(u, mb), ub = cross(mb, q);
-                    c[0] = n.x * gv.x; c[1] = n.x * gv.y; c[2] = n.x * gv.z;
-                    c[3] = n.y * gv.x; c[4] = n.y * gv.y; c[5] = n.y * gv.z;
-                    c[6] = n.z * gv.x; c[7] = n.z * gv.y; c[8] = n.z * gv.z;
-                    c[9] = ub.x * S.z - ub.z * S.x;
-                    c[10] = ub.y * S.z - ub.z * S.y;
-                    c[11] = ub.z;
-                    h0 -= ub.z * a;
-                    h1 -= ub.z * b;
-                    h2 += ub.x * a + ub.y * b;
-                    hD = hD + qb;
-                }
-            }
-            double mine = 0.0;
-#pragma unroll
-            for (int e = 0; e < 12; ++e) {
-                const double tot = wave_total(c[e]);
-                mine = lane == e ? tot : mine;
-            }
-            if (lane < 12) rowpart[RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r) + kRowPart + lane] = mine;
-        }
-        if (vj) {
-            double* qd = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
-            qd[3] = hD.x; qd[4] = hD.y; qd[5] = hD.z;
-        }
-    }
-    if (vj) {
-        double* q = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
-        q[0] = h0; q[1] = h1; q[2] = h2;
-    }
     __syncthreads();
     // lane = ((c * G + r) << 1) | h
     const int h = lane & 1, cr = lane >> 1, r = cr % G, c = cr / G;
@@ -193,6 +133,78 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
     if (act && h == 0) {
         double* q = rowpart + RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r);
         q[c] = a0 + b0; q[3 + c] = ax + bx; q[6 + c] = ay + by; q[9 + c] = az + bz;
+    }
+    if (NRM) {
+        // The normal terms.  Row sums go through the wave's (now free) LDS
+        // tile: lanes write their 12 values of a row, then lane (e, k),
+        // e < 12, k < 4, sums value e over columns 16k .. 16k+15 and the four
+        // parts are added in a fixed order.  G rows per unit on every wave
+        // (rows past the sweep's end contribute 0), so the barriers match.
+        V3<double> S = mk(0.0, 0.0, 0.0), q = S;
+        if (vj) {
+            const double* pq = ptab + 8 * (d.ptab_off + j);
+            S = mk(pq[0], pq[1], pq[2]);
+            q = mk(pq[3], pq[4], pq[5]);
+        }
+        const size_t P = (size_t)d.plane;
+        const T* g0 = gnrm + d.out_off;
+        double* buf = reinterpret_cast<double*>(&lw[wave][0][0][0]);   // 12 x 65 doubles
+        static_assert(sizeof(lw[0]) >= 12 * 65 * sizeof(double), "LDS tile too small for the normal terms");
+        V3<double> hD = mk(0.0, 0.0, 0.0);
+        const int e = lane >> 2, kq = lane & 3;
+        for (int r = 0; r < G; ++r) {
+            double cv[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) cv[k] = 0.0;
+            if (vj && r < nr) {
+                const double* R = R0 + 16 * r;
+                const size_t v = (size_t)(i0 + r) * (size_t)n_v + (size_t)j;
+                const V3<double> gv = mk((double)__builtin_nontemporal_load(g0 + v),
+                                         (double)__builtin_nontemporal_load(g0 + P + v),
+                                         (double)__builtin_nontemporal_load(g0 + 2 * P + v));
+                const V3<double> rr = mk(R[3], R[4], R[5]), ss = mk(R[6], R[7], R[8]), tt = mk(R[9], R[10], R[11]);
+                const double L = R[12], a = R[13], b = R[14];
+                const V3<double> u = mk(S.z * a, S.z * b, L - S.x * a - S.y * b);
+                const V3<double> m = cross(q, u);
+                const double mm = dot(m, m);
+                if (mm > 0.0 && mm < INFINITY) {
+                    const double inv = 1.0 / sqrt(mm);
+                    const V3<double> n = inv * m;
+                    const V3<double> gh = mk(dot(rr, gv), dot(ss, gv), dot(tt, gv));
+                    const V3<double> mb = inv * (gh - dot(gh, n) * n);
+                    const V3<double> qb = cross(u, mb), ub = cross(mb, q);
+                    cv[0] = n.x * gv.x; cv[1] = n.x * gv.y; cv[2] = n.x * gv.z;
+                    cv[3] = n.y * gv.x; cv[4] = n.y * gv.y; cv[5] = n.y * gv.z;
+                    cv[6] = n.z * gv.x; cv[7] = n.z * gv.y; cv[8] = n.z * gv.z;
+                    cv[9] = ub.x * S.z - ub.z * S.x;
+                    cv[10] = ub.y * S.z - ub.z * S.y;
+                    cv[11] = ub.z;
+                    h0 -= ub.z * a;
+                    h1 -= ub.z * b;
+                    h2 += ub.x * a + ub.y * b;
+                    hD = hD + qb;
+                }
+            }
+            __syncthreads();   // the tile's previous contents are consumed
+#pragma unroll
+            for (int k = 0; k < 12; ++k) buf[65 * k + lane] = cv[k];
+            __syncthreads();
+            double part = 0.0;
+            if (lane < 48)
+                for (int jj = 16 * kq; jj < 16 * kq + 16; ++jj) part += buf[65 * e + jj];
+            part += __shfl_xor(part, 1, 64);
+            part += __shfl_xor(part, 2, 64);
+            if (live && r < nr && lane < 48 && kq == 0)
+                rowpart[RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r) + kRowPart + e] = part;
+        }
+        if (vj) {
+            double* qd = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
+            qd[3] = hD.x; qd[4] = hD.y; qd[5] = hD.z;
+        }
+    }
+    if (vj) {
+        double* q = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
+        q[0] = h0; q[1] = h1; q[2] = h2;
     }
 }
 

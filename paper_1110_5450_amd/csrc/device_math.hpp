@@ -432,24 +432,6 @@ __device__ __forceinline__ M3<F> dpp_m3(const M3<F>& a)
     return r;
 }
 
-// Sum of x over the wave, in a fixed order (an inclusive scan by DPP whose
-// total ends in lane 63), returned to every lane.  All 64 lanes must be
-// active.
-__device__ __forceinline__ double wave_total(double x)
-{
-    const int lane = threadIdx.x & 63;
-    x += dpp_val<0x111>(x);   // lanes without a source receive 0
-    x += dpp_val<0x112>(x);
-    x += dpp_val<0x114>(x);
-    x += dpp_val<0x118>(x);
-    { const double o = dpp_val<0x142>(x); if (lane & 16) x += o; }
-    { const double o = dpp_val<0x143>(x); if (lane >= 32) x += o; }
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // Inclusive ordered product over the wave (lane 0 earliest, later factors on
 // the left): products within rows of 16 lanes (shifts 1, 2, 4, 8), then row
 // totals carried to rows 1 and 3, then lane 31 to the upper half.
