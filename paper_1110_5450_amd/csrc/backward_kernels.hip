@@ -801,24 +801,14 @@ __device__ __forceinline__ void block_pair_total(double a, double b, double (*ld
     tb = tot.y;
 }
 
-// One curve's knot and weight gradients from its per-sample adjoints:
-// records per sample, the domain-end terms of the sample parameters
+// One curve's knot and weight gradients from its per-sample records
+// (kbw_param_rec): the domain-end terms of the sample parameters
 // (u = U_p + (U_n - U_p) i/(ns-1) on an open curve), then one thread per
 // knot / weight gathers the samples whose span reaches it.
-// adj(i, xb, cb, c2b) gives the sample's dL/dC, dL/dC', dL/dC''.
-template <class Adj>
-__device__ void curve_param_grads(const DCurve& c, int ns, const int* spans, double* rec, bool want_k, bool want_w,
-                                  double* gk, double* gw, double (*lds)[3], Adj adj)
+__device__ void curve_param_grads(const DCurve& c, int ns, const int* spans, const double* rec, bool want_k,
+                                  bool want_w, double* gk, double* gw, double (*lds)[3], double* lpart)
 {
     const int p = c.p;
-    for (int i = threadIdx.x; i < ns; i += kBlock) {
-        V3<double> xb, cb, c2b;
-        adj(i, xb, cb, c2b);
-        double* r = rec + kParamRec * (size_t)i;
-        const double u = sample_param(c, i, ns);
-        r[kParamRec - 1] = param_contrib_any(c, u, spans[i], xb, cb, c2b, want_k, want_w, r, r + 2 * p);
-    }
-    __syncthreads();
     double e0 = 0.0, e1 = 0.0;   // dL/dU_p and dL/dU_n through the sample parameters
     if (want_k) {
         for (int b0 = 0; b0 < ns; b0 += kBlock) {
@@ -835,77 +825,138 @@ __device__ void curve_param_grads(const DCurve& c, int ns, const int* spans, dou
             e0 += ta;
             e1 += tb;
         }
-        // knots 0 .. n+p: samples with span in [m-p, m+p-1] reach knot m
-        for (int m = threadIdx.x; m <= c.n + p; m += kBlock) {
+        // knots 0 .. n+p: samples with span in [m-p, m+p-1] reach knot m;
+        // `parts` threads per knot each sum a contiguous piece of that range,
+        // the pieces added in part order
+        const int nk = c.n + p + 1;
+        const int parts = nk <= kBlock ? min(kMaxParts, kBlock / nk) : 1;
+        for (int t = threadIdx.x; t < nk * parts; t += kBlock) {
+            const int m = t / parts, part = t % parts;
             const int lo = lower_bound_int(spans, ns, m - p), hi = lower_bound_int(spans, ns, m + p);
+            const int a = lo + (int)((long long)(hi - lo) * part / parts);
+            const int b = lo + (int)((long long)(hi - lo) * (part + 1) / parts);
             double acc = 0.0;
-            for (int i = lo; i < hi; ++i) acc += rec[kParamRec * (size_t)i + (m - (spans[i] - p + 1))];
-            if (m == p) acc += e0;
-            if (m == c.n) acc += e1;
-            gk[m] = acc;
+            for (int i = a; i < b; ++i) acc += rec[kParamRec * (size_t)i + (m - (spans[i] - p + 1))];
+            if (parts == 1) {
+                if (m == p) acc += e0;
+                if (m == c.n) acc += e1;
+                gk[m] = acc;
+            } else {
+                lpart[t] = acc;
+            }
         }
+        __syncthreads();
+        if (parts > 1)
+            for (int m = threadIdx.x; m < nk; m += kBlock) {
+                double acc = 0.0;
+                for (int part = 0; part < parts; ++part) acc += lpart[m * parts + part];
+                if (m == p) acc += e0;
+                if (m == c.n) acc += e1;
+                gk[m] = acc;
+            }
+        __syncthreads();
     }
     if (want_w && c.w) {
         // weight l: basis indices l (and l + n on a closed curve), reached by
         // the samples with span in [k, k+p]
-        for (int l = threadIdx.x; l < c.n; l += kBlock) {
+        const int parts = c.n <= kBlock ? min(kMaxParts, kBlock / c.n) : 1;
+        for (int t = threadIdx.x; t < c.n * parts; t += kBlock) {
+            const int l = t / parts, part = t % parts;
             double acc = 0.0;
             for (int kk = l; kk < c.nb; kk += c.n) {
                 const int lo = lower_bound_int(spans, ns, kk), hi = lower_bound_int(spans, ns, kk + p + 1);
-                for (int i = lo; i < hi; ++i) acc += rec[kParamRec * (size_t)i + 2 * p + (kk - (spans[i] - p))];
+                const int a = lo + (int)((long long)(hi - lo) * part / parts);
+                const int b = lo + (int)((long long)(hi - lo) * (part + 1) / parts);
+                for (int i = a; i < b; ++i) acc += rec[kParamRec * (size_t)i + 2 * p + (kk - (spans[i] - p))];
                 if (!c.closed) break;
             }
-            gw[l] = acc;
+            if (parts == 1) gw[l] = acc;
+            else lpart[t] = acc;
         }
+        __syncthreads();
+        if (parts > 1)
+            for (int l = threadIdx.x; l < c.n; l += kBlock) {
+                double acc = 0.0;
+                for (int part = 0; part < parts; ++part) acc += lpart[l * parts + part];
+                gw[l] = acc;
+            }
     }
     __syncthreads();
 }
 
-// One block per sweep, after kbw_adjoint: xstash holds dL/dC, dL/dC',
-// dL/dC'' per path sample (9 doubles), colacc dL/dS (and dL/dS') per
-// profile sample, spans_u / spans_v the samples' spans.
+// Per-sample records of the knot and weight gradients: one block per
+// (sweep, chunk of kBlock samples) of the path (PROFILE false: adjoints from
+// xstash, dL/dC, dL/dC', dL/dC'' per sample, written by kbw_adjoint) or of
+// the profile (PROFILE true: dL/dS and dL/dS' from colacc).
+template <bool PROFILE>
+__global__ __launch_bounds__(kBlock) void kbw_param_rec(const BatchDesc* __restrict__ descs,
+                                                        const int2* __restrict__ chunks,
+                                                        const double* __restrict__ path_ctrl,
+                                                        const double* __restrict__ prof_ctrl,
+                                                        const double* __restrict__ path_w,
+                                                        const double* __restrict__ prof_w,
+                                                        const double* __restrict__ knots, const double* xstash,
+                                                        const double* colacc, const int* spans_u,
+                                                        const int* spans_v, double* recu, double* recv, int nrm,
+                                                        int want_k, int want_w)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const BatchDesc d = descs[ch.x];
+    const int i = ch.y * kBlock + threadIdx.x;
+    const int ns = PROFILE ? d.n_v : d.n_u;
+    const bool wk = want_k && (PROFILE ? d.prof_kuser_off : d.path_kuser_off) >= 0;
+    if (i >= ns || !(wk || want_w)) return;
+    const DCurve c = PROFILE
+        ? DCurve{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr, d.n_prof,
+                 d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
+                 prof_w ? prof_w + d.prof_ctrl_off : nullptr}
+        : DCurve{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr, d.n_path,
+                 d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
+    V3<double> xb, cb, c2b = mk(0.0, 0.0, 0.0);
+    if (PROFILE) {
+        const int cp = nrm ? kColPartNrm : kColPart;
+        const double* q = colacc + (size_t)cp * (d.ptab_off + i);
+        xb = mk(q[0], q[1], q[2]);
+        cb = nrm ? mk(q[3], q[4], q[5]) : mk(0.0, 0.0, 0.0);
+    } else {
+        const double* q = xstash + 9 * (d.row_off + (size_t)i);
+        xb = mk(q[0], q[1], q[2]);
+        cb = mk(q[3], q[4], q[5]);
+        c2b = mk(q[6], q[7], q[8]);
+    }
+    const size_t o = PROFILE ? d.ptab_off : d.row_off;
+    double* r = (PROFILE ? recv : recu) + kParamRec * (o + i);
+    const int s = (PROFILE ? spans_v : spans_u)[o + i];
+    r[kParamRec - 1] = param_contrib_any(c, sample_param(c, i, ns), s, xb, cb, c2b, wk, want_w, r, r + 2 * c.p);
+}
+
+// One block per sweep, after kbw_param_rec: the domain-end terms and the
+// gathers per knot and weight.
 __global__ __launch_bounds__(kBlock) void kbw_params(const BatchDesc* __restrict__ descs,
                                                      const double* __restrict__ path_ctrl,
                                                      const double* __restrict__ prof_ctrl,
                                                      const double* __restrict__ path_w,
                                                      const double* __restrict__ prof_w,
-                                                     const double* __restrict__ knots, const double* xstash,
-                                                     const double* colacc, const int* spans_u, const int* spans_v,
-                                                     double* recu, double* recv, int nrm, double* gPk, double* gQk,
-                                                     double* gPw, double* gQw)
+                                                     const double* __restrict__ knots, const int* spans_u,
+                                                     const int* spans_v, const double* recu, const double* recv,
+                                                     double* gPk, double* gQk, double* gPw, double* gQw)
 {
     __shared__ double lds3[kWaves][3];
+    __shared__ double lpart[kBlock];
     const BatchDesc d = descs[blockIdx.x];
     const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
                       d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
     const DCurve prof{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
                       d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
                       prof_w ? prof_w + d.prof_ctrl_off : nullptr};
-    const int cp = nrm ? kColPartNrm : kColPart;
     const bool pk = gPk && d.path_kuser_off >= 0, qk = gQk && d.prof_kuser_off >= 0;
     const bool pw = gPw != nullptr, qw = gQw != nullptr;
-    if (pk || pw) {
-        const double* xs = xstash + 9 * d.row_off;
+    if (pk || pw)
         curve_param_grads(path, d.n_u, spans_u + d.row_off, recu + kParamRec * d.row_off, pk, pw,
-                          pk ? gPk + d.path_kuser_off : nullptr, pw ? gPw + d.path_ctrl_off : nullptr, lds3,
-                          [&](int i, V3<double>& xb, V3<double>& cb, V3<double>& c2b) {
-                              const double* q = xs + 9 * (size_t)i;
-                              xb = mk(q[0], q[1], q[2]);
-                              cb = mk(q[3], q[4], q[5]);
-                              c2b = mk(q[6], q[7], q[8]);
-                          });
-    }
-    if (qk || qw) {
-        const double* ca = colacc + (size_t)cp * d.ptab_off;
+                          pk ? gPk + d.path_kuser_off : nullptr, pw ? gPw + d.path_ctrl_off : nullptr, lds3, lpart);
+    if (qk || qw)
         curve_param_grads(prof, d.n_v, spans_v + d.ptab_off, recv + kParamRec * d.ptab_off, qk, qw,
-                          qk ? gQk + d.prof_kuser_off : nullptr, qw ? gQw + d.prof_ctrl_off : nullptr, lds3,
-                          [&](int j, V3<double>& xb, V3<double>& cb, V3<double>& c2b) {
-                              const double* q = ca + (size_t)cp * j;
-                              xb = mk(q[0], q[1], q[2]);
-                              cb = nrm ? mk(q[3], q[4], q[5]) : mk(0.0, 0.0, 0.0);
-                              c2b = mk(0.0, 0.0, 0.0);
-                          });
-    }
+                          qk ? gQk + d.prof_kuser_off : nullptr, qw ? gQw + d.prof_ctrl_off : nullptr, lds3, lpart);
 }
 
 BackwardKernels backward_kernels(bool t64, bool nrm)
@@ -915,6 +966,8 @@ BackwardKernels backward_kernels(bool t64, bool nrm)
     else k.reduce = t64 ? (const void*)&kbw_reduce<double, false> : (const void*)&kbw_reduce<float, false>;
     k.adjoint = (const void*)&kbw_adjoint;
     k.params = (const void*)&kbw_params;
+    k.param_rec_path = (const void*)&kbw_param_rec<false>;
+    k.param_rec_prof = (const void*)&kbw_param_rec<true>;
     return k;
 }
 

@@ -199,6 +199,8 @@ struct Plan {
     int2* d_tiles = nullptr;
     int4* d_units = nullptr;       // adjoint reduction units, built on the first backward call
     int n_units = 0;
+    int2* d_uchunks_all = nullptr; // (sweep, chunk) of every path chunk, built on the first parameter-gradient call
+    int n_uchunks_all = 0;
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -215,6 +217,7 @@ struct Plan {
         if (d_descs) hipFree(d_descs);
         if (d_tiles) hipFree(d_tiles);
         if (d_units) hipFree(d_units);
+        if (d_uchunks_all) hipFree(d_uchunks_all);
         for (int p = 0; p < 8; ++p)
             if (d_sweeps[p]) hipFree(d_sweeps[p]);
         if (d_vchunks) hipFree(d_vchunks);
@@ -555,6 +558,17 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward adjoint");
         if (want_params) {
+            if (!P->d_uchunks_all) {
+                std::vector<int2> ch;
+                for (int k = 0; k < batch->n_sweeps; ++k)
+                    for (int c = 0; c * kBlock < batch->n_u[k]; ++c) ch.push_back(make_int2(k, c));
+                if ((e = hipMalloc(&P->d_uchunks_all, sizeof(int2) * ch.size())) != hipSuccess)
+                    return hip_fail(e, "plan alloc");
+                if ((e = hipMemcpy(P->d_uchunks_all, ch.data(), sizeof(int2) * ch.size(), hipMemcpyHostToDevice)) !=
+                    hipSuccess)
+                    return hip_fail(e, "plan upload");
+                P->n_uchunks_all = (int)ch.size();
+            }
             const void* xs = xstash;
             const void* ca = colacc;
             const void* su = spans_u;
@@ -565,8 +579,20 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
             double* gqk = pg.prof_knots;
             double* gpw = pg.path_weights;
             double* gqw = pg.prof_weights;
-            void* pargs[17] = {&descs, &pc, &qc, &pw, &qw, &kn, &xs, &ca, &su, &sv, &recu, &recv, &nrm_arg,
-                               &gpk, &gqk, &gpw, &gqw};
+            // per-sample records (all samples of all sweeps in parallel), then the gathers per sweep
+            for (int prof_side = 0; prof_side < 2; ++prof_side) {
+                int wk = prof_side ? pg.prof_knots != nullptr : pg.path_knots != nullptr;
+                int ww = prof_side ? pg.prof_weights != nullptr : pg.path_weights != nullptr;
+                if (!wk && !ww) continue;
+                const int2* chunks = prof_side ? P->d_vchunks : P->d_uchunks_all;
+                const unsigned grid = (unsigned)(prof_side ? P->n_vchunks : P->n_uchunks_all);
+                void* rargs[17] = {&descs, &chunks, &pc, &qc, &pw, &qw, &kn, &xs, &ca, &su, &sv, &recu, &recv,
+                                   &nrm_arg, &wk, &ww};
+                if ((e = hipLaunchKernel(prof_side ? BK.param_rec_prof : BK.param_rec_path, dim3(grid), dim3(kBlock),
+                                         rargs, 0, sm)) != hipSuccess)
+                    return hip_fail(e, "backward knot and weight records");
+            }
+            void* pargs[14] = {&descs, &pc, &qc, &pw, &qw, &kn, &su, &sv, &recu, &recv, &gpk, &gqk, &gpw, &gqw};
             if ((e = hipLaunchKernel(BK.params, dim3(batch->n_sweeps), dim3(kBlock), pargs, 0, sm)) != hipSuccess)
                 return hip_fail(e, "backward knot and weight gradients");
         }

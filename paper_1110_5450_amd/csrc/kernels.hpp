@@ -102,7 +102,9 @@ inline int bw_row_group_for(bool t64) { return t64 ? 4 : 8; }
 struct BackwardKernels {
     const void* reduce;
     const void* adjoint;
-    const void* params;    // knot and weight gradients
+    const void* params;          // knot and weight gradients: gathers per sweep
+    const void* param_rec_path;  // per-sample records, path chunks
+    const void* param_rec_prof;  // per-sample records, profile chunks
 };
 // nrm: the reduction also takes dL/dN (normal terms, longer partial records).
 BackwardKernels backward_kernels(bool t64, bool nrm);
