@@ -1,4 +1,4 @@
-"""Batched evaluation (profile, per-degree frame and surface launches,
+"""Batched evaluation (profile, frame and surface launches per frame-chain bucket,
 replayed from a HIP graph): every sweep's block agrees with evaluating that
 sweep alone (bitwise for sweeps of one chunk), matches the oracle, survives
 repeated replays with pointer changes, and the full 4096-sweep batch is
@@ -126,6 +126,31 @@ def test_batched_user_knots_and_precision_variants():
             ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
             ok, r = parity(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).cpu().numpy(), b.view(nrm, k).cpu().numpy(), tol)
             assert ok, (frame_dtype, reorth, k, r)
+
+
+def test_batched_every_chain_bucket_and_degree():
+    # Sweeps of 1, 4 and 11 u-chunks (the graph's three frame-chain buckets:
+    # up to 2 chunks, 3-8, more), every path degree in each, interleaved so
+    # that each bucket's sweeps and tiles are gathered from across the batch.
+    rng = np.random.default_rng(12)
+    specs = []
+    for k in range(21):
+        p, n_u = 1 + k % 7, [200, 1000, 2700][k % 3]
+        P = synth.random_walk(rng, int(rng.integers(p + 1, 40)))
+        Q = synth.perturbed_circle(rng, int(rng.integers(4, 12)))
+        specs.append(synth.SweepSpec(synth.CurveSpec(P, p), synth.CurveSpec(Q, 3, True), n_u, 7 + k % 5))
+    b = api.Batch.from_specs(specs)
+    say(f"[case] every bucket and degree: {len(specs)} sweeps")
+    pos, nrm = api.sweep_eval_batched(b, out_dtype=torch.float64)
+    again = api.sweep_eval_batched(b, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    assert torch.equal(pos, again[0]) and torch.equal(nrm, again[1])
+    for k, s in enumerate(specs):
+        ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
+        ok, r = parity(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).cpu().numpy(), b.view(nrm, k).cpu().numpy(),
+                       TOL[torch.float64])
+        say(f"   sweep {k} ({s.n_u}x{s.n_v}, p={s.path.degree}): {r}")
+        assert ok, (k, r)
 
 
 def test_full_batch_sampled_sweeps():
