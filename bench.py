@@ -543,9 +543,11 @@ def main():
         log("[bench] triangles ...")
         out["variants"]["triangles"] = triangles_variant(steps64)
         log("[bench] batched ...")
-        out["variants"]["batched"] = batched_variants(max(3, args.steps // 4))
+        # the batch and the adjoint take about a millisecond per step: timed
+        # over the full step count, as when run alone (--variant)
+        out["variants"]["batched"] = batched_variants(args.steps)
         log("[bench] adjoint ...")
-        out["variants"]["adjoint"] = adjoint_variant(max(3, args.steps // 4))
+        out["variants"]["adjoint"] = adjoint_variant(args.steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec)

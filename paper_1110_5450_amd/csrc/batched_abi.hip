@@ -1,12 +1,8 @@
 // batched_abi.hip -- sweep_eval_batched and sweep_backward: plans keyed by
-// batch shape, each holding the per-sweep descriptors, the frame sweep lists
-// and the surface tile list in device memory, and a HIP graph that is
-// replayed per call.  Sweeps are grouped into frame-chain buckets by the
-// number of u-chunks their frame block walks in sequence; the graph is two
-// chains, frames (bucket 0, 1, 2) and profile tables then surfaces (bucket
-// 0, 1, 2), with the surface node of a bucket also waiting for its frame
-// node, so that the surfaces of short sweeps are written while the frames
-// of long ones are still scanned.
+// batch shape, each holding the per-sweep descriptors, the per-degree sweep
+// lists and the surface tile list in device memory, and a HIP graph
+// (profile tables and one frame node per path degree, then the surface)
+// that is replayed per call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,13 +85,14 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         const int np = b->path_n[k], pp = b->path_degree[k], nq = b->prof_n[k], pq = b->prof_degree[k];
         const int qc = b->prof_closed ? b->prof_closed[k] : 1;
         const int nu = b->n_u[k], nv = b->n_v[k];
-        char what[64];
-        std::snprintf(what, sizeof what, "sweep %d path", k);
+        // (the sweep index is added to the message on the error path only:
+        // this runs for every sweep on every call)
         const double* pk = b->path_knots ? b->path_knots + pk_off : nullptr;
-        if ((st = check_curve_meta(np, pp, 0, pk, what, true)) != SWEEP_OK) return st;
-        std::snprintf(what, sizeof what, "sweep %d profile", k);
+        if ((st = check_curve_meta(np, pp, 0, pk, "path", true)) != SWEEP_OK)
+            return fail(st, "sweep %d %s", k, sweep_last_error());
         const double* qk = (b->prof_knots && !qc) ? b->prof_knots + qk_off : nullptr;
-        if ((st = check_curve_meta(nq, pq, qc, qk, what, false)) != SWEEP_OK) return st;
+        if ((st = check_curve_meta(nq, pq, qc, qk, "profile", false)) != SWEEP_OK)
+            return fail(st, "sweep %d %s", k, sweep_last_error());
         if ((st = check_grid(nu, nv)) != SWEEP_OK) {
             return fail(st, "sweep %d: %s", k, sweep_last_error());
         }
@@ -174,6 +171,7 @@ enum NodeKind { kProfile, kFrame, kSurface };
 
 struct GNode {
     NodeKind kind;
+    int deg;
     hipGraphNode_t node = nullptr;
     hipKernelNodeParams prm{};
     NodeArgs a{};
@@ -207,8 +205,8 @@ struct Plan {
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int* d_sweeps = nullptr;       // every sweep, longest n_u first
-    int* d_gsweeps = nullptr;      // the graph's frame lists: per bucket, longest n_u first
+    int* d_sweeps[8] = {};         // sweeps by path degree, longest n_u first
+    int n_deg[8] = {};
     int2* d_vchunks = nullptr;     // (sweep, chunk) of every profile chunk
     int n_vchunks = 0;
     NodeArgs a{};                  // values shared by all nodes
@@ -219,10 +217,10 @@ struct Plan {
         if (graph) hipGraphDestroy(graph);
         if (d_descs) hipFree(d_descs);
         if (d_tiles) hipFree(d_tiles);
-        if (d_gsweeps) hipFree(d_gsweeps);
         if (d_units) hipFree(d_units);
         if (d_uchunks_all) hipFree(d_uchunks_all);
-        if (d_sweeps) hipFree(d_sweeps);
+        for (int p = 0; p < 8; ++p)
+            if (d_sweeps[p]) hipFree(d_sweeps[p]);
         if (d_vchunks) hipFree(d_vchunks);
         if (d_knots) hipFree(d_knots);
     }
@@ -231,17 +229,6 @@ struct Plan {
 // Batched surface configuration for tile_config = -1: linear tiles of 1024
 // vertices with nontemporal stores.
 static SurfaceConfig batched_surface_config() { return SurfaceConfig{1, 0, 1024, 1}; }
-
-// Frame-chain bucket of a sweep: its frame block walks its u-samples in
-// chunks (frame_chunk_size()) in sequence (bucket 0: up to 2 chunks, 1: up
-// to 8, 2: more).
-static const int kBuckets = 3;
-static int chain_bucket(int n_u)
-{
-    const int cs = frame_chunk_size();
-    const int c = (n_u + cs - 1) / cs;
-    return c <= 2 ? 0 : (c <= 8 ? 1 : 2);
-}
 
 static std::mutex g_mu;
 static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
@@ -258,38 +245,22 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     P->key = std::move(key);
     P->n_sweeps = b->n_sweeps;
     P->with_nrm = with_nrm;
-    // surface tiles: (sweep, first local vertex), by bucket and within a
-    // bucket in sweep order; sweeps by path degree (and by bucket for the
-    // graph's frame nodes), longest first (the frame blocks' work is
-    // proportional to n_u); profile chunks: (sweep, chunk) of every 256
-    // v-samples
+    // surface tiles: (sweep, first local vertex) in sweep order; sweeps by
+    // path degree, longest first (the frame blocks' work is proportional to
+    // n_u); profile chunks: (sweep, chunk) of every 256 v-samples
     const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : batched_surface_config();
     // column-tile configurations map to one-row-sized linear tiles
     const int tv = cfg.kind == 1 ? cfg.tile_vertices : kBlock;
     std::vector<int2> tiles, vchunks;
-    std::vector<int> sweeps, gflat;
-    size_t tile_off[kBuckets + 1] = {}, goff[kBuckets + 1] = {};
-    for (int g = 0; g < kBuckets; ++g) {
-        tile_off[g] = tiles.size();
-        goff[g] = gflat.size();
-        for (int k = 0; k < b->n_sweeps; ++k) {
-            if (chain_bucket(b->n_u[k]) != g) continue;
-            const long long N = (long long)b->n_u[k] * b->n_v[k];
-            for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
-            gflat.push_back(k);
-        }
-    }
-    tile_off[kBuckets] = tiles.size();
-    goff[kBuckets] = gflat.size();
+    std::vector<int> sweeps[8];
     for (int k = 0; k < b->n_sweeps; ++k) {
-        sweeps.push_back(k);
+        const long long N = (long long)b->n_u[k] * b->n_v[k];
+        for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
+        sweeps[b->path_degree[k]].push_back(k);
         for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
-    auto longest_first = [&](int* first, int* last) {
-        std::stable_sort(first, last, [&](int x, int y) { return b->n_u[x] > b->n_u[y]; });
-    };
-    longest_first(sweeps.data(), sweeps.data() + sweeps.size());
-    for (int g = 0; g < kBuckets; ++g) longest_first(gflat.data() + goff[g], gflat.data() + goff[g + 1]);
+    for (auto& l : sweeps)
+        std::stable_sort(l.begin(), l.end(), [&](int x, int y) { return b->n_u[x] > b->n_u[y]; });
     if (tiles.size() > 0x7fffffffull || vchunks.size() > 0x7fffffffull)
         return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
     P->n_tiles = (int)tiles.size();
@@ -304,11 +275,13 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         (e = upload((void**)&P->d_tiles, tiles.data(), sizeof(int2) * tiles.size())) != hipSuccess ||
         (e = upload((void**)&P->d_vchunks, vchunks.data(), sizeof(int2) * vchunks.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
-    if ((e = upload((void**)&P->d_sweeps, sweeps.data(), sizeof(int) * sweeps.size())) != hipSuccess)
-        return hip_fail(e, "plan upload");
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        P->n_deg[p] = (int)sweeps[p].size();
+        if (!sweeps[p].empty() &&
+            (e = upload((void**)&P->d_sweeps[p], sweeps[p].data(), sizeof(int) * sweeps[p].size())) != hipSuccess)
+            return hip_fail(e, "plan upload");
+    }
     if (!knots.empty() && (e = upload((void**)&P->d_knots, knots.data(), sizeof(double) * knots.size())) != hipSuccess)
-        return hip_fail(e, "plan upload");
-    if ((e = upload((void**)&P->d_gsweeps, gflat.data(), sizeof(int) * gflat.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
 
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
@@ -324,14 +297,13 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
     A.reorth = o->reorthonormalize;
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
-    // sweeps / tiles: the node's own frame list or tile range
-    auto add = [&](NodeKind kind, const void* fn, unsigned grid, const int* sweeps, const int2* tiles,
+    auto add = [&](NodeKind kind, int deg, const void* fn, unsigned grid,
                    const std::vector<hipGraphNode_t>& deps) -> hipError_t {
         std::unique_ptr<GNode> n(new GNode());
         n->kind = kind;
+        n->deg = deg;
         std::memcpy(&n->a, &P->a, sizeof n->a);
-        n->a.sweeps = sweeps;
-        n->a.tiles = tiles;
+        if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg];
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
@@ -344,24 +316,16 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         P->nodes.push_back(std::move(n));
         return r;
     };
-    // Two chains: frame nodes by bucket; the profile node then surface nodes
-    // by bucket.  Each node has at most one predecessor in its own chain.
-    if ((e = add(kProfile, K.profile, (unsigned)P->n_vchunks, nullptr, nullptr, {})) != hipSuccess)
-        return hip_fail(e, "graph node");
-    hipGraphNode_t last_surface = P->nodes.back()->node, last_frame = nullptr;
-    for (int g = 0; g < kBuckets; ++g) {
-        if (goff[g + 1] == goff[g]) continue;
-        std::vector<hipGraphNode_t> fdeps;
-        if (last_frame) fdeps.push_back(last_frame);
-        if ((e = add(kFrame, K.frame, (unsigned)(goff[g + 1] - goff[g]), P->d_gsweeps + goff[g], nullptr, fdeps)) !=
-            hipSuccess)
-            return hip_fail(e, "graph node");
-        last_frame = P->nodes.back()->node;
-        if ((e = add(kSurface, K.surface, (unsigned)(tile_off[g + 1] - tile_off[g]), nullptr,
-                     P->d_tiles + tile_off[g], {last_surface, last_frame})) != hipSuccess)
-            return hip_fail(e, "graph node");
-        last_surface = P->nodes.back()->node;
+    std::vector<hipGraphNode_t> before_surface;
+    if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
+    before_surface.push_back(P->nodes.back()->node);
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        if (!P->n_deg[p]) continue;
+        if ((e = add(kFrame, p, K.frame[p], (unsigned)P->n_deg[p], {})) != hipSuccess) return hip_fail(e, "graph node");
+        before_surface.push_back(P->nodes.back()->node);
     }
+    if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, before_surface)) != hipSuccess)
+        return hip_fail(e, "graph node");
     if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
         return hip_fail(e, "graph instantiate");
     out = std::move(P);
@@ -452,11 +416,9 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     if (std::memcmp(&A, &P->a, sizeof A) != 0) {
         P->a = A;
         for (auto& n : P->nodes) {
-            const int* own_sweeps = n->a.sweeps;
-            const int2* own_tiles = n->a.tiles;
+            const int* own = n->a.sweeps;
             std::memcpy(&n->a, &A, sizeof A);
-            n->a.sweeps = own_sweeps;
-            n->a.tiles = own_tiles;
+            n->a.sweeps = own;
             if ((e = hipGraphExecKernelNodeSetParams(P->exec, n->node, &n->prm)) != hipSuccess)
                 return hip_fail(e, "graph update");
         }
@@ -543,15 +505,17 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         n.a.reorth = 1;
         n.a.rows = ws + B.rows;
         n.a.ptab = ws + B.ptab;
-        auto launch = [&](NodeKind kind, const void* fn, unsigned grid) -> hipError_t {
+        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid) -> hipError_t {
             n.kind = kind;
-            n.a.sweeps = kind == kFrame ? P->d_sweeps : nullptr;
+            n.a.sweeps = kind == kFrame ? P->d_sweeps[deg] : nullptr;
             node_args(n);
             return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, 0, sm);
         };
-        if ((e = launch(kProfile, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess ||
-            (e = launch(kFrame, FK.frame, (unsigned)P->n_sweeps)) != hipSuccess)
+        if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
+            if (P->n_deg[p] && (e = launch(kFrame, p, FK.frame[p], (unsigned)P->n_deg[p])) != hipSuccess)
+                return hip_fail(e, "backward frames");
     }
     {
         const BatchDesc* descs = P->d_descs;

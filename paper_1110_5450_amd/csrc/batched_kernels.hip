@@ -2,10 +2,9 @@
 // graph:
 //
 // kb_profile  one block per (sweep, chunk of 256 v-samples): profile tables.
-// kb_frame    one block per sweep, any path degree (a block-uniform switch
-//             on the degree selects a body with the degree as a template
-//             parameter, so the B-spline arrays stay in registers); sweeps
-//             are listed longest first.  The block walks
+// kb_frame    one block per sweep, one launch per path degree present (the
+//             degree is a template parameter, so the B-spline arrays stay in
+//             registers); sweeps are listed longest first.  The block walks
 //             its sweep's chunks of 256 u-samples in order: samples, step
 //             rotations, the block's exclusive product scan, row records,
 //             then the normal entering the next chunk (the chunk's total
@@ -115,13 +114,18 @@ __global__ __launch_bounds__(kBlock) void kb_profile(const BatchDesc* __restrict
     if (j < d.n_v) write_profile<T>(prof_of(d, prof_ctrl, prof_w, knots), j, d.n_v, ptab + 8 * d.ptab_off);
 }
 
-// Row records of one sweep whose path has degree P (the whole block).
+// Row records of the sweeps whose path has degree P: one block per sweep.
 template <int P, class F, class T>
-__device__ __forceinline__ void frame_sweep(const BatchDesc& d, const double* __restrict__ path_ctrl,
-                                            const double* __restrict__ path_w, const double* __restrict__ knots,
-                                            InitialNormal n0, int reorth, T* __restrict__ rows, ChunkLds& L,
-                                            M3<F>* lds_m)
+__global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
+                                                   const int* __restrict__ sweeps,
+                                                   const double* __restrict__ path_ctrl,
+                                                   const double* __restrict__ path_w,
+                                                   const double* __restrict__ knots, InitialNormal n0, int reorth,
+                                                   T* __restrict__ rows)
 {
+    __shared__ ChunkLds L;
+    __shared__ M3<F> lds_m[kWaves];
+    const BatchDesc d = descs[sweeps[blockIdx.x]];
     const DCurve path = path_of(d, path_ctrl, path_w, knots);
     const V3<double> fb = first_leg(path);
     const int n_u = d.n_u;
@@ -148,27 +152,6 @@ __device__ __forceinline__ void frame_sweep(const BatchDesc& d, const double* __
         if (i < n_u) write_row<F, T>(s, ex, rin, c1, c2, reorth, rows_k + 16 * (size_t)i);
         const V3<F> rn = apply(total, mk(rin[0], rin[1], rin[2]));
         rin[0] = rn.x; rin[1] = rn.y; rin[2] = rn.z;
-    }
-}
-
-// Row records: one block per listed sweep, any path degree.
-template <class F, class T>
-__global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
-                                                   const int* __restrict__ sweeps,
-                                                   const double* __restrict__ path_ctrl,
-                                                   const double* __restrict__ path_w,
-                                                   const double* __restrict__ knots, InitialNormal n0, int reorth,
-                                                   T* __restrict__ rows)
-{
-    __shared__ ChunkLds L;
-    __shared__ M3<F> lds_m[kWaves];
-    const BatchDesc d = descs[sweeps[blockIdx.x]];
-    switch (d.p_path) {
-#define SWEEP_DEG(P) \
-    case P: frame_sweep<P, F, T>(d, path_ctrl, path_w, knots, n0, reorth, rows, L, lds_m); break;
-        SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
-#undef SWEEP_DEG
-    default: break;   // degrees are validated on the host
     }
 }
 
@@ -257,7 +240,10 @@ static BatchedKernels pick(bool nrm, bool nt, int K)
 {
     BatchedKernels k;
     k.profile = (const void*)&kb_profile<T>;
-    k.frame = (const void*)&kb_frame<F, T>;
+    k.frame[0] = nullptr;
+#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>;
+    SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
+#undef SWEEP_DEG
     if (nrm) k.surface = nt ? surface_for<T, true, true>(K) : surface_for<T, true, false>(K);
     else k.surface = nt ? surface_for<T, false, true>(K) : surface_for<T, false, false>(K);
     return k;

@@ -118,7 +118,7 @@ void fastdiv_constants(int d, unsigned long long* m, int* shift);
 
 struct BatchedKernels {
     const void* profile;
-    const void* frame;      // any path degree
+    const void* frame[8];   // by path degree (index 0 unused)
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as

@@ -1,4 +1,4 @@
-"""Batched evaluation (profile, frame and surface launches per frame-chain bucket,
+"""Batched evaluation (profile, per-degree frame and surface launches,
 replayed from a HIP graph): every sweep's block agrees with evaluating that
 sweep alone (bitwise for sweeps of one chunk), matches the oracle, survives
 repeated replays with pointer changes, and the full 4096-sweep batch is
@@ -128,10 +128,10 @@ def test_batched_user_knots_and_precision_variants():
             assert ok, (frame_dtype, reorth, k, r)
 
 
-def test_batched_every_chain_bucket_and_degree():
-    # Sweeps of 1, 4 and 11 u-chunks (the graph's three frame-chain buckets:
-    # up to 2 chunks, 3-8, more), every path degree in each, interleaved so
-    # that each bucket's sweeps and tiles are gathered from across the batch.
+def test_batched_chunk_counts_and_every_degree():
+    # Sweeps of 1, 4 and 11 u-chunks (a frame block walks a sweep's chunks
+    # in sequence), every path degree at each length, interleaved; two
+    # replays agree bitwise.
     rng = np.random.default_rng(12)
     specs = []
     for k in range(21):
