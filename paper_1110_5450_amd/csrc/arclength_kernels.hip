@@ -43,6 +43,14 @@ __device__ double speed_at(const DCurve& c, int s, double u, double lam)
     return sp + (sp > 0.0 ? lam * sqrt(dot(cr, cr)) / (sp * sp) : 0.0);
 }
 
+// Weights that extrapolate the degree-7 interpolant of values at the eight
+// Gauss-Legendre nodes to the end point +1: the Lagrange basis polynomials of
+// the nodes at +1 (computed in extended precision, rounded to double; their
+// absolute values sum to 4.5).
+__device__ const double kGlEnd[8] = {-0.032020422845832404, 0.11217721020871642, -0.2208713667044389,
+                                     0.3537304181064418,    -0.5126556338013685, 0.7101568903172424,
+                                     -0.9912041583117163,   1.5806870630309555};
+
 // Piece q = (k - p) * kArcSub + m of span k: its bounds.
 __device__ __forceinline__ void piece_bounds(const DCurve& c, int q, int& k, double& lo, double& hi)
 {
@@ -169,9 +177,13 @@ __device__ __forceinline__ int span_of(const DCurve& c, double u)
     return lo;
 }
 
-// Lanes per sample in k_arc_params: lanes 0-7 evaluate the Gauss-Legendre
-// nodes of the running integral, lane 8 the speed at the iterate.
-constexpr int kArcLanes = 16;
+// Lanes per sample in k_arc_params: one Gauss-Legendre node each.  Newton's
+// derivative, the density at the iterate, is extrapolated from the eight
+// node values (kGlEnd) instead of a ninth evaluation: its relative error
+// (about 1e-12 on a piece of a smooth span) only slows the quadratic
+// convergence by that factor, and the root is that of the same
+// Gauss-Legendre integral.
+constexpr int kArcLanes = 8;
 
 // The piece search starts in a coarse copy of the table in LDS (every
 // cstride-th entry, at most kArcCoarseMax of them) and ends with a binary
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc
     __syncthreads();
     const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) / kArcLanes;
     const int l = threadIdx.x & (kArcLanes - 1);
-    if (g >= ns) return;   // whole 16-lane groups leave together
+    if (g >= ns) return;   // whole lane groups leave together
     const int i = (int)g;
     double u;
     if (i == 0) {
@@ -228,21 +240,22 @@ __global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc
         const double len = cum[q + 1] - cum[q];
         u = len > 0.0 ? plo + (target - cum[q]) / len * (phi - plo) : plo;
         double blo = plo, bhi = phi;
-        const double xl = kGlX[l & 7], wl = kGlW[l & 7];
+        const double xl = kGlX[l], wl = kGlW[l];
         // Every lane of the group holds the same u, f and speed (the sums
         // below are butterflies, whose pairwise additions commute), so the
         // group takes every branch together.
         for (int it = 0; it < 40; ++it) {
             const double mid = 0.5 * (plo + u), half = 0.5 * (u - plo);
-            double e = 0.0;
-            if (l < 8) e = wl * speed_at<P, ADAPT>(c, k, mid + half * xl, lam);
-            else if (l == 8) e = speed_at<P, ADAPT>(c, k, u, lam);
-            const double sp = __shfl(e, 8, kArcLanes);
-            double part = l < 8 ? e : 0.0;
+            const double e = speed_at<P, ADAPT>(c, k, mid + half * xl, lam);
+            double part = wl * e, sp = kGlEnd[l] * e;
             part += __shfl_xor(part, 1, kArcLanes);
+            sp += __shfl_xor(sp, 1, kArcLanes);
             part += __shfl_xor(part, 2, kArcLanes);
+            sp += __shfl_xor(sp, 2, kArcLanes);
             part += __shfl_xor(part, 4, kArcLanes);
+            sp += __shfl_xor(sp, 4, kArcLanes);
             part = __shfl(part, 0, kArcLanes);
+            sp = __shfl(sp, 0, kArcLanes);
             const double f = cum[q] + half * part - target;
             if (f == 0.0) break;
             if (f > 0.0) bhi = u; else blo = u;
