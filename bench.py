@@ -527,7 +527,9 @@ def main():
         "error_vs_oracle": err,
     }
     if not args.no_variants:
-        steps64 = max(3, args.steps // 4)
+        # every variant step takes well under a millisecond: timed over the
+        # full step count, as when run alone (--variant)
+        steps64 = args.steps
         el64, surf64, frame64, _ = time_single(spec, steps64, 1, torch.float64)
         s64 = sum(surf64) / len(surf64)
         out["variants"] = {
@@ -543,8 +545,6 @@ def main():
         log("[bench] triangles ...")
         out["variants"]["triangles"] = triangles_variant(steps64)
         log("[bench] batched ...")
-        # the batch and the adjoint take about a millisecond per step: timed
-        # over the full step count, as when run alone (--variant)
         out["variants"]["batched"] = batched_variants(args.steps)
         log("[bench] adjoint ...")
         out["variants"]["adjoint"] = adjoint_variant(args.steps)
