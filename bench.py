@@ -37,10 +37,11 @@ METRIC = "swept-surface vertices/s (pos+normal) and % HBM peak; batched/FP32 vs 
 HBM_PEAK_GBS = 8000.0
 COPY_CAL_BYTES = 512 << 20
 # Untimed calls before timing a batched entry point: on this HIP runtime one
-# of the first ten launches of a graph (the ninth, in the runs we looked at),
-# and one of the first backward calls that request knot and weight gradients,
-# stall the host once for 35-70 ms; steady-state calls take 0.1-1 ms.
-GRAPH_WARMUP = 12
+# of the first calls stalls the host once for 35-70 ms (the ninth graph
+# launch; the fourteenth positions-only backward call, with no stall over the
+# next 106; one of the first calls that request knot and weight gradients);
+# steady-state calls take 0.1-1 ms.
+GRAPH_WARMUP = 24
 COUNTERS = os.path.join(ROOT, "profiles", "surface_c2_counters.json")
 SURFACE_SRC = os.path.join(ROOT, "paper_1110_5450_amd", "csrc", "surface_kernels.hip")
 

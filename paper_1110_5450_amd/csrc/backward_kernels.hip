@@ -35,8 +35,8 @@
 
 namespace sweep {
 
-// One wave per unit (sweep, group of G rows, segment of 64 columns); every
-// wave of the block reaches the barriers.  Lane = column j loads its G x 3
+// One wave per unit (sweep, group of G rows, segment of 64 columns); each
+// wave's LDS tiles are its own (no block barriers).  Lane = column j loads its G x 3
 // values of w (coalesced) and keeps them in registers for the column sums
 //   h_j += R_i^T w_ij over the G rows;
 // the values also go to an LDS tile (rows padded to 65 elements: no bank
@@ -46,6 +46,17 @@ namespace sweep {
 // With NRM the lane also loads g for its G rows and forms the normal terms:
 // column sums in registers, row sums through the LDS tile.  grad may be null
 // (no position term).
+// The LDS tiles of kbw_reduce are private to a wave: ordering its own LDS
+// accesses needs no block barrier.  LDS operations of one wave execute in
+// order; the wave-scope fences keep the compiler from moving them across
+// this point.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <class T, bool NRM>
 __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict__ descs,
                                                      const int4* __restrict__ units, int n_units,
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
             }
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     // lane = ((c * G + r) << 1) | h
     const int h = lane & 1, cr = lane >> 1, r = cr % G, c = cr / G;
     const bool act = live && c < 3 && r < nr;
@@ -138,8 +149,7 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         // The normal terms.  Row sums go through the wave's (now free) LDS
         // tile: lanes write their 12 values of a row, then lane (e, k),
         // e < 12, k < 4, sums value e over columns 16k .. 16k+15 and the four
-        // parts are added in a fixed order.  G rows per unit on every wave
-        // (rows past the sweep's end contribute 0), so the barriers match.
+        // parts are added in a fixed order.
         V3<double> S = mk(0.0, 0.0, 0.0), q = S;
         if (vj) {
             const double* pq = ptab + 8 * (d.ptab_off + j);
@@ -185,10 +195,10 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
                     hD = hD + qb;
                 }
             }
-            __syncthreads();   // the tile's previous contents are consumed
+            wave_lds_sync();   // the tile's previous contents are consumed
 #pragma unroll
             for (int k = 0; k < 12; ++k) buf[65 * k + lane] = cv[k];
-            __syncthreads();
+            wave_lds_sync();
             double part = 0.0;
             if (lane < 48)
                 for (int jj = 16 * kq; jj < 16 * kq + 16; ++jj) part += buf[65 * e + jj];
