@@ -327,6 +327,28 @@ def batched_variants(steps: int):
     }
 
 
+def write_probe(nbytes: int = 4 << 30, reps: int = 5) -> dict:
+    """Store ceiling of this GPU: a plain coalesced fill (torch's fill kernel,
+    16-byte stores) of a 4 GiB buffer, mean of `reps` launches timed with
+    events, after one untimed launch.  A reference for the surface kernel's
+    rate, not part of the hot path."""
+    import torch
+
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    buf.fill_(1.0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        buf.fill_(0.0)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return {"GBps": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "ms": ms, "kernel": "torch fill_ (float32)"}
+
+
 def adjoint_variant(steps: int):
     """The differentiation workload: 256 sweeps of 1024 x 64, FP32, backward."""
     import numpy as np
@@ -512,6 +534,8 @@ def main():
     err = sampled_error(spec, res[0], res[1], rows, 1e-5)
     del res
     torch.cuda.empty_cache()
+    probe = write_probe()
+    log(f"[bench] write probe {probe['GBps']:.0f} GB/s")
     out = {
         "metric": METRIC, "value": value, "unit": "vertices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -523,7 +547,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
                      "kernel": "k_surface_tiles<float, true, true, 16> (surface write)", "alg_bytes_per_launch": bytes_alg,
-                     "avg_launch_ms": surf_ms},
+                     "avg_launch_ms": surf_ms,
+                     # the same rate against the measured store ceiling
+                     "write_probe": probe, "frac_of_write_probe": achieved / probe["GBps"]},
         "stages_ms": {"frame": sum(frame) / len(frame), "surface": surf_ms},
         "error_vs_oracle": err,
     }
