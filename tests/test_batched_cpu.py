@@ -40,6 +40,21 @@ def test_batched_validation():
     assert L.STATUS[st] == "SWEEP_ERR_BAD_COUNT"
 
 
+def test_batched_validation_names_the_sweep_and_curve():
+    # the message carries the failing sweep's index and which curve failed,
+    # also for a sweep after valid ones, and the details of the curve check
+    b, keep = _batch([100, 10, 300], [10, 20, 30])
+    keep["qd"][2] = 0
+    st = L.sweep_eval_batched(b, L.default_options(), 0x100000, 0, 0x100000, 1 << 40, 0)
+    msg = L.last_error()
+    assert L.STATUS[st] == "SWEEP_ERR_BAD_DEGREE" and msg.startswith("sweep 2 profile") and "degree 0" in msg
+    keep["qd"][2] = 3
+    keep["pn"][1] = 2
+    st = L.sweep_eval_batched(b, L.default_options(), 0x100000, 0, 0x100000, 1 << 40, 0)
+    msg = L.last_error()
+    assert L.STATUS[st] == "SWEEP_ERR_BAD_COUNT" and msg.startswith("sweep 1 path") and "2 control points" in msg
+
+
 def test_batched_output_elems_padded_layout():
     # plane stride = n_u*n_v rounded up to 64 elements
     b, keep = _batch([100, 7, 64], [10, 9, 3])
