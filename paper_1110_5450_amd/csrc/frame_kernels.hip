@@ -22,6 +22,12 @@
 //
 // k_frame_apply rebuilds the step rotations from the same inputs with the
 // same code as k_prep, so both see bitwise identical M_i.
+//
+// With at most kBlock chunks (and no frame mode or law), k_frame_apply_fused
+// replaces k_frame_carry + k_frame_apply: block b forms its own entry normal
+// as the ordered block product of the chunk products below it, applied to
+// r_0 (one launch fewer; the chunk products are combined in a tree instead
+// of the carry's scan, the same to rounding).
 #include "frame_common.hpp"
 
 namespace sweep {
@@ -190,6 +196,63 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply(const double* __restrict
                     rows + 16 * (size_t)i);
 }
 
+// k_frame_apply without k_frame_carry, for at most kBlock chunks: thread c
+// holds the product A_c of chunk c < b (identity above); the products of
+// chunks whose first sample has C' = 0 (not formed by k_prep) are formed
+// here, as k_frame_carry does; their ordered block product applied to r_0 is
+// the block's entry normal.
+template <class F, class T>
+__global__ __launch_bounds__(kBlock) void k_frame_apply_fused(const double* __restrict__ smp, int n_u,
+                                                              const int* __restrict__ chunk_lv,
+                                                              const int* __restrict__ chunk_fix,
+                                                              const double* __restrict__ fallback_t,
+                                                              const F* __restrict__ agg, InitialNormal n0, int reorth,
+                                                              T* __restrict__ rows)
+{
+    __shared__ int lds_i[kWaves];
+    __shared__ M3<F> lds_m[kWaves];
+    __shared__ M3<F> lds_fix;
+    __shared__ int lflag[kBlock];
+    __shared__ F lds_r[3];
+    const size_t nu = (size_t)n_u;
+    const int b = blockIdx.x, c = threadIdx.x;
+    M3<F> A = ident<F>();
+    int flagged = 0;
+    if (c < b) {
+        flagged = chunk_fix[c];
+        if (!flagged) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) A.m[e] = agg[9 * (size_t)c + e];
+        }
+    }
+    lflag[c] = flagged;
+    int last_flagged;
+    block_exclusive_max(flagged ? c : -1, lds_i, last_flagged);   // also orders lflag
+    for (int f = 1; f <= last_flagged; ++f) {   // uniform; skipped when none
+        if (!lflag[f]) continue;
+        const StepInputs sf = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, f);
+        const M3<F> prod = block_product<F>(step_of<F>(sf), lds_m);
+        if (threadIdx.x == 0) lds_fix = prod;
+        __syncthreads();
+        if (c == f) A = lds_fix;
+        __syncthreads();
+    }
+    const M3<F> P = block_product<F>(A, lds_m);   // A_{b-1} ... A_0, valid in wave 0
+    if (threadIdx.x == 0) {
+        const V3<double> d = smp_get(smp, nu, 1, 0);
+        const V3<double> t0 = dot(d, d) > 0.0 ? unit_of(d) : mk(fallback_t[0], fallback_t[1], fallback_t[2]);
+        const V3<F> r = apply(P, cvt<F>(initial_normal(t0, n0)));
+        lds_r[0] = r.x; lds_r[1] = r.y; lds_r[2] = r.z;
+    }
+    __syncthreads();
+    const F rin[3] = {lds_r[0], lds_r[1], lds_r[2]};
+    const StepInputs s = load_step_inputs(smp, n_u, chunk_lv, fallback_t, lds_i, b);
+    const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m);
+    const int i = b * kChunk + threadIdx.x;
+    if (i >= n_u) return;
+    write_row<F, T>(s, ex, rin, smp_get(smp, nu, 1, i), smp_get(smp, nu, 2, i), reorth, rows + 16 * (size_t)i);
+}
+
 // Extended row records (Frenet frame mode and/or a sweep law): the same
 // block scan for the rotation-minimizing frame; the Frenet mode replaces r by
 // the principal normal and needs the third derivative of the path, which is
@@ -248,6 +311,11 @@ hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const i
                         hipStream_t st, const FrameExt* ext)
 {
     const int nc = (n_u + kChunk - 1) / kChunk;
+    if (!ext && nc <= kBlock) {
+        hipLaunchKernelGGL((k_frame_apply_fused<F, T>), dim3(nc), dim3(kBlock), 0, st, smp, n_u, chunk_lv, chunk_fix,
+                           fallback_t, agg, n0, reorth, rows);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_frame_carry<F>, dim3(1), dim3(kBlock), 0, st, agg, nc, smp, n_u, chunk_lv, chunk_fix,
                        fallback_t, n0, r_in);
     if (ext)
