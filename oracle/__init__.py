@@ -439,18 +439,23 @@ def bbox_diag(pos: np.ndarray) -> float:
     return float(np.linalg.norm(p.max(axis=1) - p.min(axis=1)))
 
 
-def compare(pos_ref, nrm_ref, kappa_ref, pos, nrm, diag: float, kappa_max: float):
+def compare(pos_ref, nrm_ref, kappa_ref, pos, nrm, diag: float, kappa_max: float, kappa_wc: float = 10.0):
     """Parity figures of a result against the oracle on the same vertices:
-    position error relative to the bounding-box diagonal (all vertices),
-    normal error scaled by max(1, kappa) on vertices with kappa <= kappa_max,
-    and the count of masked vertices."""
+    position error relative to the bounding-box diagonal (all vertices);
+    normal error scaled by max(1, kappa) on vertices with kappa <= kappa_max
+    (nrm_scaled); the plain normal error on the same vertices (nrm_abs) and
+    on the well-conditioned ones, kappa <= kappa_wc (nrm_abs_wc, with their
+    fraction wc_frac); and the count of masked vertices (kappa > kappa_max)."""
     dpos = np.abs(np.asarray(pos, np.float64) - pos_ref).max() / diag
     out = {"pos_rel": float(dpos)}
     if nrm is not None:
         mask = np.isfinite(kappa_ref) & (kappa_ref <= kappa_max)
+        wc = mask & (kappa_ref <= kappa_wc)
         dn = np.linalg.norm(np.asarray(nrm, np.float64) - nrm_ref, axis=0)
         scaled = dn / np.maximum(1.0, np.where(mask, kappa_ref, 1.0))
         out["nrm_scaled"] = float(scaled[mask].max()) if mask.any() else 0.0
         out["nrm_abs"] = float(dn[mask].max()) if mask.any() else 0.0
+        out["nrm_abs_wc"] = float(dn[wc].max()) if wc.any() else 0.0
+        out["wc_frac"] = float(wc.mean())
         out["masked"] = int((~mask).sum())
     return out

@@ -20,10 +20,11 @@ CFLAGS = ["-O2", "-std=gnu99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"
           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 
-def build(extra_flags=None, out=LIB, quiet=True) -> str:
-    """Compile the oracle; returns the path of the shared library."""
+def build(extra_flags=None, out=LIB, quiet=True, src=SRC) -> str:
+    """Compile the oracle (or another copy of its source, ``src``); returns
+    the path of the shared library."""
     tmp = out + ".tmp"
-    cmd = ["gcc", *CFLAGS, *(extra_flags or []), SRC, "-o", tmp, "-lm"]
+    cmd = ["gcc", *CFLAGS, *(extra_flags or []), src, "-o", tmp, "-lm"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + " ".join(cmd) + "\n" + res.stderr)

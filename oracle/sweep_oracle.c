@@ -34,14 +34,6 @@
 
 #define OR_MAXP 7
 
-/* Planted-mistake switch for the pin tests (tests/test_oracle_mutants.py):
- * built with -DOR_MUTANT=k the oracle contains deliberate mistake k, and the
- * pins must catch it.  The default build (OR_MUTANT = 0) contains none. */
-#ifndef OR_MUTANT
-#define OR_MUTANT 0
-#endif
-#define MUT(k) (OR_MUTANT == (k))
-
 typedef struct {
     int n;                 /* control points; for a closed curve the m distinct ones */
     int p;                 /* degree, 1..7 */
@@ -75,7 +67,7 @@ void or_knots(int n, int p, int closed, const double *user, double *U)
     for (int k = 0; k < nk; ++k) {
         if (k <= p) U[k] = 0.0;
         else if (k >= n) U[k] = 1.0;
-        else U[k] = (double)(k - p) / (double)(n - p + (MUT(12) ? 1 : 0));
+        else U[k] = (double)(k - p) / (double)(n - p);
     }
 }
 
@@ -89,7 +81,7 @@ double or_param(int n, int p, int closed, const double *U, int i, int ns)
     if (closed) return (double)p + (double)((long long)n * (long long)i) / (double)ns;
     double a = U[p], b = U[n];
     if (i == ns - 1) return b;
-    double f = (double)i / (double)(MUT(3) ? ns : ns - 1);
+    double f = (double)i / (double)(ns - 1);
     return a + (b - a) * f;
 }
 
@@ -123,13 +115,13 @@ void or_basis(const double *U, int p, int span, double u, int nd, double *out)
             double d2 = U[k + q + 1] - U[k + 1];
             double v = 0.0;
             if (d1 != 0.0) v += (u - U[k]) / d1 * T[0][q - 1][j];
-            if (d2 != 0.0) v += (MUT(1) ? (u - U[k + 1]) : (U[k + q + 1] - u)) / d2 * T[0][q - 1][j + 1];
+            if (d2 != 0.0) v += (U[k + q + 1] - u) / d2 * T[0][q - 1][j + 1];
             T[0][q][j] = v;
             for (int d = 1; d <= nd; ++d) {
                 double w = 0.0;
                 if (d1 != 0.0) w += T[d - 1][q - 1][j] / d1;
                 if (d2 != 0.0) w -= T[d - 1][q - 1][j + 1] / d2;
-                T[d][q][j] = MUT(2) ? w : (double)q * w;
+                T[d][q][j] = (double)q * w;
             }
         }
         for (int d = 0; d <= nd; ++d) T[d][q][p + 1] = 0.0;
@@ -142,7 +134,7 @@ void or_basis(const double *U, int p, int span, double u, int nd, double *out)
 
 static const double *ctrl_pt(const or_curve *c, int k)
 {
-    return c->ctrl + 3 * (size_t)(c->closed ? (MUT(4) ? k + 1 : k) % c->n : k);
+    return c->ctrl + 3 * (size_t)(c->closed ? k % c->n : k);
 }
 
 static double weight_of(const or_curve *c, int k)
@@ -178,7 +170,7 @@ static void rational_eval(const or_curve *c, const double *B, int span, int nd, 
         for (int e = 0; e < 3; ++e) {
             double v = A[d][e];
             for (int i = 1; i <= d; ++i)
-                v -= (MUT(10) && d == 2 && i == 1 ? 1.0 : binom[d][i]) * W[i] * out[3 * (d - i) + e];
+                v -= binom[d][i] * W[i] * out[3 * (d - i) + e];
             out[3 * d + e] = v / W[0];
         }
 }
@@ -265,7 +257,7 @@ static int axis_rule(const double *v)
 {
     int a = 0;
     for (int k = 1; k < 3; ++k)
-        if (MUT(7) ? fabs(v[k]) > fabs(v[a]) : fabs(v[k]) < fabs(v[a])) a = k;
+        if (fabs(v[k]) < fabs(v[a])) a = k;
     return a;
 }
 
@@ -367,8 +359,6 @@ int or_frame(int nu, const double *x, const double *d1, const double *fallback_t
         const double *tn = rn + 6;
         double v1[3] = {x[3 * (i + 1)] - x[3 * i], x[3 * (i + 1) + 1] - x[3 * i + 1],
                         x[3 * (i + 1) + 2] - x[3 * i + 2]};
-        if (MUT(6))
-            for (int e = 0; e < 3; ++e) v1[e] = x[3 * (i + 1) + e] + x[3 * i + e];
         double c1 = dot3(v1, v1);
         if (c1 == 0.0) { memcpy(v1, ti, sizeof v1); c1 = dot3(v1, v1); }
         double rL[3], tL[3];
@@ -381,13 +371,11 @@ int or_frame(int nu, const double *x, const double *d1, const double *fallback_t
             rodrigues_apply(ti, tn, ri, r1);
             ++nfallback;
         } else {
-            if (MUT(5)) memcpy(r1, rL, sizeof r1);
-            else reflect(v2, c2, rL, r1);
+            reflect(v2, c2, rL, r1);
         }
         if (reorth) project_out(r1, tn, rn);
         else memcpy(rn, r1, sizeof r1);
-        if (MUT(13)) cross3(rn, tn, sn);
-        else cross3(tn, rn, sn);
+        cross3(tn, rn, sn);
     }
     return nfallback;
 }
@@ -434,14 +422,13 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
         for (int j = 0; j < nv; ++j) {
             const double *Sj = S + 3 * j, *dSj = dS + 3 * j;
             double X[3], Xu[3], Xv[3], cr[3];
-            double alpha = L - (MUT(8) ? -Sj[0] : Sj[0]) * a - Sj[1] * b;
+            double alpha = L - Sj[0] * a - Sj[1] * b;
             for (int e = 0; e < 3; ++e) {
                 X[e] = xi[e] + Sj[0] * r[e] + Sj[1] * s[e] + Sj[2] * t[e];
                 Xv[e] = dSj[0] * r[e] + dSj[1] * s[e] + dSj[2] * t[e];
-                Xu[e] = alpha * t[e] + (MUT(11) ? 0.0 : Sj[2] * tp[e]);
+                Xu[e] = alpha * t[e] + Sj[2] * tp[e];
             }
-            if (MUT(9)) cross3(Xu, Xv, cr);
-            else cross3(Xv, Xu, cr);
+            cross3(Xv, Xu, cr);
             double nn = norm3(cr);
             size_t v = (size_t)i * (size_t)nv + (size_t)j;
             if (pos)
@@ -457,7 +444,7 @@ void or_surface_rows(int nu, int nv, int row0, int row1,
             if (w)
                 for (int e = 0; e < 3; ++e) acc += w[e * N + v] * X[e];
             if (g && ok)
-                for (int e = 0; e < 3; ++e) acc += g[e * N + v] * (MUT(20) ? cr[e] : cr[e] / nn);
+                for (int e = 0; e < 3; ++e) acc += g[e * N + v] * (cr[e] / nn);
         }
         if (wsum) wsum[i - row0] = acc;
     }
@@ -513,7 +500,7 @@ static double density(const or_curve *c, const double *U, double u, double lam)
     if (lam == 0.0) return sp;
     double cr[3];
     cross3(o + 3, o + 6, cr);
-    return sp + (sp > 0.0 ? lam * norm3(cr) / (MUT(21) ? sp * sp * sp : sp * sp) : 0.0);
+    return sp + (sp > 0.0 ? lam * norm3(cr) / (sp * sp) : 0.0);
 }
 
 /* Integral of the density over [a, b] by the 8-point Gauss-Legendre rule. */
@@ -566,7 +553,7 @@ double or_monitor_params(const or_curve *c, int ns, double lam, double *u_out)
     for (int i = 0; i < ns; ++i) {
         if (i == 0) { u_out[i] = U[c->p]; continue; }
         if (i == ns - 1) { u_out[i] = U[nb]; continue; }
-        double target = ((double)i / (double)(MUT(18) ? ns : ns - 1)) * total;
+        double target = ((double)i / (double)(ns - 1)) * total;
         int q = 0;
         for (int r = 0; r < npc; ++r)
             if (hi[r] > lo[r] && cum[r] <= target) q = r;
@@ -635,7 +622,7 @@ long long or_triangles(int nu, int nv, int closed_v, int *tri)
             int a = i * nv + j, b = i * nv + j1, c = (i + 1) * nv + j, d = (i + 1) * nv + j1;
             if (tri) {
                 int *q = tri + 3 * t;
-                q[0] = a; q[1] = MUT(19) ? c : b; q[2] = MUT(19) ? b : c;
+                q[0] = a; q[1] = b; q[2] = c;
                 q[3] = c; q[4] = b; q[5] = d;
             }
             t += 2;
@@ -674,7 +661,7 @@ void or_frenet(int nu, const double *d1, const double *d2, const double *d3, dou
             double k[3];
             cross3(C1, C2, k);
             double kk = dot3(k, k);
-            if (kk > 0.0) omega = norm3(C1) * (dot3(k, C3) / kk) * (MUT(17) ? 2.0 : 1.0);
+            if (kk > 0.0) omega = norm3(C1) * (dot3(k, C3) / kk);
         } else {
             double e_a[3] = {0.0, 0.0, 0.0};
             e_a[axis_rule(t)] = 1.0;
@@ -726,7 +713,7 @@ void or_surface_rows_ex(int nu, int nv, int row0, int row1,
         double om = omega ? omega[i] : 0.0;
         double rt = dot3(r, tp), st = dot3(s, tp);
         for (int e = 0; e < 3; ++e) {
-            rp[e] = -rt * t[e] + (MUT(15) ? -om : om) * s[e];
+            rp[e] = -rt * t[e] + om * s[e];
             sp[e] = -st * t[e] - om * r[e];
         }
         double sg = 1.0, th = 0.0, dsg = 0.0, dth = 0.0;
@@ -739,7 +726,7 @@ void or_surface_rows_ex(int nu, int nv, int row0, int row1,
             double pr = sg * u0, ps = sg * u1, pt = sg * Sj[2];
             /* d/du of sigma Rot(theta) S = sigma' Rot S + sigma theta' Rot J S, J = [[0,-1],[1,0]] */
             double dpr = dsg * u0 - sg * dth * u1;
-            double dps = dsg * u1 + (MUT(16) ? -sg : sg) * dth * u0;
+            double dps = dsg * u1 + sg * dth * u0;
             double dpt = dsg * Sj[2];
             double qr = sg * (c * dSj[0] - sn * dSj[1]), qs = sg * (sn * dSj[0] + c * dSj[1]), qt = sg * dSj[2];
             double X[3], Xu[3], Xv[3], cr[3];
@@ -934,7 +921,7 @@ void or_fd_grad(const or_curve *path, const or_curve *prof, int nu, int nv,
         double Lp = onP ? or_loss(&c, prof, nu, nv, n0, w, g) : or_loss(path, &c, nu, nv, n0, w, g);
         cp[k] = th - h;
         double Lm = onP ? or_loss(&c, prof, nu, nv, n0, w, g) : or_loss(path, &c, nu, nv, n0, w, g);
-        double g = (Lp - Lm) / (MUT(14) ? h : 2.0 * h);
+        double g = (Lp - Lm) / (2.0 * h);
         if (onP) gP[k] = g; else gQ[k] = g;
         free(cp);
     }

@@ -11,6 +11,7 @@ namespace sweep {
 sweep_status fail(sweep_status st, const char* fmt, ...);
 sweep_status hip_fail(hipError_t e, const char* where);
 sweep_status check_curve_meta(int n, int p, int closed, const double* knots, const char* what, bool is_path);
+sweep_status check_curve(const sweep_curve* c, const char* what, bool is_path);
 sweep_status check_options(const sweep_options* o);
 sweep_status check_grid(int n_u, int n_v);
 int nbasis(int n, int p, int closed);

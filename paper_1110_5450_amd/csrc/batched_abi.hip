@@ -211,8 +211,38 @@ struct Plan {
     int n_vchunks = 0;
     NodeArgs a{};                  // values shared by all nodes
     std::vector<std::unique_ptr<GNode>> nodes;
+    // Completion markers of the plan's launches, one event per stream the
+    // plan was launched on, recorded after every launch (graph replay or
+    // adjoint kernels).  They are waited on before the graph's parameters
+    // change and before the plan is destroyed (evicted or released), so
+    // that no launch still in flight reads a kernel-argument block, a
+    // descriptor array or a graph executable that is being replaced.
+    std::vector<std::pair<hipStream_t, hipEvent_t>> done;
+    void wait_launches()
+    {
+        for (auto& d : done) hipEventSynchronize(d.second);
+    }
+    hipError_t mark_launched(hipStream_t s)
+    {
+        for (auto& d : done)
+            if (d.first == s) return hipEventRecord(d.second, s);
+        if (done.size() >= kMaxStreamsTracked) {
+            // more streams than tracked: retire the markers of the others
+            wait_launches();
+            for (auto& d : done) hipEventDestroy(d.second);
+            done.clear();
+        }
+        hipEvent_t e = nullptr;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        done.emplace_back(s, e);
+        return hipEventRecord(e, s);
+    }
+    static constexpr size_t kMaxStreamsTracked = 8;
     ~Plan()
     {
+        wait_launches();
+        for (auto& d : done) hipEventDestroy(d.second);
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         if (d_descs) hipFree(d_descs);
@@ -414,6 +444,9 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     A.pos = pos;
     A.nrm = nrm;
     if (std::memcmp(&A, &P->a, sizeof A) != 0) {
+        // a replay of this graph may still be in flight on some stream:
+        // let it finish before its node parameters are rewritten
+        P->wait_launches();
         P->a = A;
         for (auto& n : P->nodes) {
             const int* own = n->a.sweeps;
@@ -424,6 +457,7 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
         }
     }
     if ((e = hipGraphLaunch(P->exec, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "graph launch");
+    if ((e = P->mark_launched((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "launch marker");
     return SWEEP_OK;
 }
 
@@ -492,6 +526,12 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
     }
     hipStream_t sm = (hipStream_t)stream;
     char* ws = (char*)workspace;
+    // every exit after the first launch records the plan's completion marker
+    struct MarkOnExit {
+        Plan* P;
+        hipStream_t s;
+        ~MarkOnExit() { P->mark_launched(s); }
+    } marker{P, sm};
     const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64, nrm);
     {

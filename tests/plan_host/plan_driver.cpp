@@ -1,0 +1,229 @@
+// plan_driver.cpp -- drives the batched entry points (sweep_eval_batched,
+// sweep_backward_ex) of the plan code built against the CPU stand-in of the
+// HIP runtime.
+//
+//   plan_driver selftest   plants the hazards the stand-in must report (a
+//                          graph executable destroyed and memory freed while
+//                          a launch is in flight); prints the report.
+//   plan_driver plans      the four-sweep rational batch of degrees 2 to 4,
+//                          then more batch shapes than the plan cache holds
+//                          (so plans are evicted), launched on two streams
+//                          with no synchronisation between calls, output
+//                          buffers changing between calls (graph parameter
+//                          updates), adjoint calls with weight gradients in
+//                          between, and the first batch again after its plan
+//                          was evicted.  Prints the report; exit status 0
+//                          only without violations.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "../../include/sweep.h"
+#include "../../paper_1110_5450_amd/csrc/kernels.hpp"
+#include "stub_kernels.hpp"
+
+namespace {
+
+struct HostBatch {
+    std::vector<int32_t> path_n, path_deg, prof_n, prof_deg, prof_closed, n_u, n_v;
+    double* path_ctrl = nullptr;
+    double* prof_ctrl = nullptr;
+    double* path_w = nullptr;
+    double* prof_w = nullptr;
+    sweep_batch b{};
+};
+
+void* dev_alloc(size_t bytes)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        std::fprintf(stderr, "stub hipMalloc failed\n");
+        std::exit(2);
+    }
+    std::memset(p, 0, bytes);
+    return p;
+}
+
+void make_batch(HostBatch& h, const std::vector<int>& deg, const std::vector<int>& nu, const std::vector<int>& nv,
+                bool rational, std::mt19937& rng)
+{
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    const int n = (int)deg.size();
+    long long np = 0, nq = 0;
+    for (int k = 0; k < n; ++k) {
+        h.path_n.push_back(deg[k] + 5 + k % 3);
+        h.path_deg.push_back(deg[k]);
+        h.prof_n.push_back(6 + k % 4);
+        h.prof_deg.push_back(2 + k % 2);
+        h.prof_closed.push_back(1);
+        h.n_u.push_back(nu[k]);
+        h.n_v.push_back(nv[k]);
+        np += h.path_n.back();
+        nq += h.prof_n.back();
+    }
+    h.path_ctrl = (double*)dev_alloc(sizeof(double) * 3 * np);
+    h.prof_ctrl = (double*)dev_alloc(sizeof(double) * 3 * nq);
+    for (long long i = 0; i < 3 * np; ++i) h.path_ctrl[i] = U(rng);
+    for (long long i = 0; i < 3 * nq; ++i) h.prof_ctrl[i] = U(rng);
+    if (rational) {
+        h.path_w = (double*)dev_alloc(sizeof(double) * np);
+        h.prof_w = (double*)dev_alloc(sizeof(double) * nq);
+        for (long long i = 0; i < np; ++i) h.path_w[i] = 1.0 + 0.5 * U(rng);
+        for (long long i = 0; i < nq; ++i) h.prof_w[i] = 1.0 + 0.5 * U(rng);
+    }
+    sweep_batch& b = h.b;
+    b.n_sweeps = n;
+    b.path_n = h.path_n.data();
+    b.path_degree = h.path_deg.data();
+    b.prof_n = h.prof_n.data();
+    b.prof_degree = h.prof_deg.data();
+    b.prof_closed = h.prof_closed.data();
+    b.n_u = h.n_u.data();
+    b.n_v = h.n_v.data();
+    b.path_ctrl = h.path_ctrl;
+    b.prof_ctrl = h.prof_ctrl;
+    b.path_weights = h.path_w;
+    b.prof_weights = h.prof_w;
+}
+
+struct Buffers {
+    float* pos = nullptr;
+    float* nrm = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+int check(sweep_status st, const char* what)
+{
+    if (st != SWEEP_OK) {
+        std::fprintf(stderr, "%s failed: %d %s\n", what, st, sweep_last_error());
+        return 1;
+    }
+    return 0;
+}
+
+int selftest()
+{
+    hipStream_t s = (hipStream_t)0x1;
+    void* a = dev_alloc(4096);
+    void* b = dev_alloc(4096);
+    hipGraph_t g;
+    hipGraphCreate(&g, 0);
+    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024);
+    void *descs = a, *vch = a, *qc = a, *qw = nullptr, *kn = nullptr, *ptab = b;
+    void* params[6] = {&descs, &vch, &qc, &qw, &kn, &ptab};
+    hipKernelNodeParams prm{};
+    prm.func = const_cast<void*>(K.profile);
+    prm.gridDim = dim3(1);
+    prm.blockDim = dim3(256);
+    prm.kernelParams = params;
+    hipGraphNode_t node;
+    hipGraphAddKernelNode(&node, g, nullptr, 0, &prm);
+    hipGraphExec_t ex;
+    hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphLaunch(ex, s);
+    hipGraphExecKernelNodeSetParams(ex, node, &prm);   // in flight: reported
+    hipGraphExecDestroy(ex);                           // in flight: reported
+    hipFree(b);                                        // in use: reported
+    hipStreamSynchronize(s);
+    hipGraphDestroy(g);
+    hipFree(a);
+    return stub::report(true);
+}
+
+int plans()
+{
+    std::mt19937 rng(20261203);
+    hipStream_t streams[2] = {(hipStream_t)0x1, (hipStream_t)0x2};
+    sweep_options opt;
+    sweep_default_options(&opt);
+    int bad = 0;
+
+    // the four-sweep rational batch of degrees 2 to 4
+    HostBatch first;
+    make_batch(first, {3, 2, 3, 4}, {200, 999, 64, 1500}, {40, 17, 256, 9}, true, rng);
+    std::vector<HostBatch> shapes(40);
+    for (int i = 0; i < 40; ++i) {
+        std::vector<int> deg, nu, nv;
+        const int n = 1 + i % 5;
+        for (int k = 0; k < n; ++k) {
+            deg.push_back(1 + (i + k) % 7);
+            nu.push_back(16 + 37 * i + 101 * k);
+            nv.push_back(8 + (i * 13 + k * 7) % 200);
+        }
+        make_batch(shapes[i], deg, nu, nv, i % 2 == 0, rng);
+    }
+    std::vector<HostBatch*> order{&first};
+    for (auto& h : shapes) order.push_back(&h);
+    order.push_back(&first);
+
+    std::vector<Buffers> owned;
+    int call = 0;
+    for (HostBatch* h : order) {
+        for (int rep = 0; rep < 3; ++rep, ++call) {
+            const int64_t elems = sweep_batched_output_elems(&h->b);
+            Buffers B;
+            B.pos = (float*)dev_alloc(sizeof(float) * elems);
+            B.nrm = (float*)dev_alloc(sizeof(float) * elems);
+            B.ws_bytes = sweep_batched_workspace_size(&h->b, &opt);
+            B.ws = dev_alloc(B.ws_bytes);
+            owned.push_back(B);
+            bad += check(sweep_eval_batched(&h->b, &opt, B.pos, B.nrm, B.ws, B.ws_bytes, streams[call % 2]),
+                         "sweep_eval_batched");
+            if (call % 4 == 3) {
+                const size_t wb = sweep_backward_workspace_size(&h->b, &opt);
+                void* ws = dev_alloc(wb);
+                long long np = 0, nq = 0;
+                for (int k = 0; k < h->b.n_sweeps; ++k) { np += h->path_n[k]; nq += h->prof_n[k]; }
+                double* gP = (double*)dev_alloc(sizeof(double) * 3 * np);
+                double* gQ = (double*)dev_alloc(sizeof(double) * 3 * nq);
+                sweep_param_grads pg{};
+                if (h->path_w) {
+                    pg.path_weights = (double*)dev_alloc(sizeof(double) * np);
+                    pg.prof_weights = (double*)dev_alloc(sizeof(double) * nq);
+                }
+                bad += check(sweep_backward_ex(&h->b, &opt, B.pos, B.nrm, gP, gQ, h->path_w ? &pg : nullptr, ws, wb,
+                                               streams[call % 2]),
+                             "sweep_backward_ex");
+                // the caller's buffers stay allocated until the end (freeing
+                // them in flight would be the caller's mistake, not the plan's)
+                owned.push_back(Buffers{(float*)gP, (float*)gQ, ws, wb});
+                if (pg.path_weights) owned.push_back(Buffers{(float*)pg.path_weights, (float*)pg.prof_weights, nullptr, 0});
+            }
+        }
+    }
+    hipDeviceSynchronize();
+    sweep_release_caches();
+    for (auto& B : owned) {
+        hipFree(B.pos);
+        hipFree(B.nrm);
+        if (B.ws) hipFree(B.ws);
+    }
+    const int v = stub::report(true);
+    std::printf("calls %d, failed calls %d\n", call, bad);
+    return v + bad;
+}
+
+void table()
+{
+    for (const stub::KernelSig* k : stub::all_kernels()) std::printf("%s %zu\n", k->name, k->args.size());
+}
+
+}  // namespace
+
+int main(int argc, char** argv)
+{
+    const char* mode = argc > 1 ? argv[1] : "plans";
+    if (!std::strcmp(mode, "selftest")) {
+        selftest();
+        return 0;
+    }
+    if (!std::strcmp(mode, "table")) {
+        table();
+        return 0;
+    }
+    return plans() == 0 ? 0 : 1;
+}

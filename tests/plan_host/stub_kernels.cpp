@@ -1,0 +1,85 @@
+// stub_kernels.cpp -- the kernel table of the CPU stand-in (parameter lists
+// of the batched and adjoint kernels, in the order the kernels declare them)
+// and stand-ins of the plan code's kernel-table and fast-division helpers.
+#include <hip/hip_runtime.h>
+
+#include <map>
+
+#include "../../paper_1110_5450_amd/csrc/kernels.hpp"
+#include "stub_kernels.hpp"
+
+namespace stub {
+namespace {
+
+constexpr ArgSig P{sizeof(void*), kDevicePtr};
+constexpr ArgSig N{sizeof(void*), kNullablePtr};
+constexpr ArgSig I{sizeof(int), kValue};
+constexpr ArgSig N0{sizeof(sweep::InitialNormal), kValue};
+
+const KernelSig kProfile{"kb_profile", {P, P, P, N, N, P}};
+const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P}};
+const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
+const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
+const KernelSig kAdjoint{"kbw_adjoint", {P, P, P, N, N, N, N0, P, P, P, P, P, P, P, P, P, P, P, P, I, N}};
+const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, P, I, I, I}};
+const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
+
+// distinct addresses standing in for kernel entry points
+char g_profile, g_frame[8], g_surface, g_reduce, g_adjoint, g_rec_path, g_rec_prof, g_params;
+
+const std::map<const void*, const KernelSig*>& table()
+{
+    static const std::map<const void*, const KernelSig*> t = [] {
+        std::map<const void*, const KernelSig*> m;
+        m[&g_profile] = &kProfile;
+        for (int p = 1; p < 8; ++p) m[&g_frame[p]] = &kFrame;
+        m[&g_surface] = &kSurface;
+        m[&g_reduce] = &kReduce;
+        m[&g_adjoint] = &kAdjoint;
+        m[&g_rec_path] = &kParamRec;
+        m[&g_rec_prof] = &kParamRec;
+        m[&g_params] = &kParams;
+        return m;
+    }();
+    return t;
+}
+
+}  // namespace
+
+const KernelSig* lookup(const void* fn)
+{
+    auto it = table().find(fn);
+    return it == table().end() ? nullptr : it->second;
+}
+
+std::vector<const KernelSig*> all_kernels()
+{
+    return {&kProfile, &kFrame, &kSurface, &kReduce, &kAdjoint, &kParamRec, &kParams};
+}
+
+}  // namespace stub
+
+namespace sweep {
+
+BatchedKernels batched_kernels(bool, bool, bool, bool, int)
+{
+    BatchedKernels k{};
+    k.profile = &stub::g_profile;
+    k.frame[0] = nullptr;
+    for (int p = 1; p < 8; ++p) k.frame[p] = &stub::g_frame[p];
+    k.surface = &stub::g_surface;
+    return k;
+}
+
+BackwardKernels backward_kernels(bool, bool)
+{
+    return BackwardKernels{&stub::g_reduce, &stub::g_adjoint, &stub::g_params, &stub::g_rec_path, &stub::g_rec_prof};
+}
+
+void fastdiv_constants(int d, unsigned long long* m, int* shift)
+{
+    *m = (unsigned long long)d;
+    *shift = 0;
+}
+
+}  // namespace sweep

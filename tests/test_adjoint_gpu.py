@@ -87,3 +87,36 @@ def test_autograd_function_and_gradcheck():
     # normals are differentiable too (their gradients: test_adjoint_normals_gpu)
     pos, nrm = dsweep(Pt, Qt, b, out_dtype=torch.float64)
     assert nrm.requires_grad
+
+
+def test_two_forwards_on_one_batch_keep_their_own_control_points():
+    """One Batch, two differentiable calls with different control points and
+    one summed loss: each call's gradient is its own (against the oracle's
+    finite differences), the Batch itself is left unchanged, and an in-place
+    change of a control-point tensor before backward raises."""
+    rng = np.random.default_rng(31)
+    P1, P2 = synth.random_walk(rng, 8), synth.random_walk(rng, 8)
+    Q1, Q2 = synth.perturbed_circle(rng, 6), synth.perturbed_circle(rng, 6)
+    spec = synth.SweepSpec(synth.CurveSpec(P1, 3), synth.CurveSpec(Q1, 3, True), 40, 12)
+    b = api.Batch.from_specs([spec])
+    own_P, own_Q = b.path_ctrl.clone(), b.prof_ctrl.clone()
+    t = [torch.as_tensor(a).cuda().requires_grad_(True) for a in (P1, Q1, P2, Q2)]
+    w1, w2 = (rng.standard_normal((3, 40, 12)) for _ in range(2))
+    pos1, _ = dsweep(t[0], t[1], b, out_dtype=torch.float64)
+    pos2, _ = dsweep(t[2], t[3], b, out_dtype=torch.float64)
+    loss = (pos1 * b.pack([w1], torch.float64)).sum() + (pos2 * b.pack([w2], torch.float64)).sum()
+    loss.backward()
+    assert torch.equal(b.path_ctrl, own_P) and torch.equal(b.prof_ctrl, own_Q)
+    for (P, Q, w), gp, gq in (((P1, Q1, w1), t[0].grad, t[1].grad), ((P2, Q2, w2), t[2].grad, t[3].grad)):
+        s = synth.SweepSpec(synth.CurveSpec(P, 3), synth.CurveSpec(Q, 3, True), 40, 12)
+        fP, fQ = oracle.fd_grad(s.path, s.profile, 40, 12, w)
+        eP, eQ = _rel(gp.cpu().numpy(), fP), _rel(gq.cpu().numpy(), fQ)
+        say(f"    own gradient: path rel {eP:.2e} prof rel {eQ:.2e}")
+        assert eP <= 1e-7 and eQ <= 1e-7
+    Pt = torch.as_tensor(P1).cuda().requires_grad_(True)
+    leaf = Pt * 1.0
+    pos, _ = dsweep(leaf, t[1].detach(), b, out_dtype=torch.float64)
+    with torch.no_grad():
+        leaf.add_(1.0)
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        pos.sum().backward()

@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on seeded
 inputs: the plain FP64 sweep, FP32 output, every degree, user knots, open and
 non-planar profiles, ragged grids spanning several frame chunks, every fixed
-surface configuration, degenerate tangents, and the full-size large sweep
-and precision-study grids on sampled rows."""
+surface configuration, degenerate tangents, the full-size large sweep and
+precision-study grids (every vertex, streamed in row chunks), and the largest
+accepted grid on sampled rows."""
 
 import numpy as np
 import pytest
@@ -10,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import TOL, check_full, gpu_sweep, parity, say
+from tests.gpu_util import TOL, check_full, dev_ctrl, gpu_sweep, parity, say, stream_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -104,36 +105,28 @@ def test_deterministic_and_stream():
     assert torch.equal(a, b) and torch.equal(na, nb)
 
 
-def _sampled(spec, rows, out_dtype, frame_dtype=torch.float64, tol=None):
-    say(f"[case] sampled n_u={spec.n_u} n_v={spec.n_v} rows={len(rows)} out={out_dtype} frame={frame_dtype}")
-    pos, nrm = gpu_sweep(spec, out_dtype, frame_dtype)
+def test_large_sweep_full_grid():
+    """Every vertex of the 65,536 x 1,024 sweep (FP32 output, FP64 frame)
+    against the oracle, streamed in row chunks."""
+    spec = synth.c2()
+    say(f"[case] full grid n_u={spec.n_u} n_v={spec.n_v} out=float32")
+    pos, nrm = gpu_sweep(spec, torch.float32)
     torch.cuda.synchronize()
-    idx = torch.as_tensor(rows, device=pos.device)
-    gp = pos.index_select(1, idx).cpu().numpy()
-    gn = nrm.index_select(1, idx).cpu().numpy()
-    # bounding box of the whole surface: the path samples' box widened by the profile radius
-    x, _, _, _ = oracle.path_samples(spec.path, spec.n_u)
-    rp, rn, rk, R = oracle.sweep_rows(spec.path, spec.profile, spec.n_u, spec.n_v, rows)
-    diag = float(np.linalg.norm(x.max(0) - x.min(0)))
-    del pos, nrm
-    torch.cuda.empty_cache()
-    ok, r = parity(rp, rn, rk, gp, gn, TOL[out_dtype] if tol is None else tol, diag=diag)
+    ok, r = stream_parity(spec, pos, nrm, TOL[torch.float32])
     say("   ", r)
     assert ok, r
 
 
-def test_large_sweep_full_size_sampled_rows():
-    spec = synth.c2()
-    rows = np.unique(np.concatenate([[0, 1, 1023, 1024, 1025, 4095, 4096, spec.n_u - 2, spec.n_u - 1],
-                                     rng.integers(0, spec.n_u, 24)]))
-    _sampled(spec, rows, torch.float32)
-
-
-def test_precision_study_grid_sampled_rows():
+@pytest.mark.parametrize("frame_dtype,tol", [(torch.float64, 1e-5), (torch.float32, 1e-3)])
+def test_precision_study_full_grid(frame_dtype, tol):
+    """Every vertex of the 1,048,576 x 32 grid, FP64 and FP32 frame scans."""
     spec = synth.c3()
-    rows = np.unique(np.concatenate([[0, 1, spec.n_u // 2, spec.n_u - 1], rng.integers(0, spec.n_u, 24)]))
-    _sampled(spec, rows, torch.float32)
-    _sampled(spec, rows, torch.float32, frame_dtype=torch.float32, tol=1e-3)
+    say(f"[case] full grid n_u={spec.n_u} n_v={spec.n_v} frame={frame_dtype}")
+    pos, nrm = gpu_sweep(spec, torch.float32, frame_dtype)
+    torch.cuda.synchronize()
+    ok, r = stream_parity(spec, pos, nrm, tol, chunk_rows=65536)
+    say("   ", r)
+    assert ok, r
 
 
 @pytest.mark.parametrize("tile_config", [-1, 14])
@@ -191,3 +184,61 @@ def test_frames_match_oracle(name, n_u):
     drift = np.abs(G - np.eye(3)).max()
     say(f"    x {dx:.2e}  frame {dR:.2e} (bound {8 * n_u * eps:.1e})  a,b {dab:.2e}  orthonormality {drift:.2e}")
     assert dx <= 1e-14 and dR <= 8 * n_u * eps and dab <= 1e-10 and drift <= 1e-14
+
+
+def _stationary_path():
+    # degree 1 through 12 points, segments 3 and 10 of zero length: with
+    # 70,000 u-samples (274 frame chunks of 256) the stationary samples
+    # cover chunks 75-99 and 249-273, so chunks whose first sample has
+    # C' = 0 lie below and above chunk 256; the path ends stationary
+    rng = np.random.default_rng(9)
+    P = synth.random_walk(rng, 12)
+    P[4] = P[3]
+    P[11] = P[10]
+    return P
+
+
+def test_stationary_runs_beyond_256_chunks():
+    """More than 256 frame chunks take the chunk-carry route; its
+    degenerate-start chunks are formed in the carry kernel."""
+    Q = synth.perturbed_circle(rng, 7)
+    spec = synth.SweepSpec(synth.CurveSpec(_stationary_path(), 1), synth.CurveSpec(Q, 3, True), 70000, 8)
+    check_full(spec, out_dtype=torch.float64)
+
+
+def test_law_sweep_with_zero_speed_chunk_starts():
+    """A sweep law takes the chunk-carry route at any length; stationary
+    chunk starts below 256 chunks."""
+    from paper_1110_5450_amd import api
+    Q = synth.perturbed_circle(rng, 7)
+    spec = synth.SweepSpec(synth.CurveSpec(_stationary_path(), 1), synth.CurveSpec(Q, 3, True), 30000, 8)
+    law = synth.CurveSpec(np.array([[1.0, 0.0, 0.0], [1.3, 0.8, 0.0], [0.9, -0.4, 0.0], [1.1, 1.0, 0.0]]), 2)
+    say(f"[case] law + stationary chunk starts n_u={spec.n_u}")
+    ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, spec.n_v, law=law)
+    pos, nrm = gpu_sweep(spec, torch.float64, law=api.Law(dev_ctrl(law.ctrl), law.degree, None))
+    torch.cuda.synchronize()
+    ok, r = parity(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(), TOL[torch.float64])
+    say("   ", r)
+    assert ok, r
+
+
+@pytest.mark.parametrize("n_u", [5000, 60000])
+def test_fused_and_carry_frame_routes_agree(n_u):
+    """Up to 256 chunks the plain sweep forms its frame in one launch (each
+    block forms its entry normal from the chunk products below it); with a
+    sweep law the same frame goes through the chunk-carry kernel.  An
+    identity law (scale 1, twist 0) leaves the positions unchanged, so the
+    two routes agree to rounding on the same input."""
+    from paper_1110_5450_amd import api
+    Q = synth.perturbed_circle(rng, 9)
+    P = _stationary_path()
+    spec = synth.SweepSpec(synth.CurveSpec(P, 1), synth.CurveSpec(Q, 3, True), n_u, 16)
+    ident = api.Law(dev_ctrl(np.array([[1.0, 0.0, 0.0], [1.0, 0.0, 0.0]])), 1, None)
+    say(f"[case] fused vs carry route n_u={n_u}")
+    a, _ = gpu_sweep(spec, torch.float64)
+    b, _ = gpu_sweep(spec, torch.float64, law=ident)
+    torch.cuda.synchronize()
+    diag = oracle.bbox_diag(a.cpu().numpy())
+    d = (a - b).abs().max().item() / diag
+    say(f"    max |dX| / diag = {d:.2e}")
+    assert d <= 1e-13
