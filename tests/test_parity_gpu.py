@@ -200,10 +200,13 @@ def _stationary_path():
 
 def test_stationary_runs_beyond_256_chunks():
     """More than 256 frame chunks take the chunk-carry route; its
-    degenerate-start chunks are formed in the carry kernel."""
+    degenerate-start chunks are formed in the carry kernel.  The oracle
+    multiplies the 70,000 step rotations in sequence, the GPU in a tree, so
+    the frames differ by rounding that grows with the scan length: the FP64
+    bound is 8 n eps (about 1.2e-10 here) rather than 1e-12."""
     Q = synth.perturbed_circle(rng, 7)
     spec = synth.SweepSpec(synth.CurveSpec(_stationary_path(), 1), synth.CurveSpec(Q, 3, True), 70000, 8)
-    check_full(spec, out_dtype=torch.float64)
+    check_full(spec, out_dtype=torch.float64, tol=8 * spec.n_u * np.finfo(float).eps)
 
 
 def test_law_sweep_with_zero_speed_chunk_starts():
@@ -217,7 +220,10 @@ def test_law_sweep_with_zero_speed_chunk_starts():
     ref, _ = oracle.sweep_ex(spec.path, spec.profile, spec.n_u, spec.n_v, law=law)
     pos, nrm = gpu_sweep(spec, torch.float64, law=api.Law(dev_ctrl(law.ctrl), law.degree, None))
     torch.cuda.synchronize()
-    ok, r = parity(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(), TOL[torch.float64])
+    # sequential (oracle) against tree-ordered (GPU) rotation products:
+    # rounding bound 8 n eps, as in test_stationary_runs_beyond_256_chunks
+    tol = max(TOL[torch.float64], 8 * spec.n_u * np.finfo(float).eps)
+    ok, r = parity(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(), tol)
     say("   ", r)
     assert ok, r
 
