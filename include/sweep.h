@@ -210,6 +210,27 @@ size_t sweep_eval_workspace_size(const sweep_curve *path, const sweep_curve *pro
                                  int32_t n_u, int32_t n_v, const sweep_options *opt);
 
 /*
+ * sweep_eval without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  The workspace is a static device array
+ * of SWEEP_NOALLOC_WORKSPACE_BYTES bytes that the library's code object holds
+ * on every GPU it runs on, from load until the process ends; the call itself
+ * allocates and frees nothing.  Arguments, output layout and results are
+ * those of sweep_eval.  A sweep whose sweep_eval_workspace_size() exceeds
+ * the array is rejected with SWEEP_ERR_WORKSPACE before anything is
+ * enqueued (at FP32 output and FP64 frame: above about 490,000 u-samples).
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (nothing in it needs to start at zero): calls on one
+ * stream are ordered, but calls that can overlap on one GPU (different
+ * streams, or threads without ordering between them) race on the array and
+ * give undefined results.
+ */
+#define SWEEP_NOALLOC_WORKSPACE_BYTES (64u << 20)
+sweep_status sweep_eval_noalloc(const sweep_curve *path, const sweep_curve *profile,
+                                int32_t n_u, int32_t n_v, const sweep_options *opt,
+                                void *pos, void *nrm, void *stream);
+
+/*
  * The moving frame alone: for each u-sample i of the path, write the 16-value
  * row record (x_i[3], r_i[3], s_i[3], t_i[3], |C'(u_i)|, a_i, b_i, 0) with
  * a = r.C''/|C'|, b = s.C''/|C'|, in the output precision, to frames (DEVICE,

@@ -76,6 +76,9 @@ def lib():
         L.sweep_eval.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32, C.c_int32,
                                  C.POINTER(SweepOptions), vp, vp, vp, sz, vp]
         L.sweep_eval.restype = C.c_int32
+        L.sweep_eval_noalloc.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32, C.c_int32,
+                                         C.POINTER(SweepOptions), vp, vp, vp]
+        L.sweep_eval_noalloc.restype = C.c_int32
         L.sweep_eval_workspace_size.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32,
                                                 C.c_int32, C.POINTER(SweepOptions)]
         L.sweep_eval_workspace_size.restype = sz
@@ -144,6 +147,11 @@ def sweep_eval(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: S
                pos: int, nrm: int, workspace: int, ws_bytes: int, stream: int) -> int:
     return lib().sweep_eval(C.byref(path), C.byref(profile), n_u, n_v, C.byref(opt), pos, nrm, workspace,
                             ws_bytes, stream)
+
+
+def sweep_eval_noalloc(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: SweepOptions,
+                       pos: int, nrm: int, stream: int) -> int:
+    return lib().sweep_eval_noalloc(C.byref(path), C.byref(profile), n_u, n_v, C.byref(opt), pos, nrm, stream)
 
 
 def sweep_eval_workspace_size(path: SweepCurve, profile: SweepCurve, n_u: int, n_v: int, opt: SweepOptions) -> int:
