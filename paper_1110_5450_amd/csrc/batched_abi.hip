@@ -207,6 +207,7 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     int* d_sweeps[8] = {};         // sweeps by path degree, longest n_u first
     int n_deg[8] = {};
+    int n_long[8] = {};            // leading sweeps of d_sweeps[p] longer than one frame chunk
     int2* d_vchunks = nullptr;     // (sweep, chunk) of every profile chunk
     int n_vchunks = 0;
     NodeArgs a{};                  // values shared by all nodes
@@ -307,6 +308,7 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         return hip_fail(e, "plan upload");
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
         P->n_deg[p] = (int)sweeps[p].size();
+        for (int k : sweeps[p]) P->n_long[p] += b->n_u[k] > kBlock * kMaxRun ? 1 : 0;
         if (!sweeps[p].empty() &&
             (e = upload((void**)&P->d_sweeps[p], sweeps[p].data(), sizeof(int) * sweeps[p].size())) != hipSuccess)
             return hip_fail(e, "plan upload");
@@ -327,13 +329,14 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
     A.reorth = o->reorthonormalize;
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
+    // frame nodes: sweeps [first, first + grid) of the degree's list
     auto add = [&](NodeKind kind, int deg, const void* fn, unsigned grid,
-                   const std::vector<hipGraphNode_t>& deps) -> hipError_t {
+                   const std::vector<hipGraphNode_t>& deps, int first = 0) -> hipError_t {
         std::unique_ptr<GNode> n(new GNode());
         n->kind = kind;
         n->deg = deg;
         std::memcpy(&n->a, &P->a, sizeof n->a);
-        if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg];
+        if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg] + first;
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
@@ -350,9 +353,15 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
     before_surface.push_back(P->nodes.back()->node);
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-        if (!P->n_deg[p]) continue;
-        if ((e = add(kFrame, p, K.frame[p], (unsigned)P->n_deg[p], {})) != hipSuccess) return hip_fail(e, "graph node");
-        before_surface.push_back(P->nodes.back()->node);
+        const int nl = P->n_long[p], ns = P->n_deg[p] - nl;
+        if (nl) {
+            if ((e = add(kFrame, p, K.frame_long[p], (unsigned)nl, {})) != hipSuccess) return hip_fail(e, "graph node");
+            before_surface.push_back(P->nodes.back()->node);
+        }
+        if (ns) {
+            if ((e = add(kFrame, p, K.frame[p], (unsigned)ns, {}, nl)) != hipSuccess) return hip_fail(e, "graph node");
+            before_surface.push_back(P->nodes.back()->node);
+        }
     }
     if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, before_surface)) != hipSuccess)
         return hip_fail(e, "graph node");
@@ -545,17 +554,21 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         n.a.reorth = 1;
         n.a.rows = ws + B.rows;
         n.a.ptab = ws + B.ptab;
-        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid) -> hipError_t {
+        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid, int first = 0) -> hipError_t {
             n.kind = kind;
-            n.a.sweeps = kind == kFrame ? P->d_sweeps[deg] : nullptr;
+            n.a.sweeps = kind == kFrame ? P->d_sweeps[deg] + first : nullptr;
             node_args(n);
             return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, 0, sm);
         };
         if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
-        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p)
-            if (P->n_deg[p] && (e = launch(kFrame, p, FK.frame[p], (unsigned)P->n_deg[p])) != hipSuccess)
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+            const int nl = P->n_long[p], ns = P->n_deg[p] - nl;
+            if (nl && (e = launch(kFrame, p, FK.frame_long[p], (unsigned)nl)) != hipSuccess)
                 return hip_fail(e, "backward frames");
+            if (ns && (e = launch(kFrame, p, FK.frame[p], (unsigned)ns, nl)) != hipSuccess)
+                return hip_fail(e, "backward frames");
+        }
     }
     {
         const BatchDesc* descs = P->d_descs;

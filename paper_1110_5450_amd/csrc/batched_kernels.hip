@@ -4,23 +4,22 @@
 // kb_profile  one block per (sweep, chunk of 256 v-samples): profile tables.
 // kb_frame    one block per sweep, one launch per path degree present (the
 //             degree is a template parameter, so the B-spline arrays stay in
-//             registers); sweeps are listed longest first.  The block walks
-//             its sweep's chunks of 256 u-samples in order: samples, step
-//             rotations, the block's exclusive product scan, row records,
-//             then the normal entering the next chunk (the chunk's total
-//             product applied to the normal entering it) and the last sample
-//             with C' != 0 are carried in registers.  Every sample is
-//             evaluated once and no cross-block carry is needed.
+//             registers); sweeps are listed longest first.  Each thread walks
+//             a run of K consecutive u-samples (K = 1 .. 16, so that a sweep
+//             of up to 4096 samples is one chunk of kBlock runs): the run
+//             products, the block's exclusive product scan, then the row
+//             records (frame_walk.hpp).  Longer sweeps walk their chunks in
+//             order, carrying the entering normal and the last resolved
+//             tangent in registers: no cross-block carry is needed.
 // kb_surface  one block per tile of 256*K (K = 1, 2, 4, 8) consecutive
 //             vertices of one sweep, rows staged in LDS, one vertex per lane
 //             per step, six plane stores.
 //
-// The per-sample and per-chunk steps call the same device functions as the
-// single-sweep kernels in the same order (FP contraction off): a sweep of at
-// most one chunk is bitwise identical to evaluating it alone; longer sweeps
-// differ only in how the chunk products are associated (sequential here, a
-// tree scan there), i.e. by rounding.
-#include "frame_common.hpp"
+// The frame steps are the single-sweep kernels' device functions in the same
+// order: a sweep of at most kBlock u-samples (one run per sample in both) is
+// bitwise identical to evaluating it alone; longer sweeps differ in how the
+// step rotations are grouped into runs and chunks, i.e. by rounding.
+#include "frame_walk.hpp"
 #include "surface_common.hpp"
 
 namespace sweep {
@@ -39,67 +38,6 @@ __device__ __forceinline__ DCurve prof_of(const BatchDesc& d, const double* prof
                   prof_w ? prof_w + d.prof_ctrl_off : nullptr};
 }
 
-struct ChunkLds {
-    double sx[3][kChunk + 1];
-    double sd[3][kChunk + 1];
-    double d3[3];
-    int ii[kWaves];
-};
-
-// This thread's step inputs for the chunk starting at `base`, its own C' and
-// C'', given the last sample before the chunk with C' != 0 (carry_lv, -1 if
-// none) and its C' (d_carry).  Returns in `last` / `d_last` the last sample
-// up to the chunk's end with C' != 0 and its C' (the carry for the next
-// chunk).  Contains barriers; called by every thread of the block.
-template <int P>
-__device__ StepInputs seq_chunk_inputs(const DCurve& path, int n_u, int base, int carry_lv, V3<double> d_carry,
-                                       V3<double> fb, ChunkLds& L, V3<double>& c1, V3<double>& c2, int& last,
-                                       V3<double>& d_last)
-{
-    const int i = base + threadIdx.x;
-    V3<double> x0 = mk(0.0, 0.0, 0.0), d0 = x0;
-    c2 = x0;
-    if (i < n_u) {
-        V3<double> o[3];
-        sample_derivs<P, 2>(path, i, n_u, o);
-        x0 = o[0]; d0 = o[1]; c2 = o[2];
-    }
-    c1 = d0;
-    L.sx[0][threadIdx.x] = x0.x; L.sx[1][threadIdx.x] = x0.y; L.sx[2][threadIdx.x] = x0.z;
-    L.sd[0][threadIdx.x] = d0.x; L.sd[1][threadIdx.x] = d0.y; L.sd[2][threadIdx.x] = d0.z;
-    if (threadIdx.x == 0 && base + kChunk < n_u) {
-        V3<double> o[2];
-        sample_derivs<P, 1>(path, base + kChunk, n_u, o);
-        L.sx[0][kChunk] = o[0].x; L.sx[1][kChunk] = o[0].y; L.sx[2][kChunk] = o[0].z;
-        L.sd[0][kChunk] = o[1].x; L.sd[1][kChunk] = o[1].y; L.sd[2][kChunk] = o[1].z;
-    }
-    __syncthreads();
-    const bool has_step = i + 1 < n_u;
-    V3<double> x1 = x0, d1 = x0;
-    if (has_step) {
-        x1 = mk(L.sx[0][threadIdx.x + 1], L.sx[1][threadIdx.x + 1], L.sx[2][threadIdx.x + 1]);
-        d1 = mk(L.sd[0][threadIdx.x + 1], L.sd[1][threadIdx.x + 1], L.sd[2][threadIdx.x + 1]);
-    }
-    const bool valid0 = i < n_u && dot(d0, d0) > 0.0;
-    const bool valid1 = has_step && dot(d1, d1) > 0.0;
-    int total;
-    const int excl = block_exclusive_max(valid0 ? i : -1, L.ii, total);
-    const int lv = max(carry_lv, valid0 ? i : excl);
-    V3<double> d_lv = d0;
-    if (!valid0 && lv >= 0)
-        d_lv = lv >= base ? mk(L.sd[0][lv - base], L.sd[1][lv - base], L.sd[2][lv - base]) : d_carry;
-    const StepInputs s = resolve_step(x0, d0, valid0, x1, d1, valid1, has_step, lv, d_lv, fb);
-    if (total >= 0) {
-        last = total;
-        d_last = mk(L.sd[0][total - base], L.sd[1][total - base], L.sd[2][total - base]);
-    } else {
-        last = carry_lv;
-        d_last = d_carry;
-    }
-    __syncthreads();
-    return s;
-}
-
 // Profile tables: one block per (sweep, chunk of 256 v-samples).
 template <class T>
 __global__ __launch_bounds__(kBlock) void kb_profile(const BatchDesc* __restrict__ descs,
@@ -114,7 +52,18 @@ __global__ __launch_bounds__(kBlock) void kb_profile(const BatchDesc* __restrict
     if (j < d.n_v) write_profile<T>(prof_of(d, prof_ctrl, prof_w, knots), j, d.n_v, ptab + 8 * d.ptab_off);
 }
 
-// Row records of the sweeps whose path has degree P: one block per sweep.
+// Run length of a batched sweep: the smallest power of two up to
+// kMaxRun with kBlock*K >= n_u (a sweep of up to kBlock*kMaxRun u-samples is
+// one chunk).
+__device__ __forceinline__ int batch_run_length(int n_u)
+{
+    int K = 1;
+    while (K < kMaxRun && kBlock * K < n_u) K *= 2;
+    return K;
+}
+
+// Row records of a sweep of at most kBlock*kMaxRun u-samples whose path has
+// degree P: one block per sweep, one chunk.
 template <int P, class F, class T>
 __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
                                                    const int* __restrict__ sweeps,
@@ -123,35 +72,65 @@ __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__
                                                    const double* __restrict__ knots, InitialNormal n0, int reorth,
                                                    T* __restrict__ rows)
 {
-    __shared__ ChunkLds L;
+    __shared__ ChunkWalkLds L;
     __shared__ M3<F> lds_m[kWaves];
+    __shared__ double lt0[3];
     const BatchDesc d = descs[sweeps[blockIdx.x]];
     const DCurve path = path_of(d, path_ctrl, path_w, knots);
-    const V3<double> fb = first_leg(path);
     const int n_u = d.n_u;
+    const int K = batch_run_length(n_u);
+    RunInfo<P, F> R;
+    int clv;
+    V3<double> ctl;
+    chunk_products<P, F>(path, n_u, 0, K, true, first_leg(path), L, R, clv, ctl);
+    // r_0 from the resolved t_0 (sample 0 is thread 0's)
+    if (threadIdx.x == 0) { lt0[0] = R.t_first.x; lt0[1] = R.t_first.y; lt0[2] = R.t_first.z; }
+    __syncthreads();
+    const V3<F> rin = cvt<F>(initial_normal(mk(lt0[0], lt0[1], lt0[2]), n0));
+    const M3<F> ex = block_exclusive_product<F>(R.A, lds_m);
+    run_rows<P, 2, F>(path, n_u, (int)threadIdx.x * K, K, R.t_first, apply(ex, rin),
+                      PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
+}
+
+// The same for longer sweeps: the block walks chunks of kBlock*kMaxRun
+// samples in order, carrying the entering normal and the last resolved
+// tangent.  (A kernel of its own: the loop's carried state raises the
+// register allocation above that of the one-chunk kernel.)
+template <int P, class F, class T>
+__global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restrict__ descs,
+                                                        const int* __restrict__ sweeps,
+                                                        const double* __restrict__ path_ctrl,
+                                                        const double* __restrict__ path_w,
+                                                        const double* __restrict__ knots, InitialNormal n0,
+                                                        int reorth, T* __restrict__ rows)
+{
+    __shared__ ChunkWalkLds L;
+    __shared__ M3<F> lds_m[kWaves];
+    __shared__ double lt0[3];
+    const BatchDesc d = descs[sweeps[blockIdx.x]];
+    const DCurve path = path_of(d, path_ctrl, path_w, knots);
+    const int n_u = d.n_u;
+    const int K = batch_run_length(n_u);
+    const int cs = kBlock * K;
     T* rows_k = rows + 16 * (size_t)d.row_off;
-    int lv = -1;
-    V3<double> d_lv = mk(0.0, 0.0, 0.0);
-    F rin[3];
-    for (int base = 0; base < n_u; base += kChunk) {
-        V3<double> c1, c2, d_last;
-        int last;
-        const StepInputs s = seq_chunk_inputs<P>(path, n_u, base, lv, d_lv, fb, L, c1, c2, last, d_last);
-        lv = last;
-        d_lv = d_last;
+    V3<double> t_entry = first_leg(path);
+    V3<F> rin = mk(F(0), F(0), F(0));
+    for (int base = 0; base < n_u; base += cs) {
+        RunInfo<P, F> R;
+        int clv;
+        V3<double> ctl;
+        chunk_products<P, F>(path, n_u, base, K, true, t_entry, L, R, clv, ctl);
         if (base == 0) {
-            // r_0 from the resolved t_0 (sample 0 is thread 0's)
-            if (threadIdx.x == 0) { L.d3[0] = s.t0.x; L.d3[1] = s.t0.y; L.d3[2] = s.t0.z; }
+            if (threadIdx.x == 0) { lt0[0] = R.t_first.x; lt0[1] = R.t_first.y; lt0[2] = R.t_first.z; }
             __syncthreads();
-            const V3<F> r0 = cvt<F>(initial_normal(mk(L.d3[0], L.d3[1], L.d3[2]), n0));
-            rin[0] = r0.x; rin[1] = r0.y; rin[2] = r0.z;
+            rin = cvt<F>(initial_normal(mk(lt0[0], lt0[1], lt0[2]), n0));
         }
         M3<F> total;
-        const M3<F> ex = block_exclusive_product<F>(step_of<F>(s), lds_m, total);
-        const int i = base + threadIdx.x;
-        if (i < n_u) write_row<F, T>(s, ex, rin, c1, c2, reorth, rows_k + 16 * (size_t)i);
-        const V3<F> rn = apply(total, mk(rin[0], rin[1], rin[2]));
-        rin[0] = rn.x; rin[1] = rn.y; rin[2] = rn.z;
+        const M3<F> ex = block_exclusive_product<F>(R.A, lds_m, total);
+        run_rows<P, 2, F>(path, n_u, base + (int)threadIdx.x * K, K, R.t_first, apply(ex, rin),
+                          PlainRows<F, T>{rows_k, reorth});
+        rin = apply(total, rin);
+        t_entry = ctl;   // the last resolved tangent up to this chunk's end
     }
 }
 
@@ -241,7 +220,8 @@ static BatchedKernels pick(bool nrm, bool nt, int K)
     BatchedKernels k;
     k.profile = (const void*)&kb_profile<T>;
     k.frame[0] = nullptr;
-#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>;
+    k.frame_long[0] = nullptr;
+#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>; k.frame_long[P] = (const void*)&kb_frame_long<P, F, T>;
     SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
 #undef SWEEP_DEG
     if (nrm) k.surface = nt ? surface_for<T, true, true>(K) : surface_for<T, true, false>(K);

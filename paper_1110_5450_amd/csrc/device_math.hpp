@@ -23,10 +23,17 @@ template <class F> __device__ __forceinline__ V3<F> mk(F x, F y, F z) { return V
 template <class F> __device__ __forceinline__ V3<F> operator+(V3<F> a, V3<F> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 template <class F> __device__ __forceinline__ V3<F> operator-(V3<F> a, V3<F> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 template <class F> __device__ __forceinline__ V3<F> operator*(F s, V3<F> a) { return {s * a.x, s * a.y, s * a.z}; }
-template <class F> __device__ __forceinline__ F dot(V3<F> a, V3<F> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// dot and cross products as explicit fused multiply-adds (the rounding does
+// not depend on where they are inlined)
+template <class F> __device__ __forceinline__ F dot(V3<F> a, V3<F> b) { return fma(a.z, b.z, fma(a.y, b.y, a.x * b.x)); }
 template <class F> __device__ __forceinline__ V3<F> cross(V3<F> a, V3<F> b)
 {
-    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+    return {fma(a.y, b.z, -(a.z * b.y)), fma(a.z, b.x, -(a.x * b.z)), fma(a.x, b.y, -(a.y * b.x))};
+}
+// s a + b, componentwise fused
+template <class F> __device__ __forceinline__ V3<F> fmadd(F s, V3<F> a, V3<F> b)
+{
+    return {fma(s, a.x, b.x), fma(s, a.y, b.y), fma(s, a.z, b.z)};
 }
 template <class F> __device__ __forceinline__ V3<F> divs(V3<F> a, F s) { return {a.x / s, a.y / s, a.z / s}; }
 template <class G, class F> __device__ __forceinline__ V3<G> cvt(V3<F> a) { return {(G)a.x, (G)a.y, (G)a.z}; }
@@ -41,7 +48,8 @@ template <class F> __device__ __forceinline__ M3<F> ident()
     for (int k = 0; k < 9; ++k) r.m[k] = (k % 4 == 0) ? F(1) : F(0);
     return r;
 }
-// a * b
+// a * b, each entry as two fused multiply-adds (explicit, so the rounding
+// does not depend on where the function is inlined)
 template <class F> __device__ __forceinline__ M3<F> mul(const M3<F>& a, const M3<F>& b)
 {
     M3<F> r;
@@ -49,14 +57,14 @@ template <class F> __device__ __forceinline__ M3<F> mul(const M3<F>& a, const M3
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            r.m[3 * i + j] = a.m[3 * i] * b.m[j] + a.m[3 * i + 1] * b.m[3 + j] + a.m[3 * i + 2] * b.m[6 + j];
+            r.m[3 * i + j] = fma(a.m[3 * i + 2], b.m[6 + j], fma(a.m[3 * i + 1], b.m[3 + j], a.m[3 * i] * b.m[j]));
     return r;
 }
 template <class F> __device__ __forceinline__ V3<F> apply(const M3<F>& a, V3<F> v)
 {
-    return {a.m[0] * v.x + a.m[1] * v.y + a.m[2] * v.z,
-            a.m[3] * v.x + a.m[4] * v.y + a.m[5] * v.z,
-            a.m[6] * v.x + a.m[7] * v.y + a.m[8] * v.z};
+    return {fma(a.m[2], v.z, fma(a.m[1], v.y, a.m[0] * v.x)),
+            fma(a.m[5], v.z, fma(a.m[4], v.y, a.m[3] * v.x)),
+            fma(a.m[8], v.z, fma(a.m[7], v.y, a.m[6] * v.x))};
 }
 
 // ------------------------------------------------------------------ curves
@@ -357,45 +365,74 @@ __device__ __forceinline__ V3<F> axis_normal(V3<F> t)
 // to v2 = t_{i+1} - H1 t_i; M = H2 H1.  A zero chord uses v1 = t_i.  When
 // |v2|^2 <= 1e-24 the smallest rotation taking t_i to t_{i+1} is used
 // (rotation by pi about the axis-rule direction for opposite tangents).
-// Returns 1 when that fallback was taken.
+// The rotation is kept in factored form and applied to vectors (or matrix
+// columns) without forming M:
+//   kind 0:  x -> H2 H1 x,  H_k x = x - b_k (v_k . x) v_k,  b_k = 2/|v_k|^2
+//   kind 1:  x -> c x + k x x + f (k . x) k   (rotation about k = t_i x t_{i+1},
+//            c = t_i . t_{i+1}, f = (1 - c)/|k|^2)
+//   kind 2:  identity (equal tangents)
+//   kind 3:  x -> 2 (a . x) a - x   (rotation by pi about the unit vector a)
+// Kinds 1 and 3 reuse v1 (k, a), b1 (c) and b2 (f).
 template <class F>
-__device__ __forceinline__ int step_matrix(V3<F> v1, V3<F> ti, V3<F> tn, M3<F>& M)
+struct StepRot {
+    V3<F> v1, v2;
+    F b1, b2;
+    int kind;
+};
+
+template <class F>
+__device__ __forceinline__ StepRot<F> make_step(V3<F> v1, V3<F> ti, V3<F> tn)
 {
+    StepRot<F> S;
     F c1 = dot(v1, v1);
     if (c1 == F(0)) { v1 = ti; c1 = dot(v1, v1); }
     const F b1 = F(2) / c1;
-    const V3<F> tL = ti - (b1 * dot(v1, ti)) * v1;
+    const V3<F> tL = fmadd(-(b1 * dot(v1, ti)), v1, ti);
     const V3<F> v2 = tn - tL;
     const F c2 = dot(v2, v2);
     if (c2 > F(1e-24)) {
-        const F b2 = F(2) / c2;
-        const F g = b1 * b2 * dot(v1, v2);
-        const F a1[3] = {v1.x, v1.y, v1.z}, a2[3] = {v2.x, v2.y, v2.z};
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                M.m[3 * r + q] = (r == q ? F(1) : F(0)) - b1 * a1[r] * a1[q] - b2 * a2[r] * a2[q] + g * a2[r] * a1[q];
-        return 0;
+        S.kind = 0;
+        S.v1 = v1; S.b1 = b1;
+        S.v2 = v2; S.b2 = F(2) / c2;
+        return S;
     }
     const V3<F> k = cross(ti, tn);
     const F kk = dot(k, k), c = dot(ti, tn);
+    S.v2 = mk(F(0), F(0), F(0));
     if (kk > F(0)) {
-        const F f = (F(1) - c) / kk;
-        M.m[0] = c + f * k.x * k.x;  M.m[1] = -k.z + f * k.x * k.y; M.m[2] = k.y + f * k.x * k.z;
-        M.m[3] = k.z + f * k.y * k.x; M.m[4] = c + f * k.y * k.y;  M.m[5] = -k.x + f * k.y * k.z;
-        M.m[6] = -k.y + f * k.z * k.x; M.m[7] = k.x + f * k.z * k.y; M.m[8] = c + f * k.z * k.z;
+        S.kind = 1;
+        S.v1 = k; S.b1 = c; S.b2 = (F(1) - c) / kk;
     } else if (c > F(0)) {
-        M = ident<F>();
+        S.kind = 2;
+        S.v1 = k; S.b1 = F(0); S.b2 = F(0);
     } else {
-        const V3<F> a = axis_normal(ti);
-        const F aa[3] = {a.x, a.y, a.z};
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) M.m[3 * r + q] = F(2) * aa[r] * aa[q] - (r == q ? F(1) : F(0));
+        S.kind = 3;
+        S.v1 = axis_normal(ti); S.b1 = F(0); S.b2 = F(0);
     }
-    return 1;
+    return S;
+}
+
+template <class F>
+__device__ __forceinline__ V3<F> apply_step(const StepRot<F>& S, V3<F> x)
+{
+    if (S.kind == 0) {
+        x = fmadd(-(S.b1 * dot(S.v1, x)), S.v1, x);
+        return fmadd(-(S.b2 * dot(S.v2, x)), S.v2, x);
+    }
+    if (S.kind == 1) return fmadd(S.b2 * dot(S.v1, x), S.v1, fmadd(S.b1, x, cross(S.v1, x)));
+    if (S.kind == 2) return x;
+    return fmadd(F(2) * dot(S.v1, x), S.v1, mk(-x.x, -x.y, -x.z));
+}
+
+// M A for the step rotation M, column by column.
+template <class F>
+__device__ __forceinline__ void apply_step(const StepRot<F>& S, M3<F>& A)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const V3<F> y = apply_step(S, mk(A.m[j], A.m[3 + j], A.m[6 + j]));
+        A.m[j] = y.x; A.m[3 + j] = y.y; A.m[6 + j] = y.z;
+    }
 }
 
 // --------------------------------------------------------- wave/block scans

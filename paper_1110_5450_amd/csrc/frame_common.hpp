@@ -1,8 +1,7 @@
 // frame_common.hpp -- device steps of the frame computation shared by the
 // single-sweep kernels (frame_kernels.hip) and the batched kernel
-// (batched_kernels.hip).  Both call these same functions in the same order on
-// the same values, so a sweep evaluated alone or inside a batch produces
-// bitwise identical row records.
+// (batched_kernels.hip): tangents, the initial normal, the chunk carry scan,
+// row records and profile records.
 #pragma once
 
 #include "device_math.hpp"
@@ -12,40 +11,11 @@
 
 namespace sweep {
 
-// Samples per chunk of the frame scan: one per thread.
-constexpr int kChunk = kBlock;
-
-__device__ __forceinline__ V3<double> unit_of(V3<double> d) { return divs(d, sqrt(dot(d, d))); }
-
-// Positions and resolved tangents of sample i (this thread) and i+1.
-struct StepInputs {
-    V3<double> x0, x1, t0, t1;
-    bool has_step;   // i + 1 < n_u
-};
-
-// Tangent resolution for the step i -> i+1 of one block.  Inputs: own sample
-// (x0, d0 = C'_i, valid0), next sample (x1, d1, valid1, has_step), lv = the
-// last sample <= i with C' != 0 (or -1) and d_lv = its C' (used when i itself
-// is not valid), fallback tangent fb.
-__device__ __forceinline__ StepInputs resolve_step(V3<double> x0, V3<double> d0, bool valid0, V3<double> x1,
-                                                   V3<double> d1, bool valid1, bool has_step, int lv,
-                                                   V3<double> d_lv, V3<double> fb)
+// d/|d| (one division for the three components).
+__device__ __forceinline__ V3<double> unit_of(V3<double> d)
 {
-    StepInputs s;
-    s.x0 = x0;
-    s.x1 = has_step ? x1 : x0;
-    s.has_step = has_step;
-    s.t0 = valid0 ? unit_of(d0) : (lv >= 0 ? unit_of(d_lv) : fb);
-    s.t1 = (has_step && valid1) ? unit_of(d1) : s.t0;
-    return s;
-}
-
-template <class F>
-__device__ __forceinline__ M3<F> step_of(const StepInputs& s)
-{
-    M3<F> M = ident<F>();
-    if (s.has_step) step_matrix<F>(cvt<F>(s.x1 - s.x0), cvt<F>(s.t0), cvt<F>(s.t1), M);
-    return M;
+    const double inv = 1.0 / sqrt(dot(d, d));
+    return inv * d;
 }
 
 // Initial normal r_0 from the resolved t_0: the given normal projected onto
@@ -98,27 +68,28 @@ __device__ void carry_scan(const F* agg, int n_chunks, V3<double> r0d, F* __rest
     }
 }
 
-// Row record of sample i: x, r (re-orthonormalised if asked), s = t x r, t,
-// |C'|, a = r.C''/|C'|, b = s.C''/|C'| (0 where C' = 0), in precision T.
+// Row record of one sample: x, r (re-orthonormalised against t if asked),
+// s = t x r, t, |C'|, a = r.C''/|C'|, b = s.C''/|C'| (0 where C' = 0), in
+// precision T.  r is the carried normal in the frame precision F.
 template <class F, class T>
-__device__ __forceinline__ void write_row(const StepInputs& s, const M3<F>& ex, const F* rb, V3<double> C1,
-                                          V3<double> C2, int reorth, T* __restrict__ q)
+__device__ __forceinline__ void write_row(V3<double> x, V3<double> td, V3<F> r, V3<double> C1, V3<double> C2,
+                                          int reorth, T* __restrict__ q)
 {
-    const V3<F> t = cvt<F>(s.t0);
-    V3<F> r = apply(ex, mk(rb[0], rb[1], rb[2]));
+    const V3<F> t = cvt<F>(td);
     if (reorth) {
         const V3<F> w = r - dot(r, t) * t;
-        r = divs(w, (F)sqrt(dot(w, w)));
+        r = (F(1) / (F)sqrt(dot(w, w))) * w;
     }
     const V3<F> sv = cross(t, r);
     const double L = sqrt(dot(C1, C1));
     F a = F(0), b = F(0);
     if (L > 0.0) {
         const V3<F> c2 = cvt<F>(C2);
-        a = dot(r, c2) / (F)L;
-        b = dot(sv, c2) / (F)L;
+        const F inv = F(1) / (F)L;
+        a = dot(r, c2) * inv;
+        b = dot(sv, c2) * inv;
     }
-    q[0] = (T)s.x0.x; q[1] = (T)s.x0.y; q[2] = (T)s.x0.z;
+    q[0] = (T)x.x; q[1] = (T)x.y; q[2] = (T)x.z;
     q[3] = (T)r.x; q[4] = (T)r.y; q[5] = (T)r.z;
     q[6] = (T)sv.x; q[7] = (T)sv.y; q[8] = (T)sv.z;
     q[9] = (T)t.x; q[10] = (T)t.y; q[11] = (T)t.z;
@@ -145,17 +116,16 @@ struct LawSample {
 };
 
 template <class F, class T>
-__device__ __forceinline__ void write_row_ext(const StepInputs& s, const M3<F>& ex, const F* rb, V3<double> C1,
-                                              V3<double> C2, V3<double> C3, int frenet, LawSample lw, int reorth,
-                                              T* __restrict__ q)
+__device__ __forceinline__ void write_row_ext(V3<double> x, V3<double> td, V3<F> rc, V3<double> C1, V3<double> C2,
+                                              V3<double> C3, int frenet, LawSample lw, int reorth, T* __restrict__ q)
 {
-    const V3<F> t = cvt<F>(s.t0);
+    const V3<F> t = cvt<F>(td);
     V3<F> r;
     double omega = 0.0;
     if (frenet) {
         // principal normal from C'' (pointwise, FP64), torsion rate from C'''
-        const double ct = dot(C2, s.t0);
-        const V3<double> qv = C2 - ct * s.t0;
+        const double ct = dot(C2, td);
+        const V3<double> qv = C2 - ct * td;
         const double nq = sqrt(dot(qv, qv));
         V3<double> rd;
         if (nq > kFrenetEps * sqrt(dot(C2, C2))) {
@@ -164,14 +134,14 @@ __device__ __forceinline__ void write_row_ext(const StepInputs& s, const M3<F>& 
             const double kk = dot(k, k);
             if (kk > 0.0) omega = sqrt(dot(C1, C1)) * (dot(k, C3) / kk);
         } else {
-            rd = axis_normal<double>(s.t0);
+            rd = axis_normal<double>(td);
         }
         r = cvt<F>(rd);
     } else {
-        r = apply(ex, mk(rb[0], rb[1], rb[2]));
+        r = rc;
         if (reorth) {
             const V3<F> w = r - dot(r, t) * t;
-            r = divs(w, (F)sqrt(dot(w, w)));
+            r = (F(1) / (F)sqrt(dot(w, w))) * w;
         }
     }
     const V3<F> sv = cross(t, r);
@@ -179,11 +149,12 @@ __device__ __forceinline__ void write_row_ext(const StepInputs& s, const M3<F>& 
     F a = F(0), b = F(0);
     if (L > 0.0) {
         const V3<F> c2 = cvt<F>(C2);
-        a = dot(r, c2) / (F)L;
-        b = dot(sv, c2) / (F)L;
+        const F inv = F(1) / (F)L;
+        a = dot(r, c2) * inv;
+        b = dot(sv, c2) * inv;
     }
     const double c = cos(lw.th), sn = sin(lw.th);
-    q[0] = (T)s.x0.x; q[1] = (T)s.x0.y; q[2] = (T)s.x0.z;
+    q[0] = (T)x.x; q[1] = (T)x.y; q[2] = (T)x.z;
     q[3] = (T)r.x; q[4] = (T)r.y; q[5] = (T)r.z;
     q[6] = (T)sv.x; q[7] = (T)sv.y; q[8] = (T)sv.z;
     q[9] = (T)t.x; q[10] = (T)t.y; q[11] = (T)t.z;
@@ -210,12 +181,85 @@ __device__ __forceinline__ LawSample law_at(const DCurve* law, int i, int n_u, d
     return lw;
 }
 
+// C and C' of a curve of any degree p <= kMaxDeg at sample j of ns, with loops
+// over the run-time degree instead of one unrolled copy per degree: the same
+// operations in the same order as curve_derivs<P, 1>, on local arrays.  Used
+// for the profile tables, which are small and evaluated once per call, so
+// that the kernels holding them do not reserve the registers of an unrolled
+// degree-7 evaluation.
+__device__ __forceinline__ void curve_d1_any(const DCurve& c, int j, int ns, V3<double>* out)
+{
+    const int p = c.p;
+    double u;
+    int s;
+    if (c.su) {
+        u = c.su[j];
+        s = c.ss[j];
+    } else {
+        u = sample_param(c, j, ns);
+        s = sample_span(c, j, ns, u);
+    }
+    double Uk[2 * kMaxDeg];
+#pragma unroll 1
+    for (int m = 0; m < 2 * p; ++m) Uk[m] = knot(c, s - p + 1 + m);
+    double B[kMaxDeg + 1], D1[kMaxDeg + 1], nb_[kMaxDeg + 1];
+    B[0] = 1.0;
+    D1[0] = 1.0;
+#pragma unroll 1
+    for (int q = 1; q <= p; ++q) {
+        double carry = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < q; ++k) {
+            const double lo = Uk[p - q + k], hi = Uk[p + k];
+            const double tmp = B[k] / (hi - lo);
+            nb_[k] = carry + (hi - u) * tmp;
+            carry = (u - lo) * tmp;
+        }
+        nb_[q] = carry;
+#pragma unroll 1
+        for (int k = 0; k <= q; ++k) B[k] = nb_[k];
+        if (q == p - 1) {
+#pragma unroll 1
+            for (int k = 0; k <= q; ++k) D1[k] = B[k];
+        }
+    }
+    V3<double> C0 = mk(0.0, 0.0, 0.0), C1 = C0;
+    if (!c.w) {
+#pragma unroll 1
+        for (int k = 0; k <= p; ++k) C0 = C0 + B[k] * ctrl_pt(c, s - p + k);
+#pragma unroll 1
+        for (int k = 0; k < p; ++k)
+            C1 = C1 + D1[k] * (((double)p / (Uk[p + k] - Uk[k])) * (ctrl_pt(c, s - p + k + 1) - ctrl_pt(c, s - p + k)));
+    } else {
+        // homogeneous curve (w P, w) and the quotient rule
+        double W0 = 0.0, W1 = 0.0;
+#pragma unroll 1
+        for (int k = 0; k <= p; ++k) {
+            const double wk = weight_at(c, s - p + k);
+            C0 = C0 + B[k] * (wk * ctrl_pt(c, s - p + k));
+            W0 = W0 + B[k] * wk;
+        }
+        V3<double> A1 = mk(0.0, 0.0, 0.0);
+#pragma unroll 1
+        for (int k = 0; k < p; ++k) {
+            const double f = (double)p / (Uk[p + k] - Uk[k]);
+            const double w0 = weight_at(c, s - p + k), w1 = weight_at(c, s - p + k + 1);
+            A1 = A1 + D1[k] * (f * (w1 * ctrl_pt(c, s - p + k + 1) - w0 * ctrl_pt(c, s - p + k)));
+            W1 = W1 + D1[k] * (f * (w1 - w0));
+        }
+        C0 = divs(C0, W0);
+        C1 = divs(A1 - W1 * C0, W0);
+    }
+    out[0] = C0;
+    out[1] = C1;
+}
+
 // Profile record of sample j: S (3), S' (3), 0, 0.
 template <class T>
 __device__ __forceinline__ void write_profile(const DCurve& prof, int j, int n_v, T* __restrict__ tab)
 {
     V3<double> o[2];
-    sample_derivs_any<1>(prof, j, n_v, o);
+    curve_d1_any(prof, j, n_v, o);
     T* q = tab + 8 * (size_t)j;
     q[0] = (T)o[0].x; q[1] = (T)o[0].y; q[2] = (T)o[0].z;
     q[3] = (T)o[1].x; q[4] = (T)o[1].y; q[5] = (T)o[1].z;

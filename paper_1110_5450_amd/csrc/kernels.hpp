@@ -14,14 +14,32 @@ struct InitialNormal {
     double v[3];
 };
 
-int frame_chunk_size();
+// Frame of a single sweep: runs of K consecutive u-samples per thread,
+// chunks of kBlock runs (K and the chunk count for n_u samples).
+int frame_run_length(int n_u);
+int frame_chunks(int n_u);
 
-// Path samples (x, C', C'' as SoA planes of n_u doubles), per-chunk last
-// valid sample, chunk products of the step rotations (or a flag), fallback
-// tangent, and the profile table.
+// Workspace of the single-sweep frame: per-run records (kRunRec doubles),
+// per-chunk last sample with C' != 0, its tangent (3 doubles), flag, product
+// (9 values of the frame precision) and entering normal (3 values), and the
+// fallback tangent (3 doubles).
+// Per-run record between the passes: the run's product of step rotations
+// (9 values) and its resolved first tangent (3), as doubles.
+constexpr int kRunRec = 12;
+struct FrameWork {
+    double* trec;
+    int* chunk_lv;
+    double* chunk_tl;
+    int* chunk_fix;
+    double* fallback_t;
+    void* agg;
+    void* r_in;
+};
+
+// Run records, chunk products and flags of the path, and the profile table.
 template <class F, class T>
-hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, double* smp, int* chunk_lv,
-                       int* chunk_fix, double* fallback_t, F* agg, T* ptab, hipStream_t st);
+hipError_t launch_prep(const DCurve& path, int n_u, const DCurve& prof, int n_v, const FrameWork& w, T* ptab,
+                       hipStream_t st);
 // Arc-length sampling of an open curve (lam = 0), or curvature-adaptive
 // sampling with density |C'| (1 + lam kappa): piece integrals (len,
 // arc_pieces(c) values), their cumulative table (cum, one more), sample
@@ -37,18 +55,16 @@ constexpr int kRowExt = 32;
 
 // Frenet frame mode and sweep law of a single sweep (extended row records).
 struct FrameExt {
-    DCurve path;       // the path (its third derivative, Frenet mode)
     int frenet;        // 1: Frenet frame
     DCurve law;        // law curve (sigma, theta, -), valid when has_law
     int has_law;
     double du_scale;   // d(law parameter)/du
 };
 
-// Carry scan and row table: 16 values per u-row, or 32 (extended records)
+// Chunk carry and row table: 16 values per u-row, or 32 (extended records)
 // when ext is given.
 template <class F, class T>
-hipError_t launch_frame(const double* smp, int n_u, const int* chunk_lv, const int* chunk_fix,
-                        const double* fallback_t, InitialNormal n0, int reorth, F* agg, F* r_in, T* rows,
+hipError_t launch_frame(const DCurve& path, int n_u, const FrameWork& w, InitialNormal n0, int reorth, T* rows,
                         hipStream_t st, const FrameExt* ext = nullptr);
 
 // Surface write of one sweep from its row table (16 values per u-row) and
@@ -116,9 +132,14 @@ constexpr int kColPart = 3, kColPartNrm = 6;
 // Fast division constants for 0 <= v < 2^31.
 void fastdiv_constants(int d, unsigned long long* m, int* shift);
 
+// Longest batched sweep whose frame is one chunk: kBlock runs of up to
+// kMaxRun u-samples (longer sweeps take the chunk-walking frame kernel).
+constexpr int kMaxRun = 16;
+
 struct BatchedKernels {
     const void* profile;
-    const void* frame[8];   // by path degree (index 0 unused)
+    const void* frame[8];        // by path degree (index 0 unused): sweeps of n_u <= kBlock*kMaxRun
+    const void* frame_long[8];   // longer sweeps
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as

@@ -165,7 +165,7 @@ SurfaceConfig auto_surface_config(int n_u, int n_v, int t64)
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t knots_path, knots_prof, smp, chunk_lv, chunk_fix, fallback, agg, r_in, rows, prof_tab, knots_law;
+    size_t knots_path, knots_prof, trec, chunk_lv, chunk_tl, chunk_fix, fallback, agg, r_in, rows, prof_tab, knots_law;
     size_t arc_len, arc_cum, arc_u, arc_span, total;
 };
 
@@ -175,12 +175,13 @@ static SingleLayout single_layout(int np, int pp, int nq, int pq, int qclosed, i
                                   int rl = 16, int nlk = 0, bool arclength = false)
 {
     SingleLayout L{};
-    const int nc = (n_u + frame_chunk_size() - 1) / frame_chunk_size();
+    const int nc = frame_chunks(n_u);
     size_t off = 0;
     L.knots_path = off; off = align_up(off + sizeof(double) * nknots(np, pp, 0));
     L.knots_prof = off; off = align_up(off + sizeof(double) * nknots(nq, pq, qclosed));
-    L.smp = off;        off = align_up(off + sizeof(double) * 9 * (size_t)n_u);
+    L.trec = off;       off = align_up(off + sizeof(double) * kRunRec * (size_t)kBlock * (size_t)nc);
     L.chunk_lv = off;   off = align_up(off + sizeof(int) * (size_t)nc);
+    L.chunk_tl = off;   off = align_up(off + sizeof(double) * 3 * (size_t)nc);
     L.chunk_fix = off;  off = align_up(off + sizeof(int) * (size_t)nc);
     L.fallback = off;   off = align_up(off + sizeof(double) * 3);
     L.agg = off;        off = align_up(off + fsz * 9 * (size_t)nc);
@@ -205,6 +206,12 @@ static SingleLayout layout_for(const sweep_curve* path, const sweep_curve* prof,
     const int nlk = (o->law && o->law->knots) ? nknots(o->law->n_ctrl, o->law->degree, 0) : 0;
     return single_layout(path->n_ctrl, path->degree, prof->n_ctrl, prof->degree, prof->closed, n_u, n_v, fsz, tsz,
                          options_ext(o) ? kRowExt : 16, nlk, o->u_sampling != SWEEP_U_PARAMETER);
+}
+
+static FrameWork frame_work(char* ws, const SingleLayout& L)
+{
+    return FrameWork{(double*)(ws + L.trec), (int*)(ws + L.chunk_lv), (double*)(ws + L.chunk_tl),
+                     (int*)(ws + L.chunk_fix), (double*)(ws + L.fallback), ws + L.agg, ws + L.r_in};
 }
 
 // Copies given knots to the device (a blocking copy from pageable memory);
@@ -245,15 +252,11 @@ static sweep_status run_frames(const sweep_curve* path, int n_u, const sweep_opt
               nbasis(path->n_ctrl, path->degree, 0), path->weights};
     DCurve dq{nullptr, nullptr, 1, 1, 0, 1, nullptr};
     if ((s = setup_arclength(dp, n_u, o, ws, L, st)) != SWEEP_OK) return s;
-    double* smp = (double*)(ws + L.smp);
-    int* clv = (int*)(ws + L.chunk_lv);
-    double* fb = (double*)(ws + L.fallback);
-    int* cfx = (int*)(ws + L.chunk_fix);
-    hipError_t e = launch_prep<F, T>(dp, n_u, dq, 0, smp, clv, cfx, fb, (F*)(ws + L.agg), (T*)nullptr, st);
+    const FrameWork w = frame_work(ws, L);
+    hipError_t e = launch_prep<F, T>(dp, n_u, dq, 0, w, (T*)nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
-    e = launch_frame<F, T>(smp, n_u, clv, cfx, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
-                           rows, st);
+    e = launch_frame<F, T>(dp, n_u, w, n0, o->reorthonormalize, rows, st);
     if (e != hipSuccess) return hip_fail(e, "frame");
     return SWEEP_OK;
 }
@@ -275,19 +278,15 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
     DCurve dq{prof->ctrl, prof->knots ? Uq : nullptr, prof->n_ctrl, prof->degree, prof->closed,
               nbasis(prof->n_ctrl, prof->degree, prof->closed), prof->weights};
     if ((s = setup_arclength(dp, n_u, o, ws, L, st)) != SWEEP_OK) return s;
-    double* smp = (double*)(ws + L.smp);
-    int* clv = (int*)(ws + L.chunk_lv);
-    double* fb = (double*)(ws + L.fallback);
-    int* cfx = (int*)(ws + L.chunk_fix);
+    const FrameWork w = frame_work(ws, L);
     T* rows = (T*)(ws + L.rows);
     T* ptab = (T*)(ws + L.prof_tab);
-    hipError_t e = launch_prep<F, T>(dp, n_u, dq, n_v, smp, clv, cfx, fb, (F*)(ws + L.agg), ptab, st);
+    hipError_t e = launch_prep<F, T>(dp, n_u, dq, n_v, w, ptab, st);
     if (e != hipSuccess) return hip_fail(e, "curve samples");
     InitialNormal n0{o->has_initial_normal, {o->initial_normal[0], o->initial_normal[1], o->initial_normal[2]}};
     const bool ext = options_ext(o);
     FrameExt fx{};
     if (ext) {
-        fx.path = dp;
         fx.frenet = o->frame_mode == SWEEP_FRAME_FRENET;
         if (o->law) {
             const sweep_curve* lc = o->law;
@@ -299,8 +298,7 @@ static sweep_status run_single(const sweep_curve* path, const sweep_curve* prof,
             fx.du_scale = domain_length(lc) / domain_length(path);
         }
     }
-    e = launch_frame<F, T>(smp, n_u, clv, cfx, fb, n0, o->reorthonormalize, (F*)(ws + L.agg), (F*)(ws + L.r_in),
-                           rows, st, ext ? &fx : nullptr);
+    e = launch_frame<F, T>(dp, n_u, w, n0, o->reorthonormalize, rows, st, ext ? &fx : nullptr);
     if (e != hipSuccess) return hip_fail(e, "frame");
     trace_mark(1, st);
     const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config)

@@ -151,7 +151,8 @@ int plans()
         const int n = 1 + i % 5;
         for (int k = 0; k < n; ++k) {
             deg.push_back(1 + (i + k) % 7);
-            nu.push_back(16 + 37 * i + 101 * k);
+            // some sweeps longer than one frame chunk (the chunk-walking frame kernel)
+            nu.push_back(16 + 37 * i + 101 * k + (i % 7 == 3 && k == 0 ? 4500 : 0));
             nv.push_back(8 + (i * 13 + k * 7) % 200);
         }
         make_batch(shapes[i], deg, nu, nv, i % 2 == 0, rng);

@@ -18,6 +18,7 @@ constexpr ArgSig N0{sizeof(sweep::InitialNormal), kValue};
 
 const KernelSig kProfile{"kb_profile", {P, P, P, N, N, P}};
 const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P}};
+const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P}};
 const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
 const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
 const KernelSig kAdjoint{"kbw_adjoint", {P, P, P, N, N, N, N0, P, P, P, P, P, P, P, P, P, P, P, P, I, N}};
@@ -25,7 +26,7 @@ const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, 
 const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
 
 // distinct addresses standing in for kernel entry points
-char g_profile, g_frame[8], g_surface, g_reduce, g_adjoint, g_rec_path, g_rec_prof, g_params;
+char g_profile, g_frame[8], g_frame_long[8], g_surface, g_reduce, g_adjoint, g_rec_path, g_rec_prof, g_params;
 
 const std::map<const void*, const KernelSig*>& table()
 {
@@ -33,6 +34,7 @@ const std::map<const void*, const KernelSig*>& table()
         std::map<const void*, const KernelSig*> m;
         m[&g_profile] = &kProfile;
         for (int p = 1; p < 8; ++p) m[&g_frame[p]] = &kFrame;
+        for (int p = 1; p < 8; ++p) m[&g_frame_long[p]] = &kFrameLong;
         m[&g_surface] = &kSurface;
         m[&g_reduce] = &kReduce;
         m[&g_adjoint] = &kAdjoint;
@@ -54,7 +56,7 @@ const KernelSig* lookup(const void* fn)
 
 std::vector<const KernelSig*> all_kernels()
 {
-    return {&kProfile, &kFrame, &kSurface, &kReduce, &kAdjoint, &kParamRec, &kParams};
+    return {&kProfile, &kFrame, &kFrameLong, &kSurface, &kReduce, &kAdjoint, &kParamRec, &kParams};
 }
 
 }  // namespace stub
@@ -66,7 +68,9 @@ BatchedKernels batched_kernels(bool, bool, bool, bool, int)
     BatchedKernels k{};
     k.profile = &stub::g_profile;
     k.frame[0] = nullptr;
+    k.frame_long[0] = nullptr;
     for (int p = 1; p < 8; ++p) k.frame[p] = &stub::g_frame[p];
+    for (int p = 1; p < 8; ++p) k.frame_long[p] = &stub::g_frame_long[p];
     k.surface = &stub::g_surface;
     return k;
 }
