@@ -147,12 +147,24 @@ def sampled_error(spec, pos, nrm, rows, tol, frame_mode="rmf", law=None, arcleng
     return r
 
 
-def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 1000):
-    """The oracle as it stands on the same workload: the whole grid (frame
-    scan, positions and normals in FP64), repeated until about target_s of
-    work has run."""
-    import oracle
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def _oracle_rate(n_u: int, n_v: int, target_s: float, max_reps: int):
+    """vertices/s of the oracle on the large sweep at n_u x n_v, repeated for
+    about target_s seconds; (rate, reps, seconds, threads)."""
+    import oracle
+    import synth
+
+    spec = synth.c2(n_u=n_u, n_v=n_v)
     reps, total = 0, 0.0
     while reps < max_reps and (total < target_s or reps < 2):
         t0 = time.perf_counter()
@@ -160,12 +172,35 @@ def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 1000):
         total += time.perf_counter() - t0
         reps += 1
         del r
-    N = spec.n_u * spec.n_v
-    return {
-        "value": N * reps / total, "unit": "vertices/s", "cores": oracle.max_threads(), "kind": "oracle",
+    return spec.n_u * spec.n_v * reps / total, reps, total, oracle.max_threads()
+
+
+def cpu_baseline(spec, target_s: float = 10.0, max_reps: int = 1000):
+    """The oracle as it stands on the same workload: the whole grid (frame
+    scan, positions and normals in FP64), repeated until about target_s of
+    work has run, with all host threads; then one host thread in a child
+    process (OMP_NUM_THREADS=1) on the first 4096 rows of the same sweep."""
+    import subprocess
+
+    rate, reps, total, threads = _oracle_rate(spec.n_u, spec.n_v, target_s, max_reps)
+    out = {
+        "value": rate, "unit": "vertices/s", "cores": threads, "kind": "oracle",
         "sample": (f"the full {spec.n_u}x{spec.n_v} grid (frame scan, FP64 positions and normals) "
                    f"run {reps} times, {total:.1f} s in all"),
+        "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
     }
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "r = bench._oracle_rate(4096, %d, %f, 1000); print(json.dumps(r))" % (ROOT, spec.n_v, target_s / 2))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+        r1, reps1, total1, th1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": r1, "unit": "vertices/s", "cores": th1,
+                                "sample": f"the first 4096 rows ({4096}x{spec.n_v}) run {reps1} times, "
+                                          f"{total1:.1f} s in all"}
+    except Exception as e:  # the all-thread figure stands on its own
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 def rational_variant(steps: int):
@@ -272,12 +307,21 @@ def batched_variants(steps: int):
     import synth
     from paper_1110_5450_amd import api
 
+    import numpy as np
+    import oracle
+
     specs = synth.c4()
     b = api.Batch.from_specs(specs)
     N = b.n_vertices
     ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
     pos = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pos)
+    # the surface tile is chosen by the batched autotuner (untimed set-up);
+    # tile_config = -1 then uses its choice
+    t_tune = time.perf_counter()
+    tuned, tuned_ms = api.autotune_batched(b, out=(pos, nrm), workspace=ws)
+    t_tune = time.perf_counter() - t_tune
+    assert api.batched_config_for(b) == tuned
     for _ in range(GRAPH_WARMUP):
         api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
     torch.cuda.synchronize()
@@ -290,6 +334,19 @@ def batched_variants(steps: int):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     gpu_ms = ev[0].elapsed_time(ev[1]) / steps
+    # error against the oracle on 16 sampled sweeps (whole sweeps)
+    rng = np.random.default_rng(44)
+    err = {"pos_rel": 0.0, "nrm_scaled": 0.0, "nrm_abs_wc": 0.0, "masked": 0}
+    picked = sorted(int(k) for k in rng.choice(len(specs), 16, replace=False))
+    for k in picked:
+        s = specs[k]
+        ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
+        r = oracle.compare(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).double().cpu().numpy(),
+                           b.view(nrm, k).double().cpu().numpy(), oracle.bbox_diag(ref.pos), 1e6)
+        for key in ("pos_rel", "nrm_scaled", "nrm_abs_wc"):
+            err[key] = max(err[key], r[key])
+        err["masked"] += r["masked"]
+    err.update({"sweeps": picked, "tolerance": 1e-5})
     del pos, nrm, ws
     torch.cuda.empty_cache()
     # the same sweeps, one FP64 sweep_eval call each
@@ -322,9 +379,34 @@ def batched_variants(steps: int):
                     "n_u log-U[16,4096], n_v log-U[8,256]",
         "vertices": N,
         "batched_fp32_graph": {"vertices_per_s": N * steps / el, "ms_per_step": 1e3 * el / steps,
-                               "gpu_ms_per_step": gpu_ms, "output_GBps": 24.0 * N / (gpu_ms * 1e-3) / 1e9},
+                               "gpu_ms_per_step": gpu_ms, "output_GBps": 24.0 * N / (gpu_ms * 1e-3) / 1e9,
+                               "frac_of_hbm_peak": 24.0 * N / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "tile_config": tuned, "tile": api.tile_config_name(tuned),
+                               "autotune": {"best_ms": tuned_ms, "seconds": t_tune},
+                               "error_vs_oracle": err},
         "single_calls_fp64": {"vertices_per_s": N / el64, "ms_per_pass": 1e3 * el64, "calls": len(specs)},
     }
+
+
+def c1_variant(calls: int = 200):
+    """The plain single sweep (cubic path of 16 control points, closed cubic
+    profile of 8, 256 x 64, FP64 positions and normals): `calls` sweep_eval
+    calls after a warm-up, with the error against the oracle."""
+    import torch
+    import oracle
+    import synth
+
+    spec = synth.c1()
+    el, surf, frame, (pos, nrm) = time_single(spec, calls, 10, torch.float64, torch.float64, keep=True)
+    ref = oracle.sweep(spec.path, spec.profile, spec.n_u, spec.n_v)
+    err = oracle.compare(ref.pos, ref.nrm, ref.kappa, pos.cpu().numpy(), nrm.cpu().numpy(),
+                         oracle.bbox_diag(ref.pos), 1e6)
+    err["tolerance"] = 1e-12
+    N = spec.n_u * spec.n_v
+    return {"workload": "plain single sweep: cubic path 16 cps, closed cubic profile 8 cps, 256x64, FP64 out",
+            "calls": calls, "vertices_per_s": N * calls / el, "ms_per_call": 1e3 * el / calls,
+            "gpu_frame_ms": sum(frame) / len(frame), "gpu_surface_ms": sum(surf) / len(surf),
+            "error_vs_oracle": err}
 
 
 def write_probe(nbytes: int = 4 << 30, reps: int = 5) -> dict:
@@ -356,10 +438,14 @@ def adjoint_variant(steps: int):
     import synth
     from paper_1110_5450_amd import api
 
+    import oracle
+
     specs = synth.c5()
     b = api.Batch.from_specs(specs)
     N = b.n_vertices
-    g = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    # loss weights w ~ N(0, 1) per vertex and component (the configuration's)
+    wl = synth.loss_weights(specs, 55)
+    g = b.pack(wl, torch.float32)
     ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
     for _ in range(GRAPH_WARMUP):
         api.sweep_backward(b, g, workspace=ws)
@@ -369,6 +455,18 @@ def adjoint_variant(steps: int):
         api.sweep_backward(b, g, workspace=ws)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # relative gradient error against the oracle's FP64 central differences
+    # (h = 1e-6) on two sampled sweeps, with the FP32-rounded weights
+    gP, gQ = api.sweep_backward(b, g, workspace=ws)
+    gP, gQ = gP.cpu().numpy(), gQ.cpu().numpy()
+    adj_err = {"path_rel": 0.0, "prof_rel": 0.0, "sweeps": [0, 201], "tolerance": 1e-4}
+    for k in adj_err["sweeps"]:
+        s = specs[k]
+        fP, fQ = oracle.fd_grad(s.path, s.profile, s.n_u, s.n_v, wl[k].astype(np.float32).astype(np.float64))
+        adj_err["path_rel"] = max(adj_err["path_rel"],
+                                  float(np.linalg.norm(gP[b.path_slice(k)] - fP) / np.linalg.norm(fP)))
+        adj_err["prof_rel"] = max(adj_err["prof_rel"],
+                                  float(np.linalg.norm(gQ[b.prof_slice(k)] - fQ) / np.linalg.norm(fQ)))
     # positions and normals: the reduction reads both gradients
     gn = torch.randn(b.out_elems, dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(6))
     for _ in range(GRAPH_WARMUP):
@@ -415,7 +513,40 @@ def adjoint_variant(steps: int):
             "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9,
             "backward_with_normals_ms": 1e3 * el_n / steps,
             "backward_with_normals_grad_read_GBps": 24.0 * N / (el_n / steps) / 1e9,
-            "backward_with_normals_knots_weights_ms": 1e3 * el_p / steps}
+            "backward_with_normals_knots_weights_ms": 1e3 * el_p / steps,
+            "error_vs_oracle": adj_err}
+
+
+def batch_graph_only(steps: int):
+    """The 4096-sweep batch's graph replays alone (for counter runs)."""
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+
+    b = api.Batch.from_specs(synth.c4())
+    ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
+    pos = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pos)
+    for _ in range(steps):
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
+    torch.cuda.synchronize()
+    return {"vertices": b.n_vertices, "replays": steps, "tile_config": api.batched_config_for(b)}
+
+
+def adjoint_backward_only(steps: int):
+    """The differentiation workload's positions-only backward calls alone (for counter runs)."""
+    import torch
+    import synth
+    from paper_1110_5450_amd import api
+
+    specs = synth.c5()
+    b = api.Batch.from_specs(specs)
+    g = b.pack(synth.loss_weights(specs, 55), torch.float32)
+    ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
+    for _ in range(steps):
+        api.sweep_backward(b, g, workspace=ws)
+    torch.cuda.synchronize()
+    return {"vertices": b.n_vertices, "calls": steps}
 
 
 def precision_study(steps: int = 5):
@@ -476,7 +607,8 @@ def main():
     ap.add_argument("--precision-study", action="store_true")
     ap.add_argument("--variants-only", action="store_true",
                     help="run only the batched (4096 sweeps) and adjoint (256 sweeps) variants and print them")
-    ap.add_argument("--variant", choices=["rational", "frenet_law", "arclength", "triangles", "batched", "adjoint"],
+    ap.add_argument("--variant", choices=["rational", "frenet_law", "arclength", "triangles", "batched", "adjoint",
+                                          "c1", "batch-graph", "adjoint-backward"],
                     help="run only this variant and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (3 launches) whose counter readings scale "
@@ -502,13 +634,6 @@ def main():
         print(json.dumps(v), flush=True)
         return
 
-    if args.variant:
-        fn = {"rational": rational_variant, "frenet_law": frenet_law_variant, "arclength": arclength_variant,
-              "triangles": triangles_variant, "batched": batched_variants, "adjoint": adjoint_variant}[args.variant]
-        log(f"[bench] {args.variant} ...")
-        print(json.dumps({args.variant: fn(args.steps)}), flush=True)
-        return
-
     if args.copy_calibration:
         src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -518,6 +643,17 @@ def main():
         log(f"[bench] copy calibration: 3 x {COPY_CAL_BYTES} bytes read and written")
         del src, dst
         torch.cuda.empty_cache()
+
+    if args.variant:
+        fn = {"rational": rational_variant, "frenet_law": frenet_law_variant, "arclength": arclength_variant,
+              "triangles": triangles_variant, "batched": batched_variants, "adjoint": adjoint_variant,
+              "c1": lambda steps: c1_variant(), "batch-graph": batch_graph_only,
+              "adjoint-backward": adjoint_backward_only}[args.variant]
+        log(f"[bench] {args.variant} ...")
+        print(json.dumps({args.variant: fn(args.steps)}), flush=True)
+        return
+
+    from paper_1110_5450_amd import _lib, api
 
     spec = synth.c2()
     N = spec.n_u * spec.n_v
@@ -546,7 +682,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
-                     "kernel": "k_surface_tiles<float, true, true, 16> (surface write)", "alg_bytes_per_launch": bytes_alg,
+                     "kernel": "surface write, " + api.tile_config_name(
+                         _lib.sweep_surface_config_for(spec.n_u, spec.n_v, _lib.SWEEP_F32)),
+                     "alg_bytes_per_launch": bytes_alg,
                      "avg_launch_ms": surf_ms,
                      # the same rate against the measured store ceiling
                      "write_probe": probe, "frac_of_write_probe": achieved / probe["GBps"]},
@@ -563,6 +701,8 @@ def main():
             "plain_fp64_out": {"vertices_per_s": N * steps64 / el64, "ms_per_step": 1e3 * el64 / steps64,
                                "surface_ms": s64, "surface_GBps": 48.0 * N / (s64 * 1e-3) / 1e9},
         }
+        log("[bench] plain FP64 256x64 ...")
+        out["variants"]["plain_fp64_256x64"] = c1_variant()
         log("[bench] rational ...")
         out["variants"]["rational_fp32_out"] = rational_variant(steps64)
         log("[bench] frenet + law ...")

@@ -338,7 +338,9 @@ int32_t sweep_trace_read(int32_t *stage, float *ms, int32_t max);
  * tile_config = -1 in the same class use the recorded configuration.  When
  * the environment variable SWEEP_TUNE_CACHE names a file, the table is read
  * from it on first use and rewritten (to a temporary file, then renamed)
- * after each tuning.  best_config / best_ms may be NULL.
+ * after each tuning, one entry per line: kind (single / batch), architecture,
+ * CU count, the five class integers, configuration, milliseconds.
+ * best_config / best_ms may be NULL.
  */
 sweep_status sweep_autotune(const sweep_curve *path, const sweep_curve *profile, int32_t n_u, int32_t n_v,
                             const sweep_options *opt, void *pos, void *nrm, void *workspace, size_t ws_bytes,
@@ -347,6 +349,30 @@ sweep_status sweep_autotune(const sweep_curve *path, const sweep_curve *profile,
 /* The surface configuration tile_config = -1 selects for this shape and
  * output precision (the tuned one if recorded, else the built-in rule). */
 int32_t sweep_surface_config_for(int32_t n_u, int32_t n_v, int32_t out_precision);
+
+/*
+ * Batched autotuner.  Evaluates the batch once with tile_config = -1, then
+ * times the surface kernel of every linear tile configuration (256, 512,
+ * 1024 and 2048 consecutive vertices per block, plain and nontemporal
+ * stores; a batch has no column tiles) on that evaluation's row and profile
+ * tables, five launches each with HIP events on `stream` (the call waits for
+ * the stream; the outputs are rewritten with the same values), and records
+ * the fastest under the batch's shape class: device architecture and CU
+ * count, output precision, whether normals are written, floor(log2) of the
+ * sweep count, of the total vertex count and of the mean n_v.  Later
+ * sweep_eval_batched calls with tile_config = -1 in that class use it (the
+ * plan of that configuration is built on the next call).  The table is the
+ * one sweep_autotune keeps, persisted through SWEEP_TUNE_CACHE.  Arguments
+ * as sweep_eval_batched; best_config / best_ms may be NULL.
+ */
+sweep_status sweep_autotune_batched(const sweep_batch *batch, const sweep_options *opt, void *pos, void *nrm,
+                                    void *workspace, size_t ws_bytes, void *stream, int32_t *best_config,
+                                    float *best_ms);
+
+/* The tile_config index sweep_eval_batched uses for this batch and options
+ * (the tuned one for tile_config = -1 if recorded, else linear tiles of 1024
+ * vertices with nontemporal stores); -1 for an invalid batch. */
+int32_t sweep_batched_config_for(const sweep_batch *batch, const sweep_options *opt, int32_t with_normals);
 
 /*
  * Triangle list of an n_u x n_v grid (vertex (i, j) has index i*n_v + j, the
@@ -364,6 +390,10 @@ sweep_status sweep_triangles(int32_t n_u, int32_t n_v, int32_t closed_v, int32_t
 
 /* Number of fixed surface-kernel configurations accepted in tile_config. */
 int32_t sweep_tile_config_count(void);
+/* Configuration k: info (HOST, 4 int32) receives its kind (0 column tiles of
+ * 256 columns, 1 linear tiles), rows per block (kind 0), vertices per block
+ * (kind 1) and whether the stores are nontemporal. */
+sweep_status sweep_tile_config_info(int32_t k, int32_t *info);
 
 /* Thread-local text describing the last non-OK status on this thread. */
 const char *sweep_last_error(void);

@@ -106,12 +106,19 @@ def lib():
         L.sweep_autotune.argtypes = [C.POINTER(SweepCurve), C.POINTER(SweepCurve), C.c_int32, C.c_int32,
                                      C.POINTER(SweepOptions), vp, vp, vp, sz, vp, _ip, C.POINTER(C.c_float)]
         L.sweep_autotune.restype = C.c_int32
+        L.sweep_autotune_batched.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), vp, vp, vp, sz, vp, _ip,
+                                             C.POINTER(C.c_float)]
+        L.sweep_autotune_batched.restype = C.c_int32
+        L.sweep_batched_config_for.argtypes = [C.POINTER(SweepBatch), C.POINTER(SweepOptions), C.c_int32]
+        L.sweep_batched_config_for.restype = C.c_int32
         L.sweep_surface_config_for.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.sweep_surface_config_for.restype = C.c_int32
         L.sweep_triangles.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64), vp]
         L.sweep_triangles.restype = C.c_int32
         L.sweep_tile_config_count.argtypes = []
         L.sweep_tile_config_count.restype = C.c_int32
+        L.sweep_tile_config_info.argtypes = [C.c_int32, _ip]
+        L.sweep_tile_config_info.restype = C.c_int32
         L.sweep_last_error.argtypes = []
         L.sweep_last_error.restype = C.c_char_p
         L.sweep_version.argtypes = []
@@ -237,6 +244,13 @@ def sweep_tile_config_count() -> int:
     return lib().sweep_tile_config_count()
 
 
+def sweep_tile_config_info(k: int):
+    """(status, (kind, rows_per_block, tile_vertices, nontemporal))."""
+    a = (C.c_int32 * 4)()
+    st = lib().sweep_tile_config_info(k, a)
+    return st, tuple(a)
+
+
 def sweep_last_error() -> str:
     return last_error()
 
@@ -247,3 +261,17 @@ def sweep_version() -> int:
 
 def sweep_release_caches() -> None:
     lib().sweep_release_caches()
+
+
+def sweep_autotune_batched(batch: SweepBatch, opt: SweepOptions, pos: int, nrm: int, workspace: int, ws_bytes: int,
+                           stream: int):
+    """(status, best_config, best_ms)."""
+    c = C.c_int32(-1)
+    t = C.c_float(0.0)
+    st = lib().sweep_autotune_batched(C.byref(batch), C.byref(opt), pos, nrm, workspace, ws_bytes, stream,
+                                      C.byref(c), C.byref(t))
+    return st, c.value, t.value
+
+
+def sweep_batched_config_for(batch: SweepBatch, opt: SweepOptions, with_normals: int) -> int:
+    return lib().sweep_batched_config_for(C.byref(batch), C.byref(opt), with_normals)

@@ -412,6 +412,51 @@ def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=tor
     return pos, nrm
 
 
+def autotune_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
+                     reorthonormalize: bool = True, initial_normal=None, normals: bool = True, out=None,
+                     workspace: Optional[torch.Tensor] = None, stream=None):
+    """Time every batched surface tile configuration on this batch (into
+    `out` or fresh buffers) and record the fastest for its shape class;
+    returns (best_config, best_ms)."""
+    b = batch.c_struct()
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, -1)
+    ws_bytes = L.sweep_batched_workspace_size(b, opt)
+    if ws_bytes == 0:
+        L.check(L.sweep_eval_batched(b, opt, 0, 0, 0, 0, 0))
+    dev = batch.path_ctrl.device
+    if out is None:
+        pos = torch.empty(batch.out_elems, dtype=out_dtype, device=dev)
+        nrm = torch.empty(batch.out_elems, dtype=out_dtype, device=dev) if normals else None
+    else:
+        pos, nrm = out
+        _check_out(pos, batch.out_elems, out_dtype, "out[0]")
+        if nrm is not None:
+            _check_out(nrm, batch.out_elems, out_dtype, "out[1]")
+    if workspace is None or _nbytes(workspace) < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    st, cfg, ms = L.sweep_autotune_batched(b, opt, pos.data_ptr(), nrm.data_ptr() if nrm is not None else 0,
+                                           workspace.data_ptr(), _nbytes(workspace), _stream_handle(stream))
+    L.check(st)
+    return cfg, ms
+
+
+def batched_config_for(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
+                       tile_config: int = -1, normals: bool = True) -> int:
+    """The tile_config index sweep_eval_batched uses for this batch."""
+    return L.sweep_batched_config_for(batch.c_struct(),
+                                      make_options(out_dtype, frame_dtype, tile_config=tile_config), int(normals))
+
+
+def tile_config_name(k: int) -> str:
+    """Human-readable description of surface configuration k."""
+    st, (kind, rows, tv, nt) = L.sweep_tile_config_info(int(k))
+    L.check(st)
+    store = "nontemporal" if nt else "plain"
+    if kind == 0:
+        return f"config {k}: column tiles, 256 columns x {rows} row(s) per block, {store} stores"
+    return f"config {k}: linear tiles of {tv} vertices per block, {store} stores"
+
+
 def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
     return L.sweep_batched_workspace_size(batch.c_struct(), make_options(out_dtype, frame_dtype))
 

@@ -21,6 +21,12 @@ const SurfaceConfig& tile_config(int k);
 SurfaceConfig auto_surface_config(int n_u, int n_v, int t64);
 bool options_ext(const sweep_options* o);
 bool options_single_only(const sweep_options* o);
+// Autotuning table (tune_table.hip): best surface configuration per (kind,
+// device, shape class of kTuneClassInts integers), -1 if none recorded.
+constexpr int kTuneClassInts = 5;
+int tune_lookup(const char* kind, const int* cls);
+void tune_record(const char* kind, const int* cls, int config, float ms);
+int ilog2_ll(long long v);
 sweep_status upload_knots(const double* host_knots, int n, int p, double* dst, hipStream_t st);
 
 }  // namespace sweep

@@ -257,9 +257,56 @@ struct Plan {
     }
 };
 
-// Batched surface configuration for tile_config = -1: linear tiles of 1024
-// vertices with nontemporal stores.
-static SurfaceConfig batched_surface_config() { return SurfaceConfig{1, 0, 1024, 1}; }
+// Shape class of a batch for the tuning table: output precision, normals
+// written, floor(log2) of the sweep count, of the total vertex count and of
+// the mean n_v.
+static void batch_class(const sweep_batch* b, const sweep_options* o, bool with_nrm, int* cls)
+{
+    long long verts = 0, rows = 0;
+    for (int k = 0; k < b->n_sweeps; ++k) {
+        verts += (long long)b->n_u[k] * b->n_v[k];
+        rows += b->n_u[k];
+    }
+    const int c[kTuneClassInts] = {o->out_precision == SWEEP_F64 ? 1 : 0, with_nrm ? 1 : 0, ilog2_ll(b->n_sweeps),
+                                   ilog2_ll(verts), ilog2_ll(rows > 0 ? verts / rows : 1)};
+    for (int k = 0; k < kTuneClassInts; ++k) cls[k] = c[k];
+}
+
+// Built-in batched surface configuration: linear tiles of 1024 vertices with
+// nontemporal stores (tile_config index kBatchDefaultConfig).
+constexpr int kBatchDefaultConfig = 14;
+
+// Configuration index for tile_config = -1: the tuned one for the batch's
+// shape class if sweep_autotune_batched recorded one, else the built-in.
+static int batched_auto_config(const sweep_batch* b, const sweep_options* o, bool with_nrm)
+{
+    int cls[kTuneClassInts];
+    batch_class(b, o, with_nrm, cls);
+    const int c = tune_lookup("batch", cls);
+    return c >= 0 && tile_config(c).kind == 1 ? c : kBatchDefaultConfig;
+}
+
+// The options a plan is keyed and built with: tile_config = -1 resolved to
+// the configuration it selects, so that a tuned choice maps to the plan of
+// that configuration.
+static sweep_options resolved_options(const sweep_batch* b, const sweep_options* o, bool with_nrm)
+{
+    sweep_options r = *o;
+    if (r.tile_config < 0) r.tile_config = batched_auto_config(b, o, with_nrm);
+    return r;
+}
+
+// Surface tiles of tv consecutive vertices: (sweep, first local vertex) in
+// sweep order.
+static std::vector<int2> surface_tiles(const sweep_batch* b, int tv)
+{
+    std::vector<int2> tiles;
+    for (int k = 0; k < b->n_sweeps; ++k) {
+        const long long N = (long long)b->n_u[k] * b->n_v[k];
+        for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
+    }
+    return tiles;
+}
 
 static std::mutex g_mu;
 static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
@@ -279,14 +326,13 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     // surface tiles: (sweep, first local vertex) in sweep order; sweeps by
     // path degree, longest first (the frame blocks' work is proportional to
     // n_u); profile chunks: (sweep, chunk) of every 256 v-samples
-    const SurfaceConfig cfg = o->tile_config >= 0 ? tile_config(o->tile_config) : batched_surface_config();
+    const SurfaceConfig cfg = tile_config(o->tile_config);   // resolved by the caller
     // column-tile configurations map to one-row-sized linear tiles
     const int tv = cfg.kind == 1 ? cfg.tile_vertices : kBlock;
-    std::vector<int2> tiles, vchunks;
+    const std::vector<int2> tiles = surface_tiles(b, tv);
+    std::vector<int2> vchunks;
     std::vector<int> sweeps[8];
     for (int k = 0; k < b->n_sweeps; ++k) {
-        const long long N = (long long)b->n_u[k] * b->n_v[k];
-        for (long long v = 0; v < N; v += tv) tiles.push_back(make_int2(k, (int)v));
         sweeps[b->path_degree[k]].push_back(k);
         for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
@@ -428,8 +474,11 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     if (!opt) { sweep_default_options(&def); opt = &def; }
     BatchKey key;
     BatchLayout L;
-    sweep_status st = check_batch(batch, opt, &key, &L, nullptr, nullptr);
+    sweep_status st = check_batch(batch, opt, nullptr, nullptr, nullptr, nullptr);
     if (st != SWEEP_OK) return st;
+    const sweep_options ro = resolved_options(batch, opt, nrm != nullptr);
+    opt = &ro;
+    if ((st = check_batch(batch, opt, &key, &L, nullptr, nullptr)) != SWEEP_OK) return st;
     if (!pos) return fail(SWEEP_ERR_NULL_ARG, "pos is NULL");
     if (!workspace || ws_bytes < L.total)
         return fail(SWEEP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu required", workspace ? ws_bytes : (size_t)0, L.total);
@@ -496,8 +545,11 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
     if (!opt) { sweep_default_options(&def); opt = &def; }
     BatchKey key;
     BatchLayout L;
-    sweep_status st = check_batch(batch, opt, &key, &L, nullptr, nullptr);
+    sweep_status st = check_batch(batch, opt, nullptr, nullptr, nullptr, nullptr);
     if (st != SWEEP_OK) return st;
+    const sweep_options ro = resolved_options(batch, opt, true);
+    opt = &ro;
+    if ((st = check_batch(batch, opt, &key, &L, nullptr, nullptr)) != SWEEP_OK) return st;
     if (!grad_pos && !grad_nrm) return fail(SWEEP_ERR_NULL_ARG, "grad_pos and grad_nrm are both NULL");
     if (!grad_path_ctrl || !grad_prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "a gradient buffer is NULL");
     const int nrm = grad_nrm != nullptr;
@@ -651,6 +703,94 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
                 return hip_fail(e, "backward knot and weight gradients");
         }
     }
+    return SWEEP_OK;
+}
+
+int32_t sweep_batched_config_for(const sweep_batch* batch, const sweep_options* opt, int32_t with_normals)
+{
+    sweep_options def;
+    if (!opt) { sweep_default_options(&def); opt = &def; }
+    if (check_batch(batch, opt, nullptr, nullptr, nullptr, nullptr) != SWEEP_OK) return -1;
+    if (opt->tile_config >= 0) return tile_config(opt->tile_config).kind == 1 ? opt->tile_config : -1;
+    return batched_auto_config(batch, opt, with_normals != 0);
+}
+
+sweep_status sweep_autotune_batched(const sweep_batch* batch, const sweep_options* opt, void* pos, void* nrm,
+                                    void* workspace, size_t ws_bytes, void* stream, int32_t* best_config,
+                                    float* best_ms)
+{
+    sweep_options o;
+    if (opt) o = *opt; else sweep_default_options(&o);
+    o.tile_config = -1;
+    // validates everything, builds (or finds) the automatic plan and leaves
+    // the row and profile tables in the workspace
+    sweep_status st = sweep_eval_batched(batch, &o, pos, nrm, workspace, ws_bytes, stream);
+    if (st != SWEEP_OK) return st;
+    BatchLayout L;
+    if ((st = check_batch(batch, &o, nullptr, &L, nullptr, nullptr)) != SWEEP_OK) return st;
+    const sweep_options ro = resolved_options(batch, &o, nrm != nullptr);
+    BatchKey key;
+    if ((st = check_batch(batch, &ro, &key, nullptr, nullptr, nullptr)) != SWEEP_OK) return st;
+    hipError_t e = hipGetDevice(&key.device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    key.ints.push_back(nrm ? 1 : 0);
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = ro.frame_precision == SWEEP_F64, t64 = ro.out_precision == SWEEP_F64;
+    char* ws = (char*)workspace;
+    const void* rows = ws + L.rows;
+    const void* ptab = ws + L.ptab;
+    // Every linear surface configuration is timed on the plan's descriptors
+    // and tables with a tile list of its own (the surface kernel alone: the
+    // profile and frame stages do not depend on the tile).
+    std::lock_guard<std::mutex> lock(g_mu);
+    Plan* P = nullptr;
+    if ((st = get_plan(batch, &ro, nrm != nullptr, std::move(key), &P)) != SWEEP_OK) return st;
+    const BatchDesc* descs = P->d_descs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int2* d_tiles = nullptr;
+    int best = -1;
+    float best_t = 0.f;
+    const int reps = 5;
+    if ((e = hipEventCreate(&ev0)) == hipSuccess && (e = hipEventCreate(&ev1)) == hipSuccess) {
+        for (int c = 0; c < tile_config_count() && e == hipSuccess; ++c) {
+            const SurfaceConfig& cfg = tile_config(c);
+            if (cfg.kind != 1) continue;   // a batch has linear tiles only
+            const std::vector<int2> tiles = surface_tiles(batch, cfg.tile_vertices);
+            if ((e = hipMalloc(&d_tiles, sizeof(int2) * tiles.size())) != hipSuccess) break;
+            if ((e = hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
+                break;
+            const BatchedKernels K = batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices);
+            const int2* tl = d_tiles;
+            void* pp = pos;
+            void* np = nrm;
+            void* args[6] = {&descs, &tl, &rows, &ptab, &pp, &np};
+            auto run = [&]() { return hipLaunchKernel(K.surface, dim3((unsigned)tiles.size()), dim3(kBlock), args, 0, s); };
+            if ((e = run()) != hipSuccess) break;   // warm-up
+            if ((e = hipEventRecord(ev0, s)) != hipSuccess) break;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+            if (e != hipSuccess || (e = hipEventRecord(ev1, s)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess)
+                break;
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) break;
+            ms /= reps;
+            if (best < 0 || ms < best_t) { best = c; best_t = ms; }
+            // the launches have completed (the event after them was waited on)
+            hipFree(d_tiles);
+            d_tiles = nullptr;
+        }
+    }
+    if (d_tiles) {
+        hipStreamSynchronize(s);
+        hipFree(d_tiles);
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    if (e != hipSuccess) return hip_fail(e, "batched autotune");
+    int cls[kTuneClassInts];
+    batch_class(batch, &o, nrm != nullptr, cls);
+    tune_record("batch", cls, best, best_t);
+    if (best_config) *best_config = best;
+    if (best_ms) *best_ms = best_t;
     return SWEEP_OK;
 }
 

@@ -159,6 +159,18 @@ void sweep_default_options(sweep_options* opt)
 
 int32_t sweep_tile_config_count(void) { return tile_config_count(); }
 
+sweep_status sweep_tile_config_info(int32_t k, int32_t* info)
+{
+    if (!info) return fail(SWEEP_ERR_NULL_ARG, "info is NULL");
+    if (k < 0 || k >= tile_config_count()) return fail(SWEEP_ERR_BAD_OPTION, "tile_config %d outside 0..%d", k, tile_config_count() - 1);
+    const SurfaceConfig& c = tile_config(k);
+    info[0] = c.kind;
+    info[1] = c.rows_per_block;
+    info[2] = c.tile_vertices;
+    info[3] = c.nontemporal;
+    return SWEEP_OK;
+}
+
 const char* sweep_last_error(void) { return g_last_error.c_str(); }
 
 int32_t sweep_version(void) { return SWEEP_VERSION; }

@@ -52,94 +52,12 @@ static double domain_length(const sweep_curve* c)
 
 // ----------------------------------------------------------------- tuning
 
-struct TuneKey {
-    std::string arch;
-    int cus, t64, nv256, lnv, ln;
-    bool operator<(const TuneKey& o) const
-    {
-        return std::tie(arch, cus, t64, nv256, lnv, ln) < std::tie(o.arch, o.cus, o.t64, o.nv256, o.lnv, o.ln);
-    }
-};
-struct TuneVal {
-    int config;
-    float ms;
-};
-
-static std::mutex g_tune_mu;
-static std::map<TuneKey, TuneVal> g_tuned;
-static bool g_tune_loaded = false;
-static std::string g_arch;
-static int g_cus = -1;
-
-static int ilog2(long long v)
+// Shape class of a single sweep for the tuning table: output precision,
+// n_v a multiple of 256, floor(log2 n_v), floor(log2 n_u*n_v).
+static void single_class(int n_u, int n_v, int t64, int* cls)
 {
-    int l = 0;
-    while (v > 1) { v >>= 1; ++l; }
-    return l;
-}
-
-static void device_identity()
-{
-    if (g_cus >= 0) return;
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-        g_arch = prop.gcnArchName;
-        const size_t colon = g_arch.find(':');
-        if (colon != std::string::npos) g_arch.resize(colon);
-        g_cus = prop.multiProcessorCount;
-    } else {
-        (void)hipGetLastError();
-        g_arch = "unknown";
-        g_cus = 0;
-    }
-}
-
-static TuneKey tune_key(int n_u, int n_v, int t64)
-{
-    device_identity();
-    return TuneKey{g_arch, g_cus, t64, n_v % 256 == 0 ? 1 : 0, ilog2(n_v), ilog2((long long)n_u * n_v)};
-}
-
-// Cache file: one entry per line,
-//   arch cus t64 nv256 lnv ln config ms
-static void tune_load_locked()
-{
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char* path = std::getenv("SWEEP_TUNE_CACHE");
-    if (!path || !*path) return;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return;
-    char line[256];
-    while (std::fgets(line, sizeof line, f)) {
-        char arch[64];
-        TuneKey k;
-        TuneVal v;
-        if (line[0] == '#') continue;
-        if (std::sscanf(line, "%63s %d %d %d %d %d %d %f", arch, &k.cus, &k.t64, &k.nv256, &k.lnv, &k.ln, &v.config,
-                        &v.ms) == 8 &&
-            v.config >= 0 && v.config < tile_config_count()) {
-            k.arch = arch;
-            g_tuned[k] = v;
-        }
-    }
-    std::fclose(f);
-}
-
-static void tune_save_locked()
-{
-    const char* path = std::getenv("SWEEP_TUNE_CACHE");
-    if (!path || !*path) return;
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "w");
-    if (!f) return;
-    std::fprintf(f, "# sweep surface tuning: arch cus t64 nv256 log2_nv log2_vertices config ms\n");
-    for (const auto& e : g_tuned)
-        std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", e.first.arch.c_str(), e.first.cus, e.first.t64,
-                     e.first.nv256, e.first.lnv, e.first.ln, e.second.config, e.second.ms);
-    std::fclose(f);
-    std::rename(tmp.c_str(), path);
+    const int c[kTuneClassInts] = {t64, n_v % 256 == 0 ? 1 : 0, ilog2_ll(n_v), ilog2_ll((long long)n_u * n_v), 0};
+    for (int k = 0; k < kTuneClassInts; ++k) cls[k] = c[k];
 }
 
 // Built-in rule (nontemporal stores measured 15-25 % faster for this
@@ -153,11 +71,10 @@ static SurfaceConfig rule_surface_config(int n_v)
 
 SurfaceConfig auto_surface_config(int n_u, int n_v, int t64)
 {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    tune_load_locked();
-    const auto it = g_tuned.find(tune_key(n_u, n_v, t64));
-    if (it != g_tuned.end()) return tile_config(it->second.config);
-    return rule_surface_config(n_v);
+    int cls[kTuneClassInts];
+    single_class(n_u, n_v, t64, cls);
+    const int c = tune_lookup("single", cls);
+    return c >= 0 ? tile_config(c) : rule_surface_config(n_v);
 }
 
 // ---------------------------------------------------------- workspace plan
@@ -463,10 +380,9 @@ sweep_status sweep_autotune(const sweep_curve* path, const sweep_curve* profile,
     hipEventDestroy(ev1);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     {
-        std::lock_guard<std::mutex> lock(g_tune_mu);
-        tune_load_locked();
-        g_tuned[tune_key(n_u, n_v, t64)] = TuneVal{best, best_t};
-        tune_save_locked();
+        int cls[kTuneClassInts];
+        single_class(n_u, n_v, t64, cls);
+        tune_record("single", cls, best, best_t);
     }
     if (best_config) *best_config = best;
     if (best_ms) *best_ms = best_t;

@@ -208,6 +208,65 @@ int plans()
     return v + bad;
 }
 
+// The batched autotuner on the four-sweep rational batch: plans for every
+// candidate configuration, timed replays, then the automatic plan dropped and
+// rebuilt with the recorded choice.
+int tune()
+{
+    std::mt19937 rng(11);
+    HostBatch h;
+    make_batch(h, {3, 2, 3, 4}, {200, 999, 64, 5000}, {40, 17, 256, 9}, true, rng);
+    sweep_options opt;
+    sweep_default_options(&opt);
+    const int64_t elems = sweep_batched_output_elems(&h.b);
+    float* pos = (float*)dev_alloc(sizeof(float) * elems);
+    float* nrm = (float*)dev_alloc(sizeof(float) * elems);
+    const size_t wb = sweep_batched_workspace_size(&h.b, &opt);
+    void* ws = dev_alloc(wb);
+    int32_t cfg = -1;
+    float ms = -1.f;
+    int bad = check(sweep_autotune_batched(&h.b, &opt, pos, nrm, ws, wb, (hipStream_t)0x1, &cfg, &ms),
+                    "sweep_autotune_batched");
+    const int auto_cfg = sweep_batched_config_for(&h.b, &opt, 1);
+    bad += check(sweep_eval_batched(&h.b, &opt, pos, nrm, ws, wb, (hipStream_t)0x1), "sweep_eval_batched");
+    // then more batch shapes than the plan cache holds (evictions), each
+    // evaluated and differentiated, on the null stream
+    std::vector<HostBatch> more(24);
+    for (int i = 0; i < 24; ++i) {
+        std::vector<int> deg, nu, nv;
+        for (int k = 0; k < 1 + i % 4; ++k) {
+            deg.push_back(1 + (i + k) % 7);
+            nu.push_back(20 + 53 * i + 7 * k + (i % 5 == 1 ? 4200 : 0));
+            nv.push_back(5 + (i * 11 + k) % 90);
+        }
+        make_batch(more[i], deg, nu, nv, i % 3 == 0, rng);
+        const int64_t e2 = sweep_batched_output_elems(&more[i].b);
+        float* p2 = (float*)dev_alloc(sizeof(float) * e2);
+        float* n2 = (float*)dev_alloc(sizeof(float) * e2);
+        const size_t w2 = sweep_batched_workspace_size(&more[i].b, &opt);
+        void* ws2 = dev_alloc(w2);
+        bad += check(sweep_eval_batched(&more[i].b, &opt, p2, n2, ws2, w2, nullptr), "sweep_eval_batched");
+        if (i % 2 == 0) {
+            int32_t c2 = -1;
+            float m2 = 0.f;
+            bad += check(sweep_autotune_batched(&more[i].b, &opt, p2, n2, ws2, w2, nullptr, &c2, &m2),
+                         "sweep_autotune_batched");
+        }
+        const size_t wbk = sweep_backward_workspace_size(&more[i].b, &opt);
+        void* wsb = dev_alloc(wbk);
+        long long np = 0, nq = 0;
+        for (int k = 0; k < more[i].b.n_sweeps; ++k) { np += more[i].path_n[k]; nq += more[i].prof_n[k]; }
+        double* gP = (double*)dev_alloc(sizeof(double) * 3 * np);
+        double* gQ = (double*)dev_alloc(sizeof(double) * 3 * nq);
+        bad += check(sweep_backward(&more[i].b, &opt, p2, gP, gQ, wsb, wbk, nullptr), "sweep_backward");
+    }
+    hipDeviceSynchronize();
+    sweep_release_caches();
+    std::printf("tuned config %d (%.3f ms), automatic config %d\n", cfg, ms, auto_cfg);
+    const int v = stub::report(true);
+    return v + bad + (cfg < 0 || auto_cfg != cfg ? 1 : 0);
+}
+
 void table()
 {
     for (const stub::KernelSig* k : stub::all_kernels()) std::printf("%s %zu\n", k->name, k->args.size());
@@ -226,5 +285,6 @@ int main(int argc, char** argv)
         table();
         return 0;
     }
+    if (!std::strcmp(mode, "tune")) return tune() == 0 ? 0 : 1;
     return plans() == 0 ? 0 : 1;
 }

@@ -1,7 +1,8 @@
-"""Surface autotuner: it times every fixed surface configuration, its output
-still meets the parity rule against the oracle, the choice is recorded for
-the shape class (tile_config = -1 then selects it, bitwise the same as asking
-for it by index), and the table is written to the cache file."""
+"""Surface autotuners (single sweep and batch): each times its candidate
+surface configurations, the output still meets the parity rule against the
+oracle, the choice is recorded for the shape class (tile_config = -1 then
+selects it, bitwise the same as asking for it by index), and the table is
+written to the cache file."""
 
 from __future__ import annotations
 
@@ -44,7 +45,37 @@ def test_autotune_records_and_selects(tmp_path, out_dtype):
         assert torch.equal(pa, pb) and torch.equal(na, nb)
         lines = [ln.split() for ln in cache.read_text().splitlines() if not ln.startswith("#")]
         t64 = 1 if out_dtype == torch.float64 else 0
-        mine = [ln for ln in lines if ln[2] == str(t64) and ln[3] == "0" and ln[4] == str(int(np.log2(384)))]
-        assert mine and int(mine[-1][6]) == best
+        # kind arch cus t64 nv256 log2_nv log2_vertices 0 config ms
+        mine = [ln for ln in lines
+                if ln[0] == "single" and ln[3] == str(t64) and ln[4] == "0" and ln[5] == str(int(np.log2(384)))]
+        assert mine and int(mine[-1][8]) == best
+    finally:
+        os.environ.pop("SWEEP_TUNE_CACHE", None)
+
+
+def test_batched_autotune_records_and_selects(tmp_path):
+    cache = tmp_path / "tune.txt"
+    os.environ["SWEEP_TUNE_CACHE"] = str(cache)
+    try:
+        specs = synth.c4(n_sweeps=96, seed=41)
+        b = api.Batch.from_specs(specs)
+        say(f"[case] batched autotune: {len(specs)} sweeps")
+        best, ms = api.autotune_batched(b)
+        torch.cuda.synchronize()
+        say("   best", best, ms)
+        assert 0 <= best < api.L.sweep_tile_config_count() and ms > 0.0
+        assert api.batched_config_for(b) == best
+        pa, na = api.sweep_eval_batched(b)                       # tile_config = -1: the tuned one
+        pb, nb = api.sweep_eval_batched(b, tile_config=best)
+        torch.cuda.synchronize()
+        assert torch.equal(pa, pb) and torch.equal(na, nb)
+        for k, s in enumerate(specs):
+            ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
+            ok, r = parity(ref.pos, ref.nrm, ref.kappa, b.view(pa, k).double().cpu().numpy(),
+                           b.view(na, k).double().cpu().numpy(), TOL[torch.float32])
+            assert ok, (k, r)
+        lines = [ln.split() for ln in cache.read_text().splitlines() if not ln.startswith("#")]
+        mine = [ln for ln in lines if ln[0] == "batch"]
+        assert mine and int(mine[-1][8]) == best
     finally:
         os.environ.pop("SWEEP_TUNE_CACHE", None)

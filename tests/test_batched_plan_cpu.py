@@ -1,7 +1,7 @@
 """Host-side checks of the batched plan code (plan build, graph parameter
 updates, eviction, adjoint launches) on the CPU.
 
-``batched_abi.hip`` and ``host_checks.hip`` are compiled for the host only
+``batched_abi.hip``, ``host_checks.hip`` and ``tune_table.hip`` are compiled for the host only
 and linked, with AddressSanitizer and UndefinedBehaviorSanitizer, against a
 CPU stand-in of the HIP runtime (``tests/plan_host/hip_stub.cpp``) whose
 kernel table lists each kernel's parameters.  The stand-in reads every
@@ -35,6 +35,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(CLANG), reason="ROCm clang is
 def driver(tmp_path_factory):
     d = tmp_path_factory.mktemp("plan_host")
     srcs = [os.path.join(CSRC, "batched_abi.hip"), os.path.join(CSRC, "host_checks.hip"),
+            os.path.join(CSRC, "tune_table.hip"),
             os.path.join(HOST, "stub_kernels.cpp"), os.path.join(HOST, "hip_stub.cpp"),
             os.path.join(HOST, "plan_driver.cpp")]
     objs = []
@@ -74,6 +75,16 @@ def test_plans_evictions_and_updates_are_clean(driver):
     launches = int(re.search(r"graph launches (\d+)", r.stdout).group(1))
     updates = int(re.search(r"parameter updates (\d+)", r.stdout).group(1))
     assert launches == 3 * 42 and updates > 0
+
+
+def test_batched_autotuner_records_and_rebuilds(driver):
+    r = _run(driver, "tune")
+    print(r.stdout)
+    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-6000:]
+    assert r.returncode == 0, r.stdout + r.stderr[-6000:]
+    assert "violations 0" in r.stdout
+    m = re.search(r"tuned config (\d+) .* automatic config (\d+)", r.stdout)
+    assert m and m.group(1) == m.group(2)
 
 
 def _param_count(src: str, name: str) -> int:
