@@ -27,18 +27,18 @@
 // kbw_reduce   one wave per (sweep, group of G rows, 64 columns): streaming
 //              read of w through an LDS tile, per-row partials over the 64
 //              columns and per-column partials over the G rows.
-// kbw_adjoint  one block per sweep: finishes the partial sums, runs the
-//              suffix sum, the per-sample adjoint and the per-control-point
-//              gathers.
+// kbw_rows, kbw_samples, kbw_final: the rest of the adjoint (described
+//              with the kernels below).
 #include "basis_ders.hpp"
 #include "frame_common.hpp"
 
 namespace sweep {
 
-// One wave per unit (sweep, group of G rows, segment of 64 columns); each
-// wave's LDS tiles are its own (no block barriers).  Lane = column j loads its G x 3
-// values of w (coalesced) and keeps them in registers for the column sums
-//   h_j += R_i^T w_ij over the G rows;
+// One wave per unit (sweep, kBwSub groups of G rows, segment of 64 columns);
+// each wave's LDS tiles are its own (no block barriers).  For each group,
+// lane = column j loads its G x 3 values of w (coalesced) and keeps them in
+// registers for the column sums
+//   h_j += R_i^T w_ij over the unit's rows (one partial per unit);
 // the values also go to an LDS tile (rows padded to 65 elements: no bank
 // conflicts) from which lane = (component c, row r, half h) forms the row
 // sums over 32 of the 64 columns; the two halves are added in a fixed order
@@ -79,11 +79,8 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
     const BatchDesc& d = descs[un.x];
     const int n_u = d.n_u, n_v = d.n_v;
     const int g = un.y, seg = un.z;
-    const int i0 = g * G;
-    const int nr = live ? min(G, n_u - i0) : 0;
     const int j = seg * 64 + lane;
     const bool vj = live && j < n_v;
-    T w[3][G];
     {
         double S0 = 0.0, S1 = 0.0, S2 = 0.0;
         if (vj) {
@@ -91,6 +88,18 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
             S0 = q[0]; S1 = q[1]; S2 = q[2];
         }
         ls[wave][0][lane] = S0; ls[wave][1][lane] = S1; ls[wave][2][lane] = S2;
+    }
+    // column sums over the unit's kBwSub groups of G rows
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    V3<double> hD = mk(0.0, 0.0, 0.0);
+#pragma nounroll
+    for (int sub = 0; sub < kBwSub; ++sub) {
+    const int i0 = (g * kBwSub + sub) * G;
+    if (!live || i0 >= n_u) break;   // wave-uniform
+    const int nr = min(G, n_u - i0);
+    wave_lds_sync();   // the previous group's LDS tiles are consumed
+    T w[3][G];
+    {
         const size_t P = (size_t)d.plane;   // plane stride of the batched layout
         const T* w0 = grad ? grad + d.out_off : nullptr;
 #pragma unroll
@@ -109,7 +118,6 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         }
     }
     const double* R0 = rows + 16 * (d.row_off + i0);
-    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
     if (vj) {
 #pragma unroll
         for (int r = 0; r < G; ++r) {
@@ -160,7 +168,6 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         const T* g0 = gnrm + d.out_off;
         double* buf = reinterpret_cast<double*>(&lw[wave][0][0][0]);   // 12 x 65 doubles
         static_assert(sizeof(lw[0]) >= 12 * 65 * sizeof(double), "LDS tile too small for the normal terms");
-        V3<double> hD = mk(0.0, 0.0, 0.0);
         const int e = lane >> 2, kq = lane & 3;
         for (int r = 0; r < G; ++r) {
             double cv[12];
@@ -207,14 +214,12 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
             if (live && r < nr && lane < 48 && kq == 0)
                 rowpart[RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r) + kRowPart + e] = part;
         }
-        if (vj) {
-            double* qd = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
-            qd[3] = hD.x; qd[4] = hD.y; qd[5] = hD.z;
-        }
     }
+    }   // groups of G rows
     if (vj) {
         double* q = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
         q[0] = h0; q[1] = h1; q[2] = h2;
+        if (NRM) { q[3] = hD.x; q[4] = hD.y; q[5] = hD.z; }
     }
 }
 
@@ -447,39 +452,57 @@ __device__ __forceinline__ void fold_normal_frame_terms(const DCurve& path, int 
     a[9] = Gt.x; a[10] = Gt.y; a[11] = Gt.z;
 }
 
-__global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restrict__ descs,
-                                                      const double* __restrict__ path_ctrl,
-                                                      const double* __restrict__ prof_ctrl,
-                                                      const double* __restrict__ path_w,
-                                                      const double* __restrict__ prof_w,
-                                                      const double* __restrict__ knots, InitialNormal n0,
-                                                      const double* __restrict__ rows, const double* rowpart,
-                                                      const double* colpart, double* rowacc, double* colacc,
-                                                      double* rho, double* sgrad, int* spans_u, double* qgrad,
-                                                      int* spans_v, double* __restrict__ gP, double* __restrict__ gQ,
-                                                      int nrm, double* xstash)
-{
-    const int rp = nrm ? kRowPartNrm : kRowPart, cp = nrm ? kColPartNrm : kColPart;
-    __shared__ double lds3[kWaves][3];
-    __shared__ double lpart[kBlock][kColPartNrm];
-    const BatchDesc d = descs[blockIdx.x];
-    const DCurve path{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
-                      d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
-    const DCurve prof{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
-                      d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
-                      prof_w ? prof_w + d.prof_ctrl_off : nullptr};
-    const int n_u = d.n_u, n_v = d.n_v;
-    const double* rows_k = rows + 16 * d.row_off;
-    double* racc = rowacc + (size_t)rp * d.row_off;
-    double* cacc = colacc + (size_t)cp * d.ptab_off;
-    double* rho_k = rho + 3 * d.row_off;
-    double* sg = sgrad + 24 * d.row_off;
-    int* su = spans_u + d.row_off;
-    double* qg = qgrad + 24 * d.ptab_off;
-    int* sv = spans_v + d.ptab_off;
+// The adjoint after kbw_reduce, in three launches:
+//
+// kbw_rows     one block per (sweep, chunk of kBlock u-samples): finishes the
+//              row sums (fixed order over the column segments), folds in the
+//              normal terms' share of dL/dr, dL/ds, dL/dt, forms each row's
+//              direct term d_i = R_i^T rbar_i^dir and its suffix sum inside
+//              the chunk; the chunk's total goes to ctot.
+// kbw_samples  one block per (sweep, chunk): rho_i = (suffix inside the
+//              chunk) + (totals of the later chunks, added from the last one
+//              down), then the per-sample adjoint of x_i and C'_i (step
+//              adjoints, the initial-normal rule at i = 0, the tangent
+//              normalisation) and its basis contributions to the control
+//              points of the sample's span.
+// kbw_final    one block per sweep: finishes the column sums, the profile
+//              samples' basis contributions and the gathers per control point.
+// Sums run in FP64 in a fixed order: the result does not depend on
+// scheduling.
 
-    // 1. finish the partial sums (fixed order over segments / groups)
-    for (int i = threadIdx.x; i < n_u; i += kBlock) {
+__device__ __forceinline__ DCurve path_curve(const BatchDesc& d, const double* path_ctrl, const double* path_w,
+                                             const double* knots)
+{
+    return DCurve{path_ctrl + 3 * d.path_ctrl_off, d.path_knot_off >= 0 ? knots + d.path_knot_off : nullptr,
+                  d.n_path, d.p_path, 0, d.n_path, path_w ? path_w + d.path_ctrl_off : nullptr};
+}
+__device__ __forceinline__ DCurve prof_curve(const BatchDesc& d, const double* prof_ctrl, const double* prof_w,
+                                             const double* knots)
+{
+    return DCurve{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
+                  d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
+                  prof_w ? prof_w + d.prof_ctrl_off : nullptr};
+}
+
+// Chunk totals of the rows' direct terms: 3 doubles per (sweep, chunk), the
+// chunks of sweep k starting at ctot_off(k) = sum of earlier chunk counts.
+__global__ __launch_bounds__(kBlock) void kbw_rows(const BatchDesc* __restrict__ descs,
+                                                   const int2* __restrict__ chunks,
+                                                   const double* __restrict__ path_ctrl,
+                                                   const double* __restrict__ path_w,
+                                                   const double* __restrict__ knots,
+                                                   const double* __restrict__ rows, const double* rowpart,
+                                                   double* rowacc, double* sfx, double* ctot, int nrm)
+{
+    __shared__ double lds3[kWaves][3];
+    const int2 ch = chunks[blockIdx.x];
+    const BatchDesc d = descs[ch.x];
+    const DCurve path = path_curve(d, path_ctrl, path_w, knots);
+    const int rp = nrm ? kRowPartNrm : kRowPart;
+    const int n_u = d.n_u;
+    const int i = ch.y * kBlock + threadIdx.x;
+    V3<double> di = mk(0.0, 0.0, 0.0);
+    if (i < n_u) {
         double a[kRowPartNrm];
 #pragma unroll
         for (int e = 0; e < kRowPartNrm; ++e) a[e] = 0.0;
@@ -489,10 +512,163 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
             for (int e = 0; e < kRowPartNrm; ++e)
                 if (e < rp) a[e] += q[e];
         }
+        const RowRec R = row_at(rows + 16 * (d.row_off + (size_t)i));
+        if (nrm) fold_normal_frame_terms(path, i, n_u, R, a);
+        double* ra = rowacc + rp * (d.row_off + (size_t)i);
 #pragma unroll
         for (int e = 0; e < kRowPartNrm; ++e)
-            if (e < rp) racc[rp * (size_t)i + e] = a[e];
+            if (e < rp) ra[e] = a[e];
+        const V3<double> Gr = mk(a[3], a[4], a[5]), Gs = mk(a[6], a[7], a[8]);
+        const V3<double> rb = Gr + cross(Gs, R.t);
+        di = mk(dot(R.r, rb), dot(R.s, rb), dot(R.t, rb));
     }
+    V3<double> total;
+    const V3<double> s = block_suffix_sum(di, lds3, total);
+    if (i < n_u) {
+        double* q = sfx + 3 * (d.row_off + (size_t)i);
+        q[0] = s.x; q[1] = s.y; q[2] = s.z;
+    }
+    if (threadIdx.x == 0) {
+        double* q = ctot + 3 * (d.ctot_off + ch.y);
+        q[0] = total.x; q[1] = total.y; q[2] = total.z;
+    }
+}
+
+// Totals of the sweep's chunks after chunk c, added from the last one down.
+__device__ __forceinline__ V3<double> later_chunks(const double* ctot, const BatchDesc& d, int c)
+{
+    const int nc = (d.n_u + kBlock - 1) / kBlock;
+    V3<double> carry = mk(0.0, 0.0, 0.0);
+    for (int b = nc - 1; b > c; --b) {
+        const double* q = ctot + 3 * (d.ctot_off + b);
+        carry = carry + mk(q[0], q[1], q[2]);
+    }
+    return carry;
+}
+
+__global__ __launch_bounds__(kBlock) void kbw_samples(const BatchDesc* __restrict__ descs,
+                                                      const int2* __restrict__ chunks,
+                                                      const double* __restrict__ path_ctrl,
+                                                      const double* __restrict__ path_w,
+                                                      const double* __restrict__ knots, InitialNormal n0,
+                                                      const double* __restrict__ rows, const double* rowacc,
+                                                      const double* sfx, const double* ctot, double* sgrad,
+                                                      int* spans_u, int nrm, double* xstash)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const BatchDesc d = descs[ch.x];
+    const DCurve path = path_curve(d, path_ctrl, path_w, knots);
+    const int rp = nrm ? kRowPartNrm : kRowPart;
+    const int n_u = d.n_u;
+    const int i = ch.y * kBlock + threadIdx.x;
+    if (i >= n_u) return;
+    const double* rows_k = rows + 16 * d.row_off;
+    const V3<double> carry = later_chunks(ctot, d, ch.y);
+    // rho of the next sample: the next chunk's suffix plus its own carry
+    const bool next_in_chunk = threadIdx.x + 1 < kBlock;
+    const V3<double> carry_next = next_in_chunk ? carry : later_chunks(ctot, d, ch.y + 1);
+    auto rho_at = [&](int k, V3<double> c) {
+        const double* q = sfx + 3 * (d.row_off + (size_t)k);
+        return mk(q[0], q[1], q[2]) + c;
+    };
+    const RowRec R = row_at(rows_k + 16 * (size_t)i);
+    // (with the normal terms, values 3..11 hold the totals: kbw_rows)
+    const double* a = rowacc + rp * (d.row_off + (size_t)i);
+    const V3<double> g = mk(a[0], a[1], a[2]), Gs = mk(a[6], a[7], a[8]), Gt = mk(a[9], a[10], a[11]);
+    double Nv[kMaxDeg + 1], dN[kMaxDeg + 1], d2N[kMaxDeg + 1];
+    const int s = sample_basis(path, i, n_u, Nv, dN, nrm ? d2N : nullptr);
+    V3<double> C2b = mk(0.0, 0.0, 0.0);   // dL/dC'' (normal terms)
+    double Lb = 0.0;                       // dL/dL, L = |C'| (normal terms)
+    if (nrm) {
+        if (R.L > 0.0) {
+            const double* rr = rows_k + 16 * (size_t)i;
+            C2b = divs(a[21] * R.r + a[22] * R.s, R.L);
+            Lb = a[23] - (a[21] * rr[13] + a[22] * rr[14]) / R.L;
+        }
+    }
+    V3<double> xb = g;
+    V3<double> tb = Gt + cross(R.r, Gs);
+    const V3<double> rh = rho_at(i, carry);
+    const V3<double> rbar_i = rh.x * R.r + rh.y * R.s + rh.z * R.t;
+    if (i + 1 < n_u) {
+        const RowRec Rn = row_at(rows_k + 16 * (size_t)(i + 1));
+        const V3<double> rn = rho_at(i + 1, carry_next);
+        const V3<double> yb = rn.x * Rn.r + rn.y * Rn.s + rn.z * Rn.t;
+        const StepAdj sa = step_adjoint(R.x, Rn.x, R.t, Rn.t, R.r, yb);
+        xb = xb + sa.x0;
+        tb = tb + sa.t0;
+    }
+    if (i >= 1) {
+        const RowRec Rp = row_at(rows_k + 16 * (size_t)(i - 1));
+        const StepAdj sa = step_adjoint(Rp.x, R.x, Rp.t, R.t, Rp.r, rbar_i);
+        xb = xb + sa.x1;
+        tb = tb + sa.t1;
+    }
+    if (i == 0) {
+        // r_0 = q/|q|, q = e - (e.t_0) t_0 with e the initial normal or e_a
+        V3<double> e;
+        bool user = false;
+        if (n0.enabled) {
+            const V3<double> nn = mk(n0.v[0], n0.v[1], n0.v[2]);
+            const V3<double> q = nn - dot(nn, R.t) * R.t;
+            if (sqrt(dot(q, q)) > 1e-8) { e = nn; user = true; }
+        }
+        if (!user) {
+            const double ax = fabs(R.t.x), ay = fabs(R.t.y), az = fabs(R.t.z);
+            int k = 0;
+            double best = ax;
+            if (ay < best) { k = 1; best = ay; }
+            if (az < best) k = 2;
+            e = mk(k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0);
+        }
+        const double et = dot(e, R.t);
+        const V3<double> q = e - et * R.t;
+        const double ql = sqrt(dot(q, q));
+        const V3<double> qb = divs(rbar_i - dot(R.r, rbar_i) * R.r, ql);
+        tb = tb - (et * qb + dot(qb, R.t) * e);
+    }
+    // t = C'/|C'|; samples with C' = 0 carry a tangent and pass no gradient
+    V3<double> cb = mk(0.0, 0.0, 0.0);
+    if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L) + Lb * R.t;
+    spans_u[d.row_off + i] = s;
+    if (xstash) {
+        // dL/dC, dL/dC', dL/dC'' of the sample, for the knot and weight gradients
+        double* q = xstash + 9 * (d.row_off + (size_t)i);
+        q[0] = xb.x; q[1] = xb.y; q[2] = xb.z;
+        q[3] = cb.x; q[4] = cb.y; q[5] = cb.z;
+        q[6] = C2b.x; q[7] = C2b.y; q[8] = C2b.z;
+    }
+    double* sg = sgrad + 24 * (d.row_off + (size_t)i);
+    for (int j = 0; j <= path.p; ++j) {
+        V3<double> c = Nv[j] * xb + dN[j] * cb;
+        if (nrm) c = c + d2N[j] * C2b;
+        sg[3 * j] = c.x; sg[3 * j + 1] = c.y; sg[3 * j + 2] = c.z;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kbw_final(const BatchDesc* __restrict__ descs,
+                                                    const double* __restrict__ path_ctrl,
+                                                    const double* __restrict__ prof_ctrl,
+                                                    const double* __restrict__ path_w,
+                                                    const double* __restrict__ prof_w,
+                                                    const double* __restrict__ knots, const double* colpart,
+                                                    double* colacc, const double* sgrad, const int* spans_u,
+                                                    double* qgrad, int* spans_v, double* __restrict__ gP,
+                                                    double* __restrict__ gQ, int nrm)
+{
+    const int cp = nrm ? kColPartNrm : kColPart;
+    __shared__ double lpart[kBlock][kColPartNrm];
+    const BatchDesc d = descs[blockIdx.x];
+    const DCurve path = path_curve(d, path_ctrl, path_w, knots);
+    const DCurve prof = prof_curve(d, prof_ctrl, prof_w, knots);
+    const int n_u = d.n_u, n_v = d.n_v;
+    double* cacc = colacc + (size_t)cp * d.ptab_off;
+    const double* sg = sgrad + 24 * d.row_off;
+    const int* su = spans_u + d.row_off;
+    double* qg = qgrad + 24 * d.ptab_off;
+    int* sv = spans_v + d.ptab_off;
+
+    // 1. column sums over the row groups
     {
         // column sums over the row groups: `parts` threads per column, each
         // over a contiguous range of groups, combined in part order
@@ -533,107 +709,9 @@ __global__ __launch_bounds__(kBlock) void kbw_adjoint(const BatchDesc* __restric
                     if (e < cp) cacc[cp * (size_t)j + e] = h[e];
             }
     }
-    __threadfence_block();
+
     __syncthreads();
 
-    // 2. rho_i = sum_{k >= i} R_k^T rbar_k^dir, chunks from the last one
-    const int nc = (n_u + kBlock - 1) / kBlock;
-    V3<double> carry = mk(0.0, 0.0, 0.0);
-    for (int b = nc - 1; b >= 0; --b) {
-        const int i = b * kBlock + threadIdx.x;
-        V3<double> di = mk(0.0, 0.0, 0.0);
-        if (i < n_u) {
-            const RowRec R = row_at(rows_k + 16 * (size_t)i);
-            double* a = racc + rp * (size_t)i;
-            if (nrm) fold_normal_frame_terms(path, i, n_u, R, a);
-            const V3<double> Gr = mk(a[3], a[4], a[5]), Gs = mk(a[6], a[7], a[8]);
-            const V3<double> rb = Gr + cross(Gs, R.t);
-            di = mk(dot(R.r, rb), dot(R.s, rb), dot(R.t, rb));
-        }
-        V3<double> total;
-        const V3<double> sfx = block_suffix_sum(di, lds3, total) + carry;
-        if (i < n_u) { rho_k[3 * (size_t)i] = sfx.x; rho_k[3 * (size_t)i + 1] = sfx.y; rho_k[3 * (size_t)i + 2] = sfx.z; }
-        carry = carry + total;
-    }
-    __threadfence_block();
-    __syncthreads();
-
-    // 3. per-sample adjoint of x_i and C'_i, and their basis contributions
-    for (int i = threadIdx.x; i < n_u; i += kBlock) {
-        const RowRec R = row_at(rows_k + 16 * (size_t)i);
-        // (with the normal terms, values 3..11 hold the totals: step 2)
-        const double* a = racc + rp * (size_t)i;
-        const V3<double> g = mk(a[0], a[1], a[2]), Gs = mk(a[6], a[7], a[8]), Gt = mk(a[9], a[10], a[11]);
-        double Nv[kMaxDeg + 1], dN[kMaxDeg + 1], d2N[kMaxDeg + 1];
-        const int s = sample_basis(path, i, n_u, Nv, dN, nrm ? d2N : nullptr);
-        V3<double> C2b = mk(0.0, 0.0, 0.0);   // dL/dC'' (normal terms)
-        double Lb = 0.0;                       // dL/dL, L = |C'| (normal terms)
-        if (nrm) {
-            if (R.L > 0.0) {
-                const double* rr = rows_k + 16 * (size_t)i;
-                C2b = divs(a[21] * R.r + a[22] * R.s, R.L);
-                Lb = a[23] - (a[21] * rr[13] + a[22] * rr[14]) / R.L;
-            }
-        }
-        V3<double> xb = g;
-        V3<double> tb = Gt + cross(R.r, Gs);
-        const V3<double> rh = mk(rho_k[3 * (size_t)i], rho_k[3 * (size_t)i + 1], rho_k[3 * (size_t)i + 2]);
-        const V3<double> rbar_i = rh.x * R.r + rh.y * R.s + rh.z * R.t;
-        if (i + 1 < n_u) {
-            const RowRec Rn = row_at(rows_k + 16 * (size_t)(i + 1));
-            const V3<double> rn = mk(rho_k[3 * (size_t)(i + 1)], rho_k[3 * (size_t)(i + 1) + 1], rho_k[3 * (size_t)(i + 1) + 2]);
-            const V3<double> yb = rn.x * Rn.r + rn.y * Rn.s + rn.z * Rn.t;
-            const StepAdj sa = step_adjoint(R.x, Rn.x, R.t, Rn.t, R.r, yb);
-            xb = xb + sa.x0;
-            tb = tb + sa.t0;
-        }
-        if (i >= 1) {
-            const RowRec Rp = row_at(rows_k + 16 * (size_t)(i - 1));
-            const StepAdj sa = step_adjoint(Rp.x, R.x, Rp.t, R.t, Rp.r, rbar_i);
-            xb = xb + sa.x1;
-            tb = tb + sa.t1;
-        }
-        if (i == 0) {
-            // r_0 = q/|q|, q = e - (e.t_0) t_0 with e the initial normal or e_a
-            V3<double> e;
-            bool user = false;
-            if (n0.enabled) {
-                const V3<double> nn = mk(n0.v[0], n0.v[1], n0.v[2]);
-                const V3<double> q = nn - dot(nn, R.t) * R.t;
-                if (sqrt(dot(q, q)) > 1e-8) { e = nn; user = true; }
-            }
-            if (!user) {
-                const double ax = fabs(R.t.x), ay = fabs(R.t.y), az = fabs(R.t.z);
-                int k = 0;
-                double best = ax;
-                if (ay < best) { k = 1; best = ay; }
-                if (az < best) k = 2;
-                e = mk(k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0);
-            }
-            const double et = dot(e, R.t);
-            const V3<double> q = e - et * R.t;
-            const double ql = sqrt(dot(q, q));
-            const V3<double> qb = divs(rbar_i - dot(R.r, rbar_i) * R.r, ql);
-            tb = tb - (et * qb + dot(qb, R.t) * e);
-        }
-        // t = C'/|C'|; samples with C' = 0 carry a tangent and pass no gradient
-        V3<double> cb = mk(0.0, 0.0, 0.0);
-        if (R.L > 0.0) cb = divs(tb - dot(R.t, tb) * R.t, R.L) + Lb * R.t;
-        su[i] = s;
-        if (xstash) {
-            // dL/dC, dL/dC', dL/dC'' of the sample, for the knot and weight gradients
-            double* q = xstash + 9 * (d.row_off + (size_t)i);
-            q[0] = xb.x; q[1] = xb.y; q[2] = xb.z;
-            q[3] = cb.x; q[4] = cb.y; q[5] = cb.z;
-            q[6] = C2b.x; q[7] = C2b.y; q[8] = C2b.z;
-        }
-        for (int j = 0; j <= path.p; ++j) {
-            V3<double> c = Nv[j] * xb + dN[j] * cb;
-            if (nrm) c = c + d2N[j] * C2b;
-            double* q = sg + 24 * (size_t)i + 3 * j;
-            q[0] = c.x; q[1] = c.y; q[2] = c.z;
-        }
-    }
     // profile samples: dL/dS_j = h_j to the profile basis
     for (int j = threadIdx.x; j < n_v; j += kBlock) {
         double Nv[kMaxDeg + 1], dN[kMaxDeg + 1];
@@ -896,7 +974,7 @@ __device__ void curve_param_grads(const DCurve& c, int ns, const int* spans, con
 
 // Per-sample records of the knot and weight gradients: one block per
 // (sweep, chunk of kBlock samples) of the path (PROFILE false: adjoints from
-// xstash, dL/dC, dL/dC', dL/dC'' per sample, written by kbw_adjoint) or of
+// xstash, dL/dC, dL/dC', dL/dC'' per sample, written by kbw_samples) or of
 // the profile (PROFILE true: dL/dS and dL/dS' from colacc).
 template <bool PROFILE>
 __global__ __launch_bounds__(kBlock) void kbw_param_rec(const BatchDesc* __restrict__ descs,
@@ -974,7 +1052,9 @@ BackwardKernels backward_kernels(bool t64, bool nrm)
     BackwardKernels k;
     if (nrm) k.reduce = t64 ? (const void*)&kbw_reduce<double, true> : (const void*)&kbw_reduce<float, true>;
     else k.reduce = t64 ? (const void*)&kbw_reduce<double, false> : (const void*)&kbw_reduce<float, false>;
-    k.adjoint = (const void*)&kbw_adjoint;
+    k.rows = (const void*)&kbw_rows;
+    k.samples = (const void*)&kbw_samples;
+    k.final_ = (const void*)&kbw_final;
     k.params = (const void*)&kbw_params;
     k.param_rec_path = (const void*)&kbw_param_rec<false>;
     k.param_rec_prof = (const void*)&kbw_param_rec<true>;

@@ -31,12 +31,12 @@ struct BatchKey {
 struct BatchLayout {
     size_t rows, ptab, total;
     long long n_rows = 0, n_vs = 0, n_vertices = 0, n_out = 0;
-    long long n_rowpart = 0, n_colpart = 0, n_units = 0;
+    long long n_rowpart = 0, n_colpart = 0, n_units = 0, n_uchunks = 0;
 };
 
 // Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
 struct BackwardLayout {
-    size_t rows, ptab, rowpart, colpart, rowacc, colacc, rho, sgrad, spans_u, qgrad, spans_v;
+    size_t rows, ptab, rowpart, colpart, rowacc, colacc, rho, ctot, sgrad, spans_u, qgrad, spans_v;
     size_t xstash, recu, recv, total;
 };
 
@@ -53,6 +53,7 @@ static BackwardLayout backward_layout(const BatchLayout& L)
     B.rowacc = seg(8 * kRowPartNrm * (size_t)L.n_rows);
     B.colacc = seg(8 * kColPartNrm * (size_t)L.n_vs);
     B.rho = seg(8 * 3 * (size_t)L.n_rows);
+    B.ctot = seg(8 * 3 * (size_t)L.n_uchunks);
     B.sgrad = seg(8 * 24 * (size_t)L.n_rows);
     B.spans_u = seg(4 * (size_t)L.n_rows);
     B.qgrad = seg(8 * 24 * (size_t)L.n_vs);
@@ -97,7 +98,7 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             return fail(st, "sweep %d: %s", k, sweep_last_error());
         }
         const int nseg = (nv + 63) / 64;
-        const int G = bw_row_group_for(o->out_precision == SWEEP_F64);
+        const int G = bw_unit_rows_for(o->out_precision == SWEEP_F64);
         const int ngroup = (nu + G - 1) / G;
         if (descs) {
             BatchDesc d{};
@@ -115,6 +116,7 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             d.rowpart_off = L.n_rowpart; d.colpart_off = L.n_colpart; d.nseg = nseg; d.ngroup = ngroup;
             d.path_kuser_off = pk ? pk_off : -1;
             d.prof_kuser_off = qk ? qk_off : -1;
+            d.ctot_off = L.n_uchunks;
             descs->push_back(d);
         }
         if (key) {
@@ -131,6 +133,7 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         L.n_rows += nu; L.n_vs += nv;
         L.n_rowpart += (long long)nseg * nu; L.n_colpart += (long long)ngroup * nv;
         L.n_units += (long long)nseg * ngroup;
+        L.n_uchunks += (nu + kBlock - 1) / kBlock;
     }
     if (!b->path_ctrl || !b->prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "control point buffer is NULL");
     size_t off = 0;
@@ -200,7 +203,7 @@ struct Plan {
     int2* d_tiles = nullptr;
     int4* d_units = nullptr;       // adjoint reduction units, built on the first backward call
     int n_units = 0;
-    int2* d_uchunks_all = nullptr; // (sweep, chunk) of every path chunk, built on the first parameter-gradient call
+    int2* d_uchunks_all = nullptr; // (sweep, chunk) of every path chunk, built on the first backward call
     int n_uchunks_all = 0;
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
@@ -575,7 +578,7 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         std::vector<int4> units;
         units.reserve((size_t)L.n_units);
         for (int k = 0; k < batch->n_sweeps; ++k) {
-            const int G = bw_row_group_for(opt->out_precision == SWEEP_F64);
+            const int G = bw_unit_rows_for(opt->out_precision == SWEEP_F64);
             const int ng = (batch->n_u[k] + G - 1) / G, ns = (batch->n_v[k] + 63) / 64;
             for (int g = 0; g < ng; ++g)
                 for (int sg = 0; sg < ns; ++sg) units.push_back(make_int4(k, g, sg, 0));
@@ -637,8 +640,19 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         if ((e = hipLaunchKernel(BK.reduce, dim3(grid), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward reduce");
     }
+    if (!P->d_uchunks_all) {
+        // (sweep, chunk) of every path chunk of kBlock u-samples
+        std::vector<int2> ch;
+        for (int k = 0; k < batch->n_sweeps; ++k)
+            for (int c = 0; c * kBlock < batch->n_u[k]; ++c) ch.push_back(make_int2(k, c));
+        if ((e = hipMalloc(&P->d_uchunks_all, sizeof(int2) * ch.size())) != hipSuccess) return hip_fail(e, "plan alloc");
+        if ((e = hipMemcpy(P->d_uchunks_all, ch.data(), sizeof(int2) * ch.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "plan upload");
+        P->n_uchunks_all = (int)ch.size();
+    }
     {
         const BatchDesc* descs = P->d_descs;
+        const int2* uch = P->d_uchunks_all;
         const double* pc = batch->path_ctrl;
         const double* qc = batch->prof_ctrl;
         const double* pw = batch->path_weights;
@@ -650,7 +664,8 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         const void* colpart = ws + B.colpart;
         void* rowacc = ws + B.rowacc;
         void* colacc = ws + B.colacc;
-        void* rho = ws + B.rho;
+        void* sfx = ws + B.rho;
+        void* ctot = ws + B.ctot;
         void* sgrad = ws + B.sgrad;
         void* spans_u = ws + B.spans_u;
         void* qgrad = ws + B.qgrad;
@@ -659,22 +674,19 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         double* gq = grad_prof_ctrl;
         int nrm_arg = nrm;
         void* xstash = want_params ? ws + B.xstash : nullptr;
-        void* args[21] = {&descs, &pc, &qc, &pw, &qw, &kn, &n0, &rows, &rowpart, &colpart, &rowacc, &colacc,
-                          &rho, &sgrad, &spans_u, &qgrad, &spans_v, &gp, &gq, &nrm_arg, &xstash};
-        if ((e = hipLaunchKernel(BK.adjoint, dim3(batch->n_sweeps), dim3(kBlock), args, 0, sm)) != hipSuccess)
-            return hip_fail(e, "backward adjoint");
+        const unsigned nch = (unsigned)P->n_uchunks_all;
+        void* rargs[11] = {&descs, &uch, &pc, &pw, &kn, &rows, &rowpart, &rowacc, &sfx, &ctot, &nrm_arg};
+        if ((e = hipLaunchKernel(BK.rows, dim3(nch), dim3(kBlock), rargs, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward rows");
+        void* sargs[14] = {&descs, &uch, &pc, &pw, &kn, &n0, &rows, &rowacc, &sfx, &ctot, &sgrad, &spans_u, &nrm_arg,
+                           &xstash};
+        if ((e = hipLaunchKernel(BK.samples, dim3(nch), dim3(kBlock), sargs, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward samples");
+        void* fargs[15] = {&descs, &pc, &qc, &pw, &qw, &kn, &colpart, &colacc, &sgrad, &spans_u, &qgrad, &spans_v,
+                           &gp, &gq, &nrm_arg};
+        if ((e = hipLaunchKernel(BK.final_, dim3(batch->n_sweeps), dim3(kBlock), fargs, 0, sm)) != hipSuccess)
+            return hip_fail(e, "backward gathers");
         if (want_params) {
-            if (!P->d_uchunks_all) {
-                std::vector<int2> ch;
-                for (int k = 0; k < batch->n_sweeps; ++k)
-                    for (int c = 0; c * kBlock < batch->n_u[k]; ++c) ch.push_back(make_int2(k, c));
-                if ((e = hipMalloc(&P->d_uchunks_all, sizeof(int2) * ch.size())) != hipSuccess)
-                    return hip_fail(e, "plan alloc");
-                if ((e = hipMemcpy(P->d_uchunks_all, ch.data(), sizeof(int2) * ch.size(), hipMemcpyHostToDevice)) !=
-                    hipSuccess)
-                    return hip_fail(e, "plan upload");
-                P->n_uchunks_all = (int)ch.size();
-            }
             const void* xs = xstash;
             const void* ca = colacc;
             const void* su = spans_u;

@@ -67,6 +67,30 @@ template <class F> __device__ __forceinline__ V3<F> apply(const M3<F>& a, V3<F> 
             fma(a.m[8], v.z, fma(a.m[7], v.y, a.m[6] * v.x))};
 }
 
+// 1/x from the hardware reciprocal refined by Newton steps (two in FP64, one
+// in FP32): within an ulp or two of the correctly rounded quotient, with a
+// shorter dependency chain than the IEEE division, and the same instructions
+// wherever it is inlined.  Inputs outside the normal range (0, denormals,
+// huge, inf, NaN) take the IEEE division.
+__device__ __forceinline__ double recip(double x)
+{
+    const double ax = fabs(x);
+    if (!(ax > 1e-300 && ax < 1e300)) return 1.0 / x;
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float ax = fabsf(x);
+    if (!(ax > 1e-30f && ax < 1e30f)) return 1.0f / x;
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 // ------------------------------------------------------------------ curves
 
 struct DCurve {
@@ -386,14 +410,14 @@ __device__ __forceinline__ StepRot<F> make_step(V3<F> v1, V3<F> ti, V3<F> tn)
     StepRot<F> S;
     F c1 = dot(v1, v1);
     if (c1 == F(0)) { v1 = ti; c1 = dot(v1, v1); }
-    const F b1 = F(2) / c1;
+    const F b1 = F(2) * recip(c1);
     const V3<F> tL = fmadd(-(b1 * dot(v1, ti)), v1, ti);
     const V3<F> v2 = tn - tL;
     const F c2 = dot(v2, v2);
     if (c2 > F(1e-24)) {
         S.kind = 0;
         S.v1 = v1; S.b1 = b1;
-        S.v2 = v2; S.b2 = F(2) / c2;
+        S.v2 = v2; S.b2 = F(2) * recip(c2);
         return S;
     }
     const V3<F> k = cross(ti, tn);

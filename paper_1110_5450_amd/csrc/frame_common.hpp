@@ -14,7 +14,7 @@ namespace sweep {
 // d/|d| (one division for the three components).
 __device__ __forceinline__ V3<double> unit_of(V3<double> d)
 {
-    const double inv = 1.0 / sqrt(dot(d, d));
+    const double inv = recip(sqrt(dot(d, d)));
     return inv * d;
 }
 
@@ -78,14 +78,14 @@ __device__ __forceinline__ void write_row(V3<double> x, V3<double> td, V3<F> r, 
     const V3<F> t = cvt<F>(td);
     if (reorth) {
         const V3<F> w = r - dot(r, t) * t;
-        r = (F(1) / (F)sqrt(dot(w, w))) * w;
+        r = recip((F)sqrt(dot(w, w))) * w;
     }
     const V3<F> sv = cross(t, r);
     const double L = sqrt(dot(C1, C1));
     F a = F(0), b = F(0);
     if (L > 0.0) {
         const V3<F> c2 = cvt<F>(C2);
-        const F inv = F(1) / (F)L;
+        const F inv = recip((F)L);
         a = dot(r, c2) * inv;
         b = dot(sv, c2) * inv;
     }
@@ -141,7 +141,7 @@ __device__ __forceinline__ void write_row_ext(V3<double> x, V3<double> td, V3<F>
         r = rc;
         if (reorth) {
             const V3<F> w = r - dot(r, t) * t;
-            r = (F(1) / (F)sqrt(dot(w, w))) * w;
+            r = recip((F)sqrt(dot(w, w))) * w;
         }
     }
     const V3<F> sv = cross(t, r);
@@ -149,7 +149,7 @@ __device__ __forceinline__ void write_row_ext(V3<double> x, V3<double> td, V3<F>
     F a = F(0), b = F(0);
     if (L > 0.0) {
         const V3<F> c2 = cvt<F>(C2);
-        const F inv = F(1) / (F)L;
+        const F inv = recip((F)L);
         a = dot(r, c2) * inv;
         b = dot(sv, c2) * inv;
     }

@@ -28,19 +28,6 @@
 
 namespace sweep {
 
-// 1/x for a positive, normal-range x (knot differences of a non-empty span):
-// the hardware reciprocal refined by two Newton steps, within an ulp or two
-// of the correctly rounded quotient.  Cheaper than the IEEE division, and
-// the same instructions wherever it is inlined.
-__device__ __forceinline__ double recip(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
 // Open curve evaluated at samples of increasing index.  Knot span data are
 // loaded when the span changes: the 2P knots U_{s-P+1} .. U_{s+P}, the
 // reciprocals of the knot differences used by the triangular Cox-de Boor

@@ -102,6 +102,7 @@ struct BatchDesc {
     int nseg, ngroup;              // adjoint: 64-column segments, row groups
     long long path_kuser_off;      // adjoint: offset of the path's knots in the caller's packing, -1 = none
     long long prof_kuser_off;      // adjoint: the same for an open profile's knots
+    long long ctot_off;            // adjoint: first per-chunk total (chunks of kBlock u-samples)
 };
 
 // Batched output planes start on multiples of this many elements (256 B in
@@ -113,11 +114,18 @@ constexpr int kPlaneAlign = 64;
 // LDS tile of a wave holds G x 65 values per plane).
 template <class T>
 constexpr int bw_row_group() { return sizeof(T) == 8 ? 4 : 8; }
-inline int bw_row_group_for(bool t64) { return t64 ? 4 : 8; }
+// Groups of G rows per reduction unit: one column partial per unit (more
+// groups per unit write fewer partials but leave too few waves in flight:
+// 8 groups ran 10% slower on MI355X than 1).
+constexpr int kBwSub = 1;
+// Rows per reduction unit (the column partials' row groups).
+inline int bw_unit_rows_for(bool t64) { return (t64 ? 4 : 8) * kBwSub; }
 
 struct BackwardKernels {
     const void* reduce;
-    const void* adjoint;
+    const void* rows;            // row sums, direct terms and their suffix sums per chunk
+    const void* samples;         // per-sample adjoint and basis contributions per chunk
+    const void* final_;          // column sums, profile samples and the gathers per sweep
     const void* params;          // knot and weight gradients: gathers per sweep
     const void* param_rec_path;  // per-sample records, path chunks
     const void* param_rec_prof;  // per-sample records, profile chunks

@@ -260,6 +260,36 @@ int tune()
         double* gQ = (double*)dev_alloc(sizeof(double) * 3 * nq);
         bad += check(sweep_backward(&more[i].b, &opt, p2, gP, gQ, wsb, wbk, nullptr), "sweep_backward");
     }
+    {
+        // a batch of 300 sweeps of mixed lengths (short and chunk-walking
+        // frame nodes of two degrees), evaluated into two sets of buffers
+        // (node parameter updates), then differentiated
+        HostBatch big;
+        std::vector<int> deg, nu, nv;
+        for (int k = 0; k < 300; ++k) {
+            deg.push_back(2 + k % 2);
+            nu.push_back(16 + (k * 97) % 5000);
+            nv.push_back(8 + (k * 31) % 120);
+        }
+        make_batch(big, deg, nu, nv, false, rng);
+        const int64_t e3 = sweep_batched_output_elems(&big.b);
+        const size_t w3 = sweep_batched_workspace_size(&big.b, &opt);
+        for (int rep = 0; rep < 2; ++rep) {
+            float* p3 = (float*)dev_alloc(sizeof(float) * e3);
+            float* n3 = (float*)dev_alloc(sizeof(float) * e3);
+            void* ws3 = dev_alloc(w3);
+            bad += check(sweep_eval_batched(&big.b, &opt, p3, n3, ws3, w3, nullptr), "sweep_eval_batched");
+            if (rep == 1) {
+                const size_t wbk = sweep_backward_workspace_size(&big.b, &opt);
+                void* wsb = dev_alloc(wbk);
+                long long np = 0, nq = 0;
+                for (int k = 0; k < big.b.n_sweeps; ++k) { np += big.path_n[k]; nq += big.prof_n[k]; }
+                double* gP = (double*)dev_alloc(sizeof(double) * 3 * np);
+                double* gQ = (double*)dev_alloc(sizeof(double) * 3 * nq);
+                bad += check(sweep_backward(&big.b, &opt, p3, gP, gQ, wsb, wbk, nullptr), "sweep_backward");
+            }
+        }
+    }
     hipDeviceSynchronize();
     sweep_release_caches();
     std::printf("tuned config %d (%.3f ms), automatic config %d\n", cfg, ms, auto_cfg);

@@ -21,12 +21,14 @@ const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P}};
 const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P}};
 const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
 const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
-const KernelSig kAdjoint{"kbw_adjoint", {P, P, P, N, N, N, N0, P, P, P, P, P, P, P, P, P, P, P, P, I, N}};
+const KernelSig kRows{"kbw_rows", {P, P, P, N, N, P, P, P, P, P, I}};
+const KernelSig kSamples{"kbw_samples", {P, P, P, N, N, N0, P, P, P, P, P, P, I, N}};
+const KernelSig kFinal{"kbw_final", {P, P, P, N, N, N, P, P, P, P, P, P, P, P, I}};
 const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, P, I, I, I}};
 const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
 
 // distinct addresses standing in for kernel entry points
-char g_profile, g_frame[8], g_frame_long[8], g_surface, g_reduce, g_adjoint, g_rec_path, g_rec_prof, g_params;
+char g_profile, g_frame[8], g_frame_long[8], g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
 
 const std::map<const void*, const KernelSig*>& table()
 {
@@ -37,7 +39,9 @@ const std::map<const void*, const KernelSig*>& table()
         for (int p = 1; p < 8; ++p) m[&g_frame_long[p]] = &kFrameLong;
         m[&g_surface] = &kSurface;
         m[&g_reduce] = &kReduce;
-        m[&g_adjoint] = &kAdjoint;
+        m[&g_rows] = &kRows;
+        m[&g_samples] = &kSamples;
+        m[&g_final] = &kFinal;
         m[&g_rec_path] = &kParamRec;
         m[&g_rec_prof] = &kParamRec;
         m[&g_params] = &kParams;
@@ -56,7 +60,7 @@ const KernelSig* lookup(const void* fn)
 
 std::vector<const KernelSig*> all_kernels()
 {
-    return {&kProfile, &kFrame, &kFrameLong, &kSurface, &kReduce, &kAdjoint, &kParamRec, &kParams};
+    return {&kProfile, &kFrame, &kFrameLong, &kSurface, &kReduce, &kRows, &kSamples, &kFinal, &kParamRec, &kParams};
 }
 
 }  // namespace stub
@@ -77,7 +81,8 @@ BatchedKernels batched_kernels(bool, bool, bool, bool, int)
 
 BackwardKernels backward_kernels(bool, bool)
 {
-    return BackwardKernels{&stub::g_reduce, &stub::g_adjoint, &stub::g_params, &stub::g_rec_path, &stub::g_rec_prof};
+    return BackwardKernels{&stub::g_reduce, &stub::g_rows, &stub::g_samples, &stub::g_final, &stub::g_params,
+                           &stub::g_rec_path, &stub::g_rec_prof};
 }
 
 void fastdiv_constants(int d, unsigned long long* m, int* shift)
