@@ -164,7 +164,11 @@ typedef struct {
     const struct sweep_curve_s *law; /* NULL (default) or a sweep law, see above */
     int32_t u_sampling;       /* SWEEP_U_PARAMETER (default), SWEEP_U_ARCLENGTH or
                                  SWEEP_U_ADAPTIVE, see above */
-    int32_t reserved;
+    int32_t batch_stages;     /* sweep_eval_batched: 0 (default) automatic, else 1-4
+                                 pipeline stages of the frame/surface schedule
+                                 (sweeps grouped by path length; the surface of a
+                                 stage is written while the next stage's frames
+                                 are formed) */
     double u_lambda;          /* SWEEP_U_ADAPTIVE: length weight of the turning angle (>= 0, finite) */
 } sweep_options;
 

@@ -36,7 +36,7 @@ class SweepOptions(C.Structure):
     _fields_ = [("out_precision", C.c_int32), ("frame_precision", C.c_int32),
                 ("reorthonormalize", C.c_int32), ("has_initial_normal", C.c_int32),
                 ("initial_normal", C.c_double * 3), ("tile_config", C.c_int32), ("frame_mode", C.c_int32),
-                ("law", C.c_void_p), ("u_sampling", C.c_int32), ("reserved", C.c_int32),
+                ("law", C.c_void_p), ("u_sampling", C.c_int32), ("batch_stages", C.c_int32),
                 ("u_lambda", C.c_double)]
 
 

@@ -387,12 +387,14 @@ class Batch:
 def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
                        reorthonormalize: bool = True, initial_normal=None, tile_config: int = -1,
                        normals: bool = True, frame_mode: str = "rmf", out=None,
-                       workspace: Optional[torch.Tensor] = None, stream=None):
+                       workspace: Optional[torch.Tensor] = None, stream=None, stages: int = 0):
     """Flat positions and normals (or None) of a batch in the padded batched
     layout (rotation-minimizing frames; other frame modes are sweep_eval
-    only)."""
+    only).  stages: pipeline stages of the frame/surface schedule (0:
+    automatic)."""
     b = batch.c_struct()
     opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode)
+    opt.batch_stages = int(stages)
     ws_bytes = L.sweep_batched_workspace_size(b, opt)
     if ws_bytes == 0:
         L.check(L.sweep_eval_batched(b, opt, 0, 0, 0, 0, 0))

@@ -76,6 +76,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     if (options_single_only(o))
         return fail(SWEEP_ERR_UNSUPPORTED, "frame modes, laws and arc-length sampling are sweep_eval only");
     if (b->n_sweeps < 1) return fail(SWEEP_ERR_BAD_COUNT, "n_sweeps %d < 1", b->n_sweeps);
+    if (o->batch_stages < 0 || o->batch_stages > 4)
+        return fail(SWEEP_ERR_BAD_OPTION, "batch_stages %d outside 0..4", o->batch_stages);
     if (!b->path_n || !b->path_degree || !b->prof_n || !b->prof_degree || !b->n_u || !b->n_v)
         return fail(SWEEP_ERR_NULL_ARG, "a per-sweep array is NULL");
     const size_t tsz = o->out_precision == SWEEP_F64 ? 8 : 4;
@@ -142,9 +144,11 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     L.total = off;
     if (lay) *lay = L;
     if (key) {
-        const int32_t v[5] = {o->out_precision, o->frame_precision, o->reorthonormalize, o->has_initial_normal,
-                              o->tile_config};
-        key->ints.insert(key->ints.end(), v, v + 5);
+        // (rational paths stage their weights in the frame kernel's LDS: the
+        // sweeps routed to the chunk-walking kernel depend on it)
+        const int32_t v[8] = {o->out_precision, o->frame_precision, o->reorthonormalize, o->has_initial_normal,
+                              o->tile_config, o->batch_stages, b->path_weights ? 1 : 0, b->prof_weights ? 1 : 0};
+        key->ints.insert(key->ints.end(), v, v + 8);
         if (o->has_initial_normal) key->dbls.insert(key->dbls.end(), o->initial_normal, o->initial_normal + 3);
     }
     return SWEEP_OK;
@@ -208,9 +212,18 @@ struct Plan {
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int* d_sweeps[8] = {};         // sweeps by path degree, longest n_u first
+    int* d_sweeps[8] = {};         // sweeps by path degree: by stage, longest n_u first within a stage
     int n_deg[8] = {};
-    int n_long[8] = {};            // leading sweeps of d_sweeps[p] longer than one frame chunk
+    // Frame launches: sweeps [first, first + count) of d_sweeps[deg], all of
+    // one stage and all for the chunk-walking kernel (longer than one frame
+    // chunk, or a path too large to stage in LDS) or none.
+    struct FrameRange {
+        int deg, first, count, stage;
+        bool is_long;
+    };
+    std::vector<FrameRange> franges;
+    int n_stages = 1;
+    std::vector<int> stage_tiles;  // first surface tile of each stage, and the total
     int2* d_vchunks = nullptr;     // (sweep, chunk) of every profile chunk
     int n_vchunks = 0;
     NodeArgs a{};                  // values shared by all nodes
@@ -311,6 +324,26 @@ static std::vector<int2> surface_tiles(const sweep_batch* b, int tv)
     return tiles;
 }
 
+// Pipeline stages of a batch schedule.  A sweep's frame level is log2 of its
+// run length K (the smallest power of two up to kMaxRun with kBlock*K >= n_u),
+// or kMaxRunLog + 1 for a sweep longer than one frame chunk; the level range
+// is cut into S equal parts, shortest paths first.  Stage s's frame launches
+// wait for those of stage s-1, and stage s's surface launch waits only for
+// its own frames: the surfaces of the earlier stages are written while the
+// later stages' frames are formed.
+constexpr int kMaxStages = 4;
+constexpr int kDefaultStages = 1;
+static int frame_level(int n_u)
+{
+    if (n_u > kBlock * kMaxRun) return 5;
+    int K = 1, l = 0;
+    while (K < kMaxRun && kBlock * K < n_u) { K *= 2; ++l; }
+    return l;
+}
+static int frame_stage(int n_u, int S) { return frame_level(n_u) * S / 6; }
+static int resolved_stages(const sweep_options* o) { return o->batch_stages > 0 ? o->batch_stages : kDefaultStages; }
+static_assert(kMaxStages == 4, "batch_stages is validated as 0..4");
+
 static std::mutex g_mu;
 static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
 static const size_t kMaxPlans = 16;
@@ -332,15 +365,51 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     const SurfaceConfig cfg = tile_config(o->tile_config);   // resolved by the caller
     // column-tile configurations map to one-row-sized linear tiles
     const int tv = cfg.kind == 1 ? cfg.tile_vertices : kBlock;
-    const std::vector<int2> tiles = surface_tiles(b, tv);
+    const int S = resolved_stages(o);
+    P->n_stages = S;
+    // surface tiles grouped by stage (sweep order inside a stage)
+    std::vector<int2> tiles;
+    {
+        const std::vector<int2> all = surface_tiles(b, tv);
+        for (int st = 0; st < S; ++st) {
+            P->stage_tiles.push_back((int)tiles.size());
+            for (const int2& t : all)
+                if (frame_stage(b->n_u[t.x], S) == st) tiles.push_back(t);
+        }
+        P->stage_tiles.push_back((int)tiles.size());
+    }
     std::vector<int2> vchunks;
     std::vector<int> sweeps[8];
     for (int k = 0; k < b->n_sweeps; ++k) {
         sweeps[b->path_degree[k]].push_back(k);
         for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
+    // the chunk-walking frame kernel: sweeps longer than one frame chunk, or
+    // whose path does not fit the one-chunk kernel's LDS
+    const bool rat = b->path_weights != nullptr;
+    auto walks = [&](int k) {
+        return b->n_u[k] > kBlock * kMaxRun ||
+               lds_path_doubles(b->path_n[k], b->path_degree[k], rat) > kLdsPathDoubles;
+    };
     for (auto& l : sweeps)
-        std::stable_sort(l.begin(), l.end(), [&](int x, int y) { return b->n_u[x] > b->n_u[y]; });
+        std::stable_sort(l.begin(), l.end(), [&](int x, int y) {
+            const int sx = frame_stage(b->n_u[x], S), sy = frame_stage(b->n_u[y], S);
+            if (sx != sy) return sx < sy;
+            if (walks(x) != walks(y)) return walks(x);
+            return b->n_u[x] > b->n_u[y];
+        });
+    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+        const std::vector<int>& l = sweeps[p];
+        size_t i = 0;
+        while (i < l.size()) {
+            const int st = frame_stage(b->n_u[l[i]], S);
+            const bool lg = walks(l[i]);
+            size_t j = i;
+            while (j < l.size() && frame_stage(b->n_u[l[j]], S) == st && walks(l[j]) == lg) ++j;
+            P->franges.push_back(Plan::FrameRange{p, (int)i, (int)(j - i), st, lg});
+            i = j;
+        }
+    }
     if (tiles.size() > 0x7fffffffull || vchunks.size() > 0x7fffffffull)
         return fail(SWEEP_ERR_BAD_COUNT, "batch needs too many blocks");
     P->n_tiles = (int)tiles.size();
@@ -357,7 +426,6 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         return hip_fail(e, "plan upload");
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
         P->n_deg[p] = (int)sweeps[p].size();
-        for (int k : sweeps[p]) P->n_long[p] += b->n_u[k] > kBlock * kMaxRun ? 1 : 0;
         if (!sweeps[p].empty() &&
             (e = upload((void**)&P->d_sweeps[p], sweeps[p].data(), sizeof(int) * sweeps[p].size())) != hipSuccess)
             return hip_fail(e, "plan upload");
@@ -378,19 +446,21 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
     A.reorth = o->reorthonormalize;
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
-    // frame nodes: sweeps [first, first + grid) of the degree's list
+    // frame nodes: sweeps [first, first + grid) of the degree's list;
+    // surface nodes: tiles [first, first + grid)
     auto add = [&](NodeKind kind, int deg, const void* fn, unsigned grid,
-                   const std::vector<hipGraphNode_t>& deps, int first = 0) -> hipError_t {
+                   const std::vector<hipGraphNode_t>& deps, int first = 0, unsigned lds = 0) -> hipError_t {
         std::unique_ptr<GNode> n(new GNode());
         n->kind = kind;
         n->deg = deg;
         std::memcpy(&n->a, &P->a, sizeof n->a);
         if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg] + first;
+        if (kind == kSurface) n->a.tiles = P->d_tiles + first;
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
         n->prm.blockDim = dim3(kBlock);
-        n->prm.sharedMemBytes = 0;
+        n->prm.sharedMemBytes = lds;
         n->prm.kernelParams = n->ptrs;
         n->prm.extra = nullptr;
         hipError_t r = hipGraphAddKernelNode(&n->node, P->graph, deps.empty() ? nullptr : deps.data(), deps.size(),
@@ -398,22 +468,28 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         P->nodes.push_back(std::move(n));
         return r;
     };
-    std::vector<hipGraphNode_t> before_surface;
     if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
-    before_surface.push_back(P->nodes.back()->node);
-    for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-        const int nl = P->n_long[p], ns = P->n_deg[p] - nl;
-        if (nl) {
-            if ((e = add(kFrame, p, K.frame_long[p], (unsigned)nl, {})) != hipSuccess) return hip_fail(e, "graph node");
-            before_surface.push_back(P->nodes.back()->node);
+    const hipGraphNode_t profile_node = P->nodes.back()->node;
+    std::vector<hipGraphNode_t> prev_frames;
+    for (int st = 0; st < S; ++st) {
+        std::vector<hipGraphNode_t> frames;
+        for (const Plan::FrameRange& r : P->franges) {
+            if (r.stage != st) continue;
+            const void* fn = r.is_long ? K.frame_long[r.deg] : K.frame[r.deg];
+            const unsigned lds = r.is_long ? 0u : (unsigned)(sizeof(double) * kLdsPathDoubles);
+            if ((e = add(kFrame, r.deg, fn, (unsigned)r.count, prev_frames, r.first, lds)) != hipSuccess)
+                return hip_fail(e, "graph node");
+            frames.push_back(P->nodes.back()->node);
         }
-        if (ns) {
-            if ((e = add(kFrame, p, K.frame[p], (unsigned)ns, {}, nl)) != hipSuccess) return hip_fail(e, "graph node");
-            before_surface.push_back(P->nodes.back()->node);
+        const int t0 = P->stage_tiles[st], nt = P->stage_tiles[st + 1] - t0;
+        if (nt > 0) {
+            std::vector<hipGraphNode_t> deps = frames;
+            deps.push_back(profile_node);
+            if ((e = add(kSurface, 0, K.surface, (unsigned)nt, deps, t0)) != hipSuccess)
+                return hip_fail(e, "graph node");
         }
+        if (!frames.empty()) prev_frames = frames;
     }
-    if ((e = add(kSurface, 0, K.surface, (unsigned)P->n_tiles, before_surface)) != hipSuccess)
-        return hip_fail(e, "graph node");
     if ((e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0)) != hipSuccess)
         return hip_fail(e, "graph instantiate");
     out = std::move(P);
@@ -511,8 +587,10 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
         P->a = A;
         for (auto& n : P->nodes) {
             const int* own = n->a.sweeps;
+            const int2* own_tiles = n->a.tiles;
             std::memcpy(&n->a, &A, sizeof A);
             n->a.sweeps = own;
+            n->a.tiles = own_tiles;
             if ((e = hipGraphExecKernelNodeSetParams(P->exec, n->node, &n->prm)) != hipSuccess)
                 return hip_fail(e, "graph update");
         }
@@ -609,19 +687,19 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         n.a.reorth = 1;
         n.a.rows = ws + B.rows;
         n.a.ptab = ws + B.ptab;
-        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid, int first = 0) -> hipError_t {
+        auto launch = [&](NodeKind kind, int deg, const void* fn, unsigned grid, int first = 0,
+                          size_t lds = 0) -> hipError_t {
             n.kind = kind;
             n.a.sweeps = kind == kFrame ? P->d_sweeps[deg] + first : nullptr;
             node_args(n);
-            return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, 0, sm);
+            return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), n.ptrs, lds, sm);
         };
         if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
-        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
-            const int nl = P->n_long[p], ns = P->n_deg[p] - nl;
-            if (nl && (e = launch(kFrame, p, FK.frame_long[p], (unsigned)nl)) != hipSuccess)
-                return hip_fail(e, "backward frames");
-            if (ns && (e = launch(kFrame, p, FK.frame[p], (unsigned)ns, nl)) != hipSuccess)
+        for (const Plan::FrameRange& r : P->franges) {
+            const void* fn = r.is_long ? FK.frame_long[r.deg] : FK.frame[r.deg];
+            const size_t lds = r.is_long ? 0 : sizeof(double) * kLdsPathDoubles;
+            if ((e = launch(kFrame, r.deg, fn, (unsigned)r.count, r.first, lds)) != hipSuccess)
                 return hip_fail(e, "backward frames");
         }
     }

@@ -63,7 +63,9 @@ __device__ __forceinline__ int batch_run_length(int n_u)
 }
 
 // Row records of a sweep of at most kBlock*kMaxRun u-samples whose path has
-// degree P: one block per sweep, one chunk.
+// degree P: one block per sweep, one chunk.  The path is staged in LDS
+// (knots, control points, weights, per-span reciprocals; kLdsPathDoubles of
+// dynamic LDS): knot span changes read LDS only.
 template <int P, class F, class T>
 __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
                                                    const int* __restrict__ sweeps,
@@ -75,14 +77,16 @@ __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__
     __shared__ ChunkWalkLds L;
     __shared__ M3<F> lds_m[kWaves];
     __shared__ double lt0[3];
+    extern __shared__ double lds_path[];   // kLdsPathDoubles
     const BatchDesc d = descs[sweeps[blockIdx.x]];
-    const DCurve path = path_of(d, path_ctrl, path_w, knots);
+    const DCurve gpath = path_of(d, path_ctrl, path_w, knots);
+    const LdsCurve path = stage_path<P>(gpath, lds_path);
     const int n_u = d.n_u;
     const int K = batch_run_length(n_u);
     RunInfo<P, F> R;
     int clv;
     V3<double> ctl;
-    chunk_products<P, F>(path, n_u, 0, K, true, first_leg(path), L, R, clv, ctl);
+    chunk_products<P, F>(path, n_u, 0, K, true, first_leg(gpath), L, R, clv, ctl);
     // r_0 from the resolved t_0 (sample 0 is thread 0's)
     if (threadIdx.x == 0) { lt0[0] = R.t_first.x; lt0[1] = R.t_first.y; lt0[2] = R.t_first.z; }
     __syncthreads();

@@ -389,19 +389,18 @@ __device__ __forceinline__ V3<F> axis_normal(V3<F> t)
 // to v2 = t_{i+1} - H1 t_i; M = H2 H1.  A zero chord uses v1 = t_i.  When
 // |v2|^2 <= 1e-24 the smallest rotation taking t_i to t_{i+1} is used
 // (rotation by pi about the axis-rule direction for opposite tangents).
-// The rotation is kept in factored form and applied to vectors (or matrix
-// columns) without forming M:
-//   kind 0:  x -> H2 H1 x,  H_k x = x - b_k (v_k . x) v_k,  b_k = 2/|v_k|^2
-//   kind 1:  x -> c x + k x x + f (k . x) k   (rotation about k = t_i x t_{i+1},
-//            c = t_i . t_{i+1}, f = (1 - c)/|k|^2)
-//   kind 2:  identity (equal tangents)
-//   kind 3:  x -> 2 (a . x) a - x   (rotation by pi about the unit vector a)
-// Kinds 1 and 3 reuse v1 (k, a), b1 (c) and b2 (f).
+// Every case is kept as a pair of reflections, H_k x = x - b_k (v_k . x) v_k,
+// applied to vectors (or matrix columns) without forming M, with no branch:
+//   double reflection:  v1, b1 = 2/|v1|^2;  v2, b2 = 2/|v2|^2;
+//   smallest rotation:  H(t_i + t_{i+1}) H(t_i) (two mirrors through the
+//                       axis t_i x t_{i+1}, half the angle apart);
+//   equal tangents:     b1 = b2 = 0 (identity);
+//   opposite tangents:  H(a x t_i) H(t_i), a the axis-rule unit normal of t_i
+//                       (mirrors a quarter turn apart: rotation by pi about a).
 template <class F>
 struct StepRot {
     V3<F> v1, v2;
     F b1, b2;
-    int kind;
 };
 
 template <class F>
@@ -415,37 +414,31 @@ __device__ __forceinline__ StepRot<F> make_step(V3<F> v1, V3<F> ti, V3<F> tn)
     const V3<F> v2 = tn - tL;
     const F c2 = dot(v2, v2);
     if (c2 > F(1e-24)) {
-        S.kind = 0;
         S.v1 = v1; S.b1 = b1;
         S.v2 = v2; S.b2 = F(2) * recip(c2);
         return S;
     }
     const V3<F> k = cross(ti, tn);
     const F kk = dot(k, k), c = dot(ti, tn);
-    S.v2 = mk(F(0), F(0), F(0));
+    S.v1 = ti;
+    S.b1 = F(2) * recip(dot(ti, ti));
     if (kk > F(0)) {
-        S.kind = 1;
-        S.v1 = k; S.b1 = c; S.b2 = (F(1) - c) / kk;
+        S.v2 = ti + tn;
     } else if (c > F(0)) {
-        S.kind = 2;
-        S.v1 = k; S.b1 = F(0); S.b2 = F(0);
+        S.v2 = ti; S.b1 = F(0); S.b2 = F(0);
+        return S;
     } else {
-        S.kind = 3;
-        S.v1 = axis_normal(ti); S.b1 = F(0); S.b2 = F(0);
+        S.v2 = cross(axis_normal(ti), ti);
     }
+    S.b2 = F(2) * recip(dot(S.v2, S.v2));
     return S;
 }
 
 template <class F>
 __device__ __forceinline__ V3<F> apply_step(const StepRot<F>& S, V3<F> x)
 {
-    if (S.kind == 0) {
-        x = fmadd(-(S.b1 * dot(S.v1, x)), S.v1, x);
-        return fmadd(-(S.b2 * dot(S.v2, x)), S.v2, x);
-    }
-    if (S.kind == 1) return fmadd(S.b2 * dot(S.v1, x), S.v1, fmadd(S.b1, x, cross(S.v1, x)));
-    if (S.kind == 2) return x;
-    return fmadd(F(2) * dot(S.v1, x), S.v1, mk(-x.x, -x.y, -x.z));
+    x = fmadd(-(S.b1 * dot(S.v1, x)), S.v1, x);
+    return fmadd(-(S.b2 * dot(S.v2, x)), S.v2, x);
 }
 
 // M A for the step rotation M, column by column.

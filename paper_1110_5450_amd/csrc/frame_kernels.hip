@@ -20,7 +20,7 @@
 //                 applied to r_in[c], then each thread walks its run writing
 //                 row records (x, r, s, t, |C'|, a, b) in the output
 //                 precision, re-orthonormalised if asked.
-// k_frame_apply_fused  up to kBlock chunks (no frame mode or law): replaces
+// k_frame_apply_fused  up to kBlock*kFusedGroup chunks (no frame mode or law): replaces
 //                 k_frame_carry + k_frame_apply; block b forms its entry
 //                 normal as the ordered block product of the chunk products
 //                 below it (flagged chunks' products formed in the block),
@@ -30,12 +30,13 @@
 namespace sweep {
 
 // Runs per chunk (one per thread) and the run length K for n_u samples:
-// the smallest power of two up to 16 that keeps the chunks at most kBlock
-// (the fused route), i.e. about 65,536 threads or more.
+// the smallest power of two up to 16 that keeps the chunks at most
+// kBlock*kFusedGroup (the fused route): about 131,072 threads or more, two
+// waves per SIMD on 256 CUs, which the walk's register use allows.
 int frame_run_length(int n_u)
 {
     int K = 1;
-    while (K < 16 && (long long)kBlock * kBlock * K < (long long)n_u) K *= 2;
+    while (K < 16 && (long long)kBlock * kBlock * kFusedGroup * K < (long long)n_u) K *= 2;
     return K;
 }
 int frame_chunks(int n_u)
@@ -177,13 +178,15 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply(DCurve path, int n_u, in
         run_rows<P, 2, F>(path, n_u, i0, K, t_first, r, PlainRows<F, T>{rows, reorth});
 }
 
-// k_frame_apply without k_frame_carry, for at most kBlock chunks: thread c
-// holds the product A_c of chunk c < b (identity above); the products of
-// flagged chunks (not formed by k_prep) are formed here, as k_frame_carry
-// does; their ordered block product applied to r_0 is the block's entry
-// normal.  A flagged chunk b also forms its own run records here.
+// k_frame_apply without k_frame_carry, for at most kBlock*G chunks: thread c
+// holds the ordered product A_c of chunks [cG, cG + G) below b (identity
+// above); the products of flagged chunks (not formed by k_prep) are formed
+// here, as k_frame_carry does, in increasing order, and the owning thread
+// multiplies them in at their place.  The ordered block product of the A_c
+// applied to r_0 is the block's entry normal.  A flagged chunk b also forms
+// its own run records here.
 template <int P, class F, class T>
-__global__ __launch_bounds__(kBlock) void k_frame_apply_fused(DCurve path, int n_u, int K,
+__global__ __launch_bounds__(kBlock) void k_frame_apply_fused(DCurve path, int n_u, int K, int G,
                                                               const double* __restrict__ trec,
                                                               const int* __restrict__ chunk_lv,
                                                               const double* __restrict__ chunk_tl,
@@ -200,32 +203,52 @@ __global__ __launch_bounds__(kBlock) void k_frame_apply_fused(DCurve path, int n
     __shared__ F lds_r[3];
     const int b = blockIdx.x, c = threadIdx.x;
     const int cs = kBlock * K;
+    const int g0 = c * G, g1 = min(g0 + G, b);   // this thread's chunks below b: [g0, g1)
     const V3<double> fb = mk(fallback_t[0], fallback_t[1], fallback_t[2]);
-    M3<F> A = ident<F>();
     int flagged = 0, lv = -1;
-    if (c < b) {
-        flagged = chunk_fix[c];
-        lv = chunk_lv[c];
-        if (!flagged) {
-#pragma unroll
-            for (int e = 0; e < 9; ++e) A.m[e] = agg[9 * (size_t)c + e];
-        }
+    for (int cc = g0; cc < g1; ++cc) {
+        flagged |= chunk_fix[cc];
+        lv = max(lv, chunk_lv[cc]);
     }
     int lv_below_b, last_flagged;
-    lx[c] = block_exclusive_max(lv, L.ii, lv_below_b);   // last valid sample below chunk c (c <= b)
+    lx[c] = block_exclusive_max(lv, L.ii, lv_below_b);   // last valid sample below chunk g0
     lflag[c] = flagged;
     block_exclusive_max(flagged ? c : -1, L.ii, last_flagged);   // also orders lx, lflag
-    for (int f = 1; f <= last_flagged; ++f) {   // uniform; skipped when none
-        if (!lflag[f]) continue;
-        RunInfo<P, F> R;
-        int clv;
-        V3<double> ctl;
-        chunk_products<P, F>(path, n_u, f * cs, K, true, entry_tangent(lx[f], cs, chunk_tl, fb), L, R, clv, ctl);
-        const M3<F> prod = block_product<F>(R.A, lds_m);
-        if (threadIdx.x == 0) lds_fix = prod;
-        __syncthreads();
-        if (c == f) A = lds_fix;
-        __syncthreads();
+    M3<F> A = ident<F>();
+    int next = g0;   // the first chunk of the group not yet in A
+    for (int t = 0; t <= last_flagged; ++t) {   // uniform; skipped when none
+        if (!lflag[t]) continue;
+        int lvf = lx[t];
+        for (int f = t * G; f < min(t * G + G, b); ++f) {
+            if (chunk_fix[f]) {
+                RunInfo<P, F> R;
+                int clv;
+                V3<double> ctl;
+                chunk_products<P, F>(path, n_u, f * cs, K, true, entry_tangent(lvf, cs, chunk_tl, fb), L, R, clv,
+                                     ctl);
+                const M3<F> prod = block_product<F>(R.A, lds_m);
+                if (threadIdx.x == 0) lds_fix = prod;
+                __syncthreads();
+                if (c == t) {
+                    for (; next < f; ++next) {
+                        M3<F> M;
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) M.m[e] = agg[9 * (size_t)next + e];
+                        A = mul(M, A);
+                    }
+                    A = mul(lds_fix, A);
+                    next = f + 1;
+                }
+                __syncthreads();
+            }
+            lvf = max(lvf, chunk_lv[f]);
+        }
+    }
+    for (; next < g1; ++next) {
+        M3<F> M;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) M.m[e] = agg[9 * (size_t)next + e];
+        A = mul(M, A);
     }
     const M3<F> Pb = block_product<F>(A, lds_m);   // A_{b-1} ... A_0, valid in wave 0
     if (threadIdx.x == 0) {
@@ -278,8 +301,9 @@ static void launch_frame_p(const DCurve& path, int n_u, const FrameWork& w, Init
 {
     const int K = frame_run_length(n_u);
     const int nc = frame_chunks(n_u);
-    if (!ext && nc <= kBlock) {
-        hipLaunchKernelGGL((k_frame_apply_fused<P, F, T>), dim3(nc), dim3(kBlock), 0, st, path, n_u, K, w.trec,
+    if (!ext && nc <= kBlock * kFusedGroup) {
+        const int G = (nc + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((k_frame_apply_fused<P, F, T>), dim3(nc), dim3(kBlock), 0, st, path, n_u, K, G, w.trec,
                            w.chunk_lv, w.chunk_tl, w.chunk_fix, w.fallback_t, (const F*)w.agg, n0, reorth, rows);
         return;
     }

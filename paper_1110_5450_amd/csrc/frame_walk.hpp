@@ -28,6 +28,96 @@
 
 namespace sweep {
 
+// A path staged in LDS by the block that walks it (stage_path): the knot
+// vector (the given one, or the default one materialised), the control
+// points, the weights and, per knot span s, the reciprocals of the knot
+// differences of the triangular Cox-de Boor sweep,
+//   RT[(s - p) P(P+1)/2 + q(q-1)/2 + j] = 1/(U_{s+j+1} - U_{s-q+j+1}),
+// formed by the same operations as the cursor's own (identical values).
+struct LdsCurve {
+    const double* U;
+    const double* X;      // n x 3
+    const double* W;      // n weights (rational)
+    const double* RT;
+    int n, p, closed, nb;
+    bool rat, given_knots;
+    const double* su;     // never set: arc-length sampling is single-sweep only
+    const int* ss;
+};
+__device__ __forceinline__ bool is_rational(const DCurve& c) { return c.w != nullptr; }
+__device__ __forceinline__ bool is_rational(const LdsCurve& c) { return c.rat; }
+__device__ __forceinline__ double knot(const LdsCurve& c, int k) { return c.U[k]; }
+__device__ __forceinline__ V3<double> ctrl_pt(const LdsCurve& c, int k)
+{
+    const int kk = (c.closed && k >= c.n) ? k - c.n : k;
+    const double* q = c.X + 3 * kk;
+    return {q[0], q[1], q[2]};
+}
+__device__ __forceinline__ double weight_at(const LdsCurve& c, int k)
+{
+    return c.W[(c.closed && k >= c.n) ? k - c.n : k];
+}
+// Span of sample i: as sample_span (integer arithmetic for the default knots,
+// else a binary search over the staged vector).
+__device__ __forceinline__ int sample_span(const LdsCurve& c, int i, int ns, double u)
+{
+    if (!c.given_knots) {
+        if (c.closed) return c.p + (int)(((long long)c.n * (long long)i) / ns);
+        const int s = c.p + (int)(((long long)i * (long long)(c.n - c.p)) / (ns - 1));
+        return s < c.n - 1 ? s : c.n - 1;
+    }
+    if (u >= c.U[c.nb]) return c.nb - 1;
+    int lo = c.p, hi = c.nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (c.U[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+// Reciprocals of span sp's knot differences: formed, or read from the table.
+template <int P>
+__device__ __forceinline__ void span_recips(const DCurve&, int, const double* Uk, double* rt)
+{
+#pragma unroll
+    for (int q = 1; q <= P; ++q)
+#pragma unroll
+        for (int j = 0; j < q; ++j) rt[q * (q - 1) / 2 + j] = recip(Uk[P + j] - Uk[P - q + j]);
+}
+template <int P>
+__device__ __forceinline__ void span_recips(const LdsCurve& c, int sp, const double*, double* rt)
+{
+    const double* q = c.RT + (size_t)(sp - P) * (P * (P + 1) / 2);
+#pragma unroll
+    for (int e = 0; e < P * (P + 1) / 2; ++e) rt[e] = q[e];
+}
+
+// Block-cooperative staging of an open path into lds (lds_path_doubles
+// doubles, which the caller guarantees).
+template <int P>
+__device__ LdsCurve stage_path(const DCurve& g, double* lds)
+{
+    const int nk = g.nb + g.p + 1;
+    double* U = lds;
+    double* X = U + nk;
+    double* W = X + 3 * g.n;
+    double* RT = W + (g.w ? g.n : 0);
+    for (int k = threadIdx.x; k < nk; k += kBlock) U[k] = knot(g, k);
+    for (int k = threadIdx.x; k < 3 * g.n; k += kBlock) X[k] = g.ctrl[k];
+    if (g.w)
+        for (int k = threadIdx.x; k < g.n; k += kBlock) W[k] = g.w[k];
+    __syncthreads();
+    constexpr int NR = P * (P + 1) / 2;
+    for (int k = threadIdx.x; k < g.nb - P; k += kBlock) {
+        const int sp = P + k;
+#pragma unroll
+        for (int q = 1; q <= P; ++q)
+#pragma unroll
+            for (int j = 0; j < q; ++j) RT[k * NR + q * (q - 1) / 2 + j] = recip(U[sp + 1 + j] - U[sp + 1 - q + j]);
+    }
+    __syncthreads();
+    return LdsCurve{U, X, W, RT, g.n, g.p, g.closed, g.nb, g.w != nullptr, g.knots != nullptr, nullptr, nullptr};
+}
+
 // Open curve evaluated at samples of increasing index.  Knot span data are
 // loaded when the span changes: the 2P knots U_{s-P+1} .. U_{s+P}, the
 // reciprocals of the knot differences used by the triangular Cox-de Boor
@@ -36,6 +126,7 @@ namespace sweep {
 template <int P>
 struct PathCursor {
     int s = -1;
+    double ua, ub;                     // open curve: parameter range [U_p, U_n]
     double Uk[2 * P];
     double rt[P * (P + 1) / 2];        // 1/(U_{s+j+1} - U_{s-q+j+1}), q = 1..P, j < q, at q(q-1)/2 + j
     double f1[P > 0 ? P : 1];          // P/(U_{s+j+1} - U_{s-P+j+1})
@@ -44,39 +135,49 @@ struct PathCursor {
     V3<double> Pt[P + 1];
     double w[P + 1];
 
-    template <int ND>
-    __device__ __forceinline__ void load(const DCurve& c, int sp)
+    template <int ND, class C>
+    __device__ __forceinline__ void load(const C& c, int sp)
     {
         s = sp;
 #pragma unroll
         for (int m = 0; m < 2 * P; ++m) Uk[m] = knot(c, sp - P + 1 + m);
-#pragma unroll
-        for (int q = 1; q <= P; ++q)
-#pragma unroll
-            for (int j = 0; j < q; ++j) rt[q * (q - 1) / 2 + j] = recip(Uk[P + j] - Uk[P - q + j]);
+        span_recips<P>(c, sp, Uk, rt);
+        // the derivative nets' factors reuse the reciprocals of the same
+        // knot differences (q = P, P-1, P-2 above)
         if (ND >= 1) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) f1[j] = (double)P * recip(Uk[P + j] - Uk[j]);
+            for (int j = 0; j < P; ++j) f1[j] = (double)P * rt[P * (P - 1) / 2 + j];
         }
         if (ND >= 2 && P >= 2) {
 #pragma unroll
-            for (int j = 0; j + 1 < P; ++j) f2[j] = (double)(P - 1) * recip(Uk[P + j] - Uk[j + 1]);
+            for (int j = 0; j + 1 < P; ++j) f2[j] = (double)(P - 1) * rt[(P - 1) * (P - 2) / 2 + j];
         }
         if (ND >= 3 && P >= 3) {
 #pragma unroll
-            for (int j = 0; j + 2 < P; ++j) f3[j] = (double)(P - 2) * recip(Uk[P + j] - Uk[j + 2]);
+            for (int j = 0; j + 2 < P; ++j) f3[j] = (double)(P - 2) * rt[(P - 2) * (P - 3) / 2 + j];
         }
 #pragma unroll
         for (int j = 0; j <= P; ++j) {
             Pt[j] = ctrl_pt(c, sp - P + j);
-            w[j] = c.w ? weight_at(c, sp - P + j) : 1.0;
-            if (c.w) Pt[j] = w[j] * Pt[j];   // homogeneous point of a rational curve
+            w[j] = is_rational(c) ? weight_at(c, sp - P + j) : 1.0;
+            if (is_rational(c)) Pt[j] = w[j] * Pt[j];   // homogeneous point of a rational curve
         }
     }
 
-    // C and its derivatives up to order ND at sample i of ns.
-    template <int ND>
-    __device__ __forceinline__ void eval(const DCurve& c, int i, int ns, V3<double>* out)
+    // The range ends of the uniform samples (open curves), read once.
+    template <class C>
+    __device__ __forceinline__ void start(const C& c)
+    {
+        ua = c.closed ? 0.0 : knot(c, c.p);
+        ub = c.closed ? 0.0 : knot(c, c.n);
+    }
+
+    // C and its derivatives up to order ND at sample i of ns.  The samples'
+    // parameters and spans are given (arc-length sampling, c.su and c.ss),
+    // or the uniform samples are formed here with the rounding of
+    // sample_param.
+    template <int ND, class C>
+    __device__ __forceinline__ void eval(const C& c, int i, int ns, V3<double>* out)
     {
         double u;
         int sp;
@@ -84,7 +185,16 @@ struct PathCursor {
             u = c.su[i];
             sp = c.ss[i];
         } else {
-            u = sample_param(c, i, ns);
+            if (c.closed) {
+                u = (double)c.p + (double)((long long)c.n * (long long)i) / (double)ns;
+            } else if (i == ns - 1) {
+                u = ub;
+            } else {
+                const double f = (double)i / (double)(ns - 1);
+                const double w = ub - ua;
+                const double g = w * f;
+                u = ua + g;
+            }
             if (s < 0) {
                 sp = sample_span(c, i, ns, u);
             } else {
@@ -138,7 +248,7 @@ struct PathCursor {
         // Sums over the span's control points.  For a rational curve the
         // cached points are the homogeneous w P and the weight sums run
         // beside them; then the quotient rule (NURBS Book ch. 4).
-        const bool rat = c.w != nullptr;
+        const bool rat = is_rational(c);
         V3<double> C0 = mk(0.0, 0.0, 0.0);
         double W0 = 0.0;
 #pragma unroll
@@ -214,8 +324,9 @@ struct RunInfo {
     bool first_valid;
 };
 
-template <int P, class F>
-__device__ __forceinline__ RunInfo<P, F> run_product(const DCurve& path, int n_u, int i0, int K, V3<double> t_in)
+template <int P, class F, class C>
+__device__ __forceinline__ RunInfo<P, F> run_product(const C& path, int n_u, int i0, int K,
+                                                          V3<double> t_in)
 {
     RunInfo<P, F> R;
     R.A = ident<F>();
@@ -225,6 +336,7 @@ __device__ __forceinline__ RunInfo<P, F> run_product(const DCurve& path, int n_u
     R.t_last_valid = t_in;
     if (i0 >= n_u) return R;
     PathCursor<P> cur;
+    cur.start(path);
     V3<double> o[2];
     cur.template eval<1>(path, i0, n_u, o);
     V3<double> xa = o[0];
@@ -250,8 +362,8 @@ __device__ __forceinline__ RunInfo<P, F> run_product(const DCurve& path, int n_u
 // resolved tangent at i0 (t_first) and the normal entering the run (r, in the
 // frame precision).  `row(i, x, t, C', C'', r)` writes one record (ND = 2, or
 // 3 with the third derivative in o[3] for the Frenet mode).
-template <int P, int ND, class F, class RowFn>
-__device__ __forceinline__ void run_rows(const DCurve& path, int n_u, int i0, int K, V3<double> t_first, V3<F> r,
+template <int P, int ND, class F, class C, class RowFn>
+__device__ __forceinline__ void run_rows(const C& path, int n_u, int i0, int K, V3<double> t_first, V3<F> r,
                                          RowFn&& row)
 {
     if (i0 >= n_u) return;
@@ -260,20 +372,26 @@ __device__ __forceinline__ void run_rows(const DCurve& path, int n_u, int i0, in
     // passes (that kept pass 1's registers live through the scan)
     asm volatile("" : "+v"(i0));
     PathCursor<P> cur;
-    V3<double> a[ND + 1];
+    cur.start(path);
+    V3<double> a[ND + 1], b[ND + 1];
     cur.template eval<ND>(path, i0, n_u, a);
     V3<double> ta = t_first;
     const int iend = min(i0 + K, n_u);
 #pragma nounroll
     for (int i = i0; i < iend; ++i) {
+        // The next sample is evaluated before this sample's record is
+        // stored: the loads it may issue (knot span data) then wait only for
+        // the stores of the previous record, not for these (the vector
+        // memory counter retires loads and stores in issue order).
+        const bool more = i + 1 < n_u;
+        if (more) cur.template eval<ND>(path, i + 1, n_u, b);
         row(i, a, ta, r);
-        if (i + 1 >= n_u) break;
-        // the next sample, then the step to it
-        const V3<double> xa = a[0];
-        cur.template eval<ND>(path, i + 1, n_u, a);
-        const V3<double> tb = speed_nonzero(a[1]) ? unit_of(a[1]) : ta;
-        r = apply_step(make_step<F>(cvt<F>(a[0] - xa), cvt<F>(ta), cvt<F>(tb)), r);
+        if (!more) break;
+        const V3<double> tb = speed_nonzero(b[1]) ? unit_of(b[1]) : ta;
+        r = apply_step(make_step<F>(cvt<F>(b[0] - a[0]), cvt<F>(ta), cvt<F>(tb)), r);
         ta = tb;
+#pragma unroll
+        for (int d = 0; d <= ND; ++d) a[d] = b[d];
     }
 }
 
@@ -315,8 +433,8 @@ struct ChunkWalkLds {
     int flag;
 };
 
-template <int P, class F>
-__device__ bool chunk_products(const DCurve& path, int n_u, int base, int K, bool entry_known, V3<double> t_entry,
+template <int P, class F, class C>
+__device__ bool chunk_products(const C& path, int n_u, int base, int K, bool entry_known, V3<double> t_entry,
                                ChunkWalkLds& L, RunInfo<P, F>& R, int& chunk_lv, V3<double>& chunk_tl)
 {
     const int i0 = base + threadIdx.x * K;

@@ -15,7 +15,10 @@ struct InitialNormal {
 };
 
 // Frame of a single sweep: runs of K consecutive u-samples per thread,
-// chunks of kBlock runs (K and the chunk count for n_u samples).
+// chunks of kBlock runs (K and the chunk count for n_u samples).  The fused
+// frame kernel takes up to kBlock*kFusedGroup chunks (kFusedGroup per thread
+// in its carry).
+constexpr int kFusedGroup = 2;
 int frame_run_length(int n_u);
 int frame_chunks(int n_u);
 
@@ -143,6 +146,16 @@ void fastdiv_constants(int d, unsigned long long* m, int* shift);
 // Longest batched sweep whose frame is one chunk: kBlock runs of up to
 // kMaxRun u-samples (longer sweeps take the chunk-walking frame kernel).
 constexpr int kMaxRun = 16;
+// Dynamic LDS of the one-chunk batched frame kernel (the staged path:
+// lds_path_doubles of the path must not exceed it; other sweeps take the
+// chunk-walking kernel).  44 KB: two blocks per CU with the static LDS.
+constexpr int kLdsPathDoubles = 5632;
+// LDS doubles an open path of n control points and degree p needs when
+// staged: knots, control points, weights (rational), per-span reciprocals.
+constexpr long long lds_path_doubles(int n, int p, bool rat)
+{
+    return (long long)(n + p + 1) + 3LL * n + (rat ? n : 0) + (long long)(n - p) * (p * (p + 1) / 2);
+}
 
 struct BatchedKernels {
     const void* profile;

@@ -240,6 +240,7 @@ int tune()
             nv.push_back(5 + (i * 11 + k) % 90);
         }
         make_batch(more[i], deg, nu, nv, i % 3 == 0, rng);
+        opt.batch_stages = i % 5;   // one to four pipeline stages (0: automatic)
         const int64_t e2 = sweep_batched_output_elems(&more[i].b);
         float* p2 = (float*)dev_alloc(sizeof(float) * e2);
         float* n2 = (float*)dev_alloc(sizeof(float) * e2);
@@ -262,8 +263,9 @@ int tune()
     }
     {
         // a batch of 300 sweeps of mixed lengths (short and chunk-walking
-        // frame nodes of two degrees), evaluated into two sets of buffers
-        // (node parameter updates), then differentiated
+        // frame nodes of two degrees, three pipeline stages), evaluated into
+        // two sets of buffers (node parameter updates), then differentiated
+        opt.batch_stages = 3;
         HostBatch big;
         std::vector<int> deg, nu, nv;
         for (int k = 0; k < 300; ++k) {

@@ -38,6 +38,13 @@ def test_batched_validation():
     b.n_sweeps = 0
     st = L.sweep_eval_batched(b, L.default_options(), 0x100000, 0, 0x100000, 1 << 40, 0)
     assert L.STATUS[st] == "SWEEP_ERR_BAD_COUNT"
+    b, keep = _batch([100, 10, 300], [10, 20, 30])
+    for bad in (-1, 5):
+        o = L.default_options()
+        o.batch_stages = bad
+        st = L.sweep_eval_batched(b, o, 0x100000, 0, 0x100000, 1 << 40, 0)
+        assert L.STATUS[st] == "SWEEP_ERR_BAD_OPTION" and "batch_stages" in L.last_error()
+        assert L.sweep_batched_workspace_size(b, o) == 0
 
 
 def test_batched_validation_names_the_sweep_and_curve():

@@ -199,13 +199,24 @@ def _stationary_path():
 
 
 def test_stationary_runs_beyond_256_chunks():
-    """More than 256 frame chunks take the chunk-carry route; its
-    degenerate-start chunks are formed in the carry kernel.  The oracle
-    multiplies the 70,000 step rotations in sequence, the GPU in a tree, so
-    the frames differ by rounding that grows with the scan length: the FP64
-    bound is 8 n eps (about 1.2e-10 here) rather than 1e-12."""
+    """274 frame chunks: the fused frame kernel's carry takes two chunk
+    products per thread, and the degenerate-start chunks (on both sides of
+    chunk 256) are formed inside it.  The oracle multiplies the 70,000 step
+    rotations in sequence, the GPU in a tree, so the frames differ by
+    rounding that grows with the scan length: the FP64 bound is 8 n eps
+    (about 1.2e-10 here) rather than 1e-12."""
     Q = synth.perturbed_circle(rng, 7)
     spec = synth.SweepSpec(synth.CurveSpec(_stationary_path(), 1), synth.CurveSpec(Q, 3, True), 70000, 8)
+    check_full(spec, out_dtype=torch.float64, tol=8 * spec.n_u * np.finfo(float).eps)
+
+
+def test_stationary_runs_chunk_carry_route():
+    """More than 512 frame chunks (2,200,000 u-samples in runs of 16: 538
+    chunks) take the one-block chunk carry and the separate row kernel;
+    degenerate-start chunks are formed in the carry.  Bound 8 n eps as
+    above."""
+    Q = synth.perturbed_circle(rng, 7)
+    spec = synth.SweepSpec(synth.CurveSpec(_stationary_path(), 1), synth.CurveSpec(Q, 3, True), 2200000, 4)
     check_full(spec, out_dtype=torch.float64, tol=8 * spec.n_u * np.finfo(float).eps)
 
 
@@ -228,10 +239,11 @@ def test_law_sweep_with_zero_speed_chunk_starts():
     assert ok, r
 
 
-@pytest.mark.parametrize("n_u", [5000, 60000])
+@pytest.mark.parametrize("n_u", [5000, 60000, 70000])
 def test_fused_and_carry_frame_routes_agree(n_u):
-    """Up to 256 chunks the plain sweep forms its frame in one launch (each
-    block forms its entry normal from the chunk products below it); with a
+    """Up to 512 chunks the plain sweep forms its frame in one launch (each
+    block forms its entry normal from the chunk products below it, two per
+    thread above 256 chunks: 70,000 samples); with a
     sweep law the same frame goes through the chunk-carry kernel.  An
     identity law (scale 1, twist 0) leaves the positions unchanged, so the
     two routes agree to rounding on the same input."""
