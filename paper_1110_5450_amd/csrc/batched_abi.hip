@@ -212,14 +212,14 @@ struct Plan {
     double* d_knots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int* d_sweeps[8] = {};         // sweeps by path degree: by stage, longest n_u first within a stage
+    int* d_sweeps[8] = {};         // sweeps by path degree: by stage and frame kernel, longest n_u first
     int n_deg[8] = {};
-    // Frame launches: sweeps [first, first + count) of d_sweeps[deg], all of
-    // one stage and all for the chunk-walking kernel (longer than one frame
-    // chunk, or a path too large to stage in LDS) or none.
+    // Frame launches: a range of d_sweeps[deg], all of one stage and one
+    // frame kernel: chunk-walking (longer than one frame chunk, or a path too
+    // large to stage in LDS), one-chunk block, or one wave per sweep.
+    enum { kWalkFrame = 0, kBlockFrame = 1, kWaveFrame = 2 };
     struct FrameRange {
-        int deg, first, count, stage;
-        bool is_long;
+        int deg, first, grid, stage, kind;   // list entries [first, first + grid * (kWaves if wave kind else 1))
     };
     std::vector<FrameRange> franges;
     int n_stages = 1;
@@ -384,29 +384,42 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         sweeps[b->path_degree[k]].push_back(k);
         for (int c = 0; c * kBlock < b->n_v[k]; ++c) vchunks.push_back(make_int2(k, c));
     }
-    // the chunk-walking frame kernel: sweeps longer than one frame chunk, or
-    // whose path does not fit the one-chunk kernel's LDS
+    // frame kernel of a sweep: one wave per sweep up to kWaveMaxU
+    // u-samples; the one-chunk block kernel up to kBlock*kMaxRun if the path
+    // fits its LDS; else the chunk-walking kernel
     const bool rat = b->path_weights != nullptr;
-    auto walks = [&](int k) {
-        return b->n_u[k] > kBlock * kMaxRun ||
-               lds_path_doubles(b->path_n[k], b->path_degree[k], rat) > kLdsPathDoubles;
+    auto fkind = [&](int k) -> int {
+        if (b->n_u[k] <= kWaveMaxU) return Plan::kWaveFrame;
+        if (b->n_u[k] <= kBlock * kMaxRun && lds_path_doubles(b->path_n[k], b->path_degree[k], rat) <= kLdsPathDoubles)
+            return Plan::kBlockFrame;
+        return Plan::kWalkFrame;
     };
     for (auto& l : sweeps)
         std::stable_sort(l.begin(), l.end(), [&](int x, int y) {
             const int sx = frame_stage(b->n_u[x], S), sy = frame_stage(b->n_u[y], S);
             if (sx != sy) return sx < sy;
-            if (walks(x) != walks(y)) return walks(x);
+            if (fkind(x) != fkind(y)) return fkind(x) < fkind(y);
             return b->n_u[x] > b->n_u[y];
         });
+    // device lists: the sorted sweeps, each wave-kernel range padded with -1
+    // to whole blocks of kWaves sweeps
+    std::vector<int> lists[8];
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
         const std::vector<int>& l = sweeps[p];
         size_t i = 0;
         while (i < l.size()) {
             const int st = frame_stage(b->n_u[l[i]], S);
-            const bool lg = walks(l[i]);
+            const int kind = fkind(l[i]);
             size_t j = i;
-            while (j < l.size() && frame_stage(b->n_u[l[j]], S) == st && walks(l[j]) == lg) ++j;
-            P->franges.push_back(Plan::FrameRange{p, (int)i, (int)(j - i), st, lg});
+            while (j < l.size() && frame_stage(b->n_u[l[j]], S) == st && fkind(l[j]) == kind) ++j;
+            const int first = (int)lists[p].size();
+            lists[p].insert(lists[p].end(), l.begin() + i, l.begin() + j);
+            int grid = (int)(j - i);
+            if (kind == Plan::kWaveFrame) {
+                while ((lists[p].size() - first) % kWaves) lists[p].push_back(-1);
+                grid = ((int)lists[p].size() - first) / kWaves;
+            }
+            P->franges.push_back(Plan::FrameRange{p, first, grid, st, kind});
             i = j;
         }
     }
@@ -426,8 +439,8 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         return hip_fail(e, "plan upload");
     for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
         P->n_deg[p] = (int)sweeps[p].size();
-        if (!sweeps[p].empty() &&
-            (e = upload((void**)&P->d_sweeps[p], sweeps[p].data(), sizeof(int) * sweeps[p].size())) != hipSuccess)
+        if (!lists[p].empty() &&
+            (e = upload((void**)&P->d_sweeps[p], lists[p].data(), sizeof(int) * lists[p].size())) != hipSuccess)
             return hip_fail(e, "plan upload");
     }
     if (!knots.empty() && (e = upload((void**)&P->d_knots, knots.data(), sizeof(double) * knots.size())) != hipSuccess)
@@ -475,10 +488,13 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         std::vector<hipGraphNode_t> frames;
         for (const Plan::FrameRange& r : P->franges) {
             if (r.stage != st) continue;
-            const void* fn = r.is_long ? K.frame_long[r.deg] : K.frame[r.deg];
-            const unsigned lds = r.is_long ? 0u : (unsigned)(sizeof(double) * kLdsPathDoubles);
-            if ((e = add(kFrame, r.deg, fn, (unsigned)r.count, prev_frames, r.first, lds)) != hipSuccess)
-                return hip_fail(e, "graph node");
+            const void* fn = r.kind == Plan::kWalkFrame    ? K.frame_long[r.deg]
+                             : r.kind == Plan::kBlockFrame ? K.frame[r.deg]
+                                                           : K.frame_wave[r.deg];
+            const unsigned lds = r.kind == Plan::kBlockFrame ? (unsigned)(sizeof(double) * kLdsPathDoubles) : 0u;
+            if ((e = add(kFrame, r.deg, fn, (unsigned)r.grid, prev_frames, r.first, lds)) != hipSuccess)
+                return fail(SWEEP_ERR_HIP, "graph node (frame kernel %d, degree %d, %d blocks, %u B LDS): %s", r.kind,
+                            r.deg, r.grid, lds, hipGetErrorString(e));
             frames.push_back(P->nodes.back()->node);
         }
         const int t0 = P->stage_tiles[st], nt = P->stage_tiles[st + 1] - t0;
@@ -697,9 +713,11 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         if ((e = launch(kProfile, 0, FK.profile, (unsigned)P->n_vchunks)) != hipSuccess)
             return hip_fail(e, "backward frames");
         for (const Plan::FrameRange& r : P->franges) {
-            const void* fn = r.is_long ? FK.frame_long[r.deg] : FK.frame[r.deg];
-            const size_t lds = r.is_long ? 0 : sizeof(double) * kLdsPathDoubles;
-            if ((e = launch(kFrame, r.deg, fn, (unsigned)r.count, r.first, lds)) != hipSuccess)
+            const void* fn = r.kind == Plan::kWalkFrame    ? FK.frame_long[r.deg]
+                             : r.kind == Plan::kBlockFrame ? FK.frame[r.deg]
+                                                           : FK.frame_wave[r.deg];
+            const size_t lds = r.kind == Plan::kBlockFrame ? sizeof(double) * kLdsPathDoubles : 0;
+            if ((e = launch(kFrame, r.deg, fn, (unsigned)r.grid, r.first, lds)) != hipSuccess)
                 return hip_fail(e, "backward frames");
         }
     }

@@ -96,6 +96,63 @@ __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__
                       PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
 }
 
+// Run length of a sweep framed by one wave: the smallest power of two up to
+// kMaxRun with 64*K >= n_u (at most 4 for kWaveMaxU = 256).
+__device__ __forceinline__ int wave_run_length(int n_u)
+{
+    int K = 1;
+    while (K < kMaxRun && 64 * K < n_u) K *= 2;
+    return K;
+}
+
+// Row records of sweeps of at most kWaveMaxU u-samples, one wave per sweep
+// (four sweeps per block, no block barriers): lane l owns the run of K
+// samples from l*K.  The tangent carries and the exclusive product of the
+// run products are wave scans (cross-lane moves); the path is read from
+// global memory.  Entries of -1 in the sweep list (padding to whole blocks)
+// are skipped.
+template <int P, class F, class T>
+__global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restrict__ descs,
+                                                        const int* __restrict__ sweeps,
+                                                        const double* __restrict__ path_ctrl,
+                                                        const double* __restrict__ path_w,
+                                                        const double* __restrict__ knots, InitialNormal n0,
+                                                        int reorth, T* __restrict__ rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = sweeps[blockIdx.x * kWaves + (threadIdx.x >> 6)];
+    if (k < 0) return;   // wave-uniform
+    const BatchDesc d = descs[k];
+    const DCurve path = path_of(d, path_ctrl, path_w, knots);
+    const int n_u = d.n_u;
+    const int K = wave_run_length(n_u);
+    const int i0 = lane * K;
+    const V3<double> t_entry = first_leg(path);
+    RunInfo<P, F> R = run_product<P, F>(path, n_u, i0, K, t_entry);
+    // last sample with C' != 0 below this lane's run, and its tangent
+    int src = R.last_valid;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const int o = __shfl_up(src, dd, 64);
+        if (lane >= dd) src = max(src, o);
+    }
+    src = __shfl_up(src, 1, 64);
+    if (lane == 0) src = -1;
+    const int owner = src >= 0 ? src / K : 0;
+    V3<double> tc = mk(__shfl(R.t_last_valid.x, owner, 64), __shfl(R.t_last_valid.y, owner, 64),
+                       __shfl(R.t_last_valid.z, owner, 64));
+    if (src < 0) tc = t_entry;
+    // runs whose first sample has C' = 0 walk again with the carry resolved
+    // (lane 0's carry is the known entry: it never needs to)
+    if (i0 < n_u && !R.first_valid && lane > 0) R = run_product<P, F>(path, n_u, i0, K, tc);
+    // r_0 from the resolved t_0 (lane 0's first sample)
+    const V3<double> t0 = mk(__shfl(R.t_first.x, 0, 64), __shfl(R.t_first.y, 0, 64), __shfl(R.t_first.z, 0, 64));
+    const V3<F> rin = cvt<F>(initial_normal(t0, n0));
+    const M3<F> ex = wave_shift_up1<F>(wave_inclusive_product<F>(R.A));
+    run_rows<P, 2, F>(path, n_u, i0, K, R.t_first, apply(ex, rin),
+                      PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
+}
+
 // The same for longer sweeps: the block walks chunks of kBlock*kMaxRun
 // samples in order, carrying the entering normal and the last resolved
 // tangent.  (A kernel of its own: the loop's carried state raises the
@@ -225,7 +282,9 @@ static BatchedKernels pick(bool nrm, bool nt, int K)
     k.profile = (const void*)&kb_profile<T>;
     k.frame[0] = nullptr;
     k.frame_long[0] = nullptr;
-#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>; k.frame_long[P] = (const void*)&kb_frame_long<P, F, T>;
+    k.frame_wave[0] = nullptr;
+#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>; k.frame_long[P] = (const void*)&kb_frame_long<P, F, T>; \
+    k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T>;
     SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
 #undef SWEEP_DEG
     if (nrm) k.surface = nt ? surface_for<T, true, true>(K) : surface_for<T, true, false>(K);

@@ -70,25 +70,25 @@ template <class F> __device__ __forceinline__ V3<F> apply(const M3<F>& a, V3<F> 
 // 1/x from the hardware reciprocal refined by Newton steps (two in FP64, one
 // in FP32): within an ulp or two of the correctly rounded quotient, with a
 // shorter dependency chain than the IEEE division, and the same instructions
-// wherever it is inlined.  Inputs outside the normal range (0, denormals,
-// huge, inf, NaN) take the IEEE division.
+// wherever it is inlined.  No branch: where the refinement is not finite
+// (x = 0, inf, NaN, or a quotient beyond the range) the hardware value is
+// the result (inf, 0, NaN or inf).  Denormal x gives inf in FP64 (as the
+// hardware reciprocal does).
 __device__ __forceinline__ double recip(double x)
 {
-    const double ax = fabs(x);
-    if (!(ax > 1e-300 && ax < 1e300)) return 1.0 / x;
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r0, 1.0);
+    double r = fma(r0, e, r0);
     e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    r = fma(r, e, r);
+    return __builtin_isfinite(r) ? r : r0;
 }
 __device__ __forceinline__ float recip(float x)
 {
-    const float ax = fabsf(x);
-    if (!(ax > 1e-30f && ax < 1e30f)) return 1.0f / x;
-    float r = __builtin_amdgcn_rcpf(x);
-    const float e = fmaf(-x, r, 1.0f);
-    return fmaf(r, e, r);
+    const float r0 = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r0, 1.0f);
+    const float r = fmaf(r0, e, r0);
+    return __builtin_isfinite(r) ? r : r0;
 }
 
 // ------------------------------------------------------------------ curves

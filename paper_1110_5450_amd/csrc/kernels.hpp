@@ -150,6 +150,11 @@ constexpr int kMaxRun = 16;
 // lds_path_doubles of the path must not exceed it; other sweeps take the
 // chunk-walking kernel).  44 KB: two blocks per CU with the static LDS.
 constexpr int kLdsPathDoubles = 5632;
+// Sweeps of at most this many u-samples are framed by one wave each (four
+// per block, no block barriers).  Short sweeps spend most of a block's time
+// in its fixed steps; longer runs per lane than 4 lengthen a wave's serial
+// walk more than they save (measured on the 4096-sweep batch).
+constexpr int kWaveMaxU = 256;
 // LDS doubles an open path of n control points and degree p needs when
 // staged: knots, control points, weights (rational), per-span reciprocals.
 constexpr long long lds_path_doubles(int n, int p, bool rat)
@@ -160,7 +165,8 @@ constexpr long long lds_path_doubles(int n, int p, bool rat)
 struct BatchedKernels {
     const void* profile;
     const void* frame[8];        // by path degree (index 0 unused): sweeps of n_u <= kBlock*kMaxRun
-    const void* frame_long[8];   // longer sweeps
+    const void* frame_long[8];   // longer sweeps, or paths too large for the LDS staging
+    const void* frame_wave[8];   // sweeps of n_u <= kWaveMaxU, one wave each
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as

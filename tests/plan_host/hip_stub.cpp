@@ -332,6 +332,11 @@ hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGr
             return hipErrorInvalidValue;
         }
     }
+    if (prm->gridDim.x < 1 || prm->gridDim.y < 1 || prm->gridDim.z < 1 || prm->blockDim.x < 1 ||
+        prm->blockDim.x > 1024 || prm->sharedMemBytes > 65536) {
+        violation("graph kernel node with an invalid launch configuration");
+        return hipErrorInvalidConfiguration;
+    }
     const stub::KernelSig* sig = stub::lookup(prm->func);
     if (!sig) {
         violation("graph kernel node with an unknown function");
@@ -432,9 +437,13 @@ hipError_t hipGraphDestroy(hipGraph_t g)
     return hipSuccess;
 }
 
-hipError_t hipLaunchKernel(const void* f, dim3, dim3, void** args, size_t, hipStream_t s)
+hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void** args, size_t lds, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (grid.x < 1 || grid.y < 1 || grid.z < 1 || block.x < 1 || block.x > 1024 || lds > 65536) {
+        violation("launch with an invalid configuration");
+        return hipErrorInvalidConfiguration;
+    }
     const stub::KernelSig* sig = stub::lookup(f);
     if (!sig) {
         violation("launch of an unknown function");

@@ -19,6 +19,7 @@ constexpr ArgSig N0{sizeof(sweep::InitialNormal), kValue};
 const KernelSig kProfile{"kb_profile", {P, P, P, N, N, P}};
 const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P}};
 const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P}};
+const KernelSig kFrameWave{"kb_frame_wave", {P, P, P, N, N, N0, I, P}};
 const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
 const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
 const KernelSig kRows{"kbw_rows", {P, P, P, N, N, P, P, P, P, P, I}};
@@ -28,7 +29,7 @@ const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, 
 const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
 
 // distinct addresses standing in for kernel entry points
-char g_profile, g_frame[8], g_frame_long[8], g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
+char g_profile, g_frame[8], g_frame_long[8], g_frame_wave[8], g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
 
 const std::map<const void*, const KernelSig*>& table()
 {
@@ -37,6 +38,7 @@ const std::map<const void*, const KernelSig*>& table()
         m[&g_profile] = &kProfile;
         for (int p = 1; p < 8; ++p) m[&g_frame[p]] = &kFrame;
         for (int p = 1; p < 8; ++p) m[&g_frame_long[p]] = &kFrameLong;
+        for (int p = 1; p < 8; ++p) m[&g_frame_wave[p]] = &kFrameWave;
         m[&g_surface] = &kSurface;
         m[&g_reduce] = &kReduce;
         m[&g_rows] = &kRows;
@@ -60,7 +62,7 @@ const KernelSig* lookup(const void* fn)
 
 std::vector<const KernelSig*> all_kernels()
 {
-    return {&kProfile, &kFrame, &kFrameLong, &kSurface, &kReduce, &kRows, &kSamples, &kFinal, &kParamRec, &kParams};
+    return {&kProfile, &kFrame, &kFrameLong, &kFrameWave, &kSurface, &kReduce, &kRows, &kSamples, &kFinal, &kParamRec, &kParams};
 }
 
 }  // namespace stub
@@ -73,8 +75,10 @@ BatchedKernels batched_kernels(bool, bool, bool, bool, int)
     k.profile = &stub::g_profile;
     k.frame[0] = nullptr;
     k.frame_long[0] = nullptr;
+    k.frame_wave[0] = nullptr;
     for (int p = 1; p < 8; ++p) k.frame[p] = &stub::g_frame[p];
     for (int p = 1; p < 8; ++p) k.frame_long[p] = &stub::g_frame_long[p];
+    for (int p = 1; p < 8; ++p) k.frame_wave[p] = &stub::g_frame_wave[p];
     k.surface = &stub::g_surface;
     return k;
 }

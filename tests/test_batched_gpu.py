@@ -1,6 +1,6 @@
 """Batched evaluation (profile, per-degree frame and surface launches,
 replayed from a HIP graph): every sweep's block agrees with evaluating that
-sweep alone (bitwise for sweeps of one chunk), matches the oracle, survives
+sweep alone (to rounding), matches the oracle, survives
 repeated replays with pointer changes, and every sweep of the full
 4096-sweep batch matches the oracle."""
 
@@ -36,10 +36,12 @@ def _mixed(seed=0, n=24):
     return specs
 
 
-# Batched vs single for sweeps longer than one chunk of 256 u-samples: the
-# chunk products are associated differently (sequentially in the batched
-# frame kernel, by a tree scan in the single-sweep one), so the two agree to
-# rounding only.
+# Batched vs single: the batched frame kernels split a sweep's samples into
+# runs differently (one wave per sweep up to 256 u-samples with runs of up to
+# 4 per lane, one block with runs of 2 to 16 above that) from the
+# single-sweep kernels (runs of 1 per thread below 131,072 samples), so the
+# rotation products are associated differently and the two agree to
+# rounding.
 _CLOSE = {torch.float64: 1e-13, torch.float32: 1e-6}
 
 
@@ -50,22 +52,14 @@ def test_batched_equals_single(out_dtype):
     b = api.Batch.from_specs(specs)
     pos, nrm = api.sweep_eval_batched(b, out_dtype=out_dtype)
     torch.cuda.synchronize()
-    n_exact = 0
     for k, s in enumerate(specs):
         p1, n1 = gpu_sweep(s, out_dtype, tile_config=13)
         torch.cuda.synchronize()
         pb, nb = b.view(pos, k), b.view(nrm, k)
-        if s.n_u <= 256:
-            # one chunk: the same arithmetic in the same order
-            assert torch.equal(pb, p1), k
-            assert torch.equal(nb, n1), k
-            n_exact += 1
-        else:
-            ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
-            ok, r = parity(p1.cpu().numpy(), n1.cpu().numpy(), ref.kappa, pb.cpu().numpy(), nb.cpu().numpy(),
-                           _CLOSE[out_dtype])
-            assert ok, (k, r)
-    assert n_exact >= 3
+        ref = oracle.sweep(s.path, s.profile, s.n_u, s.n_v)
+        ok, r = parity(p1.cpu().numpy(), n1.cpu().numpy(), ref.kappa, pb.cpu().numpy(), nb.cpu().numpy(),
+                       _CLOSE[out_dtype])
+        assert ok, (k, r)
 
 
 def test_batched_padded_layout_zeroes_padding():
@@ -131,7 +125,8 @@ def test_batched_user_knots_and_precision_variants():
 def test_batched_chunk_counts_and_every_degree():
     # Every path degree at every length: sweeps of one chunk of runs (up to
     # 4096 u-samples: 200, 1000, 2700) and of two and three chunks (4097,
-    # 9000: the chunk-walking frame kernel), interleaved; two replays agree
+    # 9000: the chunk-walking frame kernel), interleaved, and four with
+    # stationary stretches; two replays agree
     # bitwise.  The oracle multiplies the step rotations in sequence, the GPU
     # in runs and a block scan: FP64 agreement to 8 n eps for long sweeps.
     rng = np.random.default_rng(12)
@@ -141,6 +136,15 @@ def test_batched_chunk_counts_and_every_degree():
         P = synth.random_walk(rng, int(rng.integers(p + 1, 40)))
         Q = synth.perturbed_circle(rng, int(rng.integers(4, 12)))
         specs.append(synth.SweepSpec(synth.CurveSpec(P, p), synth.CurveSpec(Q, 3, True), n_u, 7 + k % 5))
+    # stationary stretches (repeated control points of a degree-1 path): runs
+    # whose first sample has C' = 0 take the carried tangent, in the
+    # one-wave, one-block and chunk-walking kernels
+    for n_u in (300, 1000, 3000, 5000):
+        P = synth.random_walk(rng, 12)
+        P[4] = P[3]
+        P[11] = P[10]
+        Q = synth.perturbed_circle(rng, 7)
+        specs.append(synth.SweepSpec(synth.CurveSpec(P, 1), synth.CurveSpec(Q, 3, True), n_u, 8))
     b = api.Batch.from_specs(specs)
     say(f"[case] every length and degree: {len(specs)} sweeps")
     pos, nrm = api.sweep_eval_batched(b, out_dtype=torch.float64)

@@ -101,10 +101,13 @@ def test_rational_batch_matches_oracle_and_single():
                        TOL[torch.float64])
         say(f"   sweep {k}: {r}")
         assert ok, (k, r)
-        if s.n_u <= 256:
-            p1, n1 = gpu_sweep(s, torch.float64, tile_config=13)
-            torch.cuda.synchronize()
-            assert torch.equal(b.view(pos, k), p1) and torch.equal(b.view(nrm, k), n1)
+        # the single-sweep evaluation agrees to rounding (the batched frame
+        # kernels group the samples into runs differently)
+        p1, n1 = gpu_sweep(s, torch.float64, tile_config=13)
+        torch.cuda.synchronize()
+        ok, r = parity(p1.cpu().numpy(), n1.cpu().numpy(), ref.kappa, b.view(pos, k).cpu().numpy(),
+                       b.view(nrm, k).cpu().numpy(), 1e-13)
+        assert ok, (k, r)
 
 
 def test_rational_adjoint_against_fd():
