@@ -34,11 +34,12 @@
 
 namespace sweep {
 
-// One wave per unit (sweep, kBwSub groups of G rows, segment of 64 columns);
-// each wave's LDS tiles are its own (no block barriers).  For each group,
-// lane = column j loads its G x 3 values of w (coalesced) and keeps them in
-// registers for the column sums
-//   h_j += R_i^T w_ij over the unit's rows (one partial per unit);
+// One block per unit (sweep, kWaves groups of G rows, segment of 64
+// columns), one wave per group; each wave's LDS tiles are its own (no block
+// barriers until the end).  Lane = column j loads its G x 3 values of w
+// (coalesced) and keeps them in registers for the column sums
+//   h_j += R_i^T w_ij over the group's rows, added over the block's waves
+//   in wave order at the end (one column partial per unit);
 // the values also go to an LDS tile (rows padded to 65 elements: no bank
 // conflicts) from which lane = (component c, row r, half h) forms the row
 // sums over 32 of the 64 columns; the two halves are added in a fixed order
@@ -72,13 +73,13 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
     __shared__ double ls[kWaves][3][64];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int unit = blockIdx.x * kWaves + wave;
-    const bool live = unit < n_units;   // wave-uniform
+    const int unit = blockIdx.x;
+    const bool live = unit < n_units;   // block-uniform
     int4 un = make_int4(0, 0, 0, 0);
     if (live) un = units[unit];
     const BatchDesc& d = descs[un.x];
     const int n_u = d.n_u, n_v = d.n_v;
-    const int g = un.y, seg = un.z;
+    const int g = un.y * kWaves + wave, seg = un.z;   // this wave's group of G rows
     const int j = seg * 64 + lane;
     const bool vj = live && j < n_v;
     {
@@ -89,13 +90,11 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
         }
         ls[wave][0][lane] = S0; ls[wave][1][lane] = S1; ls[wave][2][lane] = S2;
     }
-    // column sums over the unit's kBwSub groups of G rows
+    // column sums over this wave's G rows
     double h0 = 0.0, h1 = 0.0, h2 = 0.0;
     V3<double> hD = mk(0.0, 0.0, 0.0);
-#pragma nounroll
-    for (int sub = 0; sub < kBwSub; ++sub) {
-    const int i0 = (g * kBwSub + sub) * G;
-    if (!live || i0 >= n_u) break;   // wave-uniform
+    const int i0 = g * G;
+    if (live && i0 < n_u) {   // wave-uniform
     const int nr = min(G, n_u - i0);
     wave_lds_sync();   // the previous group's LDS tiles are consumed
     T w[3][G];
@@ -215,11 +214,30 @@ __global__ __launch_bounds__(kBlock) void kbw_reduce(const BatchDesc* __restrict
                 rowpart[RP * (d.rowpart_off + (size_t)seg * n_u + i0 + r) + kRowPart + e] = part;
         }
     }
-    }   // groups of G rows
-    if (vj) {
-        double* q = colpart + CP * (d.colpart_off + (size_t)g * n_v + j);
-        q[0] = h0; q[1] = h1; q[2] = h2;
-        if (NRM) { q[3] = hD.x; q[4] = hD.y; q[5] = hD.z; }
+    }   // the wave's rows
+    // the unit's column partial: the waves' sums added in wave order,
+    // through the (now free) LDS tiles
+    __syncthreads();
+    double* hc = reinterpret_cast<double*>(&lw[0][0][0][0]);   // kWaves x CP x 64
+    static_assert(sizeof(lw) >= sizeof(double) * kWaves * kColPartNrm * 64, "LDS tile too small for the column sums");
+    hc[(wave * CP + 0) * 64 + lane] = h0;
+    hc[(wave * CP + 1) * 64 + lane] = h1;
+    hc[(wave * CP + 2) * 64 + lane] = h2;
+    if (NRM) {
+        hc[(wave * CP + 3) * 64 + lane] = hD.x;
+        hc[(wave * CP + 4) * 64 + lane] = hD.y;
+        hc[(wave * CP + 5) * 64 + lane] = hD.z;
+    }
+    __syncthreads();
+    if (wave == 0 && vj) {
+        double* q = colpart + CP * (d.colpart_off + (size_t)un.y * n_v + j);
+#pragma unroll
+        for (int e = 0; e < CP; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += hc[(w * CP + e) * 64 + lane];
+            q[e] = t;
+        }
     }
 }
 

@@ -732,7 +732,7 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         void* rowpart = ws + B.rowpart;
         void* colpart = ws + B.colpart;
         void* args[9] = {&descs, &units, &n_units, &g, &gn, &rows, &ptab, &rowpart, &colpart};
-        const unsigned grid = (unsigned)((n_units + kWaves - 1) / kWaves);
+        const unsigned grid = (unsigned)n_units;   // one block per unit
         if ((e = hipLaunchKernel(BK.reduce, dim3(grid), dim3(kBlock), args, 0, sm)) != hipSuccess)
             return hip_fail(e, "backward reduce");
     }

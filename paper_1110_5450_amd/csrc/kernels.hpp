@@ -117,12 +117,9 @@ constexpr int kPlaneAlign = 64;
 // LDS tile of a wave holds G x 65 values per plane).
 template <class T>
 constexpr int bw_row_group() { return sizeof(T) == 8 ? 4 : 8; }
-// Groups of G rows per reduction unit: one column partial per unit (more
-// groups per unit write fewer partials but leave too few waves in flight:
-// 8 groups ran 10% slower on MI355X than 1).
-constexpr int kBwSub = 1;
-// Rows per reduction unit (the column partials' row groups).
-inline int bw_unit_rows_for(bool t64) { return (t64 ? 4 : 8) * kBwSub; }
+// Rows per reduction unit: one block, one group of G rows per wave, one
+// column partial per unit (the column partials' row groups).
+inline int bw_unit_rows_for(bool t64) { return (t64 ? 4 : 8) * kWaves; }
 
 struct BackwardKernels {
     const void* reduce;
