@@ -36,12 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "swept-surface vertices/s (pos+normal) and % HBM peak; batched/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 COPY_CAL_BYTES = 512 << 20
-# Untimed calls before timing a batched entry point: on this HIP runtime one
-# of the first calls stalls the host once for 35-70 ms (the ninth graph
-# launch; the fourteenth positions-only backward call, with no stall over the
-# next 106; one of the first calls that request knot and weight gradients);
-# steady-state calls take 0.1-1 ms.
-GRAPH_WARMUP = 24
+# Untimed calls before timing a batched entry point.  The first call of a
+# plan builds it (descriptors, graph, the adjoint's unit and chunk lists):
+# 6 ms for the 4096-sweep batch, 13 ms for the first backward call; the
+# second call is within 0.3 ms of steady state and the later ones are
+# steady (each warm-up call is timed and reported with the result).
+GRAPH_WARMUP = 3
 COUNTERS = os.path.join(ROOT, "profiles", "surface_c2_counters.json")
 SURFACE_SRC = os.path.join(ROOT, "paper_1110_5450_amd", "csrc", "surface_kernels.hip")
 
@@ -322,8 +322,12 @@ def batched_variants(steps: int):
     tuned, tuned_ms = api.autotune_batched(b, out=(pos, nrm), workspace=ws)
     t_tune = time.perf_counter() - t_tune
     assert api.batched_config_for(b) == tuned
+    warm_ms = []
     for _ in range(GRAPH_WARMUP):
+        t1 = time.perf_counter()
         api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
+        torch.cuda.synchronize()
+        warm_ms.append(round(1e3 * (time.perf_counter() - t1), 3))
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t0 = time.perf_counter()
@@ -383,6 +387,7 @@ def batched_variants(steps: int):
                                "frac_of_hbm_peak": 24.0 * N / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                "tile_config": tuned, "tile": api.tile_config_name(tuned),
                                "autotune": {"best_ms": tuned_ms, "seconds": t_tune},
+                               "warmup_call_ms": warm_ms,
                                "error_vs_oracle": err},
         "single_calls_fp64": {"vertices_per_s": N / el64, "ms_per_pass": 1e3 * el64, "calls": len(specs)},
     }
@@ -447,8 +452,12 @@ def adjoint_variant(steps: int):
     wl = synth.loss_weights(specs, 55)
     g = b.pack(wl, torch.float32)
     ws = torch.empty(api.backward_workspace_size(b), dtype=torch.uint8, device="cuda")
+    warm_ms = []
     for _ in range(GRAPH_WARMUP):
+        t1 = time.perf_counter()
         api.sweep_backward(b, g, workspace=ws)
+        torch.cuda.synchronize()
+        warm_ms.append(round(1e3 * (time.perf_counter() - t1), 3))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -510,6 +519,7 @@ def adjoint_variant(steps: int):
     elf = time.perf_counter() - t0
     return {"workload": "256 sweeps, 64/16 cps, 1024x64, FP32", "vertices": N,
             "forward_ms": 1e3 * elf / steps, "backward_ms": 1e3 * el / steps,
+            "backward_warmup_call_ms": warm_ms,
             "backward_grad_read_GBps": 12.0 * N / (el / steps) / 1e9,
             "backward_with_normals_ms": 1e3 * el_n / steps,
             "backward_with_normals_grad_read_GBps": 24.0 * N / (el_n / steps) / 1e9,
