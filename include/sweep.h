@@ -112,8 +112,12 @@ typedef enum { SWEEP_F32 = 0, SWEEP_F64 = 1 } sweep_precision;
  *     sigma (cos th S_x - sin th S_y, sin th S_x + cos th S_y, S_z),
  * i.e. the cross-section is scaled by sigma and turned about t by theta
  * (radians); the surface normal includes d(sigma)/du and d(theta)/du.
- * Frame modes and laws are supported by sweep_eval (and sweep_autotune);
- * the other entry points return SWEEP_ERR_UNSUPPORTED for them.
+ * Frame modes and laws are supported by sweep_eval (and sweep_autotune) and
+ * by sweep_eval_batched (and sweep_autotune_batched), where the options'
+ * frame mode and law apply to every sweep of the batch (the law sampled on
+ * each sweep's own u-samples; FP64 frame precision only, else
+ * SWEEP_ERR_UNSUPPORTED); sweep_frames and the adjoint entry points return
+ * SWEEP_ERR_UNSUPPORTED for them.
  */
 typedef enum { SWEEP_FRAME_RMF = 0, SWEEP_FRAME_FRENET = 1 } sweep_frame_mode;
 

@@ -387,13 +387,14 @@ class Batch:
 def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=torch.float64,
                        reorthonormalize: bool = True, initial_normal=None, tile_config: int = -1,
                        normals: bool = True, frame_mode: str = "rmf", out=None,
-                       workspace: Optional[torch.Tensor] = None, stream=None, stages: int = 0):
+                       workspace: Optional[torch.Tensor] = None, stream=None, stages: int = 0,
+                       law: Optional[Law] = None):
     """Flat positions and normals (or None) of a batch in the padded batched
-    layout (rotation-minimizing frames; other frame modes are sweep_eval
-    only).  stages: pipeline stages of the frame/surface schedule (0:
-    automatic)."""
+    layout.  frame_mode and law apply to every sweep of the batch (one law
+    for all; they need the FP64 frame).  stages: pipeline stages of the
+    frame/surface schedule (0: automatic)."""
     b = batch.c_struct()
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law)
     opt.batch_stages = int(stages)
     ws_bytes = L.sweep_batched_workspace_size(b, opt)
     if ws_bytes == 0:
@@ -459,8 +460,11 @@ def tile_config_name(k: int) -> str:
     return f"config {k}: linear tiles of {tv} vertices per block, {store} stores"
 
 
-def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=torch.float64) -> int:
-    return L.sweep_batched_workspace_size(batch.c_struct(), make_options(out_dtype, frame_dtype))
+def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=torch.float64,
+                           frame_mode: str = "rmf", law: Optional[Law] = None) -> int:
+    """Workspace bytes of sweep_eval_batched (a frame mode or law: longer row records)."""
+    return L.sweep_batched_workspace_size(batch.c_struct(),
+                                          make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law))
 
 
 _PARAM_GRADS = ("path_knots", "prof_knots", "path_weights", "prof_weights")

@@ -73,8 +73,10 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     if (!o) return fail(SWEEP_ERR_NULL_ARG, "options are NULL");
     sweep_status st = check_options(o);
     if (st != SWEEP_OK) return st;
-    if (options_single_only(o))
-        return fail(SWEEP_ERR_UNSUPPORTED, "frame modes, laws and arc-length sampling are sweep_eval only");
+    if (o->u_sampling != SWEEP_U_PARAMETER)
+        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length and adaptive sampling are sweep_eval only");
+    if (options_ext(o) && o->frame_precision != SWEEP_F64)
+        return fail(SWEEP_ERR_UNSUPPORTED, "frame modes and laws in a batch need the FP64 frame");
     if (b->n_sweeps < 1) return fail(SWEEP_ERR_BAD_COUNT, "n_sweeps %d < 1", b->n_sweeps);
     if (o->batch_stages < 0 || o->batch_stages > 4)
         return fail(SWEEP_ERR_BAD_OPTION, "batch_stages %d outside 0..4", o->batch_stages);
@@ -139,7 +141,8 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     }
     if (!b->path_ctrl || !b->prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "control point buffer is NULL");
     size_t off = 0;
-    L.rows = off; off = align_up(off + tsz * 16 * (size_t)L.n_rows);
+    const size_t rl = options_ext(o) ? kRowExt : 16;   // row record length
+    L.rows = off; off = align_up(off + tsz * rl * (size_t)L.n_rows);
     L.ptab = off; off = align_up(off + tsz * 8 * (size_t)L.n_vs);
     L.total = off;
     if (lay) *lay = L;
@@ -149,6 +152,13 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         const int32_t v[8] = {o->out_precision, o->frame_precision, o->reorthonormalize, o->has_initial_normal,
                               o->tile_config, o->batch_stages, b->path_weights ? 1 : 0, b->prof_weights ? 1 : 0};
         key->ints.insert(key->ints.end(), v, v + 8);
+        // the frame mode and the law's shape (its control points are a call
+        // argument, its knots are uploaded with the plan)
+        const sweep_curve* lw = o->law;
+        const int32_t x[5] = {o->frame_mode, lw ? 1 : 0, lw ? lw->n_ctrl : 0, lw ? lw->degree : 0,
+                              lw && lw->knots ? 1 : 0};
+        key->ints.insert(key->ints.end(), x, x + 5);
+        if (lw && lw->knots) key->dbls.insert(key->dbls.end(), lw->knots, lw->knots + lw->n_ctrl + lw->degree + 1);
         if (o->has_initial_normal) key->dbls.insert(key->dbls.end(), o->initial_normal, o->initial_normal + 3);
     }
     return SWEEP_OK;
@@ -172,6 +182,7 @@ struct NodeArgs {
     void* ptab;
     void* pos;
     void* nrm;
+    BatchFrameExt fx;
 };
 
 enum NodeKind { kProfile, kFrame, kSurface };
@@ -182,7 +193,7 @@ struct GNode {
     hipGraphNode_t node = nullptr;
     hipKernelNodeParams prm{};
     NodeArgs a{};
-    void* ptrs[8];
+    void* ptrs[9];
 };
 
 // Parameter array of a node kind (pointers into n.a).
@@ -192,7 +203,7 @@ static int node_args(GNode& n)
     void** q = n.ptrs;
     switch (n.kind) {
     case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.prof_w, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 6; }
-    case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.path_w, &A.knots, &A.n0, &A.reorth, &A.rows}; std::memcpy(q, v, sizeof v); return 8; }
+    case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.path_w, &A.knots, &A.n0, &A.reorth, &A.rows, &A.fx}; std::memcpy(q, v, sizeof v); return 9; }
     default: { void* v[] = {&A.descs, &A.tiles, &A.rows, &A.ptab, &A.pos, &A.nrm}; std::memcpy(q, v, sizeof v); return 6; }
     }
 }
@@ -210,6 +221,7 @@ struct Plan {
     int2* d_uchunks_all = nullptr; // (sweep, chunk) of every path chunk, built on the first backward call
     int n_uchunks_all = 0;
     double* d_knots = nullptr;
+    double* d_law_knots = nullptr;  // the law's given knots
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int* d_sweeps[8] = {};         // sweeps by path degree: by stage and frame kernel, longest n_u first
@@ -270,6 +282,7 @@ struct Plan {
             if (d_sweeps[p]) hipFree(d_sweeps[p]);
         if (d_vchunks) hipFree(d_vchunks);
         if (d_knots) hipFree(d_knots);
+        if (d_law_knots) hipFree(d_law_knots);
     }
 };
 
@@ -343,6 +356,27 @@ static int frame_level(int n_u)
 static int frame_stage(int n_u, int S) { return frame_level(n_u) * S / 6; }
 static int resolved_stages(const sweep_options* o) { return o->batch_stages > 0 ? o->batch_stages : kDefaultStages; }
 static_assert(kMaxStages == 4, "batch_stages is validated as 0..4");
+
+// The frame mode and law of a batch as the frame kernels take them (every
+// field set, so that argument blocks compare bytewise).
+static void set_frame_ext(BatchFrameExt& fx, const sweep_options* o, const double* d_law_knots)
+{
+    std::memset(&fx, 0, sizeof fx);
+    fx.frenet = o->frame_mode == SWEEP_FRAME_FRENET;
+    if (const sweep_curve* lw = o->law) {
+        fx.has_law = 1;
+        fx.law_len = lw->knots ? lw->knots[lw->n_ctrl] - lw->knots[lw->degree] : 1.0;
+        DCurve c{};
+        c.ctrl = lw->ctrl;
+        c.knots = lw->knots ? d_law_knots : nullptr;
+        c.n = lw->n_ctrl;
+        c.p = lw->degree;
+        c.closed = 0;
+        c.nb = nbasis(lw->n_ctrl, lw->degree, 0);
+        c.w = lw->weights;
+        fx.law = c;
+    }
+}
 
 static std::mutex g_mu;
 static std::list<std::unique_ptr<Plan>> g_plans;   // most recently used first
@@ -446,8 +480,15 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     if (!knots.empty() && (e = upload((void**)&P->d_knots, knots.data(), sizeof(double) * knots.size())) != hipSuccess)
         return hip_fail(e, "plan upload");
 
+    const bool ext = options_ext(o);
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
-                                             with_nrm, cfg.nontemporal != 0, tv);
+                                             with_nrm, cfg.nontemporal != 0, tv, ext);
+    if (o->law && o->law->knots) {
+        const sweep_curve* lw = o->law;
+        if ((e = upload((void**)&P->d_law_knots, lw->knots, sizeof(double) * (lw->n_ctrl + lw->degree + 1))) !=
+            hipSuccess)
+            return hip_fail(e, "plan upload");
+    }
     // argument blocks are compared bytewise on every call: clear the padding
     std::memset(&P->a, 0, sizeof P->a);
     NodeArgs& A = P->a;
@@ -458,6 +499,7 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     A.n0.enabled = o->has_initial_normal;
     for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
     A.reorth = o->reorthonormalize;
+    set_frame_ext(A.fx, o, P->d_law_knots);
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
     // frame nodes: sweeps [first, first + grid) of the degree's list;
     // surface nodes: tiles [first, first + grid)
@@ -596,6 +638,7 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     A.ptab = ws + L.ptab;
     A.pos = pos;
     A.nrm = nrm;
+    set_frame_ext(A.fx, opt, P->d_law_knots);   // the law's control points are a call argument
     if (std::memcmp(&A, &P->a, sizeof A) != 0) {
         // a replay of this graph may still be in flight on some stream:
         // let it finish before its node parameters are rewritten
@@ -621,7 +664,7 @@ size_t sweep_backward_workspace_size(const sweep_batch* batch, const sweep_optio
     sweep_options def;
     if (!opt) { sweep_default_options(&def); opt = &def; }
     BatchLayout L;
-    if (check_batch(batch, opt, nullptr, &L, nullptr, nullptr) != SWEEP_OK) return 0;
+    if (options_ext(opt) || check_batch(batch, opt, nullptr, &L, nullptr, nullptr) != SWEEP_OK) return 0;
     return backward_layout(L).total;
 }
 
@@ -644,6 +687,8 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
     BatchLayout L;
     sweep_status st = check_batch(batch, opt, nullptr, nullptr, nullptr, nullptr);
     if (st != SWEEP_OK) return st;
+    if (options_ext(opt))
+        return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint differentiates rotation-minimizing frames without a law only");
     const sweep_options ro = resolved_options(batch, opt, true);
     opt = &ro;
     if ((st = check_batch(batch, opt, &key, &L, nullptr, nullptr)) != SWEEP_OK) return st;
@@ -690,7 +735,7 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         hipStream_t s;
         ~MarkOnExit() { P->mark_launched(s); }
     } marker{P, sm};
-    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock);
+    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock, false);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64, nrm);
     {
         // FP64 frame recomputation with re-orthonormalisation: profile tables, frames
@@ -854,6 +899,7 @@ sweep_status sweep_autotune_batched(const sweep_batch* batch, const sweep_option
     Plan* P = nullptr;
     if ((st = get_plan(batch, &ro, nrm != nullptr, std::move(key), &P)) != SWEEP_OK) return st;
     const BatchDesc* descs = P->d_descs;
+    const bool ext = options_ext(&ro);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int2* d_tiles = nullptr;
     int best = -1;
@@ -867,7 +913,8 @@ sweep_status sweep_autotune_batched(const sweep_batch* batch, const sweep_option
             if ((e = hipMalloc(&d_tiles, sizeof(int2) * tiles.size())) != hipSuccess) break;
             if ((e = hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
                 break;
-            const BatchedKernels K = batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices);
+            const BatchedKernels K =
+                batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices, ext);
             const int2* tl = d_tiles;
             void* pp = pos;
             void* np = nrm;

@@ -62,17 +62,36 @@ __device__ __forceinline__ int batch_run_length(int n_u)
     return K;
 }
 
+// Pass 2 of a run in a batched frame kernel: plain row records (16 values),
+// or with EXT the extended records of the batch's frame mode and law (ND = 3:
+// the Frenet frame uses the third derivative; the law's dl/du is fx.law_len
+// over this path's domain length).
+template <int P, class F, class T, bool EXT, class C>
+__device__ __forceinline__ void walk_rows(const C& path, const DCurve& gpath, const BatchDesc& d, int n_u, int i0,
+                                          int K, V3<double> t_first, V3<F> r, int reorth, const BatchFrameExt& fx,
+                                          T* __restrict__ rows)
+{
+    if constexpr (EXT) {
+        const double du = fx.has_law ? fx.law_len / (knot(gpath, gpath.n) - knot(gpath, gpath.p)) : 0.0;
+        run_rows<P, 3, F>(path, n_u, i0, K, t_first, r,
+                          ExtRows<F, T>{rows + kRowExt * (size_t)d.row_off, reorth, fx.frenet, fx.has_law, n_u, fx.law,
+                                        du});
+    } else {
+        run_rows<P, 2, F>(path, n_u, i0, K, t_first, r, PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
+    }
+}
+
 // Row records of a sweep of at most kBlock*kMaxRun u-samples whose path has
 // degree P: one block per sweep, one chunk.  The path is staged in LDS
 // (knots, control points, weights, per-span reciprocals; kLdsPathDoubles of
 // dynamic LDS): knot span changes read LDS only.
-template <int P, class F, class T>
+template <int P, class F, class T, bool EXT>
 __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
                                                    const int* __restrict__ sweeps,
                                                    const double* __restrict__ path_ctrl,
                                                    const double* __restrict__ path_w,
                                                    const double* __restrict__ knots, InitialNormal n0, int reorth,
-                                                   T* __restrict__ rows)
+                                                   T* __restrict__ rows, BatchFrameExt fx)
 {
     __shared__ ChunkWalkLds L;
     __shared__ M3<F> lds_m[kWaves];
@@ -92,8 +111,7 @@ __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__
     __syncthreads();
     const V3<F> rin = cvt<F>(initial_normal(mk(lt0[0], lt0[1], lt0[2]), n0));
     const M3<F> ex = block_exclusive_product<F>(R.A, lds_m);
-    run_rows<P, 2, F>(path, n_u, (int)threadIdx.x * K, K, R.t_first, apply(ex, rin),
-                      PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
+    walk_rows<P, F, T, EXT>(path, gpath, d, n_u, (int)threadIdx.x * K, K, R.t_first, apply(ex, rin), reorth, fx, rows);
 }
 
 // Run length of a sweep framed by one wave: the smallest power of two up to
@@ -111,13 +129,13 @@ __device__ __forceinline__ int wave_run_length(int n_u)
 // run products are wave scans (cross-lane moves); the path is read from
 // global memory.  Entries of -1 in the sweep list (padding to whole blocks)
 // are skipped.
-template <int P, class F, class T>
+template <int P, class F, class T, bool EXT>
 __global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restrict__ descs,
                                                         const int* __restrict__ sweeps,
                                                         const double* __restrict__ path_ctrl,
                                                         const double* __restrict__ path_w,
                                                         const double* __restrict__ knots, InitialNormal n0,
-                                                        int reorth, T* __restrict__ rows)
+                                                        int reorth, T* __restrict__ rows, BatchFrameExt fx)
 {
     const int lane = threadIdx.x & 63;
     const int k = sweeps[blockIdx.x * kWaves + (threadIdx.x >> 6)];
@@ -149,21 +167,20 @@ __global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restr
     const V3<double> t0 = mk(__shfl(R.t_first.x, 0, 64), __shfl(R.t_first.y, 0, 64), __shfl(R.t_first.z, 0, 64));
     const V3<F> rin = cvt<F>(initial_normal(t0, n0));
     const M3<F> ex = wave_shift_up1<F>(wave_inclusive_product<F>(R.A));
-    run_rows<P, 2, F>(path, n_u, i0, K, R.t_first, apply(ex, rin),
-                      PlainRows<F, T>{rows + 16 * (size_t)d.row_off, reorth});
+    walk_rows<P, F, T, EXT>(path, path, d, n_u, i0, K, R.t_first, apply(ex, rin), reorth, fx, rows);
 }
 
 // The same for longer sweeps: the block walks chunks of kBlock*kMaxRun
 // samples in order, carrying the entering normal and the last resolved
 // tangent.  (A kernel of its own: the loop's carried state raises the
 // register allocation above that of the one-chunk kernel.)
-template <int P, class F, class T>
+template <int P, class F, class T, bool EXT>
 __global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restrict__ descs,
                                                         const int* __restrict__ sweeps,
                                                         const double* __restrict__ path_ctrl,
                                                         const double* __restrict__ path_w,
                                                         const double* __restrict__ knots, InitialNormal n0,
-                                                        int reorth, T* __restrict__ rows)
+                                                        int reorth, T* __restrict__ rows, BatchFrameExt fx)
 {
     __shared__ ChunkWalkLds L;
     __shared__ M3<F> lds_m[kWaves];
@@ -173,7 +190,6 @@ __global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restr
     const int n_u = d.n_u;
     const int K = batch_run_length(n_u);
     const int cs = kBlock * K;
-    T* rows_k = rows + 16 * (size_t)d.row_off;
     V3<double> t_entry = first_leg(path);
     V3<F> rin = mk(F(0), F(0), F(0));
     for (int base = 0; base < n_u; base += cs) {
@@ -188,33 +204,33 @@ __global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restr
         }
         M3<F> total;
         const M3<F> ex = block_exclusive_product<F>(R.A, lds_m, total);
-        run_rows<P, 2, F>(path, n_u, base + (int)threadIdx.x * K, K, R.t_first, apply(ex, rin),
-                          PlainRows<F, T>{rows_k, reorth});
+        walk_rows<P, F, T, EXT>(path, path, d, n_u, base + (int)threadIdx.x * K, K, R.t_first, apply(ex, rin), reorth,
+                                fx, rows);
         rin = apply(total, rin);
         t_entry = ctl;   // the last resolved tangent up to this chunk's end
     }
 }
 
 // K = vertices per lane (tile of 256*K vertices per block).
-template <class T, bool NRM, bool NT, int K>
+template <class T, bool NRM, bool NT, int K, int RL>
 __global__ __launch_bounds__(kBlock) void kb_surface(const BatchDesc* __restrict__ descs,
                                                      const int2* __restrict__ tiles, const T* __restrict__ rows,
                                                      const T* __restrict__ ptab, T* __restrict__ pos,
                                                      T* __restrict__ nrm)
 {
-    __shared__ T lrow[kMaxLdsRows * 16];
+    __shared__ T lrow[kMaxLdsRows * RL];
     const int2 tl = tiles[blockIdx.x];
     const BatchDesc d = descs[tl.x];
     const FastDiv dv{d.fd_m, d.fd_shift, d.n_v};
     const long long N = (long long)d.n_u * (long long)d.n_v;
     const long long v0 = tl.y;
     const long long vlast = min(N, v0 + kBlock * K) - 1;
-    const T* rows_k = rows + 16 * d.row_off;
+    const T* rows_k = rows + RL * d.row_off;
     const int ilo = fdiv((unsigned)v0, dv);
     const int nrow = fdiv((unsigned)vlast, dv) - ilo + 1;
     const bool staged = nrow <= kMaxLdsRows;
     if (staged)
-        for (int e = threadIdx.x; e < nrow * 16; e += kBlock) lrow[e] = rows_k[16 * (size_t)ilo + e];
+        for (int e = threadIdx.x; e < nrow * RL; e += kBlock) lrow[e] = rows_k[RL * (size_t)ilo + e];
     __syncthreads();
     const T* ptab_k = ptab + 8 * d.ptab_off;
     T* pos_k = pos + d.out_off;
@@ -251,8 +267,8 @@ __global__ __launch_bounds__(kBlock) void kb_surface(const BatchDesc* __restrict
 #pragma unroll
             for (int c = 0; c < 3; ++c) X[k][c] = Nn[k][c] = T(0);
             if (v0 + threadIdx.x + k * kBlock < N)
-                vertex<T>(base + 16 * (size_t)(vi[k] - row0), qv[k][0], qv[k][1], qv[k][2], qv[k][3], qv[k][4],
-                          qv[k][5], X[k], Nn[k]);
+                vertex_rl<RL, T>(base + RL * (size_t)(vi[k] - row0), qv[k][0], qv[k][1], qv[k][2], qv[k][3],
+                                 qv[k][4], qv[k][5], X[k], Nn[k]);
         }
     };
     if (staged) form(lrow, ilo);
@@ -264,39 +280,59 @@ __global__ __launch_bounds__(kBlock) void kb_surface(const BatchDesc* __restrict
     }
 }
 
-template <class T, bool NRM, bool NT>
+template <class T, bool NRM, bool NT, int RL>
 static const void* surface_for(int K)
 {
     switch (K) {
-    case 1: return (const void*)&kb_surface<T, NRM, NT, 1>;
-    case 2: return (const void*)&kb_surface<T, NRM, NT, 2>;
-    case 4: return (const void*)&kb_surface<T, NRM, NT, 4>;
-    default: return (const void*)&kb_surface<T, NRM, NT, 8>;
+    case 1: return (const void*)&kb_surface<T, NRM, NT, 1, RL>;
+    case 2: return (const void*)&kb_surface<T, NRM, NT, 2, RL>;
+    case 4: return (const void*)&kb_surface<T, NRM, NT, 4, RL>;
+    default: return (const void*)&kb_surface<T, NRM, NT, 8, RL>;
     }
 }
 
+template <class T, int RL>
+static const void* surface_pick(bool nrm, bool nt, int K)
+{
+    if (nrm) return nt ? surface_for<T, true, true, RL>(K) : surface_for<T, true, false, RL>(K);
+    return nt ? surface_for<T, false, true, RL>(K) : surface_for<T, false, false, RL>(K);
+}
+
+// Frame kernels of a frame precision, output precision and record kind.
+template <class F, class T, bool EXT>
+static void pick_frames(BatchedKernels& k)
+{
+    k.frame[0] = k.frame_long[0] = k.frame_wave[0] = nullptr;
+#define SWEEP_DEG(P)                                                        \
+    k.frame[P] = (const void*)&kb_frame<P, F, T, EXT>;                      \
+    k.frame_long[P] = (const void*)&kb_frame_long<P, F, T, EXT>;            \
+    k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T, EXT>;
+    SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
+#undef SWEEP_DEG
+}
+
+// Extended records (a frame mode or a law) with the FP64 frame only: the
+// caller rejects them with the FP32 frame.
 template <class F, class T>
-static BatchedKernels pick(bool nrm, bool nt, int K)
+static BatchedKernels pick(bool nrm, bool nt, int K, bool ext)
 {
     BatchedKernels k;
     k.profile = (const void*)&kb_profile<T>;
-    k.frame[0] = nullptr;
-    k.frame_long[0] = nullptr;
-    k.frame_wave[0] = nullptr;
-#define SWEEP_DEG(P) k.frame[P] = (const void*)&kb_frame<P, F, T>; k.frame_long[P] = (const void*)&kb_frame_long<P, F, T>; \
-    k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T>;
-    SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
-#undef SWEEP_DEG
-    if (nrm) k.surface = nt ? surface_for<T, true, true>(K) : surface_for<T, true, false>(K);
-    else k.surface = nt ? surface_for<T, false, true>(K) : surface_for<T, false, false>(K);
+    if constexpr (sizeof(F) == 8) {
+        if (ext) pick_frames<F, T, true>(k);
+        else pick_frames<F, T, false>(k);
+    } else {
+        pick_frames<F, T, false>(k);
+    }
+    k.surface = ext ? surface_pick<T, kRowExt>(nrm, nt, K) : surface_pick<T, 16>(nrm, nt, K);
     return k;
 }
 
-BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices)
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext)
 {
     const int K = tile_vertices / kBlock;
-    if (f64) return t64 ? pick<double, double>(nrm, nontemporal, K) : pick<double, float>(nrm, nontemporal, K);
-    return t64 ? pick<float, double>(nrm, nontemporal, K) : pick<float, float>(nrm, nontemporal, K);
+    if (f64) return t64 ? pick<double, double>(nrm, nontemporal, K, ext) : pick<double, float>(nrm, nontemporal, K, ext);
+    return t64 ? pick<float, double>(nrm, nontemporal, K, ext) : pick<float, float>(nrm, nontemporal, K, ext);
 }
 
 }  // namespace sweep

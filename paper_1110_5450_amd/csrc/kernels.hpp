@@ -169,6 +169,17 @@ struct BatchedKernels {
 // Kernel entry points for a precision combination (host stubs usable as
 // graph kernel-node functions).
 // tile_vertices = vertices per surface block: 256, 512, 1024 or 2048.
-BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices);
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext);
+
+// Frame mode and sweep law of a batch (every sweep of the batch takes the
+// batch's options): Frenet frames and/or one law for all sweeps, written as
+// extended row records (kRowExt values).  law_len is the law's parameter
+// domain length; a sweep's dl/du is law_len over its path's domain length.
+struct BatchFrameExt {
+    int frenet;
+    int has_law;
+    double law_len;
+    DCurve law;
+};
 
 }  // namespace sweep

@@ -112,7 +112,7 @@ int selftest()
     void* b = dev_alloc(4096);
     hipGraph_t g;
     hipGraphCreate(&g, 0);
-    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024);
+    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024, false);
     void *descs = a, *vch = a, *qc = a, *qw = nullptr, *kn = nullptr, *ptab = b;
     void* params[6] = {&descs, &vch, &qc, &qw, &kn, &ptab};
     hipKernelNodeParams prm{};
@@ -289,6 +289,37 @@ int tune()
                 double* gP = (double*)dev_alloc(sizeof(double) * 3 * np);
                 double* gQ = (double*)dev_alloc(sizeof(double) * 3 * nq);
                 bad += check(sweep_backward(&big.b, &opt, p3, gP, gQ, wsb, wbk, nullptr), "sweep_backward");
+            }
+        }
+    }
+    {
+        // Frenet frames and a sweep law with given knots (extended row
+        // records): two evaluations into different buffers, the adjoint
+        // refused
+        HostBatch hx;
+        make_batch(hx, {3, 2, 3, 1}, {200, 1500, 5000, 90}, {40, 17, 9, 12}, false, rng);
+        sweep_options ox;
+        sweep_default_options(&ox);
+        ox.frame_mode = SWEEP_FRAME_FRENET;
+        const double lk[8] = {0, 0, 0, 0.25, 0.5, 1, 1, 1};
+        sweep_curve law{};
+        law.n_ctrl = 5;
+        law.degree = 2;
+        law.ctrl = (const double*)dev_alloc(sizeof(double) * 3 * 5);
+        law.knots = lk;
+        ox.law = &law;
+        const int64_t ex = sweep_batched_output_elems(&hx.b);
+        const size_t wx = sweep_batched_workspace_size(&hx.b, &ox);
+        for (int rep = 0; rep < 2; ++rep) {
+            float* px = (float*)dev_alloc(sizeof(float) * ex);
+            float* nx = (float*)dev_alloc(sizeof(float) * ex);
+            void* wsx = dev_alloc(wx);
+            bad += check(sweep_eval_batched(&hx.b, &ox, px, nx, wsx, wx, nullptr), "sweep_eval_batched (Frenet, law)");
+            if (rep == 1) {
+                double* gP = (double*)dev_alloc(sizeof(double) * 3 * 64);
+                double* gQ = (double*)dev_alloc(sizeof(double) * 3 * 64);
+                if (sweep_backward(&hx.b, &ox, px, gP, gQ, wsx, wx, nullptr) != SWEEP_ERR_UNSUPPORTED) ++bad;
+                if (sweep_backward_workspace_size(&hx.b, &ox) != 0) ++bad;
             }
         }
     }

@@ -15,11 +15,12 @@ constexpr ArgSig P{sizeof(void*), kDevicePtr};
 constexpr ArgSig N{sizeof(void*), kNullablePtr};
 constexpr ArgSig I{sizeof(int), kValue};
 constexpr ArgSig N0{sizeof(sweep::InitialNormal), kValue};
+constexpr ArgSig FX{sizeof(sweep::BatchFrameExt), kValue};
 
 const KernelSig kProfile{"kb_profile", {P, P, P, N, N, P}};
-const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P}};
-const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P}};
-const KernelSig kFrameWave{"kb_frame_wave", {P, P, P, N, N, N0, I, P}};
+const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P, FX}};
+const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P, FX}};
+const KernelSig kFrameWave{"kb_frame_wave", {P, P, P, N, N, N0, I, P, FX}};
 const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
 const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
 const KernelSig kRows{"kbw_rows", {P, P, P, N, N, P, P, P, P, P, I}};
@@ -69,7 +70,7 @@ std::vector<const KernelSig*> all_kernels()
 
 namespace sweep {
 
-BatchedKernels batched_kernels(bool, bool, bool, bool, int)
+BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool)
 {
     BatchedKernels k{};
     k.profile = &stub::g_profile;

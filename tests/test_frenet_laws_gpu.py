@@ -1,7 +1,7 @@
 """Frame modes and sweep laws on the GPU (next-row f2): parity with the
-oracle's Frenet frame and scale/twist laws, and the closed forms they
-produce (a cone, a twisted offset tube, an elliptic torus), computed on the
-device end to end."""
+oracle's Frenet frame and scale/twist laws, single sweeps and batches, and
+the closed forms they produce (a cone, a twisted offset tube, an elliptic
+torus), computed on the device end to end."""
 
 from __future__ import annotations
 
@@ -117,10 +117,53 @@ def test_elliptic_torus_frenet_on_the_gpu_fp32():
     assert np.abs(N[0] * (-radial[1]) + N[1] * radial[0]).max() <= 1e-5
 
 
+@pytest.mark.parametrize("mode,with_law", [("frenet", False), ("rmf", True), ("frenet", True)])
+@pytest.mark.parametrize("out_dtype", [torch.float64, torch.float32])
+def test_batched_frame_modes_and_laws_match_oracle(mode, with_law, out_dtype):
+    """A batch with the Frenet frame and/or one sweep law for every sweep:
+    sweeps framed by one wave (<= 256 u-samples), by one block (path in LDS)
+    and by the chunk-walking kernel (> 4096), path degrees 1-5, one rational
+    path; each against the oracle's sweep with the same mode and law (the
+    law's knots given).  The scan bound 8 n eps applies to the long
+    rotation-minimizing sweeps."""
+    rng = np.random.default_rng(31)
+    specs = []
+    for k, (p, n_u, n_v) in enumerate([(3, 200, 40), (2, 1500, 17), (5, 900, 33), (1, 120, 9), (3, 5000, 8),
+                                       (4, 3000, 12)]):
+        P = synth.random_walk(rng, int(rng.integers(p + 3, 30)))
+        Q = synth.perturbed_circle(rng, int(rng.integers(5, 12)))
+        specs.append(synth.SweepSpec(synth.CurveSpec(P, p), synth.CurveSpec(Q, 3, True), n_u, n_v))
+    law = _law(12, n=6, p=2)
+    law.knots = np.array([0, 0, 0, 0.2, 0.5, 0.7, 1, 1, 1], dtype=float)
+    glaw = api.Law(dev_ctrl(law.ctrl), law.degree, law.knots) if with_law else None
+    b = api.Batch.from_specs(specs)
+    say(f"[case] batch {mode} law={with_law} out={out_dtype}: {len(specs)} sweeps")
+    pos, nrm = api.sweep_eval_batched(b, out_dtype=out_dtype, frame_mode=mode, law=glaw)
+    again = api.sweep_eval_batched(b, out_dtype=out_dtype, frame_mode=mode, law=glaw)
+    torch.cuda.synchronize()
+    assert torch.equal(pos, again[0]) and torch.equal(nrm, again[1])
+    for k, s in enumerate(specs):
+        ref, _ = oracle.sweep_ex(s.path, s.profile, s.n_u, s.n_v, mode=mode, law=law if with_law else None)
+        tol = TOL[out_dtype]
+        if out_dtype == torch.float64 and mode == "rmf":
+            tol = max(tol, 8 * s.n_u * np.finfo(float).eps)
+        ok, r = parity(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).cpu().numpy(), b.view(nrm, k).cpu().numpy(), tol)
+        say(f"   sweep {k} ({s.n_u}x{s.n_v}, p={s.path.degree}): {r}")
+        assert ok, (k, r)
+
+
 def test_frame_modes_and_laws_rejected_where_unsupported():
     spec = synth.c1()
     b = api.Batch.from_specs([spec])
     with pytest.raises(_lib.SweepError, match="UNSUPPORTED"):
-        api.sweep_eval_batched(b, frame_mode="frenet")
+        api.sweep_eval_batched(b, frame_mode="frenet", frame_dtype=torch.float32)
+    g = torch.zeros(b.out_elems, dtype=torch.float32, device="cuda")
+    opt = api.make_options(frame_mode="frenet")
+    gP = torch.empty(3 * spec.path.n, dtype=torch.float64, device="cuda")
+    gQ = torch.empty(3 * spec.profile.n, dtype=torch.float64, device="cuda")
+    ws = torch.empty(1 << 24, dtype=torch.uint8, device="cuda")
+    st = _lib.sweep_backward(b.c_struct(), opt, g.data_ptr(), gP.data_ptr(), gQ.data_ptr(), ws.data_ptr(),
+                             ws.numel(), 0)
+    assert _lib.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
     with pytest.raises(_lib.SweepError, match="UNSUPPORTED"):
         api.sweep_frames(dev_ctrl(spec.path.ctrl), spec.path.degree, spec.n_u, frame_mode="frenet")
