@@ -388,13 +388,15 @@ def sweep_eval_batched(batch: Batch, *, out_dtype=torch.float32, frame_dtype=tor
                        reorthonormalize: bool = True, initial_normal=None, tile_config: int = -1,
                        normals: bool = True, frame_mode: str = "rmf", out=None,
                        workspace: Optional[torch.Tensor] = None, stream=None, stages: int = 0,
-                       law: Optional[Law] = None):
+                       law: Optional[Law] = None, u_sampling: str = "parameter", u_lambda: float = 0.0):
     """Flat positions and normals (or None) of a batch in the padded batched
-    layout.  frame_mode and law apply to every sweep of the batch (one law
-    for all; they need the FP64 frame).  stages: pipeline stages of the
+    layout.  frame_mode, law and u_sampling apply to every sweep of the
+    batch (one law for all; they need the FP64 frame; arc-length sampling
+    without a frame mode or law).  stages: pipeline stages of the
     frame/surface schedule (0: automatic)."""
     b = batch.c_struct()
-    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law)
+    opt = make_options(out_dtype, frame_dtype, reorthonormalize, initial_normal, tile_config, frame_mode, law,
+                       u_sampling, u_lambda)
     opt.batch_stages = int(stages)
     ws_bytes = L.sweep_batched_workspace_size(b, opt)
     if ws_bytes == 0:

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "abi_internal.hpp"
+#include "arclength.hpp"
 
 namespace sweep {
 
@@ -29,9 +30,10 @@ struct BatchKey {
 };
 
 struct BatchLayout {
-    size_t rows, ptab, total;
+    size_t rows, ptab, arc_len, arc_cum, arc_u, arc_s, total;
     long long n_rows = 0, n_vs = 0, n_vertices = 0, n_out = 0;
     long long n_rowpart = 0, n_colpart = 0, n_units = 0, n_uchunks = 0;
+    long long n_arc = 0;           // arc-length pieces of all paths
 };
 
 // Workspace of sweep_backward (FP64 frame recomputation and adjoint buffers).
@@ -73,8 +75,9 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
     if (!o) return fail(SWEEP_ERR_NULL_ARG, "options are NULL");
     sweep_status st = check_options(o);
     if (st != SWEEP_OK) return st;
-    if (o->u_sampling != SWEEP_U_PARAMETER)
-        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length and adaptive sampling are sweep_eval only");
+    const bool arc = o->u_sampling != SWEEP_U_PARAMETER;
+    if (arc && (options_ext(o) || o->frame_precision != SWEEP_F64))
+        return fail(SWEEP_ERR_UNSUPPORTED, "arc-length sampling in a batch needs the FP64 frame, without a frame mode or law");
     if (options_ext(o) && o->frame_precision != SWEEP_F64)
         return fail(SWEEP_ERR_UNSUPPORTED, "frame modes and laws in a batch need the FP64 frame");
     if (b->n_sweeps < 1) return fail(SWEEP_ERR_BAD_COUNT, "n_sweeps %d < 1", b->n_sweeps);
@@ -121,6 +124,7 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
             d.path_kuser_off = pk ? pk_off : -1;
             d.prof_kuser_off = qk ? qk_off : -1;
             d.ctot_off = L.n_uchunks;
+            d.arc_off = L.n_arc;
             descs->push_back(d);
         }
         if (key) {
@@ -138,12 +142,19 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         L.n_rowpart += (long long)nseg * nu; L.n_colpart += (long long)ngroup * nv;
         L.n_units += (long long)nseg * ngroup;
         L.n_uchunks += (nu + kBlock - 1) / kBlock;
+        if (arc) L.n_arc += arc_piece_count(np, pp);
     }
     if (!b->path_ctrl || !b->prof_ctrl) return fail(SWEEP_ERR_NULL_ARG, "control point buffer is NULL");
     size_t off = 0;
     const size_t rl = options_ext(o) ? kRowExt : 16;   // row record length
     L.rows = off; off = align_up(off + tsz * rl * (size_t)L.n_rows);
     L.ptab = off; off = align_up(off + tsz * 8 * (size_t)L.n_vs);
+    // arc-length tables: piece lengths, cumulative tables (one entry more
+    // per sweep), sample parameters and spans (per u-row)
+    L.arc_len = off; off = align_up(off + sizeof(double) * (size_t)L.n_arc);
+    L.arc_cum = off; off = align_up(off + sizeof(double) * (arc ? (size_t)(L.n_arc + b->n_sweeps) : 0));
+    L.arc_u = off; off = align_up(off + sizeof(double) * (arc ? (size_t)L.n_rows : 0));
+    L.arc_s = off; off = align_up(off + sizeof(int) * (arc ? (size_t)L.n_rows : 0));
     L.total = off;
     if (lay) *lay = L;
     if (key) {
@@ -155,9 +166,10 @@ static sweep_status check_batch(const sweep_batch* b, const sweep_options* o, Ba
         // the frame mode and the law's shape (its control points are a call
         // argument, its knots are uploaded with the plan)
         const sweep_curve* lw = o->law;
-        const int32_t x[5] = {o->frame_mode, lw ? 1 : 0, lw ? lw->n_ctrl : 0, lw ? lw->degree : 0,
-                              lw && lw->knots ? 1 : 0};
-        key->ints.insert(key->ints.end(), x, x + 5);
+        const int32_t x[6] = {o->frame_mode, lw ? 1 : 0, lw ? lw->n_ctrl : 0, lw ? lw->degree : 0,
+                              lw && lw->knots ? 1 : 0, o->u_sampling};
+        key->ints.insert(key->ints.end(), x, x + 6);
+        if (arc) key->dbls.push_back(o->u_sampling == SWEEP_U_ADAPTIVE ? o->u_lambda : 0.0);
         if (lw && lw->knots) key->dbls.insert(key->dbls.end(), lw->knots, lw->knots + lw->n_ctrl + lw->degree + 1);
         if (o->has_initial_normal) key->dbls.insert(key->dbls.end(), o->initial_normal, o->initial_normal + 3);
     }
@@ -183,9 +195,17 @@ struct NodeArgs {
     void* pos;
     void* nrm;
     BatchFrameExt fx;
+    // arc-length sampling
+    const int2* apch;              // (sweep, first piece) per block
+    const int2* asch;              // (sweep, first u-sample) per block
+    double lam;                    // adaptive sampling weight (0: arc length)
+    double* arc_len;
+    double* arc_cum;
+    double* arc_u;
+    int* arc_s;
 };
 
-enum NodeKind { kProfile, kFrame, kSurface };
+enum NodeKind { kProfile, kFrame, kSurface, kArcPieces, kArcCumsum, kArcParams };
 
 struct GNode {
     NodeKind kind;
@@ -204,6 +224,9 @@ static int node_args(GNode& n)
     switch (n.kind) {
     case kProfile: { void* v[] = {&A.descs, &A.vchunks, &A.prof_ctrl, &A.prof_w, &A.knots, &A.ptab}; std::memcpy(q, v, sizeof v); return 6; }
     case kFrame: { void* v[] = {&A.descs, &A.sweeps, &A.path_ctrl, &A.path_w, &A.knots, &A.n0, &A.reorth, &A.rows, &A.fx}; std::memcpy(q, v, sizeof v); return 9; }
+    case kArcPieces: { void* v[] = {&A.descs, &A.apch, &A.path_ctrl, &A.path_w, &A.knots, &A.lam, &A.arc_len}; std::memcpy(q, v, sizeof v); return 7; }
+    case kArcCumsum: { void* v[] = {&A.descs, &A.arc_len, &A.arc_cum}; std::memcpy(q, v, sizeof v); return 3; }
+    case kArcParams: { void* v[] = {&A.descs, &A.asch, &A.path_ctrl, &A.path_w, &A.knots, &A.lam, &A.arc_cum, &A.arc_u, &A.arc_s}; std::memcpy(q, v, sizeof v); return 9; }
     default: { void* v[] = {&A.descs, &A.tiles, &A.rows, &A.ptab, &A.pos, &A.nrm}; std::memcpy(q, v, sizeof v); return 6; }
     }
 }
@@ -222,6 +245,9 @@ struct Plan {
     int n_uchunks_all = 0;
     double* d_knots = nullptr;
     double* d_law_knots = nullptr;  // the law's given knots
+    int2* d_arc_pch = nullptr;      // arc-length sampling: (sweep, first piece) per block
+    int2* d_arc_sch = nullptr;      // (sweep, first u-sample) per block
+    int n_arc_pch = 0, n_arc_sch = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int* d_sweeps[8] = {};         // sweeps by path degree: by stage and frame kernel, longest n_u first
@@ -283,6 +309,8 @@ struct Plan {
         if (d_vchunks) hipFree(d_vchunks);
         if (d_knots) hipFree(d_knots);
         if (d_law_knots) hipFree(d_law_knots);
+        if (d_arc_pch) hipFree(d_arc_pch);
+        if (d_arc_sch) hipFree(d_arc_sch);
     }
 };
 
@@ -359,9 +387,12 @@ static_assert(kMaxStages == 4, "batch_stages is validated as 0..4");
 
 // The frame mode and law of a batch as the frame kernels take them (every
 // field set, so that argument blocks compare bytewise).
-static void set_frame_ext(BatchFrameExt& fx, const sweep_options* o, const double* d_law_knots)
+static void set_frame_ext(BatchFrameExt& fx, const sweep_options* o, const double* d_law_knots,
+                          const double* su = nullptr, const int* ss = nullptr)
 {
     std::memset(&fx, 0, sizeof fx);
+    fx.su = su;
+    fx.ss = ss;
     fx.frenet = o->frame_mode == SWEEP_FRAME_FRENET;
     if (const sweep_curve* lw = o->law) {
         fx.has_law = 1;
@@ -422,8 +453,10 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     // u-samples; the one-chunk block kernel up to kBlock*kMaxRun if the path
     // fits its LDS; else the chunk-walking kernel
     const bool rat = b->path_weights != nullptr;
+    const bool arc = o->u_sampling != SWEEP_U_PARAMETER;
     auto fkind = [&](int k) -> int {
         if (b->n_u[k] <= kWaveMaxU) return Plan::kWaveFrame;
+        if (arc) return Plan::kWalkFrame;   // the one-block kernel has no sample tables
         if (b->n_u[k] <= kBlock * kMaxRun && lds_path_doubles(b->path_n[k], b->path_degree[k], rat) <= kLdsPathDoubles)
             return Plan::kBlockFrame;
         return Plan::kWalkFrame;
@@ -481,8 +514,24 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         return hip_fail(e, "plan upload");
 
     const bool ext = options_ext(o);
+    const bool adaptive = o->u_sampling == SWEEP_U_ADAPTIVE && o->u_lambda != 0.0;
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
-                                             with_nrm, cfg.nontemporal != 0, tv, ext);
+                                             with_nrm, cfg.nontemporal != 0, tv, ext, arc, adaptive);
+    if (arc) {
+        // work lists of the arc-length kernels: 32 pieces and 32 u-samples
+        // per block (eight lanes each)
+        std::vector<int2> pch, sch;
+        for (int k = 0; k < b->n_sweeps; ++k) {
+            const int npc = arc_piece_count(b->path_n[k], b->path_degree[k]);
+            for (int q = 0; q < npc; q += kBlock / 8) pch.push_back(make_int2(k, q));
+            for (int i = 0; i < b->n_u[k]; i += kBlock / 8) sch.push_back(make_int2(k, i));
+        }
+        if ((e = upload((void**)&P->d_arc_pch, pch.data(), sizeof(int2) * pch.size())) != hipSuccess ||
+            (e = upload((void**)&P->d_arc_sch, sch.data(), sizeof(int2) * sch.size())) != hipSuccess)
+            return hip_fail(e, "plan upload");
+        P->n_arc_pch = (int)pch.size();
+        P->n_arc_sch = (int)sch.size();
+    }
     if (o->law && o->law->knots) {
         const sweep_curve* lw = o->law;
         if ((e = upload((void**)&P->d_law_knots, lw->knots, sizeof(double) * (lw->n_ctrl + lw->degree + 1))) !=
@@ -500,11 +549,15 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     for (int c = 0; c < 3; ++c) A.n0.v[c] = o->initial_normal[c];
     A.reorth = o->reorthonormalize;
     set_frame_ext(A.fx, o, P->d_law_knots);
+    A.apch = P->d_arc_pch;
+    A.asch = P->d_arc_sch;
+    A.lam = adaptive ? o->u_lambda : 0.0;
     if ((e = hipGraphCreate(&P->graph, 0)) != hipSuccess) return hip_fail(e, "graph");
     // frame nodes: sweeps [first, first + grid) of the degree's list;
     // surface nodes: tiles [first, first + grid)
     auto add = [&](NodeKind kind, int deg, const void* fn, unsigned grid,
-                   const std::vector<hipGraphNode_t>& deps, int first = 0, unsigned lds = 0) -> hipError_t {
+                   const std::vector<hipGraphNode_t>& deps, int first = 0, unsigned lds = 0,
+                   unsigned block = kBlock) -> hipError_t {
         std::unique_ptr<GNode> n(new GNode());
         n->kind = kind;
         n->deg = deg;
@@ -514,7 +567,7 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
-        n->prm.blockDim = dim3(kBlock);
+        n->prm.blockDim = dim3(block);
         n->prm.sharedMemBytes = lds;
         n->prm.kernelParams = n->ptrs;
         n->prm.extra = nullptr;
@@ -526,6 +579,18 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     if ((e = add(kProfile, 0, K.profile, (unsigned)P->n_vchunks, {})) != hipSuccess) return hip_fail(e, "graph node");
     const hipGraphNode_t profile_node = P->nodes.back()->node;
     std::vector<hipGraphNode_t> prev_frames;
+    if (arc) {
+        // arc-length samples of every path before any frame
+        if ((e = add(kArcPieces, 0, K.arc_pieces, (unsigned)P->n_arc_pch, {})) != hipSuccess)
+            return hip_fail(e, "graph node");
+        const hipGraphNode_t pieces = P->nodes.back()->node;
+        if ((e = add(kArcCumsum, 0, K.arc_cumsum, (unsigned)b->n_sweeps, {pieces}, 0, 0, kScanThreads)) != hipSuccess)
+            return hip_fail(e, "graph node");
+        const hipGraphNode_t cums = P->nodes.back()->node;
+        if ((e = add(kArcParams, 0, K.arc_params, (unsigned)P->n_arc_sch, {cums})) != hipSuccess)
+            return hip_fail(e, "graph node");
+        prev_frames.push_back(P->nodes.back()->node);
+    }
     for (int st = 0; st < S; ++st) {
         std::vector<hipGraphNode_t> frames;
         for (const Plan::FrameRange& r : P->franges) {
@@ -638,7 +703,15 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
     A.ptab = ws + L.ptab;
     A.pos = pos;
     A.nrm = nrm;
-    set_frame_ext(A.fx, opt, P->d_law_knots);   // the law's control points are a call argument
+    if (opt->u_sampling != SWEEP_U_PARAMETER) {
+        A.arc_len = (double*)(ws + L.arc_len);
+        A.arc_cum = (double*)(ws + L.arc_cum);
+        A.arc_u = (double*)(ws + L.arc_u);
+        A.arc_s = (int*)(ws + L.arc_s);
+    }
+    // the law's control points are a call argument; the sample tables live
+    // in the caller's workspace
+    set_frame_ext(A.fx, opt, P->d_law_knots, A.arc_u, A.arc_s);
     if (std::memcmp(&A, &P->a, sizeof A) != 0) {
         // a replay of this graph may still be in flight on some stream:
         // let it finish before its node parameters are rewritten
@@ -664,7 +737,9 @@ size_t sweep_backward_workspace_size(const sweep_batch* batch, const sweep_optio
     sweep_options def;
     if (!opt) { sweep_default_options(&def); opt = &def; }
     BatchLayout L;
-    if (options_ext(opt) || check_batch(batch, opt, nullptr, &L, nullptr, nullptr) != SWEEP_OK) return 0;
+    if (options_ext(opt) || opt->u_sampling != SWEEP_U_PARAMETER ||
+        check_batch(batch, opt, nullptr, &L, nullptr, nullptr) != SWEEP_OK)
+        return 0;
     return backward_layout(L).total;
 }
 
@@ -687,8 +762,9 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
     BatchLayout L;
     sweep_status st = check_batch(batch, opt, nullptr, nullptr, nullptr, nullptr);
     if (st != SWEEP_OK) return st;
-    if (options_ext(opt))
-        return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint differentiates rotation-minimizing frames without a law only");
+    if (options_ext(opt) || opt->u_sampling != SWEEP_U_PARAMETER)
+        return fail(SWEEP_ERR_UNSUPPORTED,
+                    "the adjoint differentiates rotation-minimizing frames of uniform samples without a law only");
     const sweep_options ro = resolved_options(batch, opt, true);
     opt = &ro;
     if ((st = check_batch(batch, opt, &key, &L, nullptr, nullptr)) != SWEEP_OK) return st;
@@ -735,7 +811,7 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         hipStream_t s;
         ~MarkOnExit() { P->mark_launched(s); }
     } marker{P, sm};
-    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock, false);
+    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock, false, false, false);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64, nrm);
     {
         // FP64 frame recomputation with re-orthonormalisation: profile tables, frames
@@ -913,8 +989,8 @@ sweep_status sweep_autotune_batched(const sweep_batch* batch, const sweep_option
             if ((e = hipMalloc(&d_tiles, sizeof(int2) * tiles.size())) != hipSuccess) break;
             if ((e = hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
                 break;
-            const BatchedKernels K =
-                batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices, ext);
+            const BatchedKernels K = batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices,
+                                                     ext, false, false);
             const int2* tl = d_tiles;
             void* pp = pos;
             void* np = nrm;

@@ -11,14 +11,18 @@
 //             records (frame_walk.hpp).  Longer sweeps walk their chunks in
 //             order, carrying the entering normal and the last resolved
 //             tangent in registers: no cross-block carry is needed.
+// kb_frame_wave  one wave per sweep of at most kWaveMaxU u-samples.
 // kb_surface  one block per tile of 256*K (K = 1, 2, 4, 8) consecutive
 //             vertices of one sweep, rows staged in LDS, one vertex per lane
 //             per step, six plane stores.
+// kb_arc_*    arc-length (or curvature-adaptive) u-samples of every path:
+//             piece lengths, one cumulative table per sweep, sample
+//             parameters (arclength.hpp, as for a single sweep).
 //
-// The frame steps are the single-sweep kernels' device functions in the same
-// order: a sweep of at most kBlock u-samples (one run per sample in both) is
-// bitwise identical to evaluating it alone; longer sweeps differ in how the
-// step rotations are grouped into runs and chunks, i.e. by rounding.
+// The frame steps are the single-sweep kernels' device functions; the
+// batch groups a sweep's step rotations into runs differently, so a batched
+// sweep and the same sweep alone agree to rounding.
+#include "arclength.hpp"
 #include "frame_walk.hpp"
 #include "surface_common.hpp"
 
@@ -36,6 +40,59 @@ __device__ __forceinline__ DCurve prof_of(const BatchDesc& d, const double* prof
     return DCurve{prof_ctrl + 3 * d.prof_ctrl_off, d.prof_knot_off >= 0 ? knots + d.prof_knot_off : nullptr,
                   d.n_prof, d.p_prof, d.closed_prof, d.closed_prof ? d.n_prof + d.p_prof : d.n_prof,
                   prof_w ? prof_w + d.prof_ctrl_off : nullptr};
+}
+
+// Arc-length tables of the batch's paths.  Pieces: a block per 32 pieces
+// of one sweep (chunk = (sweep, first piece)), eight lanes per piece.
+template <bool ADAPT>
+__global__ __launch_bounds__(kBlock) void kb_arc_pieces(const BatchDesc* __restrict__ descs,
+                                                        const int2* __restrict__ chunks,
+                                                        const double* __restrict__ path_ctrl,
+                                                        const double* __restrict__ path_w,
+                                                        const double* __restrict__ knots, double lam,
+                                                        double* __restrict__ len)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const BatchDesc d = descs[ch.x];
+    const int q = ch.y + (int)(threadIdx.x >> 3);
+    if (q >= arc_piece_count(d.n_path, d.p_path)) return;   // whole 8-lane groups
+    arc_piece_any<ADAPT>(path_of(d, path_ctrl, path_w, knots), q, threadIdx.x & 7, lam, len + d.arc_off);
+}
+
+// One block per sweep: its cumulative table at arc_off + k (one entry more
+// than its pieces).
+__global__ __launch_bounds__(kScanThreads) void kb_arc_cumsum(const BatchDesc* __restrict__ descs,
+                                                              const double* __restrict__ len,
+                                                              double* __restrict__ cum)
+{
+    const BatchDesc d = descs[blockIdx.x];
+    arc_cumsum_block(len + d.arc_off, arc_piece_count(d.n_path, d.p_path), cum + d.arc_off + blockIdx.x);
+}
+
+// Sample parameters: a block per 32 u-samples of one sweep (chunk = (sweep,
+// first sample)), kArcLanes lanes per sample; parameters and spans at the
+// sweep's row offset.
+template <bool ADAPT>
+__global__ __launch_bounds__(kBlock) void kb_arc_params(const BatchDesc* __restrict__ descs,
+                                                        const int2* __restrict__ chunks,
+                                                        const double* __restrict__ path_ctrl,
+                                                        const double* __restrict__ path_w,
+                                                        const double* __restrict__ knots, double lam,
+                                                        const double* __restrict__ cum, double* __restrict__ su,
+                                                        int* __restrict__ ss)
+{
+    __shared__ double coarse[kArcCoarseMax];
+    const int2 ch = chunks[blockIdx.x];
+    const BatchDesc d = descs[ch.x];
+    const int npc = arc_piece_count(d.n_path, d.p_path), cs = arc_coarse_stride(npc);
+    const int nc = npc / cs + 1;
+    const double* cumk = cum + d.arc_off + ch.x;
+    for (int k = threadIdx.x; k < nc; k += kBlock) coarse[k] = cumk[(long long)k * cs];
+    __syncthreads();
+    const int i = ch.y + (int)(threadIdx.x / kArcLanes);
+    if (i >= d.n_u) return;   // whole lane groups
+    arc_param_any<ADAPT>(path_of(d, path_ctrl, path_w, knots), i, threadIdx.x & (kArcLanes - 1), d.n_u, npc, cs, nc,
+                         lam, cumk, coarse, su + d.row_off, ss + d.row_off);
 }
 
 // Profile tables: one block per (sweep, chunk of 256 v-samples).
@@ -129,7 +186,7 @@ __device__ __forceinline__ int wave_run_length(int n_u)
 // run products are wave scans (cross-lane moves); the path is read from
 // global memory.  Entries of -1 in the sweep list (padding to whole blocks)
 // are skipped.
-template <int P, class F, class T, bool EXT>
+template <int P, class F, class T, bool EXT, bool ARC>
 __global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restrict__ descs,
                                                         const int* __restrict__ sweeps,
                                                         const double* __restrict__ path_ctrl,
@@ -141,7 +198,11 @@ __global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restr
     const int k = sweeps[blockIdx.x * kWaves + (threadIdx.x >> 6)];
     if (k < 0) return;   // wave-uniform
     const BatchDesc d = descs[k];
-    const DCurve path = path_of(d, path_ctrl, path_w, knots);
+    DCurve path = path_of(d, path_ctrl, path_w, knots);
+    if constexpr (ARC) {   // arc-length samples
+        path.su = fx.su + d.row_off;
+        path.ss = fx.ss + d.row_off;
+    }
     const int n_u = d.n_u;
     const int K = wave_run_length(n_u);
     const int i0 = lane * K;
@@ -174,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void kb_frame_wave(const BatchDesc* __restr
 // samples in order, carrying the entering normal and the last resolved
 // tangent.  (A kernel of its own: the loop's carried state raises the
 // register allocation above that of the one-chunk kernel.)
-template <int P, class F, class T, bool EXT>
+template <int P, class F, class T, bool EXT, bool ARC>
 __global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restrict__ descs,
                                                         const int* __restrict__ sweeps,
                                                         const double* __restrict__ path_ctrl,
@@ -186,7 +247,11 @@ __global__ __launch_bounds__(kBlock) void kb_frame_long(const BatchDesc* __restr
     __shared__ M3<F> lds_m[kWaves];
     __shared__ double lt0[3];
     const BatchDesc d = descs[sweeps[blockIdx.x]];
-    const DCurve path = path_of(d, path_ctrl, path_w, knots);
+    DCurve path = path_of(d, path_ctrl, path_w, knots);
+    if constexpr (ARC) {   // arc-length samples
+        path.su = fx.su + d.row_off;
+        path.ss = fx.ss + d.row_off;
+    }
     const int n_u = d.n_u;
     const int K = batch_run_length(n_u);
     const int cs = kBlock * K;
@@ -298,41 +363,51 @@ static const void* surface_pick(bool nrm, bool nt, int K)
     return nt ? surface_for<T, false, true, RL>(K) : surface_for<T, false, false, RL>(K);
 }
 
-// Frame kernels of a frame precision, output precision and record kind.
-template <class F, class T, bool EXT>
+// Frame kernels of a frame precision, output precision, record kind and
+// sampling (arc-length sweeps take the one-wave and chunk-walking kernels
+// only: the one-block kernel's staged path has no sample table).
+template <class F, class T, bool EXT, bool ARC>
 static void pick_frames(BatchedKernels& k)
 {
     k.frame[0] = k.frame_long[0] = k.frame_wave[0] = nullptr;
-#define SWEEP_DEG(P)                                                        \
-    k.frame[P] = (const void*)&kb_frame<P, F, T, EXT>;                      \
-    k.frame_long[P] = (const void*)&kb_frame_long<P, F, T, EXT>;            \
-    k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T, EXT>;
+#define SWEEP_DEG(P)                                                                  \
+    k.frame[P] = ARC ? nullptr : (const void*)&kb_frame<P, F, T, EXT>;               \
+    k.frame_long[P] = (const void*)&kb_frame_long<P, F, T, EXT, ARC>;                \
+    k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T, EXT, ARC>;
     SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
 #undef SWEEP_DEG
 }
 
-// Extended records (a frame mode or a law) with the FP64 frame only: the
-// caller rejects them with the FP32 frame.
+// Extended records (a frame mode or a law) and arc-length sampling with the
+// FP64 frame only, not together: the caller rejects the other combinations.
 template <class F, class T>
-static BatchedKernels pick(bool nrm, bool nt, int K, bool ext)
+static BatchedKernels pick(bool nrm, bool nt, int K, bool ext, bool arc, bool adaptive)
 {
     BatchedKernels k;
     k.profile = (const void*)&kb_profile<T>;
     if constexpr (sizeof(F) == 8) {
-        if (ext) pick_frames<F, T, true>(k);
-        else pick_frames<F, T, false>(k);
+        if (ext) pick_frames<F, T, true, false>(k);
+        else if (arc) pick_frames<F, T, false, true>(k);
+        else pick_frames<F, T, false, false>(k);
     } else {
-        pick_frames<F, T, false>(k);
+        pick_frames<F, T, false, false>(k);
     }
+    k.arc_pieces = adaptive ? (const void*)&kb_arc_pieces<true> : (const void*)&kb_arc_pieces<false>;
+    k.arc_cumsum = (const void*)&kb_arc_cumsum;
+    k.arc_params = adaptive ? (const void*)&kb_arc_params<true> : (const void*)&kb_arc_params<false>;
     k.surface = ext ? surface_pick<T, kRowExt>(nrm, nt, K) : surface_pick<T, 16>(nrm, nt, K);
     return k;
 }
 
-BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext)
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext, bool arc,
+                               bool adaptive)
 {
     const int K = tile_vertices / kBlock;
-    if (f64) return t64 ? pick<double, double>(nrm, nontemporal, K, ext) : pick<double, float>(nrm, nontemporal, K, ext);
-    return t64 ? pick<float, double>(nrm, nontemporal, K, ext) : pick<float, float>(nrm, nontemporal, K, ext);
+    if (f64)
+        return t64 ? pick<double, double>(nrm, nontemporal, K, ext, arc, adaptive)
+                   : pick<double, float>(nrm, nontemporal, K, ext, arc, adaptive);
+    return t64 ? pick<float, double>(nrm, nontemporal, K, ext, arc, adaptive)
+               : pick<float, float>(nrm, nontemporal, K, ext, arc, adaptive);
 }
 
 }  // namespace sweep

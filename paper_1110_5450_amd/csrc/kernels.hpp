@@ -106,6 +106,7 @@ struct BatchDesc {
     long long path_kuser_off;      // adjoint: offset of the path's knots in the caller's packing, -1 = none
     long long prof_kuser_off;      // adjoint: the same for an open profile's knots
     long long ctot_off;            // adjoint: first per-chunk total (chunks of kBlock u-samples)
+    long long arc_off;             // arc-length sampling: first piece length (its cumulative table at arc_off + k)
 };
 
 // Batched output planes start on multiples of this many elements (256 B in
@@ -164,12 +165,18 @@ struct BatchedKernels {
     const void* frame[8];        // by path degree (index 0 unused): sweeps of n_u <= kBlock*kMaxRun
     const void* frame_long[8];   // longer sweeps, or paths too large for the LDS staging
     const void* frame_wave[8];   // sweeps of n_u <= kWaveMaxU, one wave each
+    const void* arc_pieces;      // arc-length tables (arc-length or adaptive sampling)
+    const void* arc_cumsum;
+    const void* arc_params;
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as
 // graph kernel-node functions).
 // tile_vertices = vertices per surface block: 256, 512, 1024 or 2048.
-BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext);
+// ext: extended row records (a frame mode or law); arc: arc-length or
+// adaptive u-sampling (lam != 0: adaptive), FP64 frame only.
+BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext, bool arc,
+                               bool adaptive);
 
 // Frame mode and sweep law of a batch (every sweep of the batch takes the
 // batch's options): Frenet frames and/or one law for all sweeps, written as
@@ -180,6 +187,8 @@ struct BatchFrameExt {
     int has_law;
     double law_len;
     DCurve law;
+    const double* su;   // arc-length sampling: every sweep's sample parameters (at its row offset), else null
+    const int* ss;      // and their spans
 };
 
 }  // namespace sweep

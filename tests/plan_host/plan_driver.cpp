@@ -112,7 +112,7 @@ int selftest()
     void* b = dev_alloc(4096);
     hipGraph_t g;
     hipGraphCreate(&g, 0);
-    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024, false);
+    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024, false, false, false);
     void *descs = a, *vch = a, *qc = a, *qw = nullptr, *kn = nullptr, *ptab = b;
     void* params[6] = {&descs, &vch, &qc, &qw, &kn, &ptab};
     hipKernelNodeParams prm{};
@@ -321,6 +321,27 @@ int tune()
                 if (sweep_backward(&hx.b, &ox, px, gP, gQ, wsx, wx, nullptr) != SWEEP_ERR_UNSUPPORTED) ++bad;
                 if (sweep_backward_workspace_size(&hx.b, &ox) != 0) ++bad;
             }
+        }
+    }
+    {
+        // arc-length and curvature-adaptive samples (the arc nodes before
+        // the frames; the one-wave and chunk-walking frame kernels)
+        HostBatch ha;
+        make_batch(ha, {3, 2, 5, 1}, {200, 1500, 5000, 90}, {40, 17, 9, 12}, false, rng);
+        for (int mode = 1; mode <= 2; ++mode) {
+            sweep_options oa;
+            sweep_default_options(&oa);
+            oa.u_sampling = mode;
+            oa.u_lambda = mode == 2 ? 0.5 : 0.0;
+            const int64_t ea = sweep_batched_output_elems(&ha.b);
+            const size_t wa = sweep_batched_workspace_size(&ha.b, &oa);
+            for (int rep = 0; rep < 2; ++rep) {
+                float* pa = (float*)dev_alloc(sizeof(float) * ea);
+                float* na = (float*)dev_alloc(sizeof(float) * ea);
+                void* wsa = dev_alloc(wa);
+                bad += check(sweep_eval_batched(&ha.b, &oa, pa, na, wsa, wa, nullptr), "sweep_eval_batched (arc length)");
+            }
+            if (sweep_backward_workspace_size(&ha.b, &oa) != 0) ++bad;
         }
     }
     hipDeviceSynchronize();

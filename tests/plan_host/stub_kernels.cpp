@@ -16,11 +16,15 @@ constexpr ArgSig N{sizeof(void*), kNullablePtr};
 constexpr ArgSig I{sizeof(int), kValue};
 constexpr ArgSig N0{sizeof(sweep::InitialNormal), kValue};
 constexpr ArgSig FX{sizeof(sweep::BatchFrameExt), kValue};
+constexpr ArgSig D{sizeof(double), kValue};
 
 const KernelSig kProfile{"kb_profile", {P, P, P, N, N, P}};
 const KernelSig kFrame{"kb_frame", {P, P, P, N, N, N0, I, P, FX}};
 const KernelSig kFrameLong{"kb_frame_long", {P, P, P, N, N, N0, I, P, FX}};
 const KernelSig kFrameWave{"kb_frame_wave", {P, P, P, N, N, N0, I, P, FX}};
+const KernelSig kArcPieces{"kb_arc_pieces", {P, P, P, N, N, D, P}};
+const KernelSig kArcCumsum{"kb_arc_cumsum", {P, P, P}};
+const KernelSig kArcParams{"kb_arc_params", {P, P, P, N, N, D, P, P, P}};
 const KernelSig kSurface{"kb_surface", {P, P, P, P, P, N}};
 const KernelSig kReduce{"kbw_reduce", {P, P, I, N, N, P, P, P, P}};
 const KernelSig kRows{"kbw_rows", {P, P, P, N, N, P, P, P, P, P, I}};
@@ -30,7 +34,7 @@ const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, 
 const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
 
 // distinct addresses standing in for kernel entry points
-char g_profile, g_frame[8], g_frame_long[8], g_frame_wave[8], g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
+char g_profile, g_frame[8], g_frame_long[8], g_frame_wave[8], g_arc_pieces, g_arc_cumsum, g_arc_params, g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
 
 const std::map<const void*, const KernelSig*>& table()
 {
@@ -40,6 +44,9 @@ const std::map<const void*, const KernelSig*>& table()
         for (int p = 1; p < 8; ++p) m[&g_frame[p]] = &kFrame;
         for (int p = 1; p < 8; ++p) m[&g_frame_long[p]] = &kFrameLong;
         for (int p = 1; p < 8; ++p) m[&g_frame_wave[p]] = &kFrameWave;
+        m[&g_arc_pieces] = &kArcPieces;
+        m[&g_arc_cumsum] = &kArcCumsum;
+        m[&g_arc_params] = &kArcParams;
         m[&g_surface] = &kSurface;
         m[&g_reduce] = &kReduce;
         m[&g_rows] = &kRows;
@@ -63,14 +70,14 @@ const KernelSig* lookup(const void* fn)
 
 std::vector<const KernelSig*> all_kernels()
 {
-    return {&kProfile, &kFrame, &kFrameLong, &kFrameWave, &kSurface, &kReduce, &kRows, &kSamples, &kFinal, &kParamRec, &kParams};
+    return {&kProfile, &kFrame, &kFrameLong, &kFrameWave, &kArcPieces, &kArcCumsum, &kArcParams, &kSurface, &kReduce, &kRows, &kSamples, &kFinal, &kParamRec, &kParams};
 }
 
 }  // namespace stub
 
 namespace sweep {
 
-BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool)
+BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool, bool, bool)
 {
     BatchedKernels k{};
     k.profile = &stub::g_profile;
@@ -80,6 +87,9 @@ BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool)
     for (int p = 1; p < 8; ++p) k.frame[p] = &stub::g_frame[p];
     for (int p = 1; p < 8; ++p) k.frame_long[p] = &stub::g_frame_long[p];
     for (int p = 1; p < 8; ++p) k.frame_wave[p] = &stub::g_frame_wave[p];
+    k.arc_pieces = &stub::g_arc_pieces;
+    k.arc_cumsum = &stub::g_arc_cumsum;
+    k.arc_params = &stub::g_arc_params;
     k.surface = &stub::g_surface;
     return k;
 }

@@ -158,16 +158,62 @@ def test_arclength_large_sweep_sampled_rows():
     assert ok, r
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+@pytest.mark.parametrize("out_dtype", [torch.float64, torch.float32])
+def test_batched_arclength_matches_oracle(out_dtype, lam):
+    """Arc-length (lam = 0) and curvature-adaptive samples in a batch: the
+    tables of every path (pieces, one cumulative table per sweep, sample
+    parameters) as graph nodes before the frames; sweeps framed by one wave
+    (<= 256 u-samples) and by the chunk-walking kernel, path degrees 1-7,
+    one path with given knots; each sweep against the oracle's arc-length
+    sweep (8 n eps for the long FP64 scans)."""
+    rng = np.random.default_rng(41)
+    specs = []
+    for k, (p, n_u, n_v) in enumerate([(3, 200, 40), (2, 1500, 17), (5, 900, 33), (1, 120, 9), (3, 5000, 8),
+                                       (7, 3000, 12), (4, 64, 70)]):
+        P = synth.random_walk(rng, int(rng.integers(p + 3, 30)))
+        Q = synth.perturbed_circle(rng, int(rng.integers(5, 12)))
+        specs.append(synth.SweepSpec(synth.CurveSpec(P, p), synth.CurveSpec(Q, 3, True), n_u, n_v))
+    for s in specs:  # a batch takes knots for every path or for none
+        n, p = s.path.n, s.path.degree
+        s.path.knots = np.concatenate([np.zeros(p), np.linspace(0, 1, n - p + 1), np.ones(p)])
+    n = specs[2].path.n
+    specs[2].path.knots = np.concatenate([np.zeros(6), np.sort(rng.uniform(0, 2, n - 6)), np.full(6, 2.0)])
+    b = api.Batch.from_specs(specs)
+    kw = dict(u_sampling="adaptive", u_lambda=lam) if lam else dict(u_sampling="arclength")
+    say(f"[case] batch arclength lam={lam} out={out_dtype}: {len(specs)} sweeps")
+    pos, nrm = api.sweep_eval_batched(b, out_dtype=out_dtype, **kw)
+    again = api.sweep_eval_batched(b, out_dtype=out_dtype, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(pos, again[0]) and torch.equal(nrm, again[1])
+    for k, s in enumerate(specs):
+        ref, _ = oracle.sweep_ex(s.path, s.profile, s.n_u, s.n_v, arclength=True, lam=lam)
+        tol = TOL[out_dtype]
+        if out_dtype == torch.float64:
+            tol = max(tol, 8 * s.n_u * EPS)
+        ok, r = parity(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).cpu().numpy(), b.view(nrm, k).cpu().numpy(), tol)
+        say(f"   sweep {k} ({s.n_u}x{s.n_v}, p={s.path.degree}): {r}")
+        assert ok, (k, r)
+
+
 def test_arclength_rejected_where_unsupported():
     spec = synth.single(140, 8, 8, 64, 16)
     law = api.Law(dev_ctrl(np.array([[1, 0, 0], [1.2, 0.3, 0], [0.9, 0.5, 0.0]])), 2)
     with pytest.raises(_lib.SweepError, match="UNSUPPORTED"):
         gpu_sweep(spec, u_sampling="arclength", law=law)
     b = api.Batch.from_specs([spec])
-    opt = api.make_options(u_sampling="arclength")
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     pos = torch.empty(b.out_elems, device="cuda")
-    st = _lib.sweep_eval_batched(b.c_struct(), opt, pos.data_ptr(), 0, ws.data_ptr(), ws.numel(), 0)
+    # in a batch: not with a frame mode or the FP32 frame, and not in the adjoint
+    for opt in (api.make_options(u_sampling="arclength", frame_mode="frenet"),
+                api.make_options(u_sampling="arclength", frame_dtype=torch.float32)):
+        st = _lib.sweep_eval_batched(b.c_struct(), opt, pos.data_ptr(), 0, ws.data_ptr(), ws.numel(), 0)
+        assert _lib.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
+    opt = api.make_options(u_sampling="arclength")
+    gP = torch.empty(3 * spec.path.n, dtype=torch.float64, device="cuda")
+    gQ = torch.empty(3 * spec.profile.n, dtype=torch.float64, device="cuda")
+    st = _lib.sweep_backward(b.c_struct(), opt, pos.data_ptr(), gP.data_ptr(), gQ.data_ptr(), ws.data_ptr(),
+                             ws.numel(), 0)
     assert _lib.STATUS[st] == "SWEEP_ERR_UNSUPPORTED"
 
 
