@@ -300,6 +300,49 @@ def triangles_variant(steps: int):
             "ms": ms, "GBps": 12.0 * nt / (ms * 1e-3) / 1e9}
 
 
+def batched_mode(b, specs, steps, pos, nrm, picked, frame_mode="rmf", law=None, u_sampling="parameter",
+                 u_lambda=0.0):
+    """The batch in another mode (arc-length or adaptive path samples, or the
+    Frenet frame with one law for every sweep), FP32 output into the same
+    buffers: graph time per call and whole-sweep parity on a few sweeps."""
+    import torch
+    import oracle
+    from paper_1110_5450_amd import api
+
+    glaw = None if law is None else api.Law(torch.as_tensor(law.ctrl).cuda(), law.degree, law.knots)
+    kw = dict(frame_mode=frame_mode, law=glaw, u_sampling=u_sampling, u_lambda=u_lambda)
+    ws = torch.empty(api.batched_workspace_size(b, **kw), dtype=torch.uint8, device="cuda")
+    t1 = time.perf_counter()
+    api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws, **kw)
+    torch.cuda.synchronize()
+    first_ms = 1e3 * (time.perf_counter() - t1)
+    for _ in range(GRAPH_WARMUP - 1):
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws, **kw)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws, **kw)
+    ev[1].record()
+    torch.cuda.synchronize()
+    gpu_ms = ev[0].elapsed_time(ev[1]) / steps
+    err = {"pos_rel": 0.0, "nrm_scaled": 0.0, "nrm_abs_wc": 0.0, "masked": 0}
+    arc = u_sampling != "parameter"
+    for k in picked:
+        s = specs[k]
+        ref, _ = oracle.sweep_ex(s.path, s.profile, s.n_u, s.n_v, mode=frame_mode, law=law, arclength=arc,
+                                 lam=u_lambda if u_sampling == "adaptive" else 0.0)
+        r = oracle.compare(ref.pos, ref.nrm, ref.kappa, b.view(pos, k).double().cpu().numpy(),
+                           b.view(nrm, k).double().cpu().numpy(), oracle.bbox_diag(ref.pos), 1e6)
+        for key in ("pos_rel", "nrm_scaled", "nrm_abs_wc"):
+            err[key] = max(err[key], r[key])
+        err["masked"] += r["masked"]
+    err.update({"sweeps": list(picked), "tolerance": 1e-5})
+    del ws
+    return {"vertices_per_s": b.n_vertices / (gpu_ms * 1e-3), "gpu_ms_per_step": gpu_ms,
+            "first_call_ms": round(first_ms, 3), "error_vs_oracle": err}
+
+
 def batched_variants(steps: int):
     """The 4096-sweep batch: one graph launch (FP32) versus the same sweeps as
     single FP64 calls."""
@@ -351,6 +394,11 @@ def batched_variants(steps: int):
             err[key] = max(err[key], r[key])
         err["masked"] += r["masked"]
     err.update({"sweeps": picked, "tolerance": 1e-5})
+    modes = {"arclength_graph": batched_mode(b, specs, steps, pos, nrm, picked[:4], u_sampling="arclength"),
+             "adaptive_lambda_0.5_graph": batched_mode(b, specs, steps, pos, nrm, picked[:4],
+                                                       u_sampling="adaptive", u_lambda=0.5),
+             "frenet_law_graph": batched_mode(b, specs, steps, pos, nrm, picked[:4], frame_mode="frenet",
+                                              law=synth.sweep_law())}
     del pos, nrm, ws
     torch.cuda.empty_cache()
     # the same sweeps, one FP64 sweep_eval call each
@@ -389,6 +437,7 @@ def batched_variants(steps: int):
                                "autotune": {"best_ms": tuned_ms, "seconds": t_tune},
                                "warmup_call_ms": warm_ms,
                                "error_vs_oracle": err},
+        **modes,
         "single_calls_fp64": {"vertices_per_s": N / el64, "ms_per_pass": 1e3 * el64, "calls": len(specs)},
     }
 

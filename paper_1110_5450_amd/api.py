@@ -463,10 +463,13 @@ def tile_config_name(k: int) -> str:
 
 
 def batched_workspace_size(batch: Batch, out_dtype=torch.float32, frame_dtype=torch.float64,
-                           frame_mode: str = "rmf", law: Optional[Law] = None) -> int:
-    """Workspace bytes of sweep_eval_batched (a frame mode or law: longer row records)."""
+                           frame_mode: str = "rmf", law: Optional[Law] = None, u_sampling: str = "parameter",
+                           u_lambda: float = 0.0) -> int:
+    """Workspace bytes of sweep_eval_batched (a frame mode or law: longer row
+    records; arc-length or adaptive sampling: the length tables)."""
     return L.sweep_batched_workspace_size(batch.c_struct(),
-                                          make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law))
+                                          make_options(out_dtype, frame_dtype, frame_mode=frame_mode, law=law,
+                                                       u_sampling=u_sampling, u_lambda=u_lambda))
 
 
 _PARAM_GRADS = ("path_knots", "prof_knots", "path_weights", "prof_weights")

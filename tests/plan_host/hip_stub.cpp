@@ -46,6 +46,8 @@ struct Node {
     Graph* graph;
     const stub::KernelSig* sig;
     std::vector<std::vector<unsigned char>> args;
+    const void* fn;
+    unsigned grid;
 };
 
 struct Exec {
@@ -343,7 +345,7 @@ hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGr
         return hipErrorInvalidDeviceFunction;
     }
     if (prm->extra) violation("graph kernel node with 'extra' arguments");
-    Node* n = new Node{gr, sig, capture_args(sig, prm->kernelParams)};
+    Node* n = new Node{gr, sig, capture_args(sig, prm->kernelParams), prm->func, prm->gridDim.x};
     g_nodes.insert(n);
     gr->nodes.push_back((hipGraphNode_t)n);
     *node = (hipGraphNode_t)n;
@@ -404,6 +406,8 @@ hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s)
     l.exec = ex;
     for (Node* n : ex->nodes) {
         check_launch_args(n->sig, ex->args[n]);
+        const std::string why = stub::check_work_list(n->fn, n->grid, ex->args[n]);
+        if (!why.empty()) violation(std::string(n->sig->name) + ": " + why);
         for (const void* p : pointer_args(n->sig, ex->args[n])) l.ptrs.push_back(p);
     }
     enqueue(s, std::move(l));

@@ -162,19 +162,27 @@ int plans()
     order.push_back(&first);
 
     std::vector<Buffers> owned;
-    int call = 0;
+    int call = 0, shape = 0;
     for (HostBatch* h : order) {
+        // every third shape samples its paths at equal arc length or
+        // adaptively (arc plans built, updated and evicted among the others)
+        sweep_options o = opt;
+        if (shape % 3 == 1) {
+            o.u_sampling = shape % 2 ? SWEEP_U_ARCLENGTH : SWEEP_U_ADAPTIVE;
+            o.u_lambda = shape % 2 ? 0.0 : 0.5;
+        }
+        ++shape;
         for (int rep = 0; rep < 3; ++rep, ++call) {
             const int64_t elems = sweep_batched_output_elems(&h->b);
             Buffers B;
             B.pos = (float*)dev_alloc(sizeof(float) * elems);
             B.nrm = (float*)dev_alloc(sizeof(float) * elems);
-            B.ws_bytes = sweep_batched_workspace_size(&h->b, &opt);
+            B.ws_bytes = sweep_batched_workspace_size(&h->b, &o);
             B.ws = dev_alloc(B.ws_bytes);
             owned.push_back(B);
-            bad += check(sweep_eval_batched(&h->b, &opt, B.pos, B.nrm, B.ws, B.ws_bytes, streams[call % 2]),
+            bad += check(sweep_eval_batched(&h->b, &o, B.pos, B.nrm, B.ws, B.ws_bytes, streams[call % 2]),
                          "sweep_eval_batched");
-            if (call % 4 == 3) {
+            if (call % 4 == 3 && o.u_sampling == SWEEP_U_PARAMETER) {
                 const size_t wb = sweep_backward_workspace_size(&h->b, &opt);
                 void* ws = dev_alloc(wb);
                 long long np = 0, nq = 0;
@@ -325,10 +333,12 @@ int tune()
     }
     {
         // arc-length and curvature-adaptive samples (the arc nodes before
-        // the frames; the one-wave and chunk-walking frame kernels)
-        HostBatch ha;
-        make_batch(ha, {3, 2, 5, 1}, {200, 1500, 5000, 90}, {40, 17, 9, 12}, false, rng);
+        // the frames; the one-wave and chunk-walking frame kernels),
+        // polynomial and rational paths
+        for (int rat = 0; rat < 2; ++rat)
         for (int mode = 1; mode <= 2; ++mode) {
+            HostBatch ha;
+            make_batch(ha, {3, 2, 5, 1, 3}, {200, 1500, 5000, 90, 33}, {40, 17, 9, 12, 8}, rat != 0, rng);
             sweep_options oa;
             sweep_default_options(&oa);
             oa.u_sampling = mode;

@@ -3,8 +3,11 @@
 // and stand-ins of the plan code's kernel-table and fast-division helpers.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
+#include <string>
 
+#include "../../paper_1110_5450_amd/csrc/arclength.hpp"
 #include "../../paper_1110_5450_amd/csrc/kernels.hpp"
 #include "stub_kernels.hpp"
 
@@ -66,6 +69,24 @@ const KernelSig* lookup(const void* fn)
 {
     auto it = table().find(fn);
     return it == table().end() ? nullptr : it->second;
+}
+
+std::string check_work_list(const void* fn, unsigned grid, const std::vector<std::vector<unsigned char>>& args)
+{
+    const bool pieces = fn == &g_arc_pieces;
+    if (!pieces && fn != &g_arc_params) return "";
+    const sweep::BatchDesc* descs;
+    const int2* chunks;
+    std::memcpy(&descs, args[0].data(), sizeof descs);
+    std::memcpy(&chunks, args[1].data(), sizeof chunks);
+    for (unsigned b = 0; b < grid; ++b) {
+        const sweep::BatchDesc& d = descs[chunks[b].x];
+        const int lim = pieces ? sweep::arc_piece_count(d.n_path, d.p_path) : d.n_u;
+        if (chunks[b].y < 0 || chunks[b].y >= lim)
+            return "block " + std::to_string(b) + " starts at index " + std::to_string(chunks[b].y) + " of " +
+                   std::to_string(lim);
+    }
+    return "";
 }
 
 std::vector<const KernelSig*> all_kernels()

@@ -6,6 +6,7 @@
 #pragma once
 
 #include <cstddef>
+#include <string>
 #include <vector>
 
 namespace stub {
@@ -26,6 +27,11 @@ struct KernelSig {
 const KernelSig* lookup(const void* fn);
 // Every table entry (for comparing parameter counts with the kernel sources).
 std::vector<const KernelSig*> all_kernels();
+// For the arc-length kernels, which take a work list of (sweep, first
+// piece or u-sample) per block: whether the `grid` entries a launch reads
+// start inside their sweep; "" if so (or for other kernels), else what is
+// wrong.  Reads the stand-in's device memory (host memory).
+std::string check_work_list(const void* fn, unsigned grid, const std::vector<std::vector<unsigned char>>& args);
 // Violations counted so far (printed when print is set); reset.
 int report(bool print);
 void reset_violations();
