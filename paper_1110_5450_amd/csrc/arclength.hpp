@@ -3,17 +3,20 @@
 //
 // Arc length s(u) = integral of |C'| from the start of the domain.  Every
 // non-empty knot span is cut into kArcSub equal pieces, each integrated by
-// 8-point Gauss-Legendre (one lane per node); one block scans the piece
-// lengths into a cumulative table; a group of lanes per u-sample finds the
-// piece holding its target length i/(n_u-1) of the total (binary search)
-// and solves s(u) = target inside it by Newton's method kept in a bisection
-// bracket, the running integral again by 8-point Gauss-Legendre over
-// [piece start, u].  The sample parameters and their spans then replace the
+// 8-point Gauss-Legendre (a wave per span, four nodes per lane); one block
+// scans the piece lengths into a cumulative table; a group of lanes per
+// u-sample finds the piece holding its target length i/(n_u-1) of the total
+// (binary search) and solves s(u) = target inside it by Newton's method
+// kept in a bisection bracket, the running integral again by 8-point
+// Gauss-Legendre over [piece start, u].  C' of a polynomial path is
+// evaluated from a per-span set-up (SpanDeriv) formed once per span or per
+// sample.  The sample parameters and their spans then replace the
 // uniform parameter rule for the path.
 #pragma once
 
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "sweep.h"
 
 #pragma clang fp contract(off)
 
@@ -52,6 +55,83 @@ static __device__ const double kGlEnd[8] = {-0.032020422845832404, 0.11217721020
                                      0.3537304181064418,    -0.5126556338013685, 0.7101568903172424,
                                      -0.9912041583117163,   1.5806870630309555};
 
+// C' of a polynomial path on one non-empty span k, set up for evaluation by
+// de Boor's algorithm with multiplications only (degree d = p-1):
+//   e_t = p (P_{k-p+t+1} - P_{k-p+t}) / (U_{k+t+1} - U_{k-p+t+1}),  t = 0..p-1,
+// the control points of C' that act on the span; the reciprocals
+//   R_{r,i} = 1 / (U_{k+i+1-r} - U_{k-d+i}),  1 <= r <= i <= d,
+// of the denominators of level r of the recursion; and the knots U_{k-d+i},
+// i = 1..d.  Each of the p + d(d+1)/2 + d values is one job, so that a group
+// of lanes forms them together.  Every denominator spans an interval that
+// contains the non-empty span [U_k, U_{k+1}), so none vanishes.
+template <int P>
+struct SpanDeriv {
+    static constexpr int kD = P - 1;
+    static constexpr int kNR = kD * (kD + 1) / 2;
+    static constexpr int kR = 3 * P;           // R_{r,i} at kR + (i-1) i / 2 + r - 1
+    static constexpr int kU = kR + kNR;        // U_{k-d+i} at kU + i - 1
+    static constexpr int kJobs = P + kNR + kD;
+    static constexpr int kDoubles = kU + kD;
+};
+constexpr int kArcSetupMax = SpanDeriv<SWEEP_MAX_DEGREE>::kDoubles;
+
+template <int P>
+__device__ __forceinline__ void span_deriv_job(const DCurve& c, int k, int j, double* __restrict__ s)
+{
+    using S = SpanDeriv<P>;
+    constexpr int D = S::kD;
+    if (j < P) {
+        const double f = (double)P / (knot(c, k + j + 1) - knot(c, k - P + j + 1));
+        const V3<double> a = ctrl_pt(c, k - P + j), b = ctrl_pt(c, k - P + j + 1);
+        s[3 * j] = f * (b.x - a.x);
+        s[3 * j + 1] = f * (b.y - a.y);
+        s[3 * j + 2] = f * (b.z - a.z);
+    } else if (j < P + S::kNR) {
+        const int idx = j - P;
+        int i = 1;
+#pragma unroll
+        for (int m = 2; m <= D; ++m)
+            if (idx >= (m - 1) * m / 2) i = m;
+        const int r = idx - (i - 1) * i / 2 + 1;
+        s[S::kR + idx] = 1.0 / (knot(c, k + i + 1 - r) - knot(c, k - D + i));
+    } else if (j < S::kJobs) {
+        const int m = j - P - S::kNR;
+        s[S::kU + m] = knot(c, k - D + 1 + m);
+    }
+}
+
+// The sampling density (as speed_at) at u on the span set up in s: level r
+// of the recursion replaces e_i, i = d..r, by e_{i-1} + a (e_i - e_{i-1}),
+// a = (u - U_{k-d+i}) R_{r,i}; e_d is then C'(u).  C'' (adaptive sampling)
+// is d R_{d,d} (e_d - e_{d-1}) taken before the last level (R_{d,d} is the
+// reciprocal of the span's width).
+template <int P, bool ADAPT>
+__device__ __forceinline__ double span_speed(const double* __restrict__ s, double u, double lam)
+{
+    using S = SpanDeriv<P>;
+    constexpr int D = S::kD;
+    V3<double> e[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) e[t] = mk(s[3 * t], s[3 * t + 1], s[3 * t + 2]);
+    V3<double> c2 = mk(0.0, 0.0, 0.0);
+#pragma unroll
+    for (int r = 1; r <= D; ++r) {
+        if constexpr (ADAPT && D >= 1) {
+            if (r == D) c2 = ((double)D * s[S::kR + (D - 1) * D / 2 + D - 1]) * (e[D] - e[D - 1]);
+        }
+#pragma unroll
+        for (int i = D; i >= r; --i) {
+            const double a = (u - s[S::kU + i - 1]) * s[S::kR + (i - 1) * i / 2 + r - 1];
+            e[i] = e[i - 1] + a * (e[i] - e[i - 1]);
+        }
+    }
+    const V3<double> c1 = e[D];
+    const double sp = sqrt(dot(c1, c1));
+    if (!ADAPT) return sp;
+    const V3<double> cr = cross(c1, c2);
+    return sp + (sp > 0.0 ? lam * sqrt(dot(cr, cr)) / (sp * sp) : 0.0);
+}
+
 // Piece q = (k - p) * kArcSub + m of span k: its bounds.
 __device__ __forceinline__ void piece_bounds(const DCurve& c, int q, int& k, double& lo, double& hi)
 {
@@ -62,25 +142,44 @@ __device__ __forceinline__ void piece_bounds(const DCurve& c, int q, int& k, dou
     hi = m + 1 < kArcSub ? Uk + w * ((double)(m + 1) / kArcSub) : Uk1;
 }
 
-// Piece q's length into len[q]: eight lanes per piece (l = the lane's node),
-// one Gauss-Legendre node each; the weighted speeds are summed by a
-// butterfly over the eight lanes.
-template <int P, bool ADAPT>
-__device__ __forceinline__ void arc_piece(const DCurve& c, int q, int l, double lam, double* __restrict__ len)
+// The kArcSub piece lengths of span index si (span k = p + si) into
+// len[si kArcSub ...], by one wave: a polynomial path's span is set up once
+// (span_deriv_job, one job per lane, through the wave's LDS slice s), then
+// lane l takes four nodes of piece l / 2 (the rule is symmetric: the
+// positive nodes, mirrored on even lanes) and the two lanes of a piece add
+// their weighted sums.  A rational path (RAT) evaluates each node by
+// speed_at.  An empty span's pieces have length 0.
+template <int P, bool ADAPT, bool RAT>
+__device__ __forceinline__ void arc_span(const DCurve& c, int si, int lane, double lam, double* __restrict__ s,
+                                         double* __restrict__ len)
 {
-    int k;
-    double lo, hi;
-    piece_bounds(c, q, k, lo, hi);
-    if (!(hi > lo)) {
-        if (l == 0) len[q] = 0.0;
+    static_assert(2 * kArcSub == 64, "two lanes per piece fill a wave");
+    const int k = c.p + si, m = lane >> 1;
+    const double Uk = knot(c, k), Uk1 = knot(c, k + 1), w = Uk1 - Uk;
+    double* out = len + (long long)si * kArcSub;
+    if (!(w > 0.0)) {
+        if (lane < kArcSub) out[lane] = 0.0;
         return;
     }
-    const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
-    double part = kGlW[l] * speed_at<P, ADAPT>(c, k, mid + half * kGlX[l], lam);
-    part += __shfl_xor(part, 1, 8);
-    part += __shfl_xor(part, 2, 8);
-    part += __shfl_xor(part, 4, 8);
-    if (l == 0) len[q] = half * part;
+    if (!RAT) {
+        if (lane < SpanDeriv<P>::kJobs) span_deriv_job<P>(c, k, lane, s);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the piece's bounds as piece_bounds forms them
+    const double lo = Uk + w * ((double)m / kArcSub);
+    const double hi = m + 1 < kArcSub ? Uk + w * ((double)(m + 1) / kArcSub) : Uk1;
+    const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo), sh = (lane & 1) ? half : -half;
+    double part = 0.0;
+#pragma unroll
+    for (int t = 4; t < 8; ++t) {
+        const double x = mid + sh * kGlX[t];
+        const double e = RAT ? speed_at<P, ADAPT>(c, k, x, lam) : span_speed<P, ADAPT>(s, x, lam);
+        part += kGlW[t] * e;
+    }
+    part += __shfl_xor(part, 1, 64);
+    if (!(lane & 1)) out[m] = half * part;
 }
 
 // Inclusive scan of the piece lengths into cum[1..npc] (cum[0] = 0) by one
@@ -196,11 +295,13 @@ __host__ __device__ inline int arc_coarse_stride(int npc)
 }
 
 // Sample i's parameter and span (lane l of its kArcLanes group), given the
-// coarse table in LDS (nc = npc / cstride + 1 entries).
-template <int P, bool ADAPT>
+// coarse table in LDS (nc = npc / cstride + 1 entries).  A polynomial path's
+// span is set up once for the iteration by the group (its LDS slice gs); a
+// rational path (RAT) evaluates each node by speed_at.
+template <int P, bool ADAPT, bool RAT>
 __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns, int npc, int cstride, int nc,
                                           double lam, const double* __restrict__ cum, const double* coarse,
-                                          double* __restrict__ su, int* __restrict__ ss)
+                                          double* __restrict__ gs, double* __restrict__ su, int* __restrict__ ss)
 {
     double u;
     if (i == 0) {
@@ -233,12 +334,19 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
         u = len > 0.0 ? plo + (target - cum[q]) / len * (phi - plo) : plo;
         double blo = plo, bhi = phi;
         const double xl = kGlX[l], wl = kGlW[l];
+        if (!RAT) {
+            for (int j = l; j < SpanDeriv<P>::kJobs; j += kArcLanes) span_deriv_job<P>(c, k, j, gs);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         // Every lane of the group holds the same u, f and speed (the sums
         // below are butterflies, whose pairwise additions commute), so the
         // group takes every branch together.
         for (int it = 0; it < 40; ++it) {
             const double mid = 0.5 * (plo + u), half = 0.5 * (u - plo);
-            const double e = speed_at<P, ADAPT>(c, k, mid + half * xl, lam);
+            const double x = mid + half * xl;
+            const double e = RAT ? speed_at<P, ADAPT>(c, k, x, lam) : span_speed<P, ADAPT>(gs, x, lam);
             double part = wl * e, sp = kGlEnd[l] * e;
             part += __shfl_xor(part, 1, kArcLanes);
             sp += __shfl_xor(sp, 1, kArcLanes);
@@ -264,37 +372,6 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
     }
 }
 
-
-// Runtime path degree (one copy per degree, as the single-sweep launches
-// select at run time).
-template <bool ADAPT>
-__device__ __forceinline__ void arc_piece_any(const DCurve& c, int q, int l, double lam, double* __restrict__ len)
-{
-    switch (c.p) {
-    case 1: arc_piece<1, ADAPT>(c, q, l, lam, len); break;
-    case 2: arc_piece<2, ADAPT>(c, q, l, lam, len); break;
-    case 3: arc_piece<3, ADAPT>(c, q, l, lam, len); break;
-    case 4: arc_piece<4, ADAPT>(c, q, l, lam, len); break;
-    case 5: arc_piece<5, ADAPT>(c, q, l, lam, len); break;
-    case 6: arc_piece<6, ADAPT>(c, q, l, lam, len); break;
-    default: arc_piece<7, ADAPT>(c, q, l, lam, len); break;
-    }
-}
-template <bool ADAPT>
-__device__ __forceinline__ void arc_param_any(const DCurve& c, int i, int l, int ns, int npc, int cstride, int nc,
-                                              double lam, const double* __restrict__ cum, const double* coarse,
-                                              double* __restrict__ su, int* __restrict__ ss)
-{
-    switch (c.p) {
-    case 1: arc_param<1, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    case 2: arc_param<2, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    case 3: arc_param<3, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    case 4: arc_param<4, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    case 5: arc_param<5, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    case 6: arc_param<6, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    default: arc_param<7, ADAPT>(c, i, l, ns, npc, cstride, nc, lam, cum, coarse, su, ss); break;
-    }
-}
 
 // Pieces of an open path's arc-length table.
 __host__ __device__ inline int arc_piece_count(int n, int p) { return (n - p) * kArcSub; }

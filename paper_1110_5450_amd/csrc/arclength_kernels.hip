@@ -7,12 +7,14 @@
 
 namespace sweep {
 
-template <int P, bool ADAPT>
-__global__ __launch_bounds__(kBlock) void k_arc_pieces(DCurve c, int npc, double lam, double* __restrict__ len)
+template <int P, bool ADAPT, bool RAT>
+__global__ __launch_bounds__(kBlock) void k_arc_pieces(DCurve c, int nspan, double lam, double* __restrict__ len)
 {
-    const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) >> 3;
-    if (g >= npc) return;   // whole 8-lane groups leave together
-    arc_piece<P, ADAPT>(c, (int)g, threadIdx.x & 7, lam, len);
+    __shared__ double setup[kWaves][SpanDeriv<P>::kDoubles];
+    const int w = threadIdx.x >> 6;
+    const long long si = (long long)blockIdx.x * kWaves + w;
+    if (si >= nspan) return;   // whole waves leave together
+    arc_span<P, ADAPT, RAT>(c, (int)si, threadIdx.x & 63, lam, setup[w], len);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_arc_cumsum(const double* __restrict__ len, int npc,
@@ -21,34 +23,37 @@ __global__ __launch_bounds__(kScanThreads) void k_arc_cumsum(const double* __res
     arc_cumsum_block(len, npc, cum);
 }
 
-template <int P, bool ADAPT>
+template <int P, bool ADAPT, bool RAT>
 __global__ __launch_bounds__(kBlock) void k_arc_params(DCurve c, int ns, int npc, int cstride, double lam,
                                                        const double* __restrict__ cum, double* __restrict__ su,
                                                        int* __restrict__ ss)
 {
     __shared__ double coarse[kArcCoarseMax];
+    __shared__ double setup[kBlock / kArcLanes][SpanDeriv<P>::kDoubles];
     const int nc = npc / cstride + 1;   // coarse[k] = cum[k cstride], k cstride <= npc
     for (int k = threadIdx.x; k < nc; k += kBlock) coarse[k] = cum[(long long)k * cstride];
     __syncthreads();
     const long long g = ((long long)blockIdx.x * kBlock + threadIdx.x) / kArcLanes;
     if (g >= ns) return;   // whole lane groups leave together
-    arc_param<P, ADAPT>(c, (int)g, threadIdx.x & (kArcLanes - 1), ns, npc, cstride, nc, lam, cum, coarse, su, ss);
+    arc_param<P, ADAPT, RAT>(c, (int)g, threadIdx.x & (kArcLanes - 1), ns, npc, cstride, nc, lam, cum, coarse,
+                             setup[threadIdx.x / kArcLanes], su, ss);
 }
 
 int arc_pieces(const DCurve& c) { return arc_piece_count(c.n, c.p); }
 
-template <bool ADAPT>
+template <bool ADAPT, bool RAT>
 static hipError_t launch_arclength_t(const DCurve& c, int ns, double lam, double* len, double* cum, double* su,
                                      int* ss, hipStream_t st)
 {
-    const int npc = arc_pieces(c), cs = arc_coarse_stride(npc);
-    const dim3 gp((unsigned)(((long long)npc * 8 + kBlock - 1) / kBlock));
+    const int npc = arc_pieces(c), cs = arc_coarse_stride(npc), nspan = c.n - c.p;
+    const dim3 gp((unsigned)((nspan + kWaves - 1) / kWaves));
     const dim3 gs((unsigned)(((long long)ns * kArcLanes + kBlock - 1) / kBlock));
-#define SWEEP_CASE(P)                                                                                           \
-    case P:                                                                                                     \
-        hipLaunchKernelGGL((k_arc_pieces<P, ADAPT>), gp, dim3(kBlock), 0, st, c, npc, lam, len);                \
-        hipLaunchKernelGGL(k_arc_cumsum, dim3(1), dim3(kScanThreads), 0, st, len, npc, cum);                   \
-        hipLaunchKernelGGL((k_arc_params<P, ADAPT>), gs, dim3(kBlock), 0, st, c, ns, npc, cs, lam, cum, su, ss); \
+#define SWEEP_CASE(P)                                                                                      \
+    case P:                                                                                                \
+        hipLaunchKernelGGL((k_arc_pieces<P, ADAPT, RAT>), gp, dim3(kBlock), 0, st, c, nspan, lam, len);      \
+        hipLaunchKernelGGL(k_arc_cumsum, dim3(1), dim3(kScanThreads), 0, st, len, npc, cum);              \
+        hipLaunchKernelGGL((k_arc_params<P, ADAPT, RAT>), gs, dim3(kBlock), 0, st, c, ns, npc, cs, lam, cum, su, \
+                           ss);                                                                            \
         break;
     switch (c.p) {
         SWEEP_CASE(1) SWEEP_CASE(2) SWEEP_CASE(3) SWEEP_CASE(4) SWEEP_CASE(5) SWEEP_CASE(6) SWEEP_CASE(7)
@@ -61,8 +66,10 @@ static hipError_t launch_arclength_t(const DCurve& c, int ns, double lam, double
 hipError_t launch_arclength(const DCurve& c, int ns, double lam, double* len, double* cum, double* su, int* ss,
                             hipStream_t st)
 {
-    return lam != 0.0 ? launch_arclength_t<true>(c, ns, lam, len, cum, su, ss, st)
-                      : launch_arclength_t<false>(c, ns, lam, len, cum, su, ss, st);
+    if (c.w) return lam != 0.0 ? launch_arclength_t<true, true>(c, ns, lam, len, cum, su, ss, st)
+                               : launch_arclength_t<false, true>(c, ns, lam, len, cum, su, ss, st);
+    return lam != 0.0 ? launch_arclength_t<true, false>(c, ns, lam, len, cum, su, ss, st)
+                      : launch_arclength_t<false, false>(c, ns, lam, len, cum, su, ss, st);
 }
 
 // ------------------------------------------------------------ triangles

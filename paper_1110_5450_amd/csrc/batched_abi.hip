@@ -196,7 +196,7 @@ struct NodeArgs {
     void* nrm;
     BatchFrameExt fx;
     // arc-length sampling
-    const int2* apch;              // (sweep, first piece) per block
+    const int2* apch;              // (sweep, first span index) per block
     const int2* asch;              // (sweep, first u-sample) per block
     double lam;                    // adaptive sampling weight (0: arc length)
     double* arc_len;
@@ -245,9 +245,9 @@ struct Plan {
     int n_uchunks_all = 0;
     double* d_knots = nullptr;
     double* d_law_knots = nullptr;  // the law's given knots
-    int2* d_arc_pch = nullptr;      // arc-length sampling: (sweep, first piece) per block
+    int2* d_arc_pch = nullptr;      // arc-length sampling: (sweep, first span index) per block
     int2* d_arc_sch = nullptr;      // (sweep, first u-sample) per block
-    int n_arc_pch = 0, n_arc_sch = 0;
+    int arc_pr[9] = {}, arc_sr[9] = {};   // both lists by path degree: degree p at [r[p], r[p+1])
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int* d_sweeps[8] = {};         // sweeps by path degree: by stage and frame kernel, longest n_u first
@@ -516,21 +516,28 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     const bool ext = options_ext(o);
     const bool adaptive = o->u_sampling == SWEEP_U_ADAPTIVE && o->u_lambda != 0.0;
     const BatchedKernels K = batched_kernels(o->frame_precision == SWEEP_F64, o->out_precision == SWEEP_F64,
-                                             with_nrm, cfg.nontemporal != 0, tv, ext, arc, adaptive);
+                                             with_nrm, cfg.nontemporal != 0, tv, ext, arc, adaptive,
+                                             b->path_weights != nullptr);
     if (arc) {
-        // work lists of the arc-length kernels: 32 pieces and 32 u-samples
-        // per block (eight lanes each)
+        // work lists of the arc-length kernels, by path degree (a launch
+        // each): kWaves spans (a wave each) and 32 u-samples (eight lanes
+        // each) per block
         std::vector<int2> pch, sch;
-        for (int k = 0; k < b->n_sweeps; ++k) {
-            const int npc = arc_piece_count(b->path_n[k], b->path_degree[k]);
-            for (int q = 0; q < npc; q += kBlock / 8) pch.push_back(make_int2(k, q));
-            for (int i = 0; i < b->n_u[k]; i += kBlock / 8) sch.push_back(make_int2(k, i));
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+            P->arc_pr[p] = (int)pch.size();
+            P->arc_sr[p] = (int)sch.size();
+            for (int k = 0; k < b->n_sweeps; ++k) {
+                if (b->path_degree[k] != p) continue;
+                const int nspan = b->path_n[k] - p;
+                for (int q = 0; q < nspan; q += kWaves) pch.push_back(make_int2(k, q));
+                for (int i = 0; i < b->n_u[k]; i += kBlock / kArcLanes) sch.push_back(make_int2(k, i));
+            }
         }
+        P->arc_pr[SWEEP_MAX_DEGREE + 1] = (int)pch.size();
+        P->arc_sr[SWEEP_MAX_DEGREE + 1] = (int)sch.size();
         if ((e = upload((void**)&P->d_arc_pch, pch.data(), sizeof(int2) * pch.size())) != hipSuccess ||
             (e = upload((void**)&P->d_arc_sch, sch.data(), sizeof(int2) * sch.size())) != hipSuccess)
             return hip_fail(e, "plan upload");
-        P->n_arc_pch = (int)pch.size();
-        P->n_arc_sch = (int)sch.size();
     }
     if (o->law && o->law->knots) {
         const sweep_curve* lw = o->law;
@@ -564,6 +571,8 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
         std::memcpy(&n->a, &P->a, sizeof n->a);
         if (kind == kFrame) n->a.sweeps = P->d_sweeps[deg] + first;
         if (kind == kSurface) n->a.tiles = P->d_tiles + first;
+        if (kind == kArcPieces) n->a.apch = P->d_arc_pch + first;
+        if (kind == kArcParams) n->a.asch = P->d_arc_sch + first;
         node_args(*n);
         n->prm.func = const_cast<void*>(fn);
         n->prm.gridDim = dim3(grid);
@@ -580,16 +589,26 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     const hipGraphNode_t profile_node = P->nodes.back()->node;
     std::vector<hipGraphNode_t> prev_frames;
     if (arc) {
-        // arc-length samples of every path before any frame
-        if ((e = add(kArcPieces, 0, K.arc_pieces, (unsigned)P->n_arc_pch, {})) != hipSuccess)
-            return hip_fail(e, "graph node");
-        const hipGraphNode_t pieces = P->nodes.back()->node;
-        if ((e = add(kArcCumsum, 0, K.arc_cumsum, (unsigned)b->n_sweeps, {pieces}, 0, 0, kScanThreads)) != hipSuccess)
+        // arc-length samples of every path before any frame: the pieces of
+        // each path degree, one scan per sweep, the samples of each degree
+        std::vector<hipGraphNode_t> pieces;
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+            const int n = P->arc_pr[p + 1] - P->arc_pr[p];
+            if (n == 0) continue;
+            if ((e = add(kArcPieces, p, K.arc_pieces[p], (unsigned)n, {}, P->arc_pr[p])) != hipSuccess)
+                return hip_fail(e, "graph node");
+            pieces.push_back(P->nodes.back()->node);
+        }
+        if ((e = add(kArcCumsum, 0, K.arc_cumsum, (unsigned)b->n_sweeps, pieces, 0, 0, kScanThreads)) != hipSuccess)
             return hip_fail(e, "graph node");
         const hipGraphNode_t cums = P->nodes.back()->node;
-        if ((e = add(kArcParams, 0, K.arc_params, (unsigned)P->n_arc_sch, {cums})) != hipSuccess)
-            return hip_fail(e, "graph node");
-        prev_frames.push_back(P->nodes.back()->node);
+        for (int p = 1; p <= SWEEP_MAX_DEGREE; ++p) {
+            const int n = P->arc_sr[p + 1] - P->arc_sr[p];
+            if (n == 0) continue;
+            if ((e = add(kArcParams, p, K.arc_params[p], (unsigned)n, {cums}, P->arc_sr[p])) != hipSuccess)
+                return hip_fail(e, "graph node");
+            prev_frames.push_back(P->nodes.back()->node);
+        }
     }
     for (int st = 0; st < S; ++st) {
         std::vector<hipGraphNode_t> frames;
@@ -718,11 +737,16 @@ sweep_status sweep_eval_batched(const sweep_batch* batch, const sweep_options* o
         P->wait_launches();
         P->a = A;
         for (auto& n : P->nodes) {
+            // each node's own slice of the work lists stays
             const int* own = n->a.sweeps;
             const int2* own_tiles = n->a.tiles;
+            const int2* own_apch = n->a.apch;
+            const int2* own_asch = n->a.asch;
             std::memcpy(&n->a, &A, sizeof A);
             n->a.sweeps = own;
             n->a.tiles = own_tiles;
+            n->a.apch = own_apch;
+            n->a.asch = own_asch;
             if ((e = hipGraphExecKernelNodeSetParams(P->exec, n->node, &n->prm)) != hipSuccess)
                 return hip_fail(e, "graph update");
         }
@@ -811,7 +835,7 @@ sweep_status sweep_backward_ex(const sweep_batch* batch, const sweep_options* op
         hipStream_t s;
         ~MarkOnExit() { P->mark_launched(s); }
     } marker{P, sm};
-    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock, false, false, false);
+    const BatchedKernels FK = batched_kernels(true, true, false, false, kBlock, false, false, false, false);
     const BackwardKernels BK = backward_kernels(opt->out_precision == SWEEP_F64, nrm);
     {
         // FP64 frame recomputation with re-orthonormalisation: profile tables, frames
@@ -990,7 +1014,7 @@ sweep_status sweep_autotune_batched(const sweep_batch* batch, const sweep_option
             if ((e = hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice)) != hipSuccess)
                 break;
             const BatchedKernels K = batched_kernels(f64, t64, nrm != nullptr, cfg.nontemporal != 0, cfg.tile_vertices,
-                                                     ext, false, false);
+                                                     ext, false, false, false);
             const int2* tl = d_tiles;
             void* pp = pos;
             void* np = nrm;

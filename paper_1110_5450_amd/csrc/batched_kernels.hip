@@ -42,9 +42,10 @@ __device__ __forceinline__ DCurve prof_of(const BatchDesc& d, const double* prof
                   prof_w ? prof_w + d.prof_ctrl_off : nullptr};
 }
 
-// Arc-length tables of the batch's paths.  Pieces: a block per 32 pieces
-// of one sweep (chunk = (sweep, first piece)), eight lanes per piece.
-template <bool ADAPT>
+// Arc-length tables of the batch's paths, one launch per path degree P (RAT:
+// the paths carry weights).  Pieces: a block per kWaves spans of one sweep
+// (chunk = (sweep, first span index)), a wave per span.
+template <int P, bool ADAPT, bool RAT>
 __global__ __launch_bounds__(kBlock) void kb_arc_pieces(const BatchDesc* __restrict__ descs,
                                                         const int2* __restrict__ chunks,
                                                         const double* __restrict__ path_ctrl,
@@ -52,11 +53,13 @@ __global__ __launch_bounds__(kBlock) void kb_arc_pieces(const BatchDesc* __restr
                                                         const double* __restrict__ knots, double lam,
                                                         double* __restrict__ len)
 {
+    __shared__ double setup[kWaves][SpanDeriv<P>::kDoubles];
     const int2 ch = chunks[blockIdx.x];
     const BatchDesc d = descs[ch.x];
-    const int q = ch.y + (int)(threadIdx.x >> 3);
-    if (q >= arc_piece_count(d.n_path, d.p_path)) return;   // whole 8-lane groups
-    arc_piece_any<ADAPT>(path_of(d, path_ctrl, path_w, knots), q, threadIdx.x & 7, lam, len + d.arc_off);
+    const int w = threadIdx.x >> 6, si = ch.y + w;
+    if (d.p_path != P || si >= d.n_path - P) return;   // whole waves (the list holds degree-P sweeps only)
+    arc_span<P, ADAPT, RAT>(path_of(d, path_ctrl, path_w, knots), si, threadIdx.x & 63, lam, setup[w],
+                            len + d.arc_off);
 }
 
 // One block per sweep: its cumulative table at arc_off + k (one entry more
@@ -69,10 +72,10 @@ __global__ __launch_bounds__(kScanThreads) void kb_arc_cumsum(const BatchDesc* _
     arc_cumsum_block(len + d.arc_off, arc_piece_count(d.n_path, d.p_path), cum + d.arc_off + blockIdx.x);
 }
 
-// Sample parameters: a block per 32 u-samples of one sweep (chunk = (sweep,
-// first sample)), kArcLanes lanes per sample; parameters and spans at the
-// sweep's row offset.
-template <bool ADAPT>
+// Sample parameters (one launch per path degree): a block per 32 u-samples
+// of one sweep (chunk = (sweep, first sample)), kArcLanes lanes per sample;
+// parameters and spans at the sweep's row offset.
+template <int P, bool ADAPT, bool RAT>
 __global__ __launch_bounds__(kBlock) void kb_arc_params(const BatchDesc* __restrict__ descs,
                                                         const int2* __restrict__ chunks,
                                                         const double* __restrict__ path_ctrl,
@@ -82,8 +85,10 @@ __global__ __launch_bounds__(kBlock) void kb_arc_params(const BatchDesc* __restr
                                                         int* __restrict__ ss)
 {
     __shared__ double coarse[kArcCoarseMax];
+    __shared__ double setup[kBlock / kArcLanes][SpanDeriv<P>::kDoubles];
     const int2 ch = chunks[blockIdx.x];
     const BatchDesc d = descs[ch.x];
+    if (d.p_path != P) return;   // the list holds degree-P sweeps only
     const int npc = arc_piece_count(d.n_path, d.p_path), cs = arc_coarse_stride(npc);
     const int nc = npc / cs + 1;
     const double* cumk = cum + d.arc_off + ch.x;
@@ -91,8 +96,9 @@ __global__ __launch_bounds__(kBlock) void kb_arc_params(const BatchDesc* __restr
     __syncthreads();
     const int i = ch.y + (int)(threadIdx.x / kArcLanes);
     if (i >= d.n_u) return;   // whole lane groups
-    arc_param_any<ADAPT>(path_of(d, path_ctrl, path_w, knots), i, threadIdx.x & (kArcLanes - 1), d.n_u, npc, cs, nc,
-                         lam, cumk, coarse, su + d.row_off, ss + d.row_off);
+    arc_param<P, ADAPT, RAT>(path_of(d, path_ctrl, path_w, knots), i, threadIdx.x & (kArcLanes - 1), d.n_u, npc, cs,
+                             nc, lam, cumk, coarse, setup[threadIdx.x / kArcLanes], su + d.row_off,
+                             ss + d.row_off);
 }
 
 // Profile tables: one block per (sweep, chunk of 256 v-samples).
@@ -378,10 +384,22 @@ static void pick_frames(BatchedKernels& k)
 #undef SWEEP_DEG
 }
 
+template <bool ADAPT, bool RAT>
+static void pick_arc(BatchedKernels& k)
+{
+    k.arc_pieces[0] = k.arc_params[0] = nullptr;
+#define SWEEP_DEG(P)                                                   \
+    k.arc_pieces[P] = (const void*)&kb_arc_pieces<P, ADAPT, RAT>;     \
+    k.arc_params[P] = (const void*)&kb_arc_params<P, ADAPT, RAT>;
+    SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)
+#undef SWEEP_DEG
+    k.arc_cumsum = (const void*)&kb_arc_cumsum;
+}
+
 // Extended records (a frame mode or a law) and arc-length sampling with the
 // FP64 frame only, not together: the caller rejects the other combinations.
 template <class F, class T>
-static BatchedKernels pick(bool nrm, bool nt, int K, bool ext, bool arc, bool adaptive)
+static BatchedKernels pick(bool nrm, bool nt, int K, bool ext, bool arc, bool adaptive, bool rat)
 {
     BatchedKernels k;
     k.profile = (const void*)&kb_profile<T>;
@@ -392,22 +410,21 @@ static BatchedKernels pick(bool nrm, bool nt, int K, bool ext, bool arc, bool ad
     } else {
         pick_frames<F, T, false, false>(k);
     }
-    k.arc_pieces = adaptive ? (const void*)&kb_arc_pieces<true> : (const void*)&kb_arc_pieces<false>;
-    k.arc_cumsum = (const void*)&kb_arc_cumsum;
-    k.arc_params = adaptive ? (const void*)&kb_arc_params<true> : (const void*)&kb_arc_params<false>;
+    if (adaptive) rat ? pick_arc<true, true>(k) : pick_arc<true, false>(k);
+    else rat ? pick_arc<false, true>(k) : pick_arc<false, false>(k);
     k.surface = ext ? surface_pick<T, kRowExt>(nrm, nt, K) : surface_pick<T, 16>(nrm, nt, K);
     return k;
 }
 
 BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext, bool arc,
-                               bool adaptive)
+                               bool adaptive, bool rat)
 {
     const int K = tile_vertices / kBlock;
     if (f64)
-        return t64 ? pick<double, double>(nrm, nontemporal, K, ext, arc, adaptive)
-                   : pick<double, float>(nrm, nontemporal, K, ext, arc, adaptive);
-    return t64 ? pick<float, double>(nrm, nontemporal, K, ext, arc, adaptive)
-               : pick<float, float>(nrm, nontemporal, K, ext, arc, adaptive);
+        return t64 ? pick<double, double>(nrm, nontemporal, K, ext, arc, adaptive, rat)
+                   : pick<double, float>(nrm, nontemporal, K, ext, arc, adaptive, rat);
+    return t64 ? pick<float, double>(nrm, nontemporal, K, ext, arc, adaptive, rat)
+               : pick<float, float>(nrm, nontemporal, K, ext, arc, adaptive, rat);
 }
 
 }  // namespace sweep

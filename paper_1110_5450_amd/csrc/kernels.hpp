@@ -165,18 +165,19 @@ struct BatchedKernels {
     const void* frame[8];        // by path degree (index 0 unused): sweeps of n_u <= kBlock*kMaxRun
     const void* frame_long[8];   // longer sweeps, or paths too large for the LDS staging
     const void* frame_wave[8];   // sweeps of n_u <= kWaveMaxU, one wave each
-    const void* arc_pieces;      // arc-length tables (arc-length or adaptive sampling)
+    const void* arc_pieces[8];   // arc-length tables (arc-length or adaptive sampling), by path degree
     const void* arc_cumsum;
-    const void* arc_params;
+    const void* arc_params[8];
     const void* surface;
 };
 // Kernel entry points for a precision combination (host stubs usable as
 // graph kernel-node functions).
 // tile_vertices = vertices per surface block: 256, 512, 1024 or 2048.
 // ext: extended row records (a frame mode or law); arc: arc-length or
-// adaptive u-sampling (lam != 0: adaptive), FP64 frame only.
+// adaptive u-sampling (lam != 0: adaptive), FP64 frame only; rat: the paths
+// carry weights.
 BatchedKernels batched_kernels(bool f64, bool t64, bool nrm, bool nontemporal, int tile_vertices, bool ext, bool arc,
-                               bool adaptive);
+                               bool adaptive, bool rat);
 
 // Frame mode and sweep law of a batch (every sweep of the batch takes the
 // batch's options): Frenet frames and/or one law for all sweeps, written as

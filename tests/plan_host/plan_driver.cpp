@@ -112,7 +112,7 @@ int selftest()
     void* b = dev_alloc(4096);
     hipGraph_t g;
     hipGraphCreate(&g, 0);
-    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024, false, false, false);
+    sweep::BatchedKernels K = sweep::batched_kernels(true, false, true, true, 1024, false, false, false, false);
     void *descs = a, *vch = a, *qc = a, *qw = nullptr, *kn = nullptr, *ptab = b;
     void* params[6] = {&descs, &vch, &qc, &qw, &kn, &ptab};
     hipKernelNodeParams prm{};
@@ -332,9 +332,9 @@ int tune()
         }
     }
     {
-        // arc-length and curvature-adaptive samples (the arc nodes before
-        // the frames; the one-wave and chunk-walking frame kernels),
-        // polynomial and rational paths
+        // arc-length and curvature-adaptive samples (the arc nodes of each
+        // path degree before the frames; the one-wave and chunk-walking
+        // frame kernels), polynomial and rational paths
         for (int rat = 0; rat < 2; ++rat)
         for (int mode = 1; mode <= 2; ++mode) {
             HostBatch ha;

@@ -7,7 +7,6 @@
 #include <map>
 #include <string>
 
-#include "../../paper_1110_5450_amd/csrc/arclength.hpp"
 #include "../../paper_1110_5450_amd/csrc/kernels.hpp"
 #include "stub_kernels.hpp"
 
@@ -37,7 +36,7 @@ const KernelSig kParamRec{"kbw_param_rec", {P, P, P, P, N, N, N, N, P, P, P, P, 
 const KernelSig kParams{"kbw_params", {P, P, P, N, N, N, P, P, P, P, N, N, N, N}};
 
 // distinct addresses standing in for kernel entry points
-char g_profile, g_frame[8], g_frame_long[8], g_frame_wave[8], g_arc_pieces, g_arc_cumsum, g_arc_params, g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
+char g_profile, g_frame[8], g_frame_long[8], g_frame_wave[8], g_arc_pieces[8], g_arc_cumsum, g_arc_params[8], g_surface, g_reduce, g_rows, g_samples, g_final, g_rec_path, g_rec_prof, g_params;
 
 const std::map<const void*, const KernelSig*>& table()
 {
@@ -47,9 +46,9 @@ const std::map<const void*, const KernelSig*>& table()
         for (int p = 1; p < 8; ++p) m[&g_frame[p]] = &kFrame;
         for (int p = 1; p < 8; ++p) m[&g_frame_long[p]] = &kFrameLong;
         for (int p = 1; p < 8; ++p) m[&g_frame_wave[p]] = &kFrameWave;
-        m[&g_arc_pieces] = &kArcPieces;
+        for (int p = 1; p < 8; ++p) m[&g_arc_pieces[p]] = &kArcPieces;
         m[&g_arc_cumsum] = &kArcCumsum;
-        m[&g_arc_params] = &kArcParams;
+        for (int p = 1; p < 8; ++p) m[&g_arc_params[p]] = &kArcParams;
         m[&g_surface] = &kSurface;
         m[&g_reduce] = &kReduce;
         m[&g_rows] = &kRows;
@@ -73,15 +72,23 @@ const KernelSig* lookup(const void* fn)
 
 std::string check_work_list(const void* fn, unsigned grid, const std::vector<std::vector<unsigned char>>& args)
 {
-    const bool pieces = fn == &g_arc_pieces;
-    if (!pieces && fn != &g_arc_params) return "";
+    int deg = 0;
+    bool pieces = false;
+    for (int p = 1; p < 8; ++p) {
+        if (fn == &g_arc_pieces[p]) deg = p, pieces = true;
+        if (fn == &g_arc_params[p]) deg = p;
+    }
+    if (!deg) return "";
     const sweep::BatchDesc* descs;
     const int2* chunks;
     std::memcpy(&descs, args[0].data(), sizeof descs);
     std::memcpy(&chunks, args[1].data(), sizeof chunks);
     for (unsigned b = 0; b < grid; ++b) {
         const sweep::BatchDesc& d = descs[chunks[b].x];
-        const int lim = pieces ? sweep::arc_piece_count(d.n_path, d.p_path) : d.n_u;
+        if (d.p_path != deg)
+            return "block " + std::to_string(b) + " of the degree-" + std::to_string(deg) + " launch names a sweep of degree " +
+                   std::to_string(d.p_path);
+        const int lim = pieces ? d.n_path - deg : d.n_u;
         if (chunks[b].y < 0 || chunks[b].y >= lim)
             return "block " + std::to_string(b) + " starts at index " + std::to_string(chunks[b].y) + " of " +
                    std::to_string(lim);
@@ -98,7 +105,7 @@ std::vector<const KernelSig*> all_kernels()
 
 namespace sweep {
 
-BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool, bool, bool)
+BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool, bool, bool, bool)
 {
     BatchedKernels k{};
     k.profile = &stub::g_profile;
@@ -108,9 +115,10 @@ BatchedKernels batched_kernels(bool, bool, bool, bool, int, bool, bool, bool)
     for (int p = 1; p < 8; ++p) k.frame[p] = &stub::g_frame[p];
     for (int p = 1; p < 8; ++p) k.frame_long[p] = &stub::g_frame_long[p];
     for (int p = 1; p < 8; ++p) k.frame_wave[p] = &stub::g_frame_wave[p];
-    k.arc_pieces = &stub::g_arc_pieces;
+    k.arc_pieces[0] = k.arc_params[0] = nullptr;
+    for (int p = 1; p < 8; ++p) k.arc_pieces[p] = &stub::g_arc_pieces[p];
     k.arc_cumsum = &stub::g_arc_cumsum;
-    k.arc_params = &stub::g_arc_params;
+    for (int p = 1; p < 8; ++p) k.arc_params[p] = &stub::g_arc_params[p];
     k.surface = &stub::g_surface;
     return k;
 }

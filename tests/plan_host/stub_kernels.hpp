@@ -27,10 +27,11 @@ struct KernelSig {
 const KernelSig* lookup(const void* fn);
 // Every table entry (for comparing parameter counts with the kernel sources).
 std::vector<const KernelSig*> all_kernels();
-// For the arc-length kernels, which take a work list of (sweep, first
-// piece or u-sample) per block: whether the `grid` entries a launch reads
-// start inside their sweep; "" if so (or for other kernels), else what is
-// wrong.  Reads the stand-in's device memory (host memory).
+// For the arc-length kernels, which take a work list by path degree of
+// (sweep, first span index or u-sample) per block: whether the `grid`
+// entries a launch reads name sweeps of that degree and start inside the
+// sweep; "" if so (or for other kernels), else what is wrong.  Reads the
+// stand-in's device memory (host memory).
 std::string check_work_list(const void* fn, unsigned grid, const std::vector<std::vector<unsigned char>>& args);
 // Violations counted so far (printed when print is set); reset.
 int report(bool print);
