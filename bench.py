@@ -576,20 +576,21 @@ def adjoint_variant(steps: int):
             "error_vs_oracle": adj_err}
 
 
-def batch_graph_only(steps: int):
-    """The 4096-sweep batch's graph replays alone (for counter runs)."""
+def batch_graph_only(steps: int, **mode):
+    """The 4096-sweep batch's graph replays alone (for counter and trace
+    runs), in the plain mode or the given sampling mode."""
     import torch
     import synth
     from paper_1110_5450_amd import api
 
     b = api.Batch.from_specs(synth.c4())
-    ws = torch.empty(api.batched_workspace_size(b), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(api.batched_workspace_size(b, **mode), dtype=torch.uint8, device="cuda")
     pos = torch.empty(b.out_elems, dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pos)
     for _ in range(steps):
-        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws)
+        api.sweep_eval_batched(b, out=(pos, nrm), workspace=ws, **mode)
     torch.cuda.synchronize()
-    return {"vertices": b.n_vertices, "replays": steps, "tile_config": api.batched_config_for(b)}
+    return {"vertices": b.n_vertices, "replays": steps, "tile_config": api.batched_config_for(b), **mode}
 
 
 def adjoint_backward_only(steps: int):
@@ -667,7 +668,7 @@ def main():
     ap.add_argument("--variants-only", action="store_true",
                     help="run only the batched (4096 sweeps) and adjoint (256 sweeps) variants and print them")
     ap.add_argument("--variant", choices=["rational", "frenet_law", "arclength", "triangles", "batched", "adjoint",
-                                          "c1", "batch-graph", "adjoint-backward"],
+                                          "c1", "batch-graph", "batch-graph-arclength", "adjoint-backward"],
                     help="run only this variant and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy (3 launches) whose counter readings scale "
@@ -707,6 +708,7 @@ def main():
         fn = {"rational": rational_variant, "frenet_law": frenet_law_variant, "arclength": arclength_variant,
               "triangles": triangles_variant, "batched": batched_variants, "adjoint": adjoint_variant,
               "c1": lambda steps: c1_variant(), "batch-graph": batch_graph_only,
+              "batch-graph-arclength": lambda steps: batch_graph_only(steps, u_sampling="arclength"),
               "adjoint-backward": adjoint_backward_only}[args.variant]
         log(f"[bench] {args.variant} ...")
         print(json.dumps({args.variant: fn(args.steps)}), flush=True)

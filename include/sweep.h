@@ -132,8 +132,10 @@ typedef enum { SWEEP_FRAME_RMF = 0, SWEEP_FRAME_FRENET = 1 } sweep_frame_mode;
  * |C'| (1 + u_lambda kappa) in place of |C'| (kappa the path's curvature):
  * equal steps of arc length plus u_lambda times the tangent's turning angle,
  * so samples crowd where the path bends (u_lambda = 0 is arc length).
- * Supported by sweep_eval (not with a law) and sweep_frames; the batched and
- * adjoint entry points return SWEEP_ERR_UNSUPPORTED.
+ * Supported by sweep_eval (not with a law), sweep_frames and
+ * sweep_eval_batched (every sweep of the batch, FP64 frame, not with a frame
+ * mode or law); otherwise, and in the adjoint entry points, the call returns
+ * SWEEP_ERR_UNSUPPORTED.
  */
 typedef enum { SWEEP_U_PARAMETER = 0, SWEEP_U_ARCLENGTH = 1, SWEEP_U_ADAPTIVE = 2 } sweep_u_sampling;
 
