@@ -80,23 +80,40 @@ __device__ __forceinline__ void span_deriv_job(const DCurve& c, int k, int j, do
 {
     using S = SpanDeriv<P>;
     constexpr int D = S::kD;
+    // every job reads two knots U_a, U_b and forms one quotient (the lanes
+    // of a group take one pass instead of one per kind of job): e_t's
+    // factor p / (U_b - U_a), R_{r,i} = 1 / (U_b - U_a), or the knot U_b
+    int ia, ib, idx = 0;
+    double num;
     if (j < P) {
-        const double f = (double)P / (knot(c, k + j + 1) - knot(c, k - P + j + 1));
-        const V3<double> a = ctrl_pt(c, k - P + j), b = ctrl_pt(c, k - P + j + 1);
-        s[3 * j] = f * (b.x - a.x);
-        s[3 * j + 1] = f * (b.y - a.y);
-        s[3 * j + 2] = f * (b.z - a.z);
+        ia = k - P + j + 1;
+        ib = k + j + 1;
+        num = (double)P;
     } else if (j < P + S::kNR) {
-        const int idx = j - P;
+        idx = j - P;
         int i = 1;
 #pragma unroll
         for (int m = 2; m <= D; ++m)
             if (idx >= (m - 1) * m / 2) i = m;
         const int r = idx - (i - 1) * i / 2 + 1;
-        s[S::kR + idx] = 1.0 / (knot(c, k + i + 1 - r) - knot(c, k - D + i));
+        ia = k - D + i;
+        ib = k + i + 1 - r;
+        num = 1.0;
+    } else {
+        ia = ib = k - D + 1 + (j - P - S::kNR);
+        num = 0.0;
+    }
+    const double ua = knot(c, ia), ub = knot(c, ib);
+    const double f = num / (ub - ua);   // (a knot job's 0 / 0 is not used)
+    if (j < P) {
+        const V3<double> a = ctrl_pt(c, k - P + j), b = ctrl_pt(c, k - P + j + 1);
+        s[3 * j] = f * (b.x - a.x);
+        s[3 * j + 1] = f * (b.y - a.y);
+        s[3 * j + 2] = f * (b.z - a.z);
+    } else if (j < P + S::kNR) {
+        s[S::kR + idx] = f;
     } else if (j < S::kJobs) {
-        const int m = j - P - S::kNR;
-        s[S::kU + m] = knot(c, k - D + 1 + m);
+        s[S::kU + j - P - S::kNR] = ub;
     }
 }
 
@@ -108,28 +125,40 @@ __device__ __forceinline__ void span_deriv_job(const DCurve& c, int k, int j, do
 template <int P, bool ADAPT>
 __device__ __forceinline__ double span_speed(const double* __restrict__ s, double u, double lam)
 {
+    // component-wise with fused multiply-adds: the node values agree with
+    // the oracle's to rounding, not bitwise, either way
     using S = SpanDeriv<P>;
     constexpr int D = S::kD;
-    V3<double> e[P];
+    double ex[P], ey[P], ez[P];
 #pragma unroll
-    for (int t = 0; t < P; ++t) e[t] = mk(s[3 * t], s[3 * t + 1], s[3 * t + 2]);
-    V3<double> c2 = mk(0.0, 0.0, 0.0);
+    for (int t = 0; t < P; ++t) {
+        ex[t] = s[3 * t];
+        ey[t] = s[3 * t + 1];
+        ez[t] = s[3 * t + 2];
+    }
+    double c2x = 0.0, c2y = 0.0, c2z = 0.0;
 #pragma unroll
     for (int r = 1; r <= D; ++r) {
         if constexpr (ADAPT && D >= 1) {
-            if (r == D) c2 = ((double)D * s[S::kR + (D - 1) * D / 2 + D - 1]) * (e[D] - e[D - 1]);
+            if (r == D) {
+                const double f = (double)D * s[S::kR + (D - 1) * D / 2 + D - 1];
+                c2x = f * (ex[D] - ex[D - 1]);
+                c2y = f * (ey[D] - ey[D - 1]);
+                c2z = f * (ez[D] - ez[D - 1]);
+            }
         }
 #pragma unroll
         for (int i = D; i >= r; --i) {
             const double a = (u - s[S::kU + i - 1]) * s[S::kR + (i - 1) * i / 2 + r - 1];
-            e[i] = e[i - 1] + a * (e[i] - e[i - 1]);
+            ex[i] = fma(a, ex[i] - ex[i - 1], ex[i - 1]);
+            ey[i] = fma(a, ey[i] - ey[i - 1], ey[i - 1]);
+            ez[i] = fma(a, ez[i] - ez[i - 1], ez[i - 1]);
         }
     }
-    const V3<double> c1 = e[D];
-    const double sp = sqrt(dot(c1, c1));
+    const double sp = sqrt(fma(ex[D], ex[D], fma(ey[D], ey[D], ez[D] * ez[D])));
     if (!ADAPT) return sp;
-    const V3<double> cr = cross(c1, c2);
-    return sp + (sp > 0.0 ? lam * sqrt(dot(cr, cr)) / (sp * sp) : 0.0);
+    const double cx = ey[D] * c2z - ez[D] * c2y, cy = ez[D] * c2x - ex[D] * c2z, cz = ex[D] * c2y - ey[D] * c2x;
+    return sp + (sp > 0.0 ? lam * sqrt(fma(cx, cx, fma(cy, cy, cz * cz))) / (sp * sp) : 0.0);
 }
 
 // Piece q = (k - p) * kArcSub + m of span k: its bounds.
