@@ -333,6 +333,7 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
                                           double* __restrict__ gs, double* __restrict__ su, int* __restrict__ ss)
 {
     double u;
+    int ks = -1;   // the span of the piece holding u (interior samples)
     if (i == 0) {
         u = knot(c, c.p);
     } else if (i == ns - 1) {
@@ -359,6 +360,7 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
         double plo, phi;
         piece_bounds(c, q, k, plo, phi);
         while (q > 0 && !(phi > plo)) piece_bounds(c, --q, k, plo, phi);
+        ks = k;
         const double len = cum[q + 1] - cum[q];
         u = len > 0.0 ? plo + (target - cum[q]) / len * (phi - plo) : plo;
         double blo = plo, bhi = phi;
@@ -397,7 +399,9 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
     }
     if (l == 0) {
         su[i] = u;
-        ss[i] = span_of(c, u);
+        // u stays in its piece, so in [U_ks, U_{ks+1}]: the standard rule
+        // gives ks unless u is the span's end
+        ss[i] = ks >= 0 && u < knot(c, ks + 1) ? ks : span_of(c, u);
     }
 }
 
