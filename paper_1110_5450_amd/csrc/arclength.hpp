@@ -61,17 +61,22 @@ static __device__ const double kGlEnd[8] = {-0.032020422845832404, 0.11217721020
 // the control points of C' that act on the span; the reciprocals
 //   R_{r,i} = 1 / (U_{k+i+1-r} - U_{k-d+i}),  1 <= r <= i <= d,
 // of the denominators of level r of the recursion; and the knots U_{k-d+i},
-// i = 1..d.  Each of the p + d(d+1)/2 + d values is one job, so that a group
-// of lanes forms them together.  Every denominator spans an interval that
-// contains the non-empty span [U_k, U_{k+1}), so none vanishes.
+// i = 0..d+1 (U_k and U_{k+1} among them).  Each of the p + d(d+1)/2 + d + 2
+// values is one job, so that a group of lanes forms them together.  Every
+// denominator spans an interval that contains the span [U_k, U_{k+1}), so
+// none vanishes on a non-empty span (an empty span's quotients are not
+// used).
 template <int P>
 struct SpanDeriv {
     static constexpr int kD = P - 1;
     static constexpr int kNR = kD * (kD + 1) / 2;
     static constexpr int kR = 3 * P;           // R_{r,i} at kR + (i-1) i / 2 + r - 1
-    static constexpr int kU = kR + kNR;        // U_{k-d+i} at kU + i - 1
-    static constexpr int kJobs = P + kNR + kD;
-    static constexpr int kDoubles = kU + kD;
+    static constexpr int kU = kR + kNR;        // U_{k-d+i} at kU + i, i = 0..d+1
+    // the jobs in this order: e_t, R_{r,i}, the knots of i = 1..d (all
+    // that the evaluation needs: the first kJobsEval), then U_{k+1}, U_{k-d}
+    static constexpr int kJobsEval = P + kNR + kD;
+    static constexpr int kJobs = kJobsEval + 2;
+    static constexpr int kDoubles = kU + kD + 2;
 };
 constexpr int kArcSetupMax = SpanDeriv<SWEEP_MAX_DEGREE>::kDoubles;
 
@@ -100,7 +105,9 @@ __device__ __forceinline__ void span_deriv_job(const DCurve& c, int k, int j, do
         ib = k + i + 1 - r;
         num = 1.0;
     } else {
-        ia = ib = k - D + 1 + (j - P - S::kNR);
+        const int m = j - P - S::kNR;
+        idx = m < D ? m + 1 : (m == D ? D + 1 : 0);   // knot U_{k-d+idx}
+        ia = ib = k - D + idx;
         num = 0.0;
     }
     const double ua = knot(c, ia), ub = knot(c, ib);
@@ -113,7 +120,7 @@ __device__ __forceinline__ void span_deriv_job(const DCurve& c, int k, int j, do
     } else if (j < P + S::kNR) {
         s[S::kR + idx] = f;
     } else if (j < S::kJobs) {
-        s[S::kU + j - P - S::kNR] = ub;
+        s[S::kU + idx] = ub;
     }
 }
 
@@ -149,7 +156,7 @@ __device__ __forceinline__ double span_speed(const double* __restrict__ s, doubl
         }
 #pragma unroll
         for (int i = D; i >= r; --i) {
-            const double a = (u - s[S::kU + i - 1]) * s[S::kR + (i - 1) * i / 2 + r - 1];
+            const double a = (u - s[S::kU + i]) * s[S::kR + (i - 1) * i / 2 + r - 1];
             ex[i] = fma(a, ex[i] - ex[i - 1], ex[i - 1]);
             ey[i] = fma(a, ey[i] - ey[i - 1], ey[i - 1]);
             ez[i] = fma(a, ez[i] - ez[i - 1], ez[i - 1]);
@@ -183,18 +190,26 @@ __device__ __forceinline__ void arc_span(const DCurve& c, int si, int lane, doub
                                          double* __restrict__ len)
 {
     static_assert(2 * kArcSub == 64, "two lanes per piece fill a wave");
+    using S = SpanDeriv<P>;
     const int k = c.p + si, m = lane >> 1;
-    const double Uk = knot(c, k), Uk1 = knot(c, k + 1), w = Uk1 - Uk;
+    double Uk, Uk1;
+    if (!RAT) {
+        // the set-up first: U_k and U_{k+1} are two of its jobs
+        if (lane < S::kJobs) span_deriv_job<P>(c, k, lane, s);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Uk = s[S::kU + S::kD];
+        Uk1 = s[S::kU + S::kD + 1];
+    } else {
+        Uk = knot(c, k);
+        Uk1 = knot(c, k + 1);
+    }
+    const double w = Uk1 - Uk;
     double* out = len + (long long)si * kArcSub;
     if (!(w > 0.0)) {
         if (lane < kArcSub) out[lane] = 0.0;
         return;
-    }
-    if (!RAT) {
-        if (lane < SpanDeriv<P>::kJobs) span_deriv_job<P>(c, k, lane, s);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // the piece's bounds as piece_bounds forms them
     const double lo = Uk + w * ((double)m / kArcSub);
@@ -366,7 +381,7 @@ __device__ __forceinline__ void arc_param(const DCurve& c, int i, int l, int ns,
         double blo = plo, bhi = phi;
         const double xl = kGlX[l], wl = kGlW[l];
         if (!RAT) {
-            for (int j = l; j < SpanDeriv<P>::kJobs; j += kArcLanes) span_deriv_job<P>(c, k, j, gs);
+            for (int j = l; j < SpanDeriv<P>::kJobsEval; j += kArcLanes) span_deriv_job<P>(c, k, j, gs);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
