@@ -456,7 +456,6 @@ static sweep_status build_plan(const sweep_batch* b, const sweep_options* o, boo
     const bool arc = o->u_sampling != SWEEP_U_PARAMETER;
     auto fkind = [&](int k) -> int {
         if (b->n_u[k] <= kWaveMaxU) return Plan::kWaveFrame;
-        if (arc) return Plan::kWalkFrame;   // the one-block kernel has no sample tables
         if (b->n_u[k] <= kBlock * kMaxRun && lds_path_doubles(b->path_n[k], b->path_degree[k], rat) <= kLdsPathDoubles)
             return Plan::kBlockFrame;
         return Plan::kWalkFrame;

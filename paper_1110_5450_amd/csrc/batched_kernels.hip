@@ -148,7 +148,7 @@ __device__ __forceinline__ void walk_rows(const C& path, const DCurve& gpath, co
 // degree P: one block per sweep, one chunk.  The path is staged in LDS
 // (knots, control points, weights, per-span reciprocals; kLdsPathDoubles of
 // dynamic LDS): knot span changes read LDS only.
-template <int P, class F, class T, bool EXT>
+template <int P, class F, class T, bool EXT, bool ARC>
 __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__ descs,
                                                    const int* __restrict__ sweeps,
                                                    const double* __restrict__ path_ctrl,
@@ -161,8 +161,12 @@ __global__ __launch_bounds__(kBlock) void kb_frame(const BatchDesc* __restrict__
     __shared__ double lt0[3];
     extern __shared__ double lds_path[];   // kLdsPathDoubles
     const BatchDesc d = descs[sweeps[blockIdx.x]];
-    const DCurve gpath = path_of(d, path_ctrl, path_w, knots);
-    const LdsCurve path = stage_path<P>(gpath, lds_path);
+    DCurve gpath = path_of(d, path_ctrl, path_w, knots);
+    LdsCurve path = stage_path<P>(gpath, lds_path);
+    if constexpr (ARC) {   // arc-length samples: parameters and spans from the sweep's tables
+        gpath.su = path.su = fx.su + d.row_off;
+        gpath.ss = path.ss = fx.ss + d.row_off;
+    }
     const int n_u = d.n_u;
     const int K = batch_run_length(n_u);
     RunInfo<P, F> R;
@@ -370,14 +374,14 @@ static const void* surface_pick(bool nrm, bool nt, int K)
 }
 
 // Frame kernels of a frame precision, output precision, record kind and
-// sampling (arc-length sweeps take the one-wave and chunk-walking kernels
-// only: the one-block kernel's staged path has no sample table).
+// sampling (ARC: the sweeps' sample parameters and spans come from the
+// arc-length tables).
 template <class F, class T, bool EXT, bool ARC>
 static void pick_frames(BatchedKernels& k)
 {
     k.frame[0] = k.frame_long[0] = k.frame_wave[0] = nullptr;
 #define SWEEP_DEG(P)                                                                  \
-    k.frame[P] = ARC ? nullptr : (const void*)&kb_frame<P, F, T, EXT>;               \
+    k.frame[P] = (const void*)&kb_frame<P, F, T, EXT, ARC>;                          \
     k.frame_long[P] = (const void*)&kb_frame_long<P, F, T, EXT, ARC>;                \
     k.frame_wave[P] = (const void*)&kb_frame_wave<P, F, T, EXT, ARC>;
     SWEEP_DEG(1) SWEEP_DEG(2) SWEEP_DEG(3) SWEEP_DEG(4) SWEEP_DEG(5) SWEEP_DEG(6) SWEEP_DEG(7)

@@ -41,7 +41,7 @@ struct LdsCurve {
     const double* RT;
     int n, p, closed, nb;
     bool rat, given_knots;
-    const double* su;     // never set: arc-length sampling is single-sweep only
+    const double* su;     // arc-length samples (set by the caller), or nullptr
     const int* ss;
 };
 __device__ __forceinline__ bool is_rational(const DCurve& c) { return c.w != nullptr; }
